@@ -1,0 +1,136 @@
+/*
+ * nnls.h -- C ABI of the MI355X (gfx950) anti-lopsided NNLS library (libnnls.so).
+ *
+ * The method (Nguyen & Ho, "Anti-lopsided Algorithm for Large-scale Non-negative Least
+ * Squares", arXiv 1502.01645):
+ *   Problem (1)   minimise 1/2 ||A x - b||^2 subject to x >= 0, A in R^{d x n}.
+ *   Problem (2)   the same as f(x) = 1/2 x^T H x + h^T x with H = A^T A, h = -A^T b.
+ *   Algorithm 1   rescale to Problem (5): Q_ij = H_ij / sqrt(H_ii H_jj), q_i = h_i / sqrt(H_ii),
+ *                 solve for y, return x = y / sqrt(diag H) (rescaling (4)); H_ii = 0 keeps x_i = y_i.
+ *   Algorithm 2   from y = 0 with gradient q: passive set P = {y_i > 0 or grad_i < 0}, masked
+ *                 gradient gbar, exact step alpha = ||gbar||^2 / gbar^T Q gbar, projected update
+ *                 y <- [y - alpha gbar]_+, incremental gradient grad += Q (y_new - y).
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments are DEVICE pointers owned by the caller; the library keeps no pointer after
+ *     a call returns (a batched plan keeps the pointers it was created with, see below).
+ *   - Matrices are row-major.  A is [d, n] with leading dimension lda >= n; B is [d, k] with
+ *     ldb >= k; Q is [n, n]; q, Y0 and X are [n, k] (leading dimension k).
+ *   - Every call is asynchronous and ordered on `stream` (a hipStream_t; NULL = the null stream).
+ *     No call synchronises the device or allocates device memory: scratch space comes from the
+ *     caller's workspace `ws` of `ws_bytes` bytes, sized by nnls_workspace_bytes().
+ *   - Arguments are validated on the host before any HIP call.  The return value is a
+ *     nnls_error code; NNLS_OK means the work was enqueued.  Per-column outcomes of a solve are
+ *     written on the device as nnls_col_status values.
+ *   - Calls that share a workspace must not overlap; distinct workspaces make calls independent.
+ */
+#ifndef NNLS_H
+#define NNLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Host-side return codes. */
+enum nnls_error {
+    NNLS_OK = 0,
+    NNLS_E_ARG = -1,         /* a size, pointer, leading dimension or mode is invalid */
+    NNLS_E_WORKSPACE = -2,   /* ws_bytes is smaller than nnls_workspace_bytes() */
+    NNLS_E_HIP = -3,         /* a HIP runtime call failed (see nnls_last_hip_error) */
+    NNLS_E_UNSUPPORTED = -4  /* valid arguments this build does not handle (e.g. n too large) */
+};
+
+/* Per-column outcome of a solve, written to the device array `status`. */
+enum nnls_col_status {
+    NNLS_CONVERGED = 0,  /* relative KKT residual <= tol, or empty passive set */
+    NNLS_MAXITER = 1,    /* max_iter updates done without meeting tol */
+    NNLS_BREAKDOWN = 2,  /* line-search denominator gbar^T Q gbar not positive and finite */
+    NNLS_NONFINITE = 3,  /* NaN or Inf in the inputs or the iterate */
+    NNLS_FELL_BACK = 4   /* warm start rejected (it raised the objective); solved from y = 0 */
+};
+
+/* Arithmetic of the Gram product H = A^T A, h = -A^T B. */
+enum nnls_gram_mode {
+    NNLS_GRAM_FP64 = 0,   /* FP64 inputs, FP64 products (for dtype NNLS_F64) */
+    NNLS_GRAM_FP32 = 1,   /* FP32 inputs, plain FP32 fused multiply-adds (accuracy cross-check) */
+    NNLS_GRAM_BF16X3 = 2  /* FP32 inputs split as hi + lo bfloat16; hi*hi + hi*lo + lo*hi on the
+                             matrix cores with FP32 accumulation */
+};
+
+/* Element type of A, B, Q, q, Y0 and X. */
+enum nnls_dtype { NNLS_F32 = 0, NNLS_F64 = 1 };
+
+/* Operations for nnls_workspace_bytes. */
+enum nnls_op { NNLS_OP_PREPARE = 0, NNLS_OP_SOLVE = 1, NNLS_OP_REFINE = 2 };
+
+/* Bytes of device workspace that operation `op` needs for the given shape, mode and dtype
+ * (0 if it needs none).  Pure host function. */
+size_t nnls_workspace_bytes(int op, int64_t d, int64_t n, int64_t k, int mode, int dtype);
+
+/*
+ * nnls_prepare -- Algorithm 1 up to the call of the solver: the Gram product of Problem (2)
+ * and the rescaling to Problem (5).
+ *
+ *   d, n, k   rows of A, unknowns, right-hand sides (d >= 1, n >= 1, k >= 0)
+ *   A         [d, n] (lda >= n), element type `dtype`
+ *   B         [d, k] (ldb >= k); may be NULL when k == 0
+ *   mode      nnls_gram_mode; NNLS_F64 requires NNLS_GRAM_FP64, NNLS_F32 requires FP32/BF16X3
+ *   Q         out [n, n]: Q_ij = H_ij / (s_i s_j), Q_ii = 1 where H_ii > 0 (the Remark of
+ *             Section 3), row and column i zero where H_ii = 0
+ *   q         out [n, k]: q_ic = -(A^T B)_ic / s_i
+ *   s         out [n] FP64: s_i = ||A_i||_2 computed in FP64 from the stored entries of A,
+ *             or 1 where the column is zero
+ * Element type of Q and q is `dtype`.
+ */
+int nnls_prepare(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
+                 int64_t ldb, int mode, int dtype, void* Q, void* q, double* s, void* ws,
+                 size_t ws_bytes, void* stream);
+
+/*
+ * nnls_solve -- Algorithm 2 on every column of q (they share Q), then x = y / s (rescaling (4)).
+ *
+ *   n, k      unknowns and right-hand sides (k >= 1)
+ *   Q, q      the rescaled problem (as written by nnls_prepare, or any symmetric Q)
+ *   s         [n] FP64 scales for the unscale step, or NULL to return y itself
+ *   tol       stop when r(y) = ||min(y, Qy + q)||_2 / ||q||_2 <= tol (||q|| = 0: unnormalised);
+ *             the test runs on a freshly recomputed gradient before a column is accepted
+ *   max_iter  cap on updates per column; 0 means 5 n
+ *   Y0        [n, k] start in the rescaled variables, or NULL for y = 0 (negative entries are
+ *             clipped to 0)
+ *   X         out [n, k]: x = y / s
+ *   iters     out [k] int32 updates done; kkt out [k] FP64 r(y) of the returned iterate in the
+ *             arithmetic of the solve; status out [k] int32 nnls_col_status
+ */
+int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, const double* s,
+               double tol, int32_t max_iter, const void* Y0, void* X, int32_t* iters,
+               double* kkt, int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * nnls_refine -- FP64 check and one refinement step against the ORIGINAL data (A, B).
+ * For every column: r = A x - b and grad = A^T r in FP64; in the rescaled variables one masked
+ * exact-line-search projected step of Algorithm 2 (the step length from ||A (gbar ./ s)||^2 in
+ * FP64); the step is kept only if it lowers 1/2 ||A x - b||^2.  Writes back X (FP32 or FP64 as
+ * `dtype`) and, for the returned x:
+ *   kkt64 out [k]  relative KKT residual ||min(s .* x, grad ./ s)|| / ||A^T b ./ s|| in FP64,
+ *                  with s the FP64 column norms of A (the rescaled-space residual of y = s .* x)
+ *   obj64 out [k]  1/2 ||A x - b||^2 in FP64
+ * A, B, X have element type `dtype`.
+ */
+int nnls_refine(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
+                int64_t ldb, int dtype, void* X, double* kkt64, double* obj64, void* ws,
+                size_t ws_bytes, void* stream);
+
+/* Text of the last HIP error seen by this thread (empty if none). */
+const char* nnls_last_hip_error(void);
+
+/* Library version string. */
+const char* nnls_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNLS_H */

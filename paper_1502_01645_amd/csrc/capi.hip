@@ -1,0 +1,139 @@
+// C ABI of libnnls: argument validation, workspace sizing and dispatch to the HIP kernels.
+// Every check runs on the host before the first HIP call, so argument errors never touch the
+// device.
+#include <math.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/nnls.h"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_hip_error;
+
+int hip_fail(hipError_t e) {
+  g_last_hip_error = hipGetErrorString(e);
+  return NNLS_E_HIP;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Largest LDS the one-workgroup-per-column solver may request on gfx950 (160 KiB per CU).
+constexpr size_t kMaxLds = 160 * 1024;
+
+bool valid_dtype(int dt) { return dt == NNLS_F32 || dt == NNLS_F64; }
+size_t elem_size(int dt) { return dt == NNLS_F64 ? 8 : 4; }
+
+size_t prepare_ws(int64_t d, int64_t n, int64_t k, int mode) {
+  size_t a = nnls::colnorm_ws_bytes(d, n);
+  size_t b = mode == NNLS_GRAM_BF16X3 ? nnls::gram_bf16x3_ws_bytes(d, n, k) : 0;
+  return align_up(a > b ? a : b);
+}
+
+size_t solve_ws(int64_t n, int64_t k, int dt) { return align_up(elem_size(dt) * 3 * n * k); }
+
+}  // namespace
+
+extern "C" {
+
+const char* nnls_last_hip_error(void) { return g_last_hip_error.c_str(); }
+
+const char* nnls_version(void) { return "nnls-mi355x 0.1 (gfx950)"; }
+
+size_t nnls_workspace_bytes(int op, int64_t d, int64_t n, int64_t k, int mode, int dtype) {
+  if (n < 1 || k < 0 || !valid_dtype(dtype)) return 0;
+  switch (op) {
+    case NNLS_OP_PREPARE:
+      if (d < 1) return 0;
+      return prepare_ws(d, n, k, mode);
+    case NNLS_OP_SOLVE:
+      return k < 1 ? 0 : solve_ws(n, k, dtype);
+    case NNLS_OP_REFINE:
+      return (d < 1 || k < 1) ? 0 : align_up(nnls::refine_ws_bytes(d, n, k));
+    default:
+      return 0;
+  }
+}
+
+int nnls_prepare(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
+                 int64_t ldb, int mode, int dtype, void* Q, void* q, double* s, void* ws,
+                 size_t ws_bytes, void* stream) {
+  if (d < 1 || n < 1 || k < 0) return NNLS_E_ARG;
+  if (!valid_dtype(dtype)) return NNLS_E_ARG;
+  if (dtype == NNLS_F64 && mode != NNLS_GRAM_FP64) return NNLS_E_ARG;
+  if (dtype == NNLS_F32 && mode != NNLS_GRAM_FP32 && mode != NNLS_GRAM_BF16X3) return NNLS_E_ARG;
+  if (!A || !Q || !s || lda < n) return NNLS_E_ARG;
+  if (k > 0 && (!B || !q || ldb < k)) return NNLS_E_ARG;
+  if (n > (int64_t)1 << 30 || d > ((int64_t)1 << 40) / (n > 0 ? n : 1)) return NNLS_E_UNSUPPORTED;
+  const size_t need = prepare_ws(d, n, k, mode);
+  if (ws_bytes < need || (need > 0 && !ws)) return NNLS_E_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (dtype == NNLS_F64) {
+    e = nnls::launch_colnorm<double>(d, n, (const double*)A, lda, s, (double*)ws, st);
+    if (e != hipSuccess) return hip_fail(e);
+    e = nnls::launch_gram_fma<double>(d, n, k, (const double*)A, lda, (const double*)B, ldb, s,
+                                      (double*)Q, (double*)q, st);
+  } else {
+    e = nnls::launch_colnorm<float>(d, n, (const float*)A, lda, s, (double*)ws, st);
+    if (e != hipSuccess) return hip_fail(e);
+    if (mode == NNLS_GRAM_BF16X3)
+      e = nnls::launch_gram_bf16x3(d, n, k, (const float*)A, lda, (const float*)B, ldb, s,
+                                   (float*)Q, (float*)q, (float*)ws, st);
+    else
+      e = nnls::launch_gram_fma<float>(d, n, k, (const float*)A, lda, (const float*)B, ldb, s,
+                                       (float*)Q, (float*)q, st);
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  return NNLS_OK;
+}
+
+int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, const double* s,
+               double tol, int32_t max_iter, const void* Y0, void* X, int32_t* iters,
+               double* kkt, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  if (n < 1 || k < 1 || !valid_dtype(dtype)) return NNLS_E_ARG;
+  if (!Q || !q || !X || !iters || !kkt || !status) return NNLS_E_ARG;
+  if (!(tol >= 0.0) || !isfinite(tol) || max_iter < 0) return NNLS_E_ARG;
+  if (n > (int64_t)1 << 30 || k > (int64_t)1 << 31) return NNLS_E_UNSUPPORTED;
+  if (nnls::solve_wg_lds_bytes(n, (int)elem_size(dtype)) > kMaxLds) return NNLS_E_UNSUPPORTED;
+  const size_t need = solve_ws(n, k, dtype);
+  if (ws_bytes < need || !ws) return NNLS_E_WORKSPACE;
+  const int mi = max_iter == 0 ? (int)(5 * n < (1 << 30) ? 5 * n : (1 << 30)) : max_iter;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (dtype == NNLS_F64)
+    e = nnls::launch_solve_wg<double>(n, k, (const double*)Q, (const double*)q, s, tol, mi,
+                                      (const double*)Y0, (double*)X, iters, kkt, status,
+                                      (double*)ws, st);
+  else
+    e = nnls::launch_solve_wg<float>(n, k, (const float*)Q, (const float*)q, s, tol, mi,
+                                     (const float*)Y0, (float*)X, iters, kkt, status, (float*)ws,
+                                     st);
+  if (e != hipSuccess) return hip_fail(e);
+  return NNLS_OK;
+}
+
+int nnls_refine(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
+                int64_t ldb, int dtype, void* X, double* kkt64, double* obj64, void* ws,
+                size_t ws_bytes, void* stream) {
+  if (d < 1 || n < 1 || k < 1 || !valid_dtype(dtype)) return NNLS_E_ARG;
+  if (!A || !B || !X || !kkt64 || !obj64 || lda < n || ldb < k) return NNLS_E_ARG;
+  if (n > (int64_t)1 << 30 || k > (int64_t)1 << 31) return NNLS_E_UNSUPPORTED;
+  const size_t need = align_up(nnls::refine_ws_bytes(d, n, k));
+  if (ws_bytes < need || !ws) return NNLS_E_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (dtype == NNLS_F64)
+    e = nnls::launch_refine<double>(d, n, k, (const double*)A, lda, (const double*)B, ldb,
+                                    (double*)X, kkt64, obj64, ws, st);
+  else
+    e = nnls::launch_refine<float>(d, n, k, (const float*)A, lda, (const float*)B, ldb,
+                                   (float*)X, kkt64, obj64, ws, st);
+  if (e != hipSuccess) return hip_fail(e);
+  return NNLS_OK;
+}
+
+}  // extern "C"

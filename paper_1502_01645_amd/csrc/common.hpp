@@ -1,0 +1,98 @@
+// Device helpers shared by the NNLS kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nnls {
+
+constexpr int kWave = 64;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Round-to-nearest-even FP32 -> BF16 bits.  NaN and Inf map to NaN and Inf.
+__device__ __forceinline__ uint32_t bf16_bits_rne(float x) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  uint32_t lsb = (u >> 16) & 1u;
+  return (u + 0x7FFFu + lsb) >> 16;
+}
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint32_t b) {
+  return __builtin_bit_cast(float, b << 16);
+}
+
+// Split x = hi + lo + O(2^-16 |x|) with hi, lo bfloat16 (hi = RNE(x), lo = RNE(x - hi)).
+__device__ __forceinline__ void split_bf16(float x, uint32_t& hi, uint32_t& lo) {
+  hi = bf16_bits_rne(x);
+  float r = x - bf16_bits_to_f32(hi);
+  lo = bf16_bits_rne(r);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    T o = __shfl_xor(v, off, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// Sum over the block; every thread gets the result.  `red` is LDS scratch of >= nwaves entries.
+// Contains two barriers.
+template <typename T, int NT>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+  constexpr int NW = NT / kWave;
+  v = wave_sum(v);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  T t = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+// Exclusive prefix sum of one int per thread over the block, in thread order; `total` gets the
+// block total.  `red` is LDS scratch of >= nwaves ints.  Two barriers.
+template <int NT>
+__device__ __forceinline__ int block_exclusive_scan(int v, int* red, int& total) {
+  constexpr int NW = NT / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  int incl = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    int o = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl += o;
+  }
+  if (lane == kWave - 1) red[w] = incl;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    int r = red[i];
+    base += (i < w) ? r : 0;
+    tot += r;
+  }
+  __syncthreads();
+  total = tot;
+  return base + incl - v;
+}
+
+__device__ __forceinline__ bool is_finite_val(float v) { return __builtin_isfinite(v); }
+__device__ __forceinline__ bool is_finite_val(double v) { return __builtin_isfinite(v); }
+
+}  // namespace nnls

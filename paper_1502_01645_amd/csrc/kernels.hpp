@@ -1,0 +1,44 @@
+// Internal launchers of the NNLS kernels (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace nnls {
+
+constexpr int NNLS_CONVERGED_DEV = 0;
+constexpr int NNLS_MAXITER_DEV = 1;
+constexpr int NNLS_BREAKDOWN_DEV = 2;
+constexpr int NNLS_NONFINITE_DEV = 3;
+constexpr int NNLS_FELL_BACK_DEV = 4;
+
+// gram.hip
+size_t colnorm_ws_bytes(int64_t d, int64_t n);
+template <typename T>
+hipError_t launch_colnorm(int64_t d, int64_t n, const T* A, int64_t lda, double* s, double* ws,
+                          hipStream_t st);
+int gram_bf16x3_splits(int64_t d, int64_t n, int64_t k);
+size_t gram_bf16x3_ws_bytes(int64_t d, int64_t n, int64_t k);
+hipError_t launch_gram_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
+                              const float* B, int64_t ldb, const double* s, float* Q, float* q,
+                              float* ws, hipStream_t st);
+template <typename T>
+hipError_t launch_gram_fma(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda, const T* B,
+                           int64_t ldb, const double* s, T* Q, T* q, hipStream_t st);
+
+// solve_wg.hip
+size_t solve_wg_lds_bytes(int64_t n, int elem);
+template <typename T>
+hipError_t launch_solve_wg(int64_t n, int64_t k, const T* Q, const T* q, const double* s,
+                           double tol, int max_iter, const T* Y0, T* X, int32_t* iters,
+                           double* kkt, int32_t* status, T* ws, hipStream_t st);
+
+// refine.hip
+size_t refine_ws_bytes(int64_t d, int64_t n, int64_t k);
+template <typename T>
+hipError_t launch_refine(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda, const T* B,
+                         int64_t ldb, T* X, double* kkt64, double* obj64, void* ws,
+                         hipStream_t st);
+
+}  // namespace nnls

@@ -1,0 +1,190 @@
+"""Thin Python binding of libnnls (include/nnls.h): argument marshalling only.
+
+Tensors are PyTorch device tensors; their data pointers and torch's current HIP stream are
+handed to the C ABI unchanged.  Every step of the method runs in the library's HIP kernels;
+there is no fallback: if libnnls.so is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnnls.so")
+
+# enums of nnls.h
+OK, E_ARG, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4
+CONVERGED, MAXITER, BREAKDOWN, NONFINITE, FELL_BACK = 0, 1, 2, 3, 4
+GRAM_FP64, GRAM_FP32, GRAM_BF16X3 = 0, 1, 2
+F32, F64 = 0, 1
+OP_PREPARE, OP_SOLVE, OP_REFINE = 0, 1, 2
+
+_ERRORS = {E_ARG: "invalid argument", E_WORKSPACE: "workspace too small",
+           E_HIP: "HIP runtime error", E_UNSUPPORTED: "unsupported shape"}
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_sz = ctypes.c_size_t
+
+
+class NNLSError(RuntimeError):
+    pass
+
+
+def lib():
+    """The loaded libnnls.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise NNLSError(f"libnnls.so not built at {LIB_PATH}; run paper_1502_01645_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        L.nnls_workspace_bytes.argtypes = [ctypes.c_int, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int]
+        L.nnls_workspace_bytes.restype = _sz
+        L.nnls_prepare.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, ctypes.c_int,
+                                   _vp, _vp, _vp, _vp, _sz, _vp]
+        L.nnls_prepare.restype = ctypes.c_int
+        L.nnls_solve.argtypes = [_i64, _i64, ctypes.c_int, _vp, _vp, _vp, ctypes.c_double, _i32, _vp,
+                                 _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.nnls_solve.restype = ctypes.c_int
+        L.nnls_refine.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _vp, _vp, _vp,
+                                  _vp, _sz, _vp]
+        L.nnls_refine.restype = ctypes.c_int
+        L.nnls_last_hip_error.argtypes = []
+        L.nnls_last_hip_error.restype = ctypes.c_char_p
+        L.nnls_version.argtypes = []
+        L.nnls_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        msg = _ERRORS.get(rc, f"error {rc}")
+        if rc == E_HIP:
+            msg += ": " + lib().nnls_last_hip_error().decode()
+        raise NNLSError(f"{what}: {msg}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise NNLSError(f"unsupported dtype {t.dtype}")
+
+
+def workspace_bytes(op: int, d: int, n: int, k: int, mode: int, dtype: int) -> int:
+    return int(lib().nnls_workspace_bytes(op, d, n, k, mode, dtype))
+
+
+def _workspace(nbytes: int, device, ws=None):
+    if nbytes == 0:
+        return None
+    if ws is not None and ws.numel() >= nbytes:
+        return ws
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def prepare(A: torch.Tensor, B: torch.Tensor | None = None, mode: int | None = None, out=None,
+            ws=None):
+    """Gram product and rescale (Algorithm 1).  Returns (Q, q, s)."""
+    assert A.dim() == 2 and A.stride(1) == 1
+    d, n = A.shape
+    dt = _dtype_code(A)
+    if mode is None:
+        mode = GRAM_FP64 if dt == F64 else GRAM_BF16X3
+    if B is not None:
+        if B.dim() == 1:
+            B = B.reshape(d, 1)
+        assert B.shape[0] == d and B.stride(1) == 1 and B.dtype == A.dtype
+        k = B.shape[1]
+    else:
+        k = 0
+    if out is None:
+        Q = torch.empty((n, n), dtype=A.dtype, device=A.device)
+        q = torch.empty((n, max(k, 1)), dtype=A.dtype, device=A.device)[:, :k]
+        s = torch.empty(n, dtype=torch.float64, device=A.device)
+    else:
+        Q, q, s = out
+    wsb = workspace_bytes(OP_PREPARE, d, n, k, mode, dt)
+    ws = _workspace(wsb, A.device, ws)
+    rc = lib().nnls_prepare(d, n, k, _ptr(A), A.stride(0), _ptr(B), B.stride(0) if B is not None else 0,
+                            mode, dt, _ptr(Q), _ptr(q) if k > 0 else None, _ptr(s), _ptr(ws), wsb,
+                            _stream(A.device))
+    _check(rc, "nnls_prepare")
+    return Q, q, s
+
+
+def solve(Q: torch.Tensor, q: torch.Tensor, s: torch.Tensor | None = None, tol: float = 1e-5,
+          max_iter: int = 0, Y0: torch.Tensor | None = None, out=None, ws=None):
+    """Algorithm 2 on every column of q, then x = y / s.  Returns (X, iters, kkt, status)."""
+    n = Q.shape[0]
+    if q.dim() == 1:
+        q = q.reshape(n, 1)
+    k = q.shape[1]
+    dt = _dtype_code(Q)
+    assert Q.is_contiguous() and q.is_contiguous() and q.dtype == Q.dtype
+    if Y0 is not None:
+        Y0 = Y0.reshape(n, k)
+        assert Y0.is_contiguous() and Y0.dtype == Q.dtype
+    if out is None:
+        X = torch.empty((n, k), dtype=Q.dtype, device=Q.device)
+        iters = torch.empty(k, dtype=torch.int32, device=Q.device)
+        kkt = torch.empty(k, dtype=torch.float64, device=Q.device)
+        status = torch.empty(k, dtype=torch.int32, device=Q.device)
+    else:
+        X, iters, kkt, status = out
+    wsb = workspace_bytes(OP_SOLVE, 0, n, k, 0, dt)
+    ws = _workspace(wsb, Q.device, ws)
+    rc = lib().nnls_solve(n, k, dt, _ptr(Q), _ptr(q), _ptr(s), float(tol), int(max_iter), _ptr(Y0),
+                          _ptr(X), _ptr(iters), _ptr(kkt), _ptr(status), _ptr(ws), wsb,
+                          _stream(Q.device))
+    _check(rc, "nnls_solve")
+    return X, iters, kkt, status
+
+
+def refine(A: torch.Tensor, B: torch.Tensor, X: torch.Tensor, out=None, ws=None):
+    """FP64 check + one refinement step against (A, B); X is updated in place.
+    Returns (kkt64, obj64)."""
+    d, n = A.shape
+    if B.dim() == 1:
+        B = B.reshape(d, 1)
+    k = B.shape[1]
+    dt = _dtype_code(A)
+    assert X.shape == (n, k) and X.is_contiguous() and X.dtype == A.dtype
+    if out is None:
+        kkt64 = torch.empty(k, dtype=torch.float64, device=A.device)
+        obj64 = torch.empty(k, dtype=torch.float64, device=A.device)
+    else:
+        kkt64, obj64 = out
+    wsb = workspace_bytes(OP_REFINE, d, n, k, 0, dt)
+    ws = _workspace(wsb, A.device, ws)
+    rc = lib().nnls_refine(d, n, k, _ptr(A), A.stride(0), _ptr(B), B.stride(0), dt, _ptr(X),
+                           _ptr(kkt64), _ptr(obj64), _ptr(ws), wsb, _stream(A.device))
+    _check(rc, "nnls_refine")
+    return kkt64, obj64
+
+
+def nnls(A: torch.Tensor, B: torch.Tensor, tol: float = 1e-5, max_iter: int = 0,
+         mode: int | None = None, refine_step: bool = True, inner_tol: float | None = None):
+    """Algorithm 1 end to end on the GPU: prepare, solve, FP64 refine.
+    Returns dict(X, iters, kkt, status, kkt64, obj64)."""
+    Q, q, s = prepare(A, B, mode)
+    X, iters, kkt, status = solve(Q, q, s, tol if inner_tol is None else inner_tol, max_iter)
+    res = dict(X=X, iters=iters, kkt=kkt, status=status, Q=Q, q=q, s=s)
+    if refine_step:
+        kkt64, obj64 = refine(A, B, X)
+        res.update(kkt64=kkt64, obj64=obj64)
+    return res

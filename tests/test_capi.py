@@ -1,0 +1,123 @@
+"""The C ABI without a GPU: the library loads, exports every function nnls.h declares, sizes
+workspaces, and rejects bad arguments on the host before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nnls.h")
+LIB = os.path.join(ROOT, "paper_1502_01645_amd", "libnnls.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(nnls_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(LIB):
+        from paper_1502_01645_amd import build
+        build.build()
+    from paper_1502_01645_amd import nnls
+    return nnls.lib()
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for required in ["nnls_prepare", "nnls_solve", "nnls_refine", "nnls_workspace_bytes"]:
+        assert required in names
+
+
+def test_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_workspace_sizes(L):
+    from paper_1502_01645_amd import nnls as N
+    assert N.workspace_bytes(N.OP_SOLVE, 0, 100, 3, 0, N.F32) >= 3 * 100 * 3 * 4
+    assert N.workspace_bytes(N.OP_SOLVE, 0, 100, 3, 0, N.F64) >= 3 * 100 * 3 * 8
+    assert N.workspace_bytes(N.OP_PREPARE, 1000, 100, 1, N.GRAM_BF16X3, N.F32) > 0
+    assert N.workspace_bytes(N.OP_REFINE, 1000, 100, 1, 0, N.F32) > 0
+    # invalid shapes size to 0
+    assert N.workspace_bytes(N.OP_SOLVE, 0, 0, 3, 0, N.F32) == 0
+    assert N.workspace_bytes(N.OP_SOLVE, 0, 10, 3, 0, 7) == 0
+    assert N.workspace_bytes(99, 10, 10, 3, 0, N.F32) == 0
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+
+def test_prepare_rejects_bad_arguments(L):
+    from paper_1502_01645_amd import nnls as N
+    ws = ctypes.c_size_t(1 << 40)
+    cases = [
+        dict(d=0), dict(n=0), dict(k=-1), dict(lda=5), dict(ldb=0), dict(A=None), dict(Q=None),
+        dict(s=None), dict(B=None), dict(q=None), dict(dtype=5), dict(mode=N.GRAM_FP64),
+        dict(mode=7),
+    ]
+    for c in cases:
+        a = dict(d=100, n=10, k=2, A=FAKE, lda=10, B=FAKE, ldb=2, mode=N.GRAM_BF16X3, dtype=N.F32,
+                 Q=FAKE, q=FAKE, s=FAKE)
+        a.update(c)
+        rc = L.nnls_prepare(a["d"], a["n"], a["k"], a["A"], a["lda"], a["B"], a["ldb"], a["mode"],
+                            a["dtype"], a["Q"], a["q"], a["s"], FAKE, ws, None)
+        assert rc == N.E_ARG, c
+    # FP64 data must use the FP64 Gram
+    rc = L.nnls_prepare(100, 10, 2, FAKE, 10, FAKE, 2, N.GRAM_BF16X3, N.F64, FAKE, FAKE, FAKE, FAKE,
+                        ws, None)
+    assert rc == N.E_ARG
+    # workspace too small
+    rc = L.nnls_prepare(100, 10, 2, FAKE, 10, FAKE, 2, N.GRAM_BF16X3, N.F32, FAKE, FAKE, FAKE, FAKE,
+                        0, None)
+    assert rc == N.E_WORKSPACE
+
+
+def test_solve_rejects_bad_arguments(L):
+    from paper_1502_01645_amd import nnls as N
+    big = 1 << 40
+    base = dict(n=10, k=2, dt=N.F32, Q=FAKE, q=FAKE, tol=1e-5, mi=0, X=FAKE, it=FAKE, kkt=FAKE,
+                st=FAKE, ws=FAKE, wsb=big)
+    cases = [dict(n=0), dict(k=0), dict(dt=3), dict(Q=None), dict(q=None), dict(X=None),
+             dict(it=None), dict(kkt=None), dict(st=None), dict(tol=-1.0), dict(tol=float("nan")),
+             dict(tol=float("inf")), dict(mi=-1)]
+    for c in cases:
+        a = dict(base)
+        a.update(c)
+        rc = L.nnls_solve(a["n"], a["k"], a["dt"], a["Q"], a["q"], None, a["tol"], a["mi"], None,
+                          a["X"], a["it"], a["kkt"], a["st"], a["ws"], a["wsb"], None)
+        assert rc == N.E_ARG, c
+    rc = L.nnls_solve(10, 2, N.F32, FAKE, FAKE, None, 1e-5, 0, None, FAKE, FAKE, FAKE, FAKE, FAKE, 4,
+                      None)
+    assert rc == N.E_WORKSPACE
+    rc = L.nnls_solve(10, 2, N.F32, FAKE, FAKE, None, 1e-5, 0, None, FAKE, FAKE, FAKE, FAKE, None,
+                      big, None)
+    assert rc == N.E_WORKSPACE
+
+
+def test_refine_rejects_bad_arguments(L):
+    from paper_1502_01645_amd import nnls as N
+    big = 1 << 40
+    base = dict(d=50, n=10, k=2, A=FAKE, lda=10, B=FAKE, ldb=2, dt=N.F32, X=FAKE, kk=FAKE, ob=FAKE)
+    for c in [dict(d=0), dict(n=0), dict(k=0), dict(A=None), dict(B=None), dict(X=None),
+              dict(kk=None), dict(ob=None), dict(lda=9), dict(ldb=1), dict(dt=9)]:
+        a = dict(base)
+        a.update(c)
+        rc = L.nnls_refine(a["d"], a["n"], a["k"], a["A"], a["lda"], a["B"], a["ldb"], a["dt"],
+                           a["X"], a["kk"], a["ob"], FAKE, big, None)
+        assert rc == N.E_ARG, c
+    rc = L.nnls_refine(50, 10, 2, FAKE, 10, FAKE, 2, N.F32, FAKE, FAKE, FAKE, FAKE, 8, None)
+    assert rc == N.E_WORKSPACE
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_1502_01645_amd import nnls as N
+    monkeypatch.setattr(N, "_lib", None)
+    monkeypatch.setattr(N, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(N.NNLSError):
+        N.lib()

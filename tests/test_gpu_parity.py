@@ -1,0 +1,221 @@
+"""HIP path against the FP64 oracle, element by element where the result is unique.
+
+Every call goes through the C ABI (paper_1502_01645_amd.nnls is only ctypes marshalling).
+Sizes span several 128-wide Gram tiles with ragged tails; the end-to-end cases check the
+method's own tolerances: relative KKT residual in FP64 against the original data (the metric
+the oracle computes) and the relative objective gap against the oracle's tight solution.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import DEV, dev, gram_abs_tol, host, orc, say
+from oracle import oracle as O
+from paper_1502_01645_amd import nnls as N
+from paper_1502_01645_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _uniform_case(seed, d, n, k, dtype=np.float32):
+    rng = np.random.default_rng(seed)
+    A = rng.random((d, n)).astype(dtype)
+    X = np.where(rng.random((n, k)) < 0.6, 0.0, rng.random((n, k)))
+    B = (A.astype(np.float64) @ X + 0.01 * rng.standard_normal((d, k))).astype(dtype)
+    return A, B
+
+
+# ---------------------------------------------------------------------------- prepare ---------
+@pytest.mark.parametrize("d,n,k", [(300, 300, 3), (1000, 130, 1), (257, 129, 0), (64, 5, 2),
+                                   (1, 7, 1), (513, 384, 130)])
+@pytest.mark.parametrize("mode", ["bf16x3", "fp32"])
+def test_prepare_fp32_parity(d, n, k, mode):
+    say(f"prepare {mode} d={d} n={n} k={k}")
+    rng = np.random.default_rng(d * 7 + n)
+    A = (rng.standard_normal((d, n)) * rng.random(n)[None, :] * 3).astype(np.float32)
+    B = rng.standard_normal((d, k)).astype(np.float32) if k else None
+    m = N.GRAM_BF16X3 if mode == "bf16x3" else N.GRAM_FP32
+    Q, q, s = N.prepare(dev(A), dev(B) if k else None, mode=m)
+    s_o, Q_o, q_o = orc().prepare(A, B if k else np.zeros((d, 0)))
+    tol = gram_abs_tol(d, mode)
+    assert np.allclose(host(s), s_o, rtol=1e-12, atol=0)
+    Qh = host(Q).astype(np.float64)
+    assert np.abs(Qh - Q_o).max() <= tol
+    assert np.array_equal(Qh, Qh.T)
+    assert np.all(np.diag(Qh) == 1.0)
+    if k:
+        bn = np.linalg.norm(B.astype(np.float64), axis=0)
+        err = np.abs(host(q).astype(np.float64) - q_o) / bn[None, :]
+        assert err.max() <= tol
+
+
+def test_prepare_splitk_parity():
+    d, n, k = 20000, 100, 20
+    say(f"prepare split-K d={d} n={n} k={k}")
+    rng = np.random.default_rng(3)
+    A = np.abs(rng.standard_normal((d, n))).astype(np.float32)
+    B = rng.random((d, k)).astype(np.float32)
+    Q, q, s = N.prepare(dev(A), dev(B))
+    s_o, Q_o, q_o = orc().prepare(A, B)
+    tol = gram_abs_tol(d, "bf16x3")
+    assert np.abs(host(Q) - Q_o).max() <= tol
+    bn = np.linalg.norm(B.astype(np.float64), axis=0)
+    assert (np.abs(host(q) - q_o) / bn[None, :]).max() <= tol
+
+
+def test_prepare_fp64_parity():
+    A, b, _ = W.make_small()
+    say("prepare fp64 200x50")
+    Q, q, s = N.prepare(dev(A), dev(b))
+    s_o, Q_o, q_o = orc().prepare(A, b)
+    assert np.allclose(host(s), s_o, rtol=1e-14)
+    assert np.abs(host(Q) - Q_o).max() <= 1e-13
+    assert np.allclose(host(q), q_o, rtol=1e-12, atol=1e-12 * np.abs(q_o).max())
+
+
+def test_prepare_zero_column():
+    say("prepare zero column")
+    A, B = _uniform_case(5, 300, 140, 2)
+    A[:, 17] = 0.0
+    Q, q, s = N.prepare(dev(A), dev(B))
+    Qh, qh, sh = host(Q), host(q), host(s)
+    assert sh[17] == 1.0 and np.all(Qh[17, :] == 0) and np.all(Qh[:, 17] == 0)
+    assert np.all(qh[17] == 0)
+
+
+# ---------------------------------------------------------------------------- solve -----------
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_solve_steps_match_oracle(dtype):
+    """One update of Algorithm 2 from the same state, element by element: starting from the
+    oracle's iterate y_m (m = 0, 1, 2, 5, 20), one GPU update must land on the oracle's y_{m+1}.
+    Starting every comparison from the oracle's state keeps rounding differences from
+    compounding over iterations of an ill-conditioned problem."""
+    say(f"solve single steps {np.dtype(dtype).name}")
+    A, B = _uniform_case(11, 400, 300, 4, dtype)
+    Q, q, s = N.prepare(dev(A), dev(B))
+    Qh, qh = host(Q).astype(np.float64), host(q).astype(np.float64)
+    n, k = qh.shape
+    eps = 2.0 ** -52 if dtype == np.float64 else 2.0 ** -23
+    for m in [0, 1, 2, 5, 20]:
+        Ym = np.zeros((n, k))
+        Yn = np.zeros((n, k))
+        for c in range(k):
+            Ym[:, c] = orc().nqp(Qh, qh[:, c], 0.0, m)[0] if m else 0.0
+        Ym_dev = dev(Ym.astype(dtype)) if m else None
+        # the state handed to the GPU is y_m rounded to the working type; the oracle continues
+        # from that same rounded state
+        Ystart = Ym.astype(dtype).astype(np.float64)
+        for c in range(k):
+            Yn[:, c] = orc().nqp(Qh, qh[:, c], 0.0, 1, y0=Ystart[:, c])[0]
+        Y, iters, kkt, st = N.solve(Q, q, None, tol=0.0, max_iter=1, Y0=Ym_dev)
+        Yh = host(Y).astype(np.float64)
+        assert np.all(host(iters) == 1)
+        for c in range(k):
+            err = np.abs(Yh[:, c] - Yn[:, c]).max()
+            scale = np.abs(Ystart[:, c]).max() + np.abs(Yn[:, c]).max()
+            # one update: gradient over n terms, two reductions over n terms, one multiply-add;
+            # allow 8 n eps relative to the size of the iterates
+            assert err <= 8 * n * eps * scale, (m, c, err / scale)
+
+
+def _check_solution(A, B, X, tol, ref, what):
+    r, F = orc().kkt_x(A, B, X)
+    gap = O.relative_gap(F, ref)
+    say(f"{what}: max r={r.max():.3e} max gap={gap.max():.3e}")
+    assert np.all(X >= 0)
+    assert r.max() <= tol, r.max()
+    assert gap.max() <= 1e-6, gap.max()
+    return r, gap
+
+
+def test_end_to_end_small_fp64():
+    """The 200 x 50 FP64 instance, tolerance 1e-8 (the small plain-method workload)."""
+    A, b, _ = W.make_small()
+    say("e2e small fp64")
+    res = N.nnls(dev(A), dev(b), tol=1e-8, max_iter=100000, inner_tol=5e-9)
+    st = host(res["status"])
+    assert st[0] == N.CONVERGED
+    ref = O.reference_solution(A, b)
+    X = host(res["X"])
+    _check_solution(A, b, X, 1e-8, ref, "small fp64")
+    r_o, _ = orc().kkt_x(A, b, X)
+    assert abs(host(res["kkt64"])[0] - r_o[0]) <= 1e-6 * r_o[0] + 1e-15
+
+
+@pytest.mark.parametrize("d,n,k,seed", [(2000, 500, 1, 1), (3000, 700, 2, 2), (1500, 257, 6, 3)])
+def test_end_to_end_fp32(d, n, k, seed):
+    say(f"e2e fp32 d={d} n={n} k={k}")
+    A, B = _uniform_case(seed, d, n, k)
+    res = N.nnls(dev(A), dev(B), tol=1e-5, max_iter=100000, inner_tol=3e-6)
+    assert np.all(host(res["status"]) == N.CONVERGED)
+    ref = O.reference_solution(A, B)
+    X = host(res["X"])
+    r, _ = _check_solution(A, B, X, 1e-5, ref, "fp32")
+    assert np.allclose(host(res["kkt64"]), r, rtol=1e-6, atol=1e-14)
+
+
+def test_many_rhs_small():
+    """Scaled-down many-RHS workload (|N(0,1)| dictionary, Gamma(2,1) codes, 1 % noise)."""
+    A, B, _ = W.make_manyrhs(seed=4, d=2000, n=96, k=37)
+    say("many-rhs small")
+    res = N.nnls(dev(A), dev(B), tol=1e-5, max_iter=100000, inner_tol=3e-6)
+    assert np.all(host(res["status"]) == N.CONVERGED)
+    ref = O.reference_solution(A, B)
+    _check_solution(A, B, host(res["X"]), 1e-5, ref, "many-rhs")
+
+
+# ---------------------------------------------------------------------------- edge cases ------
+def test_n_equals_one():
+    say("n = 1")
+    rng = np.random.default_rng(8)
+    A = (rng.random((50, 1)) + 0.1).astype(np.float64)
+    b = rng.standard_normal((50, 3))
+    b[:, 1] = -np.abs(b[:, 1]) - 1  # a^T b < 0: x = 0
+    res = N.nnls(dev(A), dev(b), tol=1e-12, max_iter=10)
+    X = host(res["X"])
+    x_cf = np.maximum(0.0, A[:, 0] @ b) / (A[:, 0] @ A[:, 0])
+    assert np.allclose(X[0], x_cf, rtol=1e-12, atol=1e-14)
+    its = host(res["iters"])
+    assert list(its) == [1 if v > 0 else 0 for v in x_cf]
+
+
+def test_nonnegative_q_gives_zero():
+    say("q >= 0")
+    rng = np.random.default_rng(9)
+    A = rng.random((100, 40)).astype(np.float32)
+    b = -rng.random((100, 1)).astype(np.float32)
+    res = N.nnls(dev(A), dev(b), tol=1e-6)
+    assert np.all(host(res["X"]) == 0) and host(res["iters"])[0] == 0
+    assert host(res["status"])[0] == N.CONVERGED
+
+
+def test_status_maxiter_and_nonfinite():
+    say("statuses")
+    A, B = _uniform_case(12, 300, 200, 2)
+    Q, q, s = N.prepare(dev(A), dev(B))
+    X, it, kkt, st = N.solve(Q, q, s, tol=1e-12, max_iter=3)
+    assert np.all(host(st) == N.MAXITER) and np.all(host(it) == 3)
+    qb = q.clone()
+    qb[5, 1] = float("nan")
+    X, it, kkt, st = N.solve(Q, qb, s, tol=1e-6, max_iter=50)
+    sth = host(st)
+    assert sth[1] == N.NONFINITE and sth[0] != N.NONFINITE
+
+
+def test_breakdown_on_indefinite_q():
+    say("breakdown")
+    Q = torch.tensor([[1.0, 0.0], [0.0, -1.0]], dtype=torch.float64, device=DEV)
+    q = torch.tensor([[0.0], [-1.0]], dtype=torch.float64, device=DEV)
+    X, it, kkt, st = N.solve(Q, q, None, tol=1e-10, max_iter=50)
+    assert host(st)[0] == N.BREAKDOWN
+
+
+def test_warm_start_at_solution():
+    """Y0 = the converged y: the solve stops at once with the same point."""
+    say("warm start at solution")
+    A, B = _uniform_case(13, 800, 150, 3)
+    Q, q, s = N.prepare(dev(A), dev(B))
+    Y, it, kkt, st = N.solve(Q, q, None, tol=1e-6, max_iter=100000)
+    Y2, it2, kkt2, st2 = N.solve(Q, q, None, tol=1e-6, max_iter=100000, Y0=Y)
+    assert np.all(host(it2) == 0) and np.all(host(st2) == N.CONVERGED)
+    assert np.array_equal(host(Y2), host(Y))
