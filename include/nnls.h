@@ -64,10 +64,17 @@ enum nnls_gram_mode {
 enum nnls_dtype { NNLS_F32 = 0, NNLS_F64 = 1 };
 
 /* Operations for nnls_workspace_bytes. */
-enum nnls_op { NNLS_OP_PREPARE = 0, NNLS_OP_SOLVE = 1, NNLS_OP_REFINE = 2 };
+enum nnls_op {
+    NNLS_OP_PREPARE = 0,
+    NNLS_OP_SOLVE = 1,
+    NNLS_OP_REFINE = 2,
+    NNLS_OP_SCALES = 3,
+    NNLS_OP_GRAM = 4
+};
 
 /* Bytes of device workspace that operation `op` needs for the given shape, mode and dtype
- * (0 if it needs none).  Pure host function. */
+ * (0 if it needs none).  Host function; for NNLS_OP_SOLVE it reads the compute-unit count of the
+ * current device (the whole-GPU solver keeps one partial vector per workgroup). */
 size_t nnls_workspace_bytes(int op, int64_t d, int64_t n, int64_t k, int mode, int dtype);
 
 /*
@@ -90,6 +97,24 @@ int nnls_prepare(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, co
                  size_t ws_bytes, void* stream);
 
 /*
+ * nnls_prepare is these two calls in sequence; they are exported so a caller can time or reuse
+ * them separately.
+ *
+ * nnls_column_scales -- the scale vector of the rescaling (4): s_i = ||A_i||_2 in FP64, 1 where
+ * the column is zero.  A [d, n] (lda >= n) of element type `dtype`; s out [n] FP64.
+ * Workspace: nnls_workspace_bytes(NNLS_OP_SCALES, ...).
+ *
+ * nnls_gram_rescaled -- the Gram product of Problem (2) with the rescale of Problem (5) applied
+ * in the epilogue, given s from nnls_column_scales: Q, q as for nnls_prepare.
+ * Workspace: nnls_workspace_bytes(NNLS_OP_GRAM, ...).
+ */
+int nnls_column_scales(int64_t d, int64_t n, const void* A, int64_t lda, int dtype, double* s,
+                       void* ws, size_t ws_bytes, void* stream);
+int nnls_gram_rescaled(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, int mode, int dtype, const double* s, void* Q,
+                       void* q, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * nnls_solve -- Algorithm 2 on every column of q (they share Q), then x = y / s (rescaling (4)).
  *
  *   n, k      unknowns and right-hand sides (k >= 1)
@@ -103,10 +128,18 @@ int nnls_prepare(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, co
  *   X         out [n, k]: x = y / s
  *   iters     out [k] int32 updates done; kkt out [k] FP64 r(y) of the returned iterate in the
  *             arithmetic of the solve; status out [k] int32 nnls_col_status
+ *   rows_read out [k] int64, may be NULL: rows of Q the solve's products read in total (passive
+ *             rows of the line-search products, clipped rows of the gradient corrections, rows
+ *             of exact gradient recomputations); 4 n bytes each for FP32 Q.  This is the
+ *             S(n)-weighted work of the complexity lemma of Section 4.
+ * The workspace size depends on the solver chosen for the shape; NNLS_OP_SOLVE sizes it for
+ * the current device.  The environment variable NNLS_SOLVER=wg|persistent forces the
+ * one-workgroup-per-column or the whole-GPU single-right-hand-side solver where valid.
  */
 int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, const double* s,
                double tol, int32_t max_iter, const void* Y0, void* X, int32_t* iters,
-               double* kkt, int32_t* status, void* ws, size_t ws_bytes, void* stream);
+               double* kkt, int32_t* status, int64_t* rows_read, void* ws, size_t ws_bytes,
+               void* stream);
 
 /*
  * nnls_refine -- FP64 check and one refinement step against the ORIGINAL data (A, B).

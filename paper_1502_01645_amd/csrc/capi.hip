@@ -2,6 +2,7 @@
 // Every check runs on the host before the first HIP call, so argument errors never touch the
 // device.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <string>
@@ -27,13 +28,52 @@ constexpr size_t kMaxLds = 160 * 1024;
 bool valid_dtype(int dt) { return dt == NNLS_F32 || dt == NNLS_F64; }
 size_t elem_size(int dt) { return dt == NNLS_F64 ? 8 : 4; }
 
-size_t prepare_ws(int64_t d, int64_t n, int64_t k, int mode) {
-  size_t a = nnls::colnorm_ws_bytes(d, n);
-  size_t b = mode == NNLS_GRAM_BF16X3 ? nnls::gram_bf16x3_ws_bytes(d, n, k) : 0;
-  return align_up(a > b ? a : b);
+size_t gram_ws(int64_t d, int64_t n, int64_t k, int mode) {
+  return align_up(mode == NNLS_GRAM_BF16X3 ? nnls::gram_bf16x3_ws_bytes(d, n, k) : 0);
 }
 
-size_t solve_ws(int64_t n, int64_t k, int dt) { return align_up(elem_size(dt) * 3 * n * k); }
+// The scale pass and the Gram run one after the other on the stream, so they share the buffer.
+size_t prepare_ws(int64_t d, int64_t n, int64_t k, int mode) {
+  size_t a = align_up(nnls::colnorm_ws_bytes(d, n));
+  size_t b = gram_ws(d, n, k, mode);
+  return a > b ? a : b;
+}
+
+// Solver choice: one right-hand side of FP32 with n at least kPersistentMinN goes to the
+// persistent whole-GPU kernel; everything else to the one-workgroup-per-column kernel.
+// NNLS_SOLVER=wg or NNLS_SOLVER=persistent in the environment forces a choice (when valid).
+constexpr int64_t kPersistentMinN = 1536;
+
+enum SolverKind { SOLVER_WG = 0, SOLVER_PERSISTENT = 1 };
+
+int solver_override() {
+  const char* v = getenv("NNLS_SOLVER");
+  if (!v) return -1;
+  if (strcmp(v, "wg") == 0) return SOLVER_WG;
+  if (strcmp(v, "persistent") == 0) return SOLVER_PERSISTENT;
+  return -1;
+}
+
+SolverKind pick_solver(int64_t n, int64_t k, int dt) {
+  const bool can_p = dt == NNLS_F32 && nnls::solve_persistent_supported(n, k);
+  const bool can_w = nnls::solve_wg_lds_bytes(n, (int)elem_size(dt)) <= kMaxLds;
+  const int o = solver_override();
+  if (o == SOLVER_PERSISTENT && can_p) return SOLVER_PERSISTENT;
+  if (o == SOLVER_WG && can_w) return SOLVER_WG;
+  if (can_p && (n >= kPersistentMinN || !can_w)) return SOLVER_PERSISTENT;
+  return SOLVER_WG;
+}
+
+bool solver_supported(int64_t n, int64_t k, int dt) {
+  return (dt == NNLS_F32 && nnls::solve_persistent_supported(n, k)) ||
+         nnls::solve_wg_lds_bytes(n, (int)elem_size(dt)) <= kMaxLds;
+}
+
+size_t solve_ws(int64_t n, int64_t k, int dt) {
+  if (pick_solver(n, k, dt) == SOLVER_PERSISTENT)
+    return align_up(nnls::solve_persistent_ws_bytes(n));
+  return align_up(elem_size(dt) * 3 * n * k);
+}
 
 }  // namespace
 
@@ -53,65 +93,120 @@ size_t nnls_workspace_bytes(int op, int64_t d, int64_t n, int64_t k, int mode, i
       return k < 1 ? 0 : solve_ws(n, k, dtype);
     case NNLS_OP_REFINE:
       return (d < 1 || k < 1) ? 0 : align_up(nnls::refine_ws_bytes(d, n, k));
+    case NNLS_OP_SCALES:
+      return d < 1 ? 0 : align_up(nnls::colnorm_ws_bytes(d, n));
+    case NNLS_OP_GRAM:
+      return d < 1 ? 0 : gram_ws(d, n, k, mode);
     default:
       return 0;
   }
 }
 
-int nnls_prepare(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
-                 int64_t ldb, int mode, int dtype, void* Q, void* q, double* s, void* ws,
-                 size_t ws_bytes, void* stream) {
+static int validate_scales(int64_t d, int64_t n, const void* A, int64_t lda, int dtype,
+                           const double* s) {
+  if (d < 1 || n < 1 || !valid_dtype(dtype)) return NNLS_E_ARG;
+  if (!A || !s || lda < n) return NNLS_E_ARG;
+  if (n > (int64_t)1 << 30 || d > ((int64_t)1 << 40) / n) return NNLS_E_UNSUPPORTED;
+  return NNLS_OK;
+}
+
+static int validate_gram(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda,
+                         const void* B, int64_t ldb, int mode, int dtype, const void* Q,
+                         const void* q) {
   if (d < 1 || n < 1 || k < 0) return NNLS_E_ARG;
   if (!valid_dtype(dtype)) return NNLS_E_ARG;
   if (dtype == NNLS_F64 && mode != NNLS_GRAM_FP64) return NNLS_E_ARG;
   if (dtype == NNLS_F32 && mode != NNLS_GRAM_FP32 && mode != NNLS_GRAM_BF16X3) return NNLS_E_ARG;
-  if (!A || !Q || !s || lda < n) return NNLS_E_ARG;
+  if (!A || !Q || lda < n) return NNLS_E_ARG;
   if (k > 0 && (!B || !q || ldb < k)) return NNLS_E_ARG;
-  if (n > (int64_t)1 << 30 || d > ((int64_t)1 << 40) / (n > 0 ? n : 1)) return NNLS_E_UNSUPPORTED;
+  if (n > (int64_t)1 << 30 || d > ((int64_t)1 << 40) / n) return NNLS_E_UNSUPPORTED;
+  return NNLS_OK;
+}
+
+static hipError_t run_scales(int64_t d, int64_t n, const void* A, int64_t lda, int dtype,
+                             double* s, void* ws, hipStream_t st) {
+  if (dtype == NNLS_F64)
+    return nnls::launch_colnorm<double>(d, n, (const double*)A, lda, s, (double*)ws, st);
+  return nnls::launch_colnorm<float>(d, n, (const float*)A, lda, s, (double*)ws, st);
+}
+
+static hipError_t run_gram(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda,
+                           const void* B, int64_t ldb, int mode, int dtype, const double* s,
+                           void* Q, void* q, void* ws, hipStream_t st) {
+  if (dtype == NNLS_F64)
+    return nnls::launch_gram_fma<double>(d, n, k, (const double*)A, lda, (const double*)B, ldb,
+                                         s, (double*)Q, (double*)q, st);
+  if (mode == NNLS_GRAM_BF16X3)
+    return nnls::launch_gram_bf16x3(d, n, k, (const float*)A, lda, (const float*)B, ldb, s,
+                                    (float*)Q, (float*)q, (float*)ws, st);
+  return nnls::launch_gram_fma<float>(d, n, k, (const float*)A, lda, (const float*)B, ldb, s,
+                                      (float*)Q, (float*)q, st);
+}
+
+int nnls_column_scales(int64_t d, int64_t n, const void* A, int64_t lda, int dtype, double* s,
+                       void* ws, size_t ws_bytes, void* stream) {
+  int rc = validate_scales(d, n, A, lda, dtype, s);
+  if (rc != NNLS_OK) return rc;
+  const size_t need = align_up(nnls::colnorm_ws_bytes(d, n));
+  if (ws_bytes < need || !ws) return NNLS_E_WORKSPACE;
+  hipError_t e = run_scales(d, n, A, lda, dtype, s, ws, (hipStream_t)stream);
+  return e == hipSuccess ? NNLS_OK : hip_fail(e);
+}
+
+int nnls_gram_rescaled(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, int mode, int dtype, const double* s, void* Q,
+                       void* q, void* ws, size_t ws_bytes, void* stream) {
+  int rc = validate_gram(d, n, k, A, lda, B, ldb, mode, dtype, Q, q);
+  if (rc != NNLS_OK) return rc;
+  if (!s) return NNLS_E_ARG;
+  const size_t need = gram_ws(d, n, k, mode);
+  if (ws_bytes < need || (need > 0 && !ws)) return NNLS_E_WORKSPACE;
+  hipError_t e = run_gram(d, n, k, A, lda, B, ldb, mode, dtype, s, Q, q, ws, (hipStream_t)stream);
+  return e == hipSuccess ? NNLS_OK : hip_fail(e);
+}
+
+int nnls_prepare(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
+                 int64_t ldb, int mode, int dtype, void* Q, void* q, double* s, void* ws,
+                 size_t ws_bytes, void* stream) {
+  int rc = validate_gram(d, n, k, A, lda, B, ldb, mode, dtype, Q, q);
+  if (rc != NNLS_OK) return rc;
+  if (!s) return NNLS_E_ARG;
   const size_t need = prepare_ws(d, n, k, mode);
   if (ws_bytes < need || (need > 0 && !ws)) return NNLS_E_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e;
-  if (dtype == NNLS_F64) {
-    e = nnls::launch_colnorm<double>(d, n, (const double*)A, lda, s, (double*)ws, st);
-    if (e != hipSuccess) return hip_fail(e);
-    e = nnls::launch_gram_fma<double>(d, n, k, (const double*)A, lda, (const double*)B, ldb, s,
-                                      (double*)Q, (double*)q, st);
-  } else {
-    e = nnls::launch_colnorm<float>(d, n, (const float*)A, lda, s, (double*)ws, st);
-    if (e != hipSuccess) return hip_fail(e);
-    if (mode == NNLS_GRAM_BF16X3)
-      e = nnls::launch_gram_bf16x3(d, n, k, (const float*)A, lda, (const float*)B, ldb, s,
-                                   (float*)Q, (float*)q, (float*)ws, st);
-    else
-      e = nnls::launch_gram_fma<float>(d, n, k, (const float*)A, lda, (const float*)B, ldb, s,
-                                       (float*)Q, (float*)q, st);
-  }
+  hipError_t e = run_scales(d, n, A, lda, dtype, s, ws, st);
   if (e != hipSuccess) return hip_fail(e);
-  return NNLS_OK;
+  e = run_gram(d, n, k, A, lda, B, ldb, mode, dtype, s, Q, q, ws, st);
+  return e == hipSuccess ? NNLS_OK : hip_fail(e);
 }
 
 int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, const double* s,
                double tol, int32_t max_iter, const void* Y0, void* X, int32_t* iters,
-               double* kkt, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+               double* kkt, int32_t* status, int64_t* rows_read, void* ws, size_t ws_bytes,
+               void* stream) {
   if (n < 1 || k < 1 || !valid_dtype(dtype)) return NNLS_E_ARG;
   if (!Q || !q || !X || !iters || !kkt || !status) return NNLS_E_ARG;
   if (!(tol >= 0.0) || !isfinite(tol) || max_iter < 0) return NNLS_E_ARG;
   if (n > (int64_t)1 << 30 || k > (int64_t)1 << 31) return NNLS_E_UNSUPPORTED;
-  if (nnls::solve_wg_lds_bytes(n, (int)elem_size(dtype)) > kMaxLds) return NNLS_E_UNSUPPORTED;
+  if (!solver_supported(n, k, dtype)) return NNLS_E_UNSUPPORTED;
   const size_t need = solve_ws(n, k, dtype);
   if (ws_bytes < need || !ws) return NNLS_E_WORKSPACE;
   const int mi = max_iter == 0 ? (int)(5 * n < (1 << 30) ? 5 * n : (1 << 30)) : max_iter;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
-  if (dtype == NNLS_F64)
+  if (pick_solver(n, k, dtype) == SOLVER_PERSISTENT) {
+    if (((uintptr_t)Q & 15) != 0) return NNLS_E_ARG;  // rows are read as 16-byte vectors
+    e = nnls::launch_solve_persistent(n, (const float*)Q, (const float*)q, s, tol, mi,
+                                      (const float*)Y0, (float*)X, iters, kkt, status,
+                                      rows_read, ws, st);
+  } else if (dtype == NNLS_F64)
     e = nnls::launch_solve_wg<double>(n, k, (const double*)Q, (const double*)q, s, tol, mi,
                                       (const double*)Y0, (double*)X, iters, kkt, status,
-                                      (double*)ws, st);
+                                      rows_read, (double*)ws, st);
   else
     e = nnls::launch_solve_wg<float>(n, k, (const float*)Q, (const float*)q, s, tol, mi,
-                                     (const float*)Y0, (float*)X, iters, kkt, status, (float*)ws,
-                                     st);
+                                     (const float*)Y0, (float*)X, iters, kkt, status, rows_read,
+                                     (float*)ws, st);
   if (e != hipSuccess) return hip_fail(e);
   return NNLS_OK;
 }

@@ -32,7 +32,16 @@ size_t solve_wg_lds_bytes(int64_t n, int elem);
 template <typename T>
 hipError_t launch_solve_wg(int64_t n, int64_t k, const T* Q, const T* q, const double* s,
                            double tol, int max_iter, const T* Y0, T* X, int32_t* iters,
-                           double* kkt, int32_t* status, T* ws, hipStream_t st);
+                           double* kkt, int32_t* status, int64_t* rows_read, T* ws,
+                           hipStream_t st);
+
+// solve_persistent.hip
+bool solve_persistent_supported(int64_t n, int64_t k);
+size_t solve_persistent_ws_bytes(int64_t n);
+hipError_t launch_solve_persistent(int64_t n, const float* Q, const float* q, const double* s,
+                                   double tol, int max_iter, const float* Y0, float* X,
+                                   int32_t* iters, double* kkt, int32_t* status,
+                                   int64_t* rows_read, void* ws, hipStream_t st);
 
 // refine.hip
 size_t refine_ws_bytes(int64_t d, int64_t n, int64_t k);

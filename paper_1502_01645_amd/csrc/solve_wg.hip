@@ -52,7 +52,8 @@ __device__ __forceinline__ T row_combo(const T* __restrict__ Q, int64_t n, int64
 
 template <typename T>
 __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int32_t* iters_out,
-                             double* kkt_out, int32_t* status_out, T* lds_val, int* lds_idx,
+                             double* kkt_out, int32_t* status_out, int64_t* rows_out,
+                             T* lds_val, int* lds_idx,
                              T* lds_val2, int* lds_idx2, T* redT, int* redI) {
   const int tid = threadIdx.x;
   const int64_t n = P.n;
@@ -80,6 +81,7 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
   const T scale = qnorm > (T)0 ? qnorm : (T)1;
   __syncthreads();
 
+  int64_t rows = 0;  // rows of Q read by the products
   // Recompute grad = Q y + q exactly over the rows with y_j > 0.
   auto refresh_gradient = [&]() {
     int cnt = 0;
@@ -95,7 +97,9 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
       }
     }
     __syncthreads();
-    for (int64_t i = tid; i < n; i += SW_NT) g[i] = P.q[i * P.qs] + row_combo(Q, n, i, lds_idx2, lds_val2, total);
+    for (int64_t i = tid; i < n; i += SW_NT)
+      g[i] = P.q[i * P.qs] + row_combo(Q, n, i, lds_idx2, lds_val2, total);
+    rows += total;
     __syncthreads();
   };
 
@@ -167,6 +171,7 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
     }
 
     // Line-search product w = Q gbar over the passive rows; den = gbar^T w.
+    rows += total;
     T den = 0;
     for (int64_t i = tid; i < n; i += SW_NT) {
       const T w = row_combo(Q, n, i, lds_idx, lds_val, total);
@@ -213,6 +218,7 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
       y[i] = v > (T)0 ? v : (T)0;
       g[i] = gn;
     }
+    rows += ctotal;
     __syncthreads();
     ++it;
     fresh = false;
@@ -226,6 +232,7 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
     *iters_out = it;
     *kkt_out = status == NNLS_NONFINITE_DEV ? __builtin_nan("") : r_final;
     *status_out = status;
+    if (rows_out) *rows_out = rows;
   }
 }
 
@@ -255,7 +262,8 @@ __global__ __launch_bounds__(SW_NT) void solve_wg_kernel(int64_t n, int64_t k, c
                                                          const T* q, const double* s, double tol,
                                                          int max_iter, const T* Y0, T* X,
                                                          int32_t* iters, double* kkt,
-                                                         int32_t* status, T* ws) {
+                                                         int32_t* status, int64_t* rows_read,
+                                                         T* ws) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int64_t c = blockIdx.x;
   const SwLdsLayout L = sw_lds_layout(n, sizeof(T));
@@ -276,8 +284,9 @@ __global__ __launch_bounds__(SW_NT) void solve_wg_kernel(int64_t n, int64_t k, c
   P.w = P.g + n;
   P.x = X + c;
   P.s = s;
-  solve_column<T>(P, tol, max_iter, iters + c, kkt + c, status + c, lds_val, lds_idx, lds_val2,
-                  lds_idx2, redT, redI);
+  solve_column<T>(P, tol, max_iter, iters + c, kkt + c, status + c,
+                  rows_read ? rows_read + c : nullptr, lds_val, lds_idx, lds_val2, lds_idx2, redT,
+                  redI);
 }
 
 size_t solve_wg_lds_bytes(int64_t n, int elem) { return sw_lds_layout(n, elem).total; }
@@ -285,20 +294,23 @@ size_t solve_wg_lds_bytes(int64_t n, int elem) { return sw_lds_layout(n, elem).t
 template <typename T>
 hipError_t launch_solve_wg(int64_t n, int64_t k, const T* Q, const T* q, const double* s,
                            double tol, int max_iter, const T* Y0, T* X, int32_t* iters,
-                           double* kkt, int32_t* status, T* ws, hipStream_t st) {
+                           double* kkt, int32_t* status, int64_t* rows_read, T* ws,
+                           hipStream_t st) {
   const size_t lds = solve_wg_lds_bytes(n, sizeof(T));
   hipError_t e = hipFuncSetAttribute((const void*)solve_wg_kernel<T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(solve_wg_kernel<T>, dim3((unsigned)k), dim3(SW_NT), lds, st, n, k, Q, q, s,
-                     tol, max_iter, Y0, X, iters, kkt, status, ws);
+                     tol, max_iter, Y0, X, iters, kkt, status, rows_read, ws);
   return hipGetLastError();
 }
 template hipError_t launch_solve_wg<float>(int64_t, int64_t, const float*, const float*,
                                           const double*, double, int, const float*, float*,
-                                          int32_t*, double*, int32_t*, float*, hipStream_t);
+                                          int32_t*, double*, int32_t*, int64_t*, float*,
+                                          hipStream_t);
 template hipError_t launch_solve_wg<double>(int64_t, int64_t, const double*, const double*,
                                            const double*, double, int, const double*, double*,
-                                           int32_t*, double*, int32_t*, double*, hipStream_t);
+                                           int32_t*, double*, int32_t*, int64_t*, double*,
+                                           hipStream_t);
 
 }  // namespace nnls

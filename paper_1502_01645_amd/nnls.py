@@ -19,7 +19,7 @@ OK, E_ARG, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4
 CONVERGED, MAXITER, BREAKDOWN, NONFINITE, FELL_BACK = 0, 1, 2, 3, 4
 GRAM_FP64, GRAM_FP32, GRAM_BF16X3 = 0, 1, 2
 F32, F64 = 0, 1
-OP_PREPARE, OP_SOLVE, OP_REFINE = 0, 1, 2
+OP_PREPARE, OP_SOLVE, OP_REFINE, OP_SCALES, OP_GRAM = 0, 1, 2, 3, 4
 
 _ERRORS = {E_ARG: "invalid argument", E_WORKSPACE: "workspace too small",
            E_HIP: "HIP runtime error", E_UNSUPPORTED: "unsupported shape"}
@@ -48,7 +48,12 @@ def lib():
                                    _vp, _vp, _vp, _vp, _sz, _vp]
         L.nnls_prepare.restype = ctypes.c_int
         L.nnls_solve.argtypes = [_i64, _i64, ctypes.c_int, _vp, _vp, _vp, ctypes.c_double, _i32, _vp,
-                                 _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+                                 _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.nnls_column_scales.argtypes = [_i64, _i64, _vp, _i64, ctypes.c_int, _vp, _vp, _sz, _vp]
+        L.nnls_column_scales.restype = ctypes.c_int
+        L.nnls_gram_rescaled.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int,
+                                         ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.nnls_gram_rescaled.restype = ctypes.c_int
         L.nnls_solve.restype = ctypes.c_int
         L.nnls_refine.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _vp, _vp, _vp,
                                   _vp, _sz, _vp]
@@ -127,9 +132,47 @@ def prepare(A: torch.Tensor, B: torch.Tensor | None = None, mode: int | None = N
     return Q, q, s
 
 
+def column_scales(A: torch.Tensor, out=None, ws=None):
+    """s_i = ||A_i|| in FP64 (1 for a zero column): the scale of the rescaling (4)."""
+    d, n = A.shape
+    dt = _dtype_code(A)
+    s = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+    wsb = workspace_bytes(OP_SCALES, d, n, 0, 0, dt)
+    ws = _workspace(wsb, A.device, ws)
+    rc = lib().nnls_column_scales(d, n, _ptr(A), A.stride(0), dt, _ptr(s), _ptr(ws), wsb,
+                                  _stream(A.device))
+    _check(rc, "nnls_column_scales")
+    return s
+
+
+def gram_rescaled(A: torch.Tensor, B: torch.Tensor | None, s: torch.Tensor, mode: int | None = None,
+                  out=None, ws=None):
+    """Gram product with the rescale epilogue, given s.  Returns (Q, q)."""
+    d, n = A.shape
+    dt = _dtype_code(A)
+    if mode is None:
+        mode = GRAM_FP64 if dt == F64 else GRAM_BF16X3
+    k = 0 if B is None else B.reshape(d, -1).shape[1]
+    if B is not None:
+        B = B.reshape(d, k)
+    if out is None:
+        Q = torch.empty((n, n), dtype=A.dtype, device=A.device)
+        q = torch.empty((n, max(k, 1)), dtype=A.dtype, device=A.device)[:, :k]
+    else:
+        Q, q = out
+    wsb = workspace_bytes(OP_GRAM, d, n, k, mode, dt)
+    ws = _workspace(wsb, A.device, ws)
+    rc = lib().nnls_gram_rescaled(d, n, k, _ptr(A), A.stride(0), _ptr(B),
+                                  B.stride(0) if B is not None else 0, mode, dt, _ptr(s), _ptr(Q),
+                                  _ptr(q) if k > 0 else None, _ptr(ws), wsb, _stream(A.device))
+    _check(rc, "nnls_gram_rescaled")
+    return Q, q
+
+
 def solve(Q: torch.Tensor, q: torch.Tensor, s: torch.Tensor | None = None, tol: float = 1e-5,
-          max_iter: int = 0, Y0: torch.Tensor | None = None, out=None, ws=None):
-    """Algorithm 2 on every column of q, then x = y / s.  Returns (X, iters, kkt, status)."""
+          max_iter: int = 0, Y0: torch.Tensor | None = None, out=None, ws=None, rows_read=None):
+    """Algorithm 2 on every column of q, then x = y / s.  Returns (X, iters, kkt, status).
+    rows_read (optional int64 [k] tensor) receives the rows of Q the products read."""
     n = Q.shape[0]
     if q.dim() == 1:
         q = q.reshape(n, 1)
@@ -149,8 +192,8 @@ def solve(Q: torch.Tensor, q: torch.Tensor, s: torch.Tensor | None = None, tol: 
     wsb = workspace_bytes(OP_SOLVE, 0, n, k, 0, dt)
     ws = _workspace(wsb, Q.device, ws)
     rc = lib().nnls_solve(n, k, dt, _ptr(Q), _ptr(q), _ptr(s), float(tol), int(max_iter), _ptr(Y0),
-                          _ptr(X), _ptr(iters), _ptr(kkt), _ptr(status), _ptr(ws), wsb,
-                          _stream(Q.device))
+                          _ptr(X), _ptr(iters), _ptr(kkt), _ptr(status), _ptr(rows_read), _ptr(ws),
+                          wsb, _stream(Q.device))
     _check(rc, "nnls_solve")
     return X, iters, kkt, status
 

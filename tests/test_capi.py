@@ -90,14 +90,30 @@ def test_solve_rejects_bad_arguments(L):
         a = dict(base)
         a.update(c)
         rc = L.nnls_solve(a["n"], a["k"], a["dt"], a["Q"], a["q"], None, a["tol"], a["mi"], None,
-                          a["X"], a["it"], a["kkt"], a["st"], a["ws"], a["wsb"], None)
+                          a["X"], a["it"], a["kkt"], a["st"], None, a["ws"], a["wsb"], None)
         assert rc == N.E_ARG, c
-    rc = L.nnls_solve(10, 2, N.F32, FAKE, FAKE, None, 1e-5, 0, None, FAKE, FAKE, FAKE, FAKE, FAKE, 4,
-                      None)
+    rc = L.nnls_solve(10, 2, N.F32, FAKE, FAKE, None, 1e-5, 0, None, FAKE, FAKE, FAKE, FAKE, None,
+                      FAKE, 4, None)
     assert rc == N.E_WORKSPACE
     rc = L.nnls_solve(10, 2, N.F32, FAKE, FAKE, None, 1e-5, 0, None, FAKE, FAKE, FAKE, FAKE, None,
-                      big, None)
+                      None, big, None)
     assert rc == N.E_WORKSPACE
+
+
+def test_split_prepare_rejects_bad_arguments(L):
+    from paper_1502_01645_amd import nnls as N
+    big = 1 << 40
+    assert L.nnls_column_scales(0, 10, FAKE, 10, N.F32, FAKE, FAKE, big, None) == N.E_ARG
+    assert L.nnls_column_scales(10, 10, None, 10, N.F32, FAKE, FAKE, big, None) == N.E_ARG
+    assert L.nnls_column_scales(10, 10, FAKE, 9, N.F32, FAKE, FAKE, big, None) == N.E_ARG
+    assert L.nnls_column_scales(10, 10, FAKE, 10, N.F32, None, FAKE, big, None) == N.E_ARG
+    assert L.nnls_column_scales(10, 10, FAKE, 10, N.F32, FAKE, FAKE, 0, None) == N.E_WORKSPACE
+    assert L.nnls_gram_rescaled(10, 10, 1, FAKE, 10, FAKE, 1, N.GRAM_BF16X3, N.F32, None, FAKE,
+                                FAKE, FAKE, big, None) == N.E_ARG
+    assert L.nnls_gram_rescaled(10, 10, 1, FAKE, 10, None, 1, N.GRAM_BF16X3, N.F32, FAKE, FAKE,
+                                FAKE, FAKE, big, None) == N.E_ARG
+    assert L.nnls_gram_rescaled(10, 10, 1, FAKE, 10, FAKE, 1, N.GRAM_FP64, N.F32, FAKE, FAKE,
+                                FAKE, FAKE, big, None) == N.E_ARG
 
 
 def test_refine_rejects_bad_arguments(L):

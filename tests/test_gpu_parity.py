@@ -219,3 +219,72 @@ def test_warm_start_at_solution():
     Y2, it2, kkt2, st2 = N.solve(Q, q, None, tol=1e-6, max_iter=100000, Y0=Y)
     assert np.all(host(it2) == 0) and np.all(host(st2) == N.CONVERGED)
     assert np.array_equal(host(Y2), host(Y))
+
+
+# ---------------------------------------------------------------------------- persistent solver
+@pytest.fixture
+def force_persistent(monkeypatch):
+    monkeypatch.setenv("NNLS_SOLVER", "persistent")
+    yield
+    monkeypatch.delenv("NNLS_SOLVER", raising=False)
+
+
+@pytest.mark.parametrize("n", [512, 1024, 2000])
+def test_persistent_steps_match_oracle(n, force_persistent):
+    """Whole-GPU solver, one update from the oracle's state (as for the per-column solver)."""
+    say(f"persistent single steps n={n}")
+    A, B = _uniform_case(21, 2 * n, n, 1)
+    Q, q, s = N.prepare(dev(A), dev(B))
+    Qh, qh = host(Q).astype(np.float64), host(q).astype(np.float64)[:, 0]
+    eps = 2.0 ** -23
+    for m in [0, 1, 2, 5, 20]:
+        ym = orc().nqp(Qh, qh, 0.0, m)[0] if m else np.zeros(n)
+        ystart = ym.astype(np.float32).astype(np.float64)
+        yn = orc().nqp(Qh, qh, 0.0, 1, y0=ystart)[0]
+        Y, iters, kkt, st = N.solve(Q, q, None, tol=0.0, max_iter=1,
+                                    Y0=dev(ym.astype(np.float32).reshape(n, 1)) if m else None)
+        Yh = host(Y)[:, 0].astype(np.float64)
+        assert host(iters)[0] == 1
+        err = np.abs(Yh - yn).max()
+        scale = np.abs(ystart).max() + np.abs(yn).max()
+        assert err <= 8 * n * eps * scale, (m, err / scale)
+
+
+@pytest.mark.parametrize("d,n,seed", [(1500, 512, 4), (6000, 2000, 5), (9000, 3072, 6)])
+def test_persistent_end_to_end(d, n, seed):
+    """Large single right-hand sides (n >= 1536 takes the whole-GPU solver by default)."""
+    say(f"persistent e2e d={d} n={n}")
+    A, b, _ = W.make_large(seed=seed, d=d, n=n)
+    import os
+    old = os.environ.get("NNLS_SOLVER")
+    os.environ["NNLS_SOLVER"] = "persistent"
+    try:
+        res = N.nnls(dev(A), dev(b), tol=1e-5, max_iter=100000, inner_tol=3e-6)
+    finally:
+        if old is None:
+            del os.environ["NNLS_SOLVER"]
+        else:
+            os.environ["NNLS_SOLVER"] = old
+    assert host(res["status"])[0] == N.CONVERGED
+    ref = O.reference_solution(A, b)
+    _check_solution(A, b, host(res["X"]), 1e-5, ref, f"persistent n={n}")
+
+
+def test_persistent_statuses(force_persistent):
+    say("persistent statuses")
+    A, B = _uniform_case(22, 3000, 1024, 1)
+    Q, q, s = N.prepare(dev(A), dev(B))
+    X, it, kkt, st = N.solve(Q, q, s, tol=1e-12, max_iter=4)
+    assert host(st)[0] == N.MAXITER and host(it)[0] == 4
+    Y, it, kkt, st = N.solve(Q, q, None, tol=1e-6, max_iter=100000)
+    assert host(st)[0] == N.CONVERGED
+    Y2, it2, kkt2, st2 = N.solve(Q, q, None, tol=1e-6, max_iter=100000, Y0=Y)
+    assert host(it2)[0] == 0 and host(st2)[0] == N.CONVERGED
+    assert np.array_equal(host(Y2), host(Y))
+    qb = q.clone()
+    qb[7, 0] = float("nan")
+    X, it, kkt, st = N.solve(Q, qb, s, tol=1e-6, max_iter=50)
+    assert host(st)[0] == N.NONFINITE
+    qp = q.abs()
+    X, it, kkt, st = N.solve(Q, qp, s, tol=1e-6, max_iter=50)
+    assert host(st)[0] == N.CONVERGED and host(it)[0] == 0 and np.all(host(X) == 0)
