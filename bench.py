@@ -28,7 +28,9 @@ PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2516.6
 PEAK_BF16X3_TFLOPS = PEAK_BF16_TFLOPS / 3.0   # three bf16 products per FP32-equivalent product
 TOL = 1e-5
-INNER_TOL = 5e-6
+# The solve runs to 0.8 tol in FP32 on the BF16x3 Q; the FP64 check against (A, b) is what
+# must meet tol (it differs from the FP32 residual by ~1e-7 at this workload).
+INNER_TOL = 8e-6
 
 
 def _src_sha(path):

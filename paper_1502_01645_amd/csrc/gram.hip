@@ -11,6 +11,8 @@
 //               accuracy cross-check).
 // Split-K over the rows of A is available for shapes with few output tiles; the partial tiles
 // then go through gram_splitk_epilogue.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -90,13 +92,29 @@ __device__ __forceinline__ void decode_tile(int tile, int tiles_aug, int& ti, in
 
 // ---------------------------------------------------------------------------------------------
 // BF16x3 Gram on the matrix cores.  128 x 128 tile per workgroup of 4 waves (2 x 2 waves of
-// 64 x 64), K staged 32 rows at a time.  LDS holds hi and lo parts of both panels, column-major
-// (32 consecutive k of one column contiguous, rows padded to 40 bf16 = 80 bytes so that the
-// 16-byte accesses of 16 consecutive lanes hit distinct banks).
+// 64 x 64), K staged 32 rows at a time through a two-slot LDS ring: while the waves run the
+// MFMAs of slot s, the next chunk (already in registers) is converted and written to slot s^1
+// and the chunk after it is fetched from memory, so one barrier per K step suffices.
+// LDS holds the hi and lo parts of both panels, column-major (32 consecutive k of one column
+// contiguous, padded to 40 bf16 = 80 bytes so the 16-byte accesses of 16 consecutive lanes hit
+// distinct banks).  The split uses the hardware packed conversion (round to nearest even).
+//
+// Tile schedule: workgroup b runs on XCD b % 8 (round-robin dispatch).  Tiles are grouped in
+// blocks of 4 tile rows x 8 tile columns; group g belongs to XCD g % 8, so the ~32 tiles an XCD
+// runs at a time read 4 + 8 panels through its own L2 instead of up to 64.
 // ---------------------------------------------------------------------------------------------
 constexpr int GB_BM = 128;
 constexpr int GB_BK = 32;
 constexpr int GB_LDK = 40;  // padded k stride in bf16 units
+constexpr int GB_PANEL = GB_BM * GB_LDK;     // bf16 per panel part (hi or lo)
+constexpr int GB_SLOT = 4 * GB_PANEL;        // Xh, Xl, Yh, Yl
+constexpr int GB_LDS_BYTES = 2 * GB_SLOT * 2;
+constexpr int GB_GROUP_ROWS = 4;
+constexpr int GB_GROUP_COLS = 8;
+constexpr int GB_XCDS = 8;
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 struct GramPanelPtr {
   const float* base;
@@ -120,17 +138,88 @@ __device__ __forceinline__ GramPanelPtr panel_column(int64_t col, int64_t n, int
   return p;
 }
 
-__global__ __launch_bounds__(256) void gram_bf16x3_kernel(
+// Number of tiles (ti, tj), ti <= tj, in group (band, chunk).
+__device__ __forceinline__ int group_size(int band, int chunk, int tiles_a, int tiles_aug) {
+  const int r0 = band * GB_GROUP_ROWS;
+  const int r1 = min(r0 + GB_GROUP_ROWS, tiles_a);
+  const int c0 = r0 + chunk * GB_GROUP_COLS;
+  const int c1 = min(c0 + GB_GROUP_COLS, tiles_aug);
+  int cnt = 0;
+  for (int ti = r0; ti < r1; ++ti) {
+    const int lo = max(c0, ti);
+    cnt += c1 > lo ? c1 - lo : 0;
+  }
+  return cnt;
+}
+
+// Tile of workgroup b under the XCD-grouped schedule; false if b has no tile.
+__device__ bool schedule_tile(int b, int tiles_a, int tiles_aug, int& ti, int& tj) {
+  const int xcd = b % GB_XCDS;
+  int slot = b / GB_XCDS;
+  const int bands = (tiles_a + GB_GROUP_ROWS - 1) / GB_GROUP_ROWS;
+  int g = 0;
+  for (int band = 0; band < bands; ++band) {
+    const int r0 = band * GB_GROUP_ROWS;
+    const int chunks = (tiles_aug - r0 + GB_GROUP_COLS - 1) / GB_GROUP_COLS;
+    for (int chunk = 0; chunk < chunks; ++chunk, ++g) {
+      if (g % GB_XCDS != xcd) continue;
+      const int sz = group_size(band, chunk, tiles_a, tiles_aug);
+      if (slot >= sz) {
+        slot -= sz;
+        continue;
+      }
+      const int c0 = r0 + chunk * GB_GROUP_COLS;
+      const int c1 = min(c0 + GB_GROUP_COLS, tiles_aug);
+      const int r1 = min(r0 + GB_GROUP_ROWS, tiles_a);
+      for (int t = r0; t < r1; ++t) {
+        const int lo = max(c0, t);
+        const int w = c1 > lo ? c1 - lo : 0;
+        if (slot < w) {
+          ti = t;
+          tj = lo + slot;
+          return true;
+        }
+        slot -= w;
+      }
+    }
+  }
+  return false;
+}
+
+// Host mirror of the schedule: workgroups needed = 8 x the largest per-XCD tile count.
+static int schedule_blocks(int tiles_a, int tiles_aug) {
+  int per[GB_XCDS] = {0};
+  const int bands = (tiles_a + GB_GROUP_ROWS - 1) / GB_GROUP_ROWS;
+  int g = 0;
+  for (int band = 0; band < bands; ++band) {
+    const int r0 = band * GB_GROUP_ROWS;
+    const int chunks = (tiles_aug - r0 + GB_GROUP_COLS - 1) / GB_GROUP_COLS;
+    for (int chunk = 0; chunk < chunks; ++chunk, ++g) {
+      const int c0 = r0 + chunk * GB_GROUP_COLS;
+      const int c1 = std::min(c0 + GB_GROUP_COLS, tiles_aug);
+      const int r1 = std::min(r0 + GB_GROUP_ROWS, tiles_a);
+      int cnt = 0;
+      for (int ti = r0; ti < r1; ++ti) {
+        const int lo = std::max(c0, ti);
+        cnt += c1 > lo ? c1 - lo : 0;
+      }
+      per[g % GB_XCDS] += cnt;
+    }
+  }
+  int mx = 0;
+  for (int x = 0; x < GB_XCDS; ++x) mx = std::max(mx, per[x]);
+  return mx * GB_XCDS;
+}
+
+__global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
     int64_t d, int64_t n, int64_t k, const float* __restrict__ A, int64_t lda,
     const float* __restrict__ B, int64_t ldb, const double* __restrict__ s, float* __restrict__ Q,
-    float* __restrict__ q, float* __restrict__ partial, int tiles_aug, int64_t rows_per_split) {
-  __shared__ __attribute__((aligned(16))) uint16_t sXh[GB_BM * GB_LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t sXl[GB_BM * GB_LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t sYh[GB_BM * GB_LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t sYl[GB_BM * GB_LDK];
+    float* __restrict__ q, float* __restrict__ partial, int tiles_a, int tiles_aug,
+    int64_t rows_per_split) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
 
   int ti, tj;
-  decode_tile(blockIdx.x, tiles_aug, ti, tj);
+  if (!schedule_tile(blockIdx.x, tiles_a, tiles_aug, ti, tj)) return;
   const bool diag = (ti == tj);
   const int64_t i0 = (int64_t)ti * GB_BM, j0 = (int64_t)tj * GB_BM;
   const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
@@ -161,67 +250,86 @@ __global__ __launch_bounds__(256) void gram_bf16x3_kernel(
       ry[u] = (!diag && ok && py.base) ? py.base[r * py.ld] : 0.f;
     }
   };
-  auto store_chunk = [&]() {
-    uint32_t hx[8], lx[8], hy[8], ly[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      uint32_t h0, l0, h1, l1;
-      split_bf16(rx[2 * u], h0, l0);
-      split_bf16(rx[2 * u + 1], h1, l1);
-      hx[u] = h0 | (h1 << 16);
-      lx[u] = l0 | (l1 << 16);
-      if (!diag) {
-        split_bf16(ry[2 * u], h0, l0);
-        split_bf16(ry[2 * u + 1], h1, l1);
-        hy[u] = h0 | (h1 << 16);
-        ly[u] = l0 | (l1 << 16);
-      }
-    }
+  // hi / lo split of one pair of staged values (hardware round to nearest even)
+  auto split_pair = [](float v0, float v1, uint32_t& h, uint32_t& l) {
+    const f32x2 x = {v0, v1};
+    const bf16x2 hb = __builtin_convertvector(x, bf16x2);
+    const f32x2 hf = __builtin_convertvector(hb, f32x2);
+    const bf16x2 lb = __builtin_convertvector(x - hf, bf16x2);
+    h = __builtin_bit_cast(uint32_t, hb);
+    l = __builtin_bit_cast(uint32_t, lb);
+  };
+  uint32_t hx[8], lx[8], hy[8], ly[8];
+  auto write_chunk = [&](int slot) {
+    uint16_t* base = lds + slot * GB_SLOT;
     const int off = lc * GB_LDK + kh * 16;
-    *(u32x4*)&sXh[off] = (u32x4){hx[0], hx[1], hx[2], hx[3]};
-    *(u32x4*)&sXh[off + 8] = (u32x4){hx[4], hx[5], hx[6], hx[7]};
-    *(u32x4*)&sXl[off] = (u32x4){lx[0], lx[1], lx[2], lx[3]};
-    *(u32x4*)&sXl[off + 8] = (u32x4){lx[4], lx[5], lx[6], lx[7]};
+    *(u32x4*)&base[off] = (u32x4){hx[0], hx[1], hx[2], hx[3]};
+    *(u32x4*)&base[off + 8] = (u32x4){hx[4], hx[5], hx[6], hx[7]};
+    *(u32x4*)&base[GB_PANEL + off] = (u32x4){lx[0], lx[1], lx[2], lx[3]};
+    *(u32x4*)&base[GB_PANEL + off + 8] = (u32x4){lx[4], lx[5], lx[6], lx[7]};
     if (!diag) {
-      *(u32x4*)&sYh[off] = (u32x4){hy[0], hy[1], hy[2], hy[3]};
-      *(u32x4*)&sYh[off + 8] = (u32x4){hy[4], hy[5], hy[6], hy[7]};
-      *(u32x4*)&sYl[off] = (u32x4){ly[0], ly[1], ly[2], ly[3]};
-      *(u32x4*)&sYl[off + 8] = (u32x4){ly[4], ly[5], ly[6], ly[7]};
+      *(u32x4*)&base[2 * GB_PANEL + off] = (u32x4){hy[0], hy[1], hy[2], hy[3]};
+      *(u32x4*)&base[2 * GB_PANEL + off + 8] = (u32x4){hy[4], hy[5], hy[6], hy[7]};
+      *(u32x4*)&base[3 * GB_PANEL + off] = (u32x4){ly[0], ly[1], ly[2], ly[3]};
+      *(u32x4*)&base[3 * GB_PANEL + off + 8] = (u32x4){ly[4], ly[5], ly[6], ly[7]};
     }
   };
 
-  const uint16_t* yh = diag ? sXh : sYh;
-  const uint16_t* yl = diag ? sXl : sYl;
   const int wm = (wave >> 1) * 64;
   const int wn = (wave & 1) * 64;
   const int frag_row = lane & 15;
   const int frag_k = (lane >> 4) * 8;
 
-  if (r_begin < r_end) load_chunk(r_begin);
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += GB_BK) {
-    __syncthreads();  // previous chunk fully consumed
-    store_chunk();
+  const int64_t nsteps = r_end > r_begin ? (r_end - r_begin + GB_BK - 1) / GB_BK : 0;
+  if (nsteps > 0) {
+    load_chunk(r_begin);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      split_pair(rx[2 * u], rx[2 * u + 1], hx[u], lx[u]);
+      split_pair(ry[2 * u], ry[2 * u + 1], hy[u], ly[u]);
+    }
+    write_chunk(0);
+    if (nsteps > 1) load_chunk(r_begin + GB_BK);
     __syncthreads();
-    if (r0 + GB_BK < r_end) load_chunk(r0 + GB_BK);  // prefetch overlaps the MFMAs below
-
+  }
+  for (int64_t step = 0; step < nsteps; ++step) {
+    const int slot = (int)(step & 1);
+    const uint16_t* xh = lds + slot * GB_SLOT;
+    const uint16_t* xl = xh + GB_PANEL;
+    const uint16_t* yh = diag ? xh : xh + 2 * GB_PANEL;
+    const uint16_t* yl = diag ? xl : xh + 3 * GB_PANEL;
     bf16x8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int xo = (wm + t * 16 + frag_row) * GB_LDK + frag_k;
       const int yo = (wn + t * 16 + frag_row) * GB_LDK + frag_k;
-      ah[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&sXh[xo]);
-      al[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&sXl[xo]);
+      ah[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&xh[xo]);
+      al[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&xl[xo]);
       bh[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&yh[yo]);
       bl[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&yl[yo]);
     }
+    // MFMAs of this slot with the split of the staged next chunk interleaved: the conversion
+    // is independent register work the wave issues while the matrix core is busy.  (On the
+    // last step the staged registers hold stale values; converting and writing them to the
+    // idle slot is harmless.)
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+      for (int u = 2 * a; u < 2 * a + 2; ++u) {
+        split_pair(rx[2 * u], rx[2 * u + 1], hx[u], lx[u]);
+        split_pair(ry[2 * u], ry[2 * u + 1], hy[u], ly[u]);
+      }
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
       }
+      // the staged registers are free once the last pair is split
+      if (a == 3 && step + 2 < nsteps) load_chunk(r_begin + (step + 2) * GB_BK);
+    }
+    write_chunk(slot ^ 1);
+    __syncthreads();
   }
 
   // D fragment layout of the 16x16 MFMA: lane holds column (lane & 15), rows 4*(lane>>4)+e.
@@ -239,7 +347,12 @@ __global__ __launch_bounds__(256) void gram_bf16x3_kernel(
           gram_emit<float, float>(i, j, acc[a][b][e], n, k, s, Q, q, diag);
         }
   } else {
-    float* dst = partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (GB_BM * GB_BM);
+    // partial tiles are indexed by (ti, tj) in the plain row-major tile order
+    int tile = 0;
+    for (int t = 0; t < ti; ++t) tile += tiles_aug - t;
+    tile += tj - ti;
+    const int ntiles = tiles_a * tiles_aug - tiles_a * (tiles_a - 1) / 2;
+    float* dst = partial + ((int64_t)blockIdx.y * ntiles + tile) * (GB_BM * GB_BM);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -394,9 +507,13 @@ hipError_t launch_gram_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, i
   const int splits = gram_bf16x3_splits(d, n, k);
   int64_t rows = (d + splits - 1) / splits;
   rows = (rows + GB_BK - 1) / GB_BK * GB_BK;
-  dim3 grid((unsigned)nt, (unsigned)splits);
-  hipLaunchKernelGGL(gram_bf16x3_kernel, grid, dim3(256), 0, st, d, n, k, A, lda, B, ldb, s, Q, q,
-                     splits > 1 ? ws : (float*)nullptr, taug, rows);
+  const int blocks = schedule_blocks(ta, taug);
+  dim3 grid((unsigned)blocks, (unsigned)splits);
+  hipError_t e = hipFuncSetAttribute((const void*)gram_bf16x3_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, GB_LDS_BYTES);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gram_bf16x3_kernel, grid, dim3(256), GB_LDS_BYTES, st, d, n, k, A, lda, B,
+                     ldb, s, Q, q, splits > 1 ? ws : (float*)nullptr, ta, taug, rows);
   if (splits > 1)
     hipLaunchKernelGGL(gram_splitk_epilogue_kernel, dim3((unsigned)nt), dim3(256), 0, st, n, k,
                        (const float*)ws, splits, nt, taug, s, Q, q);

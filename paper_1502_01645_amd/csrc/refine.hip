@@ -47,6 +47,132 @@ __global__ __launch_bounds__(256) void rows_residual_kernel(int64_t d, int64_t n
   }
 }
 
+// Vectorized form of the same product for FP32 A with 16-byte aligned rows (lda % 4 == 0): each
+// wave takes RF_RPW rows at once, each lane 4 consecutive columns per step, so one load of x
+// serves RF_RPW rows and RF_RPW independent 16-byte loads of A are in flight per step.
+constexpr int RF_RPW = 4;
+
+template <typename TX>
+__device__ __forceinline__ void load_x4(const TX* X, int64_t i, int64_t k, int c, double* xv) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) xv[e] = (double)X[(i + e) * k + c];
+}
+
+template <typename TX>
+__global__ __launch_bounds__(256) void rows_residual_vec_kernel(int64_t d, int64_t n, int64_t k,
+                                                                const float* __restrict__ A,
+                                                                int64_t lda,
+                                                                const TX* __restrict__ X,
+                                                                const float* __restrict__ B,
+                                                                int64_t ldb,
+                                                                double* __restrict__ R) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RF_RPW;
+  if (r0 >= d) return;
+  double acc[RF_RPW][RF_SMALL_K];
+#pragma unroll
+  for (int q = 0; q < RF_RPW; ++q)
+#pragma unroll
+    for (int c = 0; c < RF_SMALL_K; ++c) acc[q][c] = 0.0;
+  for (int64_t i = 4 * lane; i < n; i += 256) {
+    f32x4 a[RF_RPW];
+#pragma unroll
+    for (int q = 0; q < RF_RPW; ++q)
+      a[q] = (r0 + q < d) ? *(const f32x4*)(A + (r0 + q) * lda + i) : (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < RF_SMALL_K; ++c) {
+      if (c < k) {
+        double xv[4];
+        load_x4(X, i, k, c, xv);
+#pragma unroll
+        for (int q = 0; q < RF_RPW; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[q][c] += (double)a[q][e] * xv[e];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RF_RPW; ++q) {
+#pragma unroll
+    for (int c = 0; c < RF_SMALL_K; ++c) {
+      if (c < k) {
+        const double v = wave_sum(acc[q][c]);
+        if (lane == 0 && r0 + q < d)
+          R[(r0 + q) * k + c] = v - (B ? (double)B[(r0 + q) * ldb + c] : 0.0);
+      }
+    }
+  }
+}
+
+// Vectorized A^T V for FP32 A with aligned rows: each thread owns 4 consecutive columns of a
+// 1024-column block and walks the rows of its chunk 8 at a time (8 independent 16-byte loads in
+// flight).  Same partial layout as cols_partial_kernel.
+template <int KV>
+__global__ __launch_bounds__(256) void cols_partial_vec_kernel(int64_t d, int64_t n,
+                                                               const float* __restrict__ A,
+                                                               int64_t lda,
+                                                               const double* __restrict__ R,
+                                                               const float* __restrict__ B,
+                                                               int64_t ldb, int with_b,
+                                                               int64_t rows_per_chunk,
+                                                               double* __restrict__ partial) {
+  constexpr int k = KV;
+  const int64_t i = (int64_t)blockIdx.x * 1024 + 4 * threadIdx.x;
+  const int64_t chunk = blockIdx.y;
+  if (i >= n) return;
+  const int64_t r0 = chunk * rows_per_chunk;
+  const int64_t r1 = r0 + rows_per_chunk < d ? r0 + rows_per_chunk : d;
+  const int nvec = with_b ? 2 * k + 1 : k;
+  double acc[2 * KV + 1][4];
+#pragma unroll
+  for (int m = 0; m < 2 * KV + 1; ++m)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[m][e] = 0.0;
+  int64_t r = r0;
+  for (; r + 7 < r1; r += 8) {
+    f32x4 a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = *(const f32x4*)(A + (r + u) * lda + i);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+#pragma unroll
+      for (int c = 0; c < k; ++c) {
+        const double rv = R[(r + u) * k + c];
+        const double bv = with_b ? (double)B[(r + u) * ldb + c] : 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          acc[c][e] += (double)a[u][e] * rv;
+          if (with_b) acc[k + c][e] += (double)a[u][e] * bv;
+        }
+      }
+      if (with_b) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[2 * k][e] += (double)a[u][e] * (double)a[u][e];
+      }
+    }
+  }
+  for (; r < r1; ++r) {
+    const f32x4 a = *(const f32x4*)(A + r * lda + i);
+#pragma unroll
+    for (int c = 0; c < k; ++c) {
+      const double rv = R[r * k + c];
+      const double bv = with_b ? (double)B[r * ldb + c] : 0.0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc[c][e] += (double)a[e] * rv;
+        if (with_b) acc[k + c][e] += (double)a[e] * bv;
+      }
+    }
+    if (with_b) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[2 * k][e] += (double)a[e] * (double)a[e];
+    }
+  }
+  for (int m = 0; m < nvec; ++m)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) partial[(chunk * nvec + m) * n + i + e] = acc[m][e];
+}
+
 // partial[chunk, m, i] = sum over rows of the chunk of A[r, i] * V_m[r] where the m-th vector is
 // column m of R (m < k), column m - k of B (k <= m < 2k), and A[r, i] itself (m = 2k, giving the
 // squared column norm).  nvec = 2k + 1 when with_b, else k.
@@ -299,9 +425,11 @@ struct RefineWs {
   int64_t chunks;
 };
 
+// Row chunks of the A^T V passes: enough workgroups to fill the GPU a few times over with
+// 1024-column (vector path) or 256-column blocks; the partial sums cost chunks * n doubles.
 static int64_t refine_chunks(int64_t d, int64_t n) {
-  const int64_t bx = (n + 255) / 256;
-  int64_t chunks = (1024 + bx - 1) / bx;
+  const int64_t bx = (n + 1023) / 1024;
+  int64_t chunks = (768 + bx - 1) / bx;
   if (chunks > d) chunks = d;
   return chunks < 1 ? 1 : chunks;
 }
@@ -328,11 +456,23 @@ size_t refine_ws_bytes(int64_t d, int64_t n, int64_t k) {
   return el * sizeof(double) + 256;
 }
 
+static bool vec_ok(const void* A, int64_t lda, int64_t n, size_t elem) {
+  return elem == 4 && (lda % 4) == 0 && (n % 4) == 0 && (((uintptr_t)A) & 15) == 0;
+}
+
 template <typename T>
 static void launch_resid(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda,
                          const void* X, bool x_is_double, const T* B, int64_t ldb, double* R,
                          hipStream_t st) {
-  if (k <= RF_SMALL_K) {
+  if (k <= RF_SMALL_K && vec_ok(A, lda, n, sizeof(T))) {
+    dim3 grid((unsigned)((d + 4 * RF_RPW - 1) / (4 * RF_RPW)));
+    if (x_is_double)
+      hipLaunchKernelGGL(rows_residual_vec_kernel<double>, grid, dim3(256), 0, st, d, n, k,
+                         (const float*)A, lda, (const double*)X, (const float*)B, ldb, R);
+    else
+      hipLaunchKernelGGL(rows_residual_vec_kernel<float>, grid, dim3(256), 0, st, d, n, k,
+                         (const float*)A, lda, (const float*)X, (const float*)B, ldb, R);
+  } else if (k <= RF_SMALL_K) {
     dim3 grid((unsigned)((d + 3) / 4));
     if (x_is_double)
       hipLaunchKernelGGL((rows_residual_kernel<T, double>), grid, dim3(256), 0, st, d, n, k, A, lda,
@@ -355,7 +495,21 @@ template <typename T>
 static void launch_atr(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda, const double* R,
                        const T* B, int64_t ldb, bool with_b, RefineWs& w, double* G,
                        hipStream_t st) {
-  if (k <= RF_SMALL_K) {
+  if (k <= RF_SMALL_K && vec_ok(A, lda, n, sizeof(T))) {
+    const int64_t rows = (d + w.chunks - 1) / w.chunks;
+    dim3 g1((unsigned)((n + 1023) / 1024), (unsigned)w.chunks);
+    const float* Af = (const float*)A;
+    const float* Bf = (const float*)B;
+    const int wb = with_b ? 1 : 0;
+    switch (k) {
+      case 1: hipLaunchKernelGGL(cols_partial_vec_kernel<1>, g1, dim3(256), 0, st, d, n, Af, lda, R, Bf, ldb, wb, rows, w.partial); break;
+      case 2: hipLaunchKernelGGL(cols_partial_vec_kernel<2>, g1, dim3(256), 0, st, d, n, Af, lda, R, Bf, ldb, wb, rows, w.partial); break;
+      case 3: hipLaunchKernelGGL(cols_partial_vec_kernel<3>, g1, dim3(256), 0, st, d, n, Af, lda, R, Bf, ldb, wb, rows, w.partial); break;
+      default: hipLaunchKernelGGL(cols_partial_vec_kernel<4>, g1, dim3(256), 0, st, d, n, Af, lda, R, Bf, ldb, wb, rows, w.partial); break;
+    }
+    hipLaunchKernelGGL(cols_finalize_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+                       k, wb, w.chunks, (const double*)w.partial, G, w.Atb, w.s);
+  } else if (k <= RF_SMALL_K) {
     const int64_t rows = (d + w.chunks - 1) / w.chunks;
     dim3 g1((unsigned)((n + 255) / 256), (unsigned)w.chunks);
     hipLaunchKernelGGL(cols_partial_kernel<T>, g1, dim3(256), 0, st, d, n, k, A, lda, R, B, ldb,

@@ -4,16 +4,18 @@
 //   phase 1  every workgroup owns a (column block, passive-row group) pair of the product
 //            w = Q gbar.  Q is symmetric, so only the rows of Q in the passive set are read, each
 //            row segment contiguous; the workgroup writes its partial w over its column block and
-//            its share of den = gbar^T Q gbar.
+//            its share of den = gbar^T Q gbar.  Everything phase 2 needs that does not depend on
+//            alpha (stop statistics, clip thresholds, the owner's own entries) is loaded here too,
+//            so its latency hides behind the product.
 //   -- barrier --
 //   phase 2  every workgroup forms den and alpha, and the clipped set C (entries whose
-//            projection hits zero, known from per-entry thresholds y_i / gbar_i); the owner of each
-//            64-entry chunk sums the partials of w, adds the clip correction Q[C, i] * delta_C,
-//            updates y and the gradient, and publishes the next passive mask, masked gradient,
-//            clip thresholds and its share of the stop statistics.
+//            projection hits zero: y_i / gbar_i < alpha); the owner of each 64-entry chunk sums
+//            the partials of w, adds the clip correction Q[C, i] * delta_C, updates y and the
+//            gradient, and publishes the next passive mask, masked gradient, clip thresholds
+//            and its share of the stop statistics.
 //   -- barrier --
-// The gradient of a converged iterate is recomputed exactly (Q y + q over rows with y > 0)
-// before the stop is accepted.
+// The stop test of an iterate is evaluated during the next phase 1; a converged gradient is
+// recomputed exactly (Q y + q over the rows with y > 0) before the stop is accepted.
 //
 // Cross-workgroup state (y, gradient, masks, partials, statistics) is written and read with
 // agent-scope relaxed atomics, which on gfx950 are sc1 accesses that bypass the per-XCD L2, so
@@ -27,12 +29,16 @@
 
 namespace nnls {
 
-constexpr int SP_NT = 256;     // threads per workgroup
-constexpr int SP_CB = 1024;    // columns per block in phase 1 (4 per thread)
+constexpr int SP_NT = 512;     // threads per workgroup (8 waves)
+constexpr int SP_NW = SP_NT / kWave;
+constexpr int SP_CB = 1024;    // columns per block in phase 1 (4 per thread, two row halves)
 constexpr int SP_CHUNK = 64;   // entries per owner chunk (one wave, one 64-bit mask word)
 constexpr int SP_GROUPS = 8;   // barrier arrival groups
 constexpr int SP_BAR_WORDS = 1024;
-constexpr int SP_TPT = 64;     // clip thresholds held per thread: n <= SP_NT * SP_TPT
+constexpr int SP_TPT = 32;     // clip thresholds held per thread: n <= SP_NT * SP_TPT
+constexpr int64_t SP_MAX_N = (int64_t)SP_NT * SP_TPT;
+constexpr size_t SP_MAX_LDS = 160 * 1024;
+constexpr int SP_RPT = 4;      // row-range entries per thread in phase 1: n / R <= SP_NT * SP_RPT
 
 __device__ __forceinline__ float ld_sc(const float* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -48,7 +54,7 @@ __device__ __forceinline__ void st_sc(uint64_t* p, uint64_t v) {
 }
 
 struct SpArgs {
-  int n, G, nb, R, nw, cmax, rows_max;
+  int n, G, nb, R, nw, rows_max;
   const float* Q;
   const float* q;
   const double* s;
@@ -97,129 +103,120 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, int G, unsigned& epo
   __syncthreads();
 }
 
-// Sum of one float per thread over the workgroup (two barriers).
 __device__ __forceinline__ float sp_block_sum(float v, float* red) {
   return block_sum<float, SP_NT>(v, red);
 }
 
-// Compacted positions [lo, hi) of the set bits of mask[0..nw) in index order, written to
-// idx[0..hi-lo).  Each thread scans a contiguous run of words.  Returns the total bit count.
-__device__ int select_bits(const uint64_t* mask, int nw, int lo, int hi, int* idx, int* redI) {
-  const int per = (nw + SP_NT - 1) / SP_NT;
-  const int w0 = threadIdx.x * per;
-  const int w1 = w0 + per < nw ? w0 + per : nw;
-  int cnt = 0;
-  for (int m = w0; m < w1; ++m) cnt += __popcll(ld_sc(mask + m));
-  int total;
-  int pos = block_exclusive_scan<SP_NT>(cnt, redI, total);
-  for (int m = w0; m < w1 && pos < hi; ++m) {
-    uint64_t bits = ld_sc(mask + m);
-    while (bits) {
-      const int b = __ffsll((long long)bits) - 1;
-      bits &= bits - 1;
-      if (pos >= lo && pos < hi) idx[pos - lo] = m * 64 + b;
-      ++pos;
-    }
-  }
-  __syncthreads();
-  return total;
-}
+struct SpLds {
+  int* rowidx;    // [rows_max]
+  float* rowval;  // [rows_max]
+  int* cidx;      // [n]
+  float* cval;    // [n]
+  float* half;    // [256 * 4] second-half partial of the row product
+  float* wred;    // [SP_NW][64]
+  float* cred;    // [SP_NW][64]
+  float* stats;   // [8]
+  float* redF;    // [SP_NW]
+  int* redI;      // [SP_NW]
+};
 
-// Phase-1 product over the rows selected by `mask` with row weights vec[row]: this workgroup's
-// rows are the compacted range of its row group; the partial over its column block goes to
-// part[r, block].  Returns this workgroup's share of dot(result, vec_block) (only meaningful
-// for the line-search product, where vec = gbar).
+// Phase-1 product over the rows selected by `mask` with row weights vec[row].  Workgroup g is
+// (column block g % nb, row group g / nb); row group r takes the selected rows whose index lies
+// in [n r / R, n (r + 1) / R), so it needs only its own mask words and weights (one round of
+// loads, no grid-wide scan).  Threads t and t + 256 share 4 columns and split the rows by
+// parity.  The partial over the block goes to part[r, block]; returns this workgroup's share of
+// dot(result, vec).
 __device__ float rows_product(const SpArgs& A, const uint64_t* mask, const float* vec,
-                             int* rowidx, float* rowval, int* redI, float* redF, int& nrows) {
+                             const SpLds& L) {
   const int g = blockIdx.x;
   const int c = g % A.nb;
   const int r = g / A.nb;
   const bool active = r < A.R;
-  // every workgroup joins the scan (it contains barriers)
-  int total = 0;
-  int lo = 0, hi = 0;
-  {
-    // first pass: total count to derive this group's range
-    const int per = (A.nw + SP_NT - 1) / SP_NT;
-    const int w0 = threadIdx.x * per;
-    const int w1 = w0 + per < A.nw ? w0 + per : A.nw;
-    int cnt = 0;
-    for (int m = w0; m < w1; ++m) cnt += __popcll(ld_sc(mask + m));
-    total = (int)block_sum<float, SP_NT>((float)cnt, redF);
+  const int n = A.n;
+  const int quad = threadIdx.x & 255;
+  const int half = threadIdx.x >> 8;
+  const int col = c * SP_CB + 4 * quad;
+  const bool own_col = active && col < n;
+  const int i_lo = active ? (int)(((int64_t)n * r) / A.R) : 0;
+  const int i_hi = active ? (int)(((int64_t)n * (r + 1)) / A.R) : 0;
+  const int w_lo = i_lo / 64;
+  const int nwords = active ? (i_hi + 63) / 64 - w_lo : 0;
+  // one round: mask words, row weights of the range, and vec over the own columns
+  uint64_t* words = (uint64_t*)L.half;  // scratch until the partial reduction below
+  for (int m = threadIdx.x; m < nwords; m += SP_NT) words[m] = ld_sc(mask + w_lo + m);
+  const int span = i_hi - i_lo;
+  float wv[SP_RPT];
+#pragma unroll
+  for (int u = 0; u < SP_RPT; ++u) {
+    const int i = i_lo + threadIdx.x + u * SP_NT;
+    wv[u] = (threadIdx.x + u * SP_NT < span) ? ld_sc(vec + i) : 0.f;
   }
-  nrows = total;
-  if (active) {
-    lo = (int)(((int64_t)total * r) / A.R);
-    hi = (int)(((int64_t)total * (r + 1)) / A.R);
+  f32x4 pv = {0.f, 0.f, 0.f, 0.f};
+  if (half == 0 && own_col) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) pv[e] = ld_sc(vec + col + e);
   }
-  select_bits(mask, A.nw, lo, hi, rowidx, redI);
-  const int cnt = hi - lo;
-  for (int k = threadIdx.x; k < cnt; k += SP_NT) rowval[k] = ld_sc(vec + rowidx[k]);
   __syncthreads();
-
-  float dot = 0.f;
-  if (active) {
-    const int col0 = c * SP_CB;
-    const int col = col0 + 4 * threadIdx.x;
-    const int n = A.n;
-    if (col < n) {
-      const int nvalid = n - col < 4 ? n - col : 4;
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      const float* Qc = A.Q + col;
-      int k = 0;
-      if (nvalid == 4) {
-        for (; k + 15 < cnt; k += 16) {
-          f32x4 v[16];
+  int cnt = 0;
 #pragma unroll
-          for (int u = 0; u < 16; ++u) v[u] = *(const f32x4*)(Qc + (int64_t)rowidx[k + u] * n);
+  for (int u = 0; u < SP_RPT; ++u) {
+    const int off = threadIdx.x + u * SP_NT;
+    const int i = i_lo + off;
+    if (off < span && ((words[i / 64 - w_lo] >> (i & 63)) & 1ull)) ++cnt;
+  }
+  int total;
+  int pos = block_exclusive_scan<SP_NT>(cnt, L.redI, total);
 #pragma unroll
-          for (int u = 0; u < 16; ++u) acc += rowval[k + u] * v[u];
-        }
-        for (; k + 3 < cnt; k += 4) {
-          f32x4 v[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) v[u] = *(const f32x4*)(Qc + (int64_t)rowidx[k + u] * n);
-#pragma unroll
-          for (int u = 0; u < 4; ++u) acc += rowval[k + u] * v[u];
-        }
-        for (; k < cnt; ++k) acc += rowval[k] * *(const f32x4*)(Qc + (int64_t)rowidx[k] * n);
-      } else {
-        for (; k < cnt; ++k) {
-          const float* row = Qc + (int64_t)rowidx[k] * n;
-          const float wv = rowval[k];
-          for (int e = 0; e < nvalid; ++e) acc[e] += wv * row[e];
-        }
-      }
-      float* dst = A.part + (int64_t)r * n + col;
-      for (int e = 0; e < nvalid; ++e) {
-        st_sc(dst + e, acc[e]);
-        dot += acc[e] * ld_sc(vec + col + e);
-      }
+  for (int u = 0; u < SP_RPT; ++u) {
+    const int off = threadIdx.x + u * SP_NT;
+    const int i = i_lo + off;
+    if (off < span && ((words[i / 64 - w_lo] >> (i & 63)) & 1ull)) {
+      L.rowidx[pos] = i;
+      L.rowval[pos] = wv[u];
+      ++pos;
     }
   }
-  return sp_block_sum(dot, redF);
-}
+  __syncthreads();
+  const int cnt_rows = total;
 
-// Sum over row groups of the phase-1 partials at entry i, split over the waves: wave v adds
-// groups r = v, v + 4, ...; the caller combines the four wave sums.
-__device__ __forceinline__ float partial_sum(const SpArgs& A, int i, int wave) {
-  constexpr int NW = SP_NT / kWave;
-  float s = 0.f;
-  int r = wave;
-  // eight independent loads in flight per round
-  for (; r + 7 * NW < A.R; r += 8 * NW) {
-    float v[8];
+  float dot = 0.f;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  if (own_col) {
+    const float* Qc = A.Q + col;
+    int k = half;
+    for (; k + 30 < cnt_rows; k += 32) {
+      f32x4 v[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = ld_sc(A.part + (int64_t)(r + u * NW) * A.n + i);
+      for (int u = 0; u < 16; ++u) v[u] = *(const f32x4*)(Qc + (int64_t)L.rowidx[k + 2 * u] * n);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s += v[u];
+      for (int u = 0; u < 16; ++u) acc += L.rowval[k + 2 * u] * v[u];
+    }
+    for (; k + 6 < cnt_rows; k += 8) {
+      f32x4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = *(const f32x4*)(Qc + (int64_t)L.rowidx[k + 2 * u] * n);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += L.rowval[k + 2 * u] * v[u];
+    }
+    for (; k < cnt_rows; k += 2) acc += L.rowval[k] * *(const f32x4*)(Qc + (int64_t)L.rowidx[k] * n);
   }
-  for (; r < A.R; r += NW) s += ld_sc(A.part + (int64_t)r * A.n + i);
-  return s;
+  if (half == 1) *(f32x4*)(L.half + 4 * quad) = acc;
+  __syncthreads();
+  if (half == 0 && own_col) {
+    acc += *(const f32x4*)(L.half + 4 * quad);
+    float* dst = A.part + (int64_t)r * n + col;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      st_sc(dst + e, acc[e]);
+      dot += acc[e] * pv[e];
+    }
+  }
+  return sp_block_sum(dot, L.redF);
 }
 
-// Owner update of one 64-entry chunk by wave 0 after the wave sums are in LDS, publishing the
-// next mask words, masked gradient, thresholds and statistics (accumulated in stats[0..3]).
+// Owner update of one 64-entry chunk by wave 0: publishes y, gradient, masked gradient, clip
+// threshold and mask words into copy `dst`, and adds the chunk's statistics to stats[0..3]
+// (sum of gbar^2, sum of min(y, grad)^2, passive count, non-finite count, count of y > 0).
 __device__ __forceinline__ void publish_entry(const SpArgs& A, int dst, int i, bool valid,
                                               float yi, float gi, int chunk, float* stats) {
   const bool pas = valid && ((yi > 0.f) || (gi < 0.f));
@@ -239,115 +236,176 @@ __device__ __forceinline__ void publish_entry(const SpArgs& A, int dst, int i, b
   }
   const float m = yi < gi ? yi : gi;
   const bool bad = valid && (!__builtin_isfinite(yi) || !__builtin_isfinite(gi));
-  float s_num = wave_sum(valid ? pi * pi : 0.f);
-  float s_res = wave_sum(valid ? m * m : 0.f);
-  float s_cnt = wave_sum(pas ? 1.f : 0.f);
-  float s_bad = wave_sum(bad ? 1.f : 0.f);
+  const float s_num = wave_sum(valid ? pi * pi : 0.f);
+  const float s_res = wave_sum(valid ? m * m : 0.f);
+  const float s_cnt = wave_sum(pas ? 1.f : 0.f);
+  const float s_bad = wave_sum(bad ? 1.f : 0.f);
+  const float s_pos = wave_sum((valid && yi > 0.f) ? 1.f : 0.f);
   if ((threadIdx.x & 63) == 0) {
     stats[0] += s_num;
     stats[1] += s_res;
     stats[2] += s_cnt;
     stats[3] += s_bad;
+    stats[4] += s_pos;
   }
+}
+
+// Sum over row groups of the phase-1 partials at entry i for the groups r = wave (mod 8).
+__device__ __forceinline__ float partial_sum(const SpArgs& A, int i, int wave) {
+  float s = 0.f;
+  int r = wave;
+  for (; r + 7 * SP_NW < A.R; r += 8 * SP_NW) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ld_sc(A.part + (int64_t)(r + u * SP_NW) * A.n + i);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; r < A.R; r += SP_NW) s += ld_sc(A.part + (int64_t)r * A.n + i);
+  return s;
+}
+
+__device__ __forceinline__ void publish_stats(const SpArgs& A, const SpLds& L) {
+  __syncthreads();
+  if (threadIdx.x < 5) st_sc(A.scal + blockIdx.x * 8 + 1 + threadIdx.x, L.stats[threadIdx.x]);
 }
 
 __global__ __launch_bounds__(SP_NT) void solve_persistent_kernel(SpArgs A) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  int* rowidx = (int*)smem;
-  float* rowval = (float*)(rowidx + A.rows_max);
-  int* cidx = (int*)(rowval + A.rows_max);
-  float* cval = (float*)(cidx + A.cmax);
-  float* wred = cval + A.cmax;                 // [4][64] wave partials
-  float* cred = wred + 4 * 64;                 // [4][64]
-  float* stats = cred + 4 * 64;                // [8]
-  float* redF = stats + 8;                     // [8]
-  int* redI = (int*)(redF + 8);                // [8]
+  SpLds L;
+  {
+    unsigned char* p = smem;
+    auto take = [&](size_t bytes) {
+      unsigned char* r = p;
+      p += (bytes + 15) & ~(size_t)15;
+      return (void*)r;
+    };
+    L.rowidx = (int*)take(sizeof(int) * A.rows_max);
+    L.rowval = (float*)take(sizeof(float) * A.rows_max);
+    L.cidx = (int*)take(sizeof(int) * A.n);
+    L.cval = (float*)take(sizeof(float) * A.n);
+    L.half = (float*)take(sizeof(float) * 1024);
+    L.wred = (float*)take(sizeof(float) * SP_NW * 64);
+    L.cred = (float*)take(sizeof(float) * SP_NW * 64);
+    L.stats = (float*)take(sizeof(float) * 8);
+    L.redF = (float*)take(sizeof(float) * SP_NW);
+    L.redI = (int*)take(sizeof(int) * SP_NW);
+  }
 
   const int n = A.n, G = A.G;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nchunks = A.nw;
+  // each workgroup owns at most one 64-entry chunk (n <= 64 G is required on the host)
+  const int chunk = blockIdx.x;
+  const bool owner = chunk < A.nw;
+  const int oi = chunk * SP_CHUNK + lane;  // owned entry of this lane (wave 0)
+  const bool ovalid = owner && oi < n;
   unsigned epoch = 0;
 
-  // ---- start point: y = max(Y0, 0) or 0, gradient = q (refreshed below for a warm start)
-  if (threadIdx.x < 8) stats[threadIdx.x] = 0.f;
+  // ---- start point: y = max(Y0, 0) or 0, gradient = q (refreshed first for a warm start)
+  if (threadIdx.x < 8) L.stats[threadIdx.x] = 0.f;
   __syncthreads();
-  for (int ch = blockIdx.x; ch < nchunks; ch += G) {
-    if (wave == 0) {
-      const int i = ch * SP_CHUNK + lane;
-      const bool valid = i < n;
-      float yi = 0.f, gi = 0.f;
-      if (valid) {
-        gi = A.q[i];
-        if (A.Y0) {
-          yi = A.Y0[i];
-          yi = yi > 0.f ? yi : 0.f;
-        }
+  if (owner && wave == 0) {
+    float yi = 0.f, gi = 0.f;
+    if (ovalid) {
+      gi = A.q[oi];
+      if (A.Y0) {
+        yi = A.Y0[oi];
+        yi = yi > 0.f ? yi : 0.f;
       }
-      publish_entry(A, 0, i, valid, yi, gi, ch, stats);
     }
+    publish_entry(A, 0, oi, ovalid, yi, gi, chunk, L.stats);
   }
-  __syncthreads();
-  if (threadIdx.x < 4) st_sc(A.scal + blockIdx.x * 8 + 1 + threadIdx.x, stats[threadIdx.x]);
+  publish_stats(A, L);
+  float qn2;
+  {
+    float acc = 0.f;
+    for (int i = threadIdx.x; i < n; i += SP_NT) acc += A.q[i] * A.q[i];
+    qn2 = sp_block_sum(acc, L.redF);
+  }
+  const double qscale = qn2 > 0.f ? sqrt((double)qn2) : 1.0;
   grid_barrier(A.bar, G, epoch);
-  int cur = 0;
 
+  int cur = 0;
   int it = 0;
   int64_t rows = 0;  // rows of Q read by the products
   bool fresh = (A.Y0 == nullptr);
   bool need_refresh = (A.Y0 != nullptr);
   int status = NNLS_MAXITER_DEV;
   double r_now = 0.0;
-  float qn2;
-  {
-    float acc = 0.f;
-    for (int i = threadIdx.x; i < n; i += SP_NT) acc += A.q[i] * A.q[i];
-    qn2 = sp_block_sum(acc, redF);
-  }
-  const double qscale = qn2 > 0.f ? sqrt((double)qn2) : 1.0;
 
   for (;;) {
     if (need_refresh) {
       // gradient = Q y + q over the rows with y > 0
-      int nr;
-      rows_product(A, A.ymask[cur], A.y[cur], rowidx, rowval, redI, redF, nr);
-      rows += nr;
+      {
+        const float v = (threadIdx.x < G) ? ld_sc(A.scal + threadIdx.x * 8 + 5) : 0.f;
+        rows += (int64_t)sp_block_sum(v, L.redF);
+      }
+      rows_product(A, A.ymask[cur], A.y[cur], L);
       grid_barrier(A.bar, G, epoch);
-      if (threadIdx.x < 8) stats[threadIdx.x] = 0.f;
+      if (threadIdx.x < 8) L.stats[threadIdx.x] = 0.f;
       __syncthreads();
-      for (int ch = blockIdx.x; ch < nchunks; ch += G) {
-        const int i = ch * SP_CHUNK + lane;
-        const bool valid = i < n;
-        wred[wave * 64 + lane] = valid ? partial_sum(A, i, wave) : 0.f;
+      if (owner) {
+        L.wred[wave * 64 + lane] = (oi < n) ? partial_sum(A, oi, wave) : 0.f;
         __syncthreads();
         if (wave == 0) {
-          const float w = wred[lane] + wred[64 + lane] + wred[128 + lane] + wred[192 + lane];
-          const float yi = valid ? ld_sc(A.y[cur] + i) : 0.f;
-          const float gi = valid ? A.q[i] + w : 0.f;
-          publish_entry(A, cur ^ 1, i, valid, yi, gi, ch, stats);
+          float w = 0.f;
+#pragma unroll
+          for (int v = 0; v < SP_NW; ++v) w += L.wred[v * 64 + lane];
+          const float yi = ovalid ? ld_sc(A.y[cur] + oi) : 0.f;
+          const float gi = ovalid ? A.q[oi] + w : 0.f;
+          publish_entry(A, cur ^ 1, oi, ovalid, yi, gi, chunk, L.stats);
         }
-        __syncthreads();
       }
-      if (threadIdx.x < 4) st_sc(A.scal + blockIdx.x * 8 + 1 + threadIdx.x, stats[threadIdx.x]);
+      publish_stats(A, L);
       grid_barrier(A.bar, G, epoch);
       cur ^= 1;
       need_refresh = false;
       fresh = true;
     }
 
-    // ---- statistics of the current iterate (same order in every workgroup)
-    float num = 0.f, res = 0.f, npass = 0.f, bad = 0.f;
+    // ---- phase 1.  Loads that do not depend on alpha go first.
+    float sv[4] = {0.f, 0.f, 0.f, 0.f};
+    if (threadIdx.x < G) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sv[u] = ld_sc(A.scal + threadIdx.x * 8 + 1 + u);
+    }
+    // thresholds of entries threadIdx.x + u * SP_NT (coalesced across the wave)
+    float tv[SP_TPT];
+#pragma unroll
+    for (int u = 0; u < SP_TPT; ++u) {
+      const int j = threadIdx.x + u * SP_NT;
+      tv[u] = (j < n) ? ld_sc(A.t[cur] + j) : __builtin_inff();
+    }
+    float y0 = 0.f, g0 = 0.f, p0 = 0.f;
+    if (ovalid && wave == 0) {
+      y0 = ld_sc(A.y[cur] + oi);
+      g0 = ld_sc(A.g[cur] + oi);
+      p0 = ld_sc(A.p[cur] + oi);
+    }
+    const float den_part = rows_product(A, A.pmask[cur], A.p[cur], L);
+    if (threadIdx.x == 0) st_sc(A.scal + blockIdx.x * 8 + 0, den_part);
+
+    // stop test of the current iterate (identical in every workgroup): one four-wide
+    // reduction of the published statistics
+    float num, res, npass, bad;
     {
-      float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f;
-      for (int w = threadIdx.x; w < G; w += SP_NT) {
-        v0 += ld_sc(A.scal + w * 8 + 1);
-        v1 += ld_sc(A.scal + w * 8 + 2);
-        v2 += ld_sc(A.scal + w * 8 + 3);
-        v3 += ld_sc(A.scal + w * 8 + 4);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sv[u] = wave_sum(sv[u]);
+      if (lane == 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) L.wred[u * SP_NW + wave] = sv[u];
       }
-      num = sp_block_sum(v0, redF);
-      res = sp_block_sum(v1, redF);
-      npass = sp_block_sum(v2, redF);
-      bad = sp_block_sum(v3, redF);
+      __syncthreads();
+      float tot[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < SP_NW; ++v) tot[u] += L.wred[u * SP_NW + v];
+      __syncthreads();
+      num = tot[0];
+      res = tot[1];
+      npass = tot[2];
+      bad = tot[3];
     }
     if (bad > 0.f) {
       status = NNLS_NONFINITE_DEV;
@@ -370,96 +428,77 @@ __global__ __launch_bounds__(SP_NT) void solve_persistent_kernel(SpArgs A) {
       status = NNLS_MAXITER_DEV;
       break;
     }
-
-    // ---- phase 1: w = Q gbar over passive rows, den shares
-    int nr;
-    const float den_part =
-        rows_product(A, A.pmask[cur], A.p[cur], rowidx, rowval, redI, redF, nr);
-    rows += nr;
-    if (threadIdx.x == 0) st_sc(A.scal + blockIdx.x * 8 + 0, den_part);
+    rows += (int64_t)npass;
     grid_barrier(A.bar, G, epoch);
 
     // ---- phase 2
-    float den;
-    {
-      float v = 0.f;
-      for (int w = threadIdx.x; w < G; w += SP_NT) v += ld_sc(A.scal + w * 8 + 0);
-      den = sp_block_sum(v, redF);
-    }
+    float dv = (threadIdx.x < G) ? ld_sc(A.scal + threadIdx.x * 8 + 0) : 0.f;
+    float wsum = 0.f;
+    if (owner) wsum = (oi < n) ? partial_sum(A, oi, wave) : 0.f;
+    const float den = sp_block_sum(dv, L.redF);
     if (!(den > 0.f) || !__builtin_isfinite(den)) {
       status = NNLS_BREAKDOWN_DEV;
       break;
     }
     const float alpha = num / den;
 
-    // clipped set: entries with threshold y_i / gbar_i < alpha, in index order, with
-    // delta_i = alpha * gbar_i - y_i.  Each thread holds the thresholds of a contiguous range
-    // of SP_TPT entries in registers (all loads in flight at once).
+    // clipped set (thread-major order): entries with threshold < alpha
     int ccount;
     {
-      const int base = threadIdx.x * SP_TPT;
-      float tv[SP_TPT];
-#pragma unroll
-      for (int u = 0; u < SP_TPT; ++u)
-        tv[u] = (base + u < n) ? ld_sc(A.t[cur] + base + u) : __builtin_inff();
       int cnt = 0;
 #pragma unroll
       for (int u = 0; u < SP_TPT; ++u) cnt += (tv[u] < alpha);
-      int pos = block_exclusive_scan<SP_NT>(cnt, redI, ccount);
+      int pos = block_exclusive_scan<SP_NT>(cnt, L.redI, ccount);
 #pragma unroll
       for (int u = 0; u < SP_TPT; ++u) {
         if (tv[u] < alpha) {
-          cidx[pos] = base + u;
+          L.cidx[pos] = threadIdx.x + u * SP_NT;
           ++pos;
         }
       }
       __syncthreads();
-      rows += ccount;
       for (int m = threadIdx.x; m < ccount; m += SP_NT) {
-        const int j = cidx[m];
-        cval[m] = alpha * ld_sc(A.p[cur] + j) - ld_sc(A.y[cur] + j);
+        const int j = L.cidx[m];
+        L.cval[m] = alpha * ld_sc(A.p[cur] + j) - ld_sc(A.y[cur] + j);  // delta_j
       }
       __syncthreads();
     }
+    rows += ccount;
 
-    if (threadIdx.x < 8) stats[threadIdx.x] = 0.f;
-    __syncthreads();
-    for (int ch = blockIdx.x; ch < nchunks; ch += G) {
-      const int i = ch * SP_CHUNK + lane;
-      const bool valid = i < n;
-      float wsum = 0.f, csum = 0.f;
-      if (valid) {
-        wsum = partial_sum(A, i, wave);
+    if (threadIdx.x < 8) L.stats[threadIdx.x] = 0.f;
+    if (owner) {
+      float csum = 0.f;
+      if (oi < n) {
         int m = wave;
-        constexpr int NW = SP_NT / kWave;
-        for (; m + 3 * NW < ccount; m += 4 * NW) {
+        for (; m + 3 * SP_NW < ccount; m += 4 * SP_NW) {
           float v[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) v[u] = A.Q[(int64_t)cidx[m + u * NW] * n + i];
+          for (int u = 0; u < 4; ++u) v[u] = A.Q[(int64_t)L.cidx[m + u * SP_NW] * n + oi];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) csum += cval[m + u * NW] * v[u];
+          for (int u = 0; u < 4; ++u) csum += L.cval[m + u * SP_NW] * v[u];
         }
-        for (; m < ccount; m += NW) csum += cval[m] * A.Q[(int64_t)cidx[m] * n + i];
+        for (; m < ccount; m += SP_NW) csum += L.cval[m] * A.Q[(int64_t)L.cidx[m] * n + oi];
       }
-      wred[wave * 64 + lane] = wsum;
-      cred[wave * 64 + lane] = csum;
+      L.wred[wave * 64 + lane] = wsum;
+      L.cred[wave * 64 + lane] = csum;
       __syncthreads();
       if (wave == 0) {
-        const float w = wred[lane] + wred[64 + lane] + wred[128 + lane] + wred[192 + lane];
-        const float corr = cred[lane] + cred[64 + lane] + cred[128 + lane] + cred[192 + lane];
+        float w = 0.f, corr = 0.f;
+#pragma unroll
+        for (int v = 0; v < SP_NW; ++v) {
+          w += L.wred[v * 64 + lane];
+          corr += L.cred[v * 64 + lane];
+        }
         float yi = 0.f, gi = 0.f;
-        if (valid) {
-          const float y0 = ld_sc(A.y[cur] + i), g0 = ld_sc(A.g[cur] + i);
-          const float p0 = ld_sc(A.p[cur] + i);
+        if (ovalid) {
           const float v = y0 - alpha * p0;
           yi = v > 0.f ? v : 0.f;
           gi = g0 - alpha * w + corr;
         }
-        publish_entry(A, cur ^ 1, i, valid, yi, gi, ch, stats);
+        publish_entry(A, cur ^ 1, oi, ovalid, yi, gi, chunk, L.stats);
       }
-      __syncthreads();
     }
-    if (threadIdx.x < 4) st_sc(A.scal + blockIdx.x * 8 + 1 + threadIdx.x, stats[threadIdx.x]);
+    publish_stats(A, L);
     grid_barrier(A.bar, G, epoch);
     cur ^= 1;
     ++it;
@@ -467,14 +506,9 @@ __global__ __launch_bounds__(SP_NT) void solve_persistent_kernel(SpArgs A) {
   }
 
   // ---- outputs
-  for (int ch = blockIdx.x; ch < nchunks; ch += G) {
-    if (wave == 0) {
-      const int i = ch * SP_CHUNK + lane;
-      if (i < n) {
-        const float yi = ld_sc(A.y[cur] + i);
-        A.X[i] = A.s ? (float)((double)yi / A.s[i]) : yi;
-      }
-    }
+  if (ovalid && wave == 0) {
+    const float yi = ld_sc(A.y[cur] + oi);
+    A.X[oi] = A.s ? (float)((double)yi / A.s[oi]) : yi;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     A.iters[0] = it;
@@ -490,7 +524,7 @@ __global__ void solve_persistent_init_kernel(unsigned* bar) {
 
 // ---- host side ------------------------------------------------------------------------------
 struct SpPlan {
-  int G, nb, R, nw, cmax, rows_max;
+  int G, nb, R, nw, rows_max;
   size_t lds;
 };
 
@@ -510,18 +544,20 @@ static SpPlan sp_plan(int64_t n, int cus) {
   if (P.nb > P.G) P.nb = P.G;
   P.R = P.G / P.nb;
   P.nw = (int)((n + SP_CHUNK - 1) / SP_CHUNK);
-  P.cmax = (int)n;
   P.rows_max = (int)((n + P.R - 1) / P.R) + 1;
-  P.lds = sizeof(int) * P.rows_max + sizeof(float) * P.rows_max + sizeof(int) * P.cmax +
-          sizeof(float) * P.cmax + sizeof(float) * (4 * 64 * 2 + 16) + sizeof(int) * 8 + 64;
+  auto a16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
+  P.lds = a16(sizeof(int) * P.rows_max) + a16(sizeof(float) * P.rows_max) +
+          a16(sizeof(int) * n) + a16(sizeof(float) * n) + a16(sizeof(float) * 1024) +
+          2 * a16(sizeof(float) * SP_NW * 64) + a16(sizeof(float) * 8) +
+          a16(sizeof(float) * SP_NW) + a16(sizeof(int) * SP_NW);
   return P;
 }
 
-// Largest n the persistent solver takes (the clipped list of up to n entries lives in LDS).
-constexpr int64_t SP_MAX_N = SP_NT * SP_TPT;
-
 bool solve_persistent_supported(int64_t n, int64_t k) {
-  return k == 1 && n >= 1 && n <= SP_MAX_N && (n % 4) == 0;
+  if (k != 1 || n < 1 || n > SP_MAX_N || (n % 4) != 0) return false;
+  const SpPlan P = sp_plan(n, sp_device_cus());
+  return n <= (int64_t)SP_CHUNK * P.G && P.lds <= SP_MAX_LDS &&
+         (n + P.R - 1) / P.R <= (int64_t)SP_NT * SP_RPT;
 }
 
 size_t solve_persistent_ws_bytes(int64_t n) {
@@ -546,7 +582,6 @@ hipError_t launch_solve_persistent(int64_t n, const float* Q, const float* q, co
   A.nb = P.nb;
   A.R = P.R;
   A.nw = P.nw;
-  A.cmax = P.cmax;
   A.rows_max = P.rows_max;
   A.Q = Q;
   A.q = q;
