@@ -13,7 +13,7 @@
  *
  * Conventions shared by every entry point:
  *   - Array arguments are DEVICE pointers owned by the caller; the library keeps no pointer after
- *     a call returns (a batched plan keeps the pointers it was created with, see below).
+ *     a call returns (a batched plan keeps the pointers it was created with).
  *   - Matrices are row-major.  A is [d, n] with leading dimension lda >= n; B is [d, k] with
  *     ldb >= k; Q is [n, n]; q, Y0 and X are [n, k] (leading dimension k).
  *   - Every call is asynchronous and ordered on `stream` (a hipStream_t; NULL = the null stream).
@@ -155,6 +155,48 @@ int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, co
 int nnls_refine(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
                 int64_t ldb, int dtype, void* X, double* kkt64, double* obj64, void* ws,
                 size_t ws_bytes, void* stream);
+
+/*
+ * Uneven batch: many independent problems (each Problem (1) with its own A_i [d_i, n_i] and a
+ * single right-hand side b_i), solved by Algorithm 1 each, as one captured hipGraph (a batched
+ * Gram with the rescale of Problem (5), then a resident grid that takes problems from an atomic
+ * queue in longest-first order and runs Algorithm 2 on each).  FP32 data, BF16x3 Gram,
+ * n_i <= 1024.
+ *
+ * Pools are caller-owned device arrays; descriptor offsets are element offsets into them:
+ *   A_pool  FP32, problem i's A_i row-major [d_i, n_i] at offA
+ *   B_pool  FP32, b_i [d_i] at offB
+ *   Q_pool  FP32 out, Q_i [n_i, n_i] at offQ
+ *   q_pool  FP32 out, q_i [n_i] at offq;  s_pool FP64 out, s_i [n_i] at offq
+ *           (s_i = sqrt of the computed Gram diagonal, 1 where it is 0)
+ *   X_pool  FP32 out, x_i [n_i] at offX
+ *   iters, kkt, status, rows_read (may be NULL): per problem, as for nnls_solve
+ * The plan keeps these pointers; each launch recomputes every output.
+ */
+typedef struct {
+    int64_t d, n, offA, offB, offQ, offq, offX;
+} nnls_problem_desc;
+typedef struct nnls_plan nnls_plan;
+
+/* Device workspace bytes a plan over these problems needs (descriptors, order, queue and three
+ * FP32 vectors per unknown); 0 for invalid arguments.  Host function. */
+size_t nnls_batched_workspace_bytes(const nnls_problem_desc* host_desc, int64_t count);
+
+/* Validates the descriptors, copies them and the longest-first order into `ws` (a blocking
+ * host-to-device copy, done once here), captures the graph on capture_stream (a created stream,
+ * not the null stream) and instantiates it.  The workspace must stay allocated and unused by other calls while the plan lives.
+ * tol and max_iter as for nnls_solve (max_iter 0: 5 n_i per problem). */
+int nnls_batched_plan_create(const nnls_problem_desc* host_desc, int64_t count, double tol,
+                             int32_t max_iter, const float* A_pool, const float* B_pool,
+                             float* Q_pool, float* q_pool, double* s_pool, float* X_pool,
+                             int32_t* iters, double* kkt, int32_t* status, int64_t* rows_read,
+                             void* ws, size_t ws_bytes, void* capture_stream, nnls_plan** out);
+
+/* One launch of the plan's graph on `stream` (asynchronous). */
+int nnls_batched_plan_launch(nnls_plan* plan, void* stream);
+
+/* Releases the plan's graph (not the pools or the workspace). */
+void nnls_batched_plan_destroy(nnls_plan* plan);
 
 /* Text of the last HIP error seen by this thread (empty if none). */
 const char* nnls_last_hip_error(void);

@@ -19,6 +19,12 @@ int hip_fail(hipError_t e) {
   return NNLS_E_HIP;
 }
 
+}  // namespace
+
+void nnls::record_hip_error(hipError_t e) { g_last_hip_error = hipGetErrorString(e); }
+
+namespace {
+
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -39,40 +45,52 @@ size_t prepare_ws(int64_t d, int64_t n, int64_t k, int mode) {
   return a > b ? a : b;
 }
 
-// Solver choice: one right-hand side of FP32 with n at least kPersistentMinN goes to the
-// persistent whole-GPU kernel; everything else to the one-workgroup-per-column kernel.
-// NNLS_SOLVER=wg or NNLS_SOLVER=persistent in the environment forces a choice (when valid).
+// Solver choice (FP32):
+//   one right-hand side with n >= kPersistentMinN  -> persistent whole-GPU kernel
+//   several right-hand sides, n small enough for LDS -> matrix-core many-RHS kernel
+//   otherwise (and FP64)                             -> one workgroup per column
+// NNLS_SOLVER=wg|persistent|mrhs in the environment forces a choice where it is valid.
 constexpr int64_t kPersistentMinN = 1536;
 
-enum SolverKind { SOLVER_WG = 0, SOLVER_PERSISTENT = 1 };
+enum SolverKind { SOLVER_WG = 0, SOLVER_PERSISTENT = 1, SOLVER_MRHS = 2 };
 
 int solver_override() {
   const char* v = getenv("NNLS_SOLVER");
   if (!v) return -1;
   if (strcmp(v, "wg") == 0) return SOLVER_WG;
   if (strcmp(v, "persistent") == 0) return SOLVER_PERSISTENT;
+  if (strcmp(v, "mrhs") == 0) return SOLVER_MRHS;
   return -1;
 }
 
 SolverKind pick_solver(int64_t n, int64_t k, int dt) {
   const bool can_p = dt == NNLS_F32 && nnls::solve_persistent_supported(n, k);
+  const bool can_m = dt == NNLS_F32 && nnls::solve_mrhs_supported(n, k);
   const bool can_w = nnls::solve_wg_lds_bytes(n, (int)elem_size(dt)) <= kMaxLds;
   const int o = solver_override();
   if (o == SOLVER_PERSISTENT && can_p) return SOLVER_PERSISTENT;
+  if (o == SOLVER_MRHS && can_m) return SOLVER_MRHS;
   if (o == SOLVER_WG && can_w) return SOLVER_WG;
   if (can_p && (n >= kPersistentMinN || !can_w)) return SOLVER_PERSISTENT;
+  if (can_m) return SOLVER_MRHS;
   return SOLVER_WG;
 }
 
 bool solver_supported(int64_t n, int64_t k, int dt) {
   return (dt == NNLS_F32 && nnls::solve_persistent_supported(n, k)) ||
+         (dt == NNLS_F32 && nnls::solve_mrhs_supported(n, k)) ||
          nnls::solve_wg_lds_bytes(n, (int)elem_size(dt)) <= kMaxLds;
 }
 
 size_t solve_ws(int64_t n, int64_t k, int dt) {
-  if (pick_solver(n, k, dt) == SOLVER_PERSISTENT)
-    return align_up(nnls::solve_persistent_ws_bytes(n));
-  return align_up(elem_size(dt) * 3 * n * k);
+  switch (pick_solver(n, k, dt)) {
+    case SOLVER_PERSISTENT:
+      return align_up(nnls::solve_persistent_ws_bytes(n));
+    case SOLVER_MRHS:
+      return align_up(nnls::solve_mrhs_ws_bytes());
+    default:
+      return align_up(elem_size(dt) * 3 * n * k);
+  }
 }
 
 }  // namespace
@@ -194,7 +212,13 @@ int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, co
   const int mi = max_iter == 0 ? (int)(5 * n < (1 << 30) ? 5 * n : (1 << 30)) : max_iter;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
-  if (pick_solver(n, k, dtype) == SOLVER_PERSISTENT) {
+  const SolverKind kind = pick_solver(n, k, dtype);
+  if (kind == SOLVER_MRHS) {
+    if (((uintptr_t)Q & 15) != 0) return NNLS_E_ARG;  // rows are read as 16-byte vectors
+    e = nnls::launch_solve_mrhs(n, k, (const float*)Q, (const float*)q, s, tol, mi,
+                                (const float*)Y0, (float*)X, iters, kkt, status, rows_read, ws,
+                                st);
+  } else if (kind == SOLVER_PERSISTENT) {
     if (((uintptr_t)Q & 15) != 0) return NNLS_E_ARG;  // rows are read as 16-byte vectors
     e = nnls::launch_solve_persistent(n, (const float*)Q, (const float*)q, s, tol, mi,
                                       (const float*)Y0, (float*)X, iters, kkt, status,

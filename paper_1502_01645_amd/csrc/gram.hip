@@ -49,8 +49,14 @@ __global__ __launch_bounds__(256) void colnorm_finalize_kernel(int64_t n, int64_
                                                                const double* partial, double* s) {
   const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (col >= n) return;
-  double acc = 0.0;
-  for (int64_t c = 0; c < nchunks; ++c) acc += partial[c * n + col];
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t c = 0;
+  for (; c + 3 < nchunks; c += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] += partial[(c + u) * n + col];
+  }
+  for (; c < nchunks; ++c) a[0] += partial[c * n + col];
+  const double acc = (a[0] + a[1]) + (a[2] + a[3]);
   s[col] = acc > 0.0 ? sqrt(acc) : 1.0;
 }
 
@@ -211,30 +217,18 @@ static int schedule_blocks(int tiles_a, int tiles_aug) {
   return mx * GB_XCDS;
 }
 
-__global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
-    int64_t d, int64_t n, int64_t k, const float* __restrict__ A, int64_t lda,
-    const float* __restrict__ B, int64_t ldb, const double* __restrict__ s, float* __restrict__ Q,
-    float* __restrict__ q, float* __restrict__ partial, int tiles_a, int tiles_aug,
-    int64_t rows_per_split) {
-  extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
-
-  int ti, tj;
-  if (!schedule_tile(blockIdx.x, tiles_a, tiles_aug, ti, tj)) return;
-  const bool diag = (ti == tj);
-  const int64_t i0 = (int64_t)ti * GB_BM, j0 = (int64_t)tj * GB_BM;
-  const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
-  const int64_t r_end = r_begin + rows_per_split < d ? r_begin + rows_per_split : d;
-
+// One 128 x 128 tile of [A | B]^T [A | B] over rows [r_begin, r_end): px / py locate the two
+// panels (this thread's column of each), diag marks px == py.  Leaves the FP32 accumulators in
+// acc (16x16 MFMA D layout) and LDS free for reuse.  Called by all 256 threads.
+__device__ __forceinline__ void gram_tile_bf16x3(f32x4 (&acc)[4][4], int64_t r_begin,
+                                                 int64_t r_end, GramPanelPtr px, GramPanelPtr py,
+                                                 bool diag, uint16_t* lds) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int lc = tid & 127;     // column of the panel this thread stages
   const int kh = tid >> 7;      // which 16-row half of the K chunk
 
-  const GramPanelPtr px = panel_column(i0 + lc, n, k, A, lda, B, ldb);
-  const GramPanelPtr py = panel_column(j0 + lc, n, k, A, lda, B, ldb);
-
-  f32x4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -332,6 +326,33 @@ __global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
     __syncthreads();
   }
 
+}
+
+__global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
+    int64_t d, int64_t n, int64_t k, const float* __restrict__ A, int64_t lda,
+    const float* __restrict__ B, int64_t ldb, const double* __restrict__ s, float* __restrict__ Q,
+    float* __restrict__ q, float* __restrict__ partial, int tiles_a, int tiles_aug,
+    int64_t rows_per_split) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
+
+  int ti, tj;
+  if (!schedule_tile(blockIdx.x, tiles_a, tiles_aug, ti, tj)) return;
+  const bool diag = (ti == tj);
+  const int64_t i0 = (int64_t)ti * GB_BM, j0 = (int64_t)tj * GB_BM;
+  const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r_end = r_begin + rows_per_split < d ? r_begin + rows_per_split : d;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int lc = tid & 127;
+  const GramPanelPtr px = panel_column(i0 + lc, n, k, A, lda, B, ldb);
+  const GramPanelPtr py = panel_column(j0 + lc, n, k, A, lda, B, ldb);
+  f32x4 acc[4][4];
+  gram_tile_bf16x3(acc, r_begin, r_end, px, py, diag, lds);
+  const int wm = (wave >> 1) * 64;
+  const int wn = (wave & 1) * 64;
+
   // D fragment layout of the 16x16 MFMA: lane holds column (lane & 15), rows 4*(lane>>4)+e.
   const int out_col = lane & 15;
   const int out_row = (lane >> 4) * 4;
@@ -364,6 +385,118 @@ __global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
           dst[li * GB_BM + lj] = acc[a][b][e];
         }
   }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Uneven batch: one workgroup per problem walks that problem's tiles of [A | b]^T [A | b] with
+// the same BF16x3 tile routine.  Diagonal tiles go first; each yields the scales of its block
+// from its own diagonal (s_i = sqrt(H_ii), 1 where H_ii = 0), which the off-diagonal tiles and
+// the right-hand side column then use in the rescale epilogue.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void batched_emit(int64_t i, int64_t j, float val, int64_t n,
+                                             const double* s_l, float* Q, float* q,
+                                             bool diag_tile) {
+  if (i >= n) return;
+  if (j < n) {
+    if (diag_tile && i > j) return;
+    float out;
+    if (i == j) out = val > 0.f ? 1.f : 0.f;
+    else out = (float)((double)val / (s_l[i] * s_l[j]));
+    Q[i * n + j] = out;
+    if (i != j) Q[j * n + i] = out;
+  } else if (j == n) {
+    q[i] = (float)(-(double)val / s_l[i]);
+  }
+}
+
+constexpr int BG_MAX_N = 1024;
+
+__global__ __launch_bounds__(256, 1) void batched_gram_kernel(const BatchDesc* __restrict__ desc,
+                                                           const float* __restrict__ A_pool,
+                                                           const float* __restrict__ B_pool,
+                                                           float* __restrict__ Q_pool,
+                                                           float* __restrict__ q_pool,
+                                                           double* __restrict__ s_pool) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
+  double* s_l = (double*)((unsigned char*)lds + GB_LDS_BYTES);
+  float* dg = (float*)(s_l + BG_MAX_N);
+  const BatchDesc D = desc[blockIdx.x];
+  const int64_t n = D.n, d = D.d;
+  const float* A = A_pool + D.offA;
+  const float* B = B_pool + D.offB;
+  float* Q = Q_pool + D.offQ;
+  float* q = q_pool + D.offq;
+  const int T = (int)((n + GB_BM - 1) / GB_BM);
+  const int Taug = (int)((n + 1 + GB_BM - 1) / GB_BM);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lc = tid & 127;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int out_col = lane & 15, out_row = (lane >> 4) * 4;
+  f32x4 acc[4][4];
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int ti = 0; ti < T; ++ti) {
+      const int tj_lo = pass == 0 ? ti : ti + 1;
+      const int tj_hi = pass == 0 ? ti + 1 : Taug;
+      for (int tj = tj_lo; tj < tj_hi; ++tj) {
+        const bool diag = ti == tj;
+        const int64_t i0 = (int64_t)ti * GB_BM, j0 = (int64_t)tj * GB_BM;
+        const GramPanelPtr px = panel_column(i0 + lc, n, 1, A, n, B, 1);
+        const GramPanelPtr py = panel_column(j0 + lc, n, 1, A, n, B, 1);
+        gram_tile_bf16x3(acc, 0, d, px, py, diag, lds);
+        if (diag) {
+          // diagonal entries of the block -> scales
+          if (wm == wn) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+              const int e = out_col - out_row;
+              if (e >= 0 && e < 4) {
+#pragma unroll
+                for (int ee = 0; ee < 4; ++ee)
+                  if (ee == e) dg[wm + a * 16 + out_col] = acc[a][a][ee];
+              }
+            }
+          }
+          __syncthreads();
+          if (tid < GB_BM) {
+            const int64_t i = i0 + tid;
+            if (i < n) {
+              const float h = dg[tid];
+              const double si = h > 0.f ? sqrt((double)h) : 1.0;
+              s_l[i] = si;
+              s_pool[D.offq + i] = si;
+            }
+          }
+          __syncthreads();
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              batched_emit(i0 + wm + a * 16 + out_row + e, j0 + wn + b * 16 + out_col,
+                           acc[a][b][e], n, s_l, Q, q, diag);
+      }
+    }
+  }
+}
+
+size_t batched_gram_lds_bytes() {
+  return GB_LDS_BYTES + sizeof(double) * BG_MAX_N + sizeof(float) * GB_BM;
+}
+
+hipError_t prepare_batched_gram() {
+  return hipFuncSetAttribute((const void*)batched_gram_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)batched_gram_lds_bytes());
+}
+
+hipError_t launch_batched_gram(const BatchDesc* desc, int64_t count, const float* A_pool,
+                               const float* B_pool, float* Q_pool, float* q_pool,
+                               double* s_pool, hipStream_t st) {
+  const size_t lds = batched_gram_lds_bytes();
+  hipLaunchKernelGGL(batched_gram_kernel, dim3((unsigned)count), dim3(256), lds, st, desc, A_pool,
+                     B_pool, Q_pool, q_pool, s_pool);
+  return hipGetLastError();
 }
 
 // Sum of split-K partial tiles in fixed split order, then the rescale epilogue.
@@ -452,6 +585,7 @@ __global__ __launch_bounds__(256) void gram_fma_kernel(int64_t d, int64_t n, int
 static int64_t colnorm_chunks(int64_t d, int64_t n) {
   const int64_t bx = (n + 255) / 256;
   int64_t chunks = (2048 + bx - 1) / bx;
+  if (chunks > 256) chunks = 256;  // the finalize pass sums this many partials per column
   if (chunks > d) chunks = d;
   if (chunks < 1) chunks = 1;
   return chunks;

@@ -13,6 +13,16 @@ constexpr int NNLS_BREAKDOWN_DEV = 2;
 constexpr int NNLS_NONFINITE_DEV = 3;
 constexpr int NNLS_FELL_BACK_DEV = 4;
 
+// Remembers the text of a failed HIP call for nnls_last_hip_error (capi.hip).
+void record_hip_error(hipError_t e);
+
+// One problem of an uneven batch (device copy of the caller's descriptor): A is [d, n] at
+// A_pool + offA, b is [d] at B_pool + offB, Q is [n, n] at Q_pool + offQ, q, s and x are [n] at
+// offset offq of their pools (s in the FP64 pool), x at X_pool + offX.
+struct BatchDesc {
+  int64_t d, n, offA, offB, offQ, offq, offX, pad;
+};
+
 // gram.hip
 size_t colnorm_ws_bytes(int64_t d, int64_t n);
 template <typename T>
@@ -26,6 +36,13 @@ hipError_t launch_gram_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, i
 template <typename T>
 hipError_t launch_gram_fma(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda, const T* B,
                            int64_t ldb, const double* s, T* Q, T* q, hipStream_t st);
+
+constexpr int64_t BATCH_MAX_N = 1024;
+size_t batched_gram_lds_bytes();
+hipError_t prepare_batched_gram();
+hipError_t launch_batched_gram(const BatchDesc* desc, int64_t count, const float* A_pool,
+                               const float* B_pool, float* Q_pool, float* q_pool,
+                               double* s_pool, hipStream_t st);
 
 // solve_wg.hip
 size_t solve_wg_lds_bytes(int64_t n, int elem);
@@ -42,6 +59,14 @@ hipError_t launch_solve_persistent(int64_t n, const float* Q, const float* q, co
                                    double tol, int max_iter, const float* Y0, float* X,
                                    int32_t* iters, double* kkt, int32_t* status,
                                    int64_t* rows_read, void* ws, hipStream_t st);
+
+// solve_mrhs.hip
+bool solve_mrhs_supported(int64_t n, int64_t k);
+size_t solve_mrhs_ws_bytes();
+hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* q,
+                             const double* s, double tol, int max_iter, const float* Y0,
+                             float* X, int32_t* iters, double* kkt, int32_t* status,
+                             int64_t* rows_read, void* ws, hipStream_t st);
 
 // refine.hip
 size_t refine_ws_bytes(int64_t d, int64_t n, int64_t k);

@@ -216,8 +216,14 @@ __global__ __launch_bounds__(256) void cols_finalize_kernel(int64_t n, int64_t k
   if (i >= n) return;
   const int nvec = with_b ? (int)(2 * k + 1) : (int)k;
   for (int m = 0; m < nvec; ++m) {
-    double acc = 0.0;
-    for (int64_t c = 0; c < nchunks; ++c) acc += partial[(c * nvec + m) * n + i];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t c = 0;
+    for (; c + 3 < nchunks; c += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] += partial[((c + u) * nvec + m) * n + i];
+    }
+    for (; c < nchunks; ++c) a[0] += partial[(c * nvec + m) * n + i];
+    const double acc = (a[0] + a[1]) + (a[2] + a[3]);
     if (m < k) G[i * k + m] = acc;
     else if (m < 2 * k) Atb[i * k + (m - k)] = acc;
     else s[i] = acc > 0.0 ? sqrt(acc) : 1.0;

@@ -1,0 +1,472 @@
+// Algorithm 2 for many right-hand sides sharing Q (an NMF-style update: small n, large k).
+//
+// A workgroup owns 16 column slots.  Per update, for all its active columns at once:
+//   gbar = masked gradient (passive set per column), num_c = ||gbar_c||^2, residual r_c;
+//   W = Q * Gbar on the FP32 matrix cores (v_mfma_f32_16x16x4f32): 16 output columns, Q read
+//   from L2 (every workgroup streams the same n x n matrix);
+//   den_c = gbar_c^T W_c, alpha_c = num_c / den_c;  y' = [y - alpha gbar]_+;
+//   grad' = grad - alpha W + Q[:, C] delta_C, the clip correction applied with vector FMAs over
+//   the clipped entries only (delta = (y' - y) + alpha gbar is nonzero just there).
+// A column whose residual meets tol has its gradient recomputed exactly (Q y + q, one more
+// matrix-core product over all slots) before it retires; it then writes x = y / s, its
+// iteration count, residual and status, and the slot takes the next column from a queue.
+// State lives in LDS as [row][slot] arrays; rows are padded to a multiple of 16.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace nnls {
+
+constexpr int MR_NT = 256;
+constexpr int MR_SLOTS = 16;
+constexpr int MR_CAP = 1024;  // clipped (row, slot) pairs applied per pass
+
+struct MrArgs {
+  int n, np, k;
+  const float* Q;
+  const float* q;
+  const double* s;
+  const float* Y0;
+  float* X;
+  double tol;
+  int max_iter;
+  int32_t* iters;
+  double* kkt;
+  int32_t* status;
+  int64_t* rows_read;
+  int* queue;  // next unassigned column (starts at 16 * gridDim.x)
+};
+
+// W[0..np)[0..16) = Q * V (V: [np][16] in LDS), rows and columns of Q beyond n read as 0.
+// Wave w computes row tiles w, w + 4, ...; for each 16-wide k block a lane loads 4 consecutive
+// Q entries of one row (16 bytes) and feeds them to 4 MFMAs; the k index of MFMA e for lane
+// group g is k0 + 4 g + e, for both operands.  Eight k blocks are loaded before their MFMAs so
+// the L2 latency is paid once per eight.
+__device__ void mfma_product(const MrArgs& A, const float* V, float* W) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = A.n, np = A.np;
+  const int tiles = np / 16;
+  const int lr = lane & 15, lg = lane >> 4;
+  constexpr int KB = 8;  // k blocks (of 16) whose Q fragments are in flight together
+  for (int t = wave; t < tiles; t += MR_NT / kWave) {
+    const int m = t * 16 + lr;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const float* qrow = A.Q + (int64_t)m * n;
+    for (int k0 = 0; k0 < np; k0 += 16 * KB) {
+      f32x4 a[KB];
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        const int kk = k0 + 16 * u + 4 * lg;
+        a[u] = (m < n && kk < n) ? *(const f32x4*)(qrow + kk) : (f32x4){0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        const int kk = k0 + 16 * u + 4 * lg;
+        if (k0 + 16 * u < np) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float b = V[(kk + e) * MR_SLOTS + lr];
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][e], b, acc, 0, 0, 0);
+          }
+        }
+      }
+    }
+    // D layout: lane holds column (lane & 15), rows 4 * (lane >> 4) + e of the tile
+#pragma unroll
+    for (int e = 0; e < 4; ++e) W[(t * 16 + 4 * lg + e) * MR_SLOTS + lr] = acc[e];
+  }
+}
+
+__global__ __launch_bounds__(MR_NT) void solve_mrhs_kernel(MrArgs A) {
+  extern __shared__ __attribute__((aligned(16))) float sm[];
+  const int np = A.np, n = A.n;
+  float* Y = sm;                       // [np][16]
+  float* Gr = Y + np * MR_SLOTS;       // [np][16] gradient
+  float* P = Gr + np * MR_SLOTS;       // [np][16] masked gradient / product operand
+  float* W = P + np * MR_SLOTS;        // [np][16] product result
+  int* cj = (int*)(W + np * MR_SLOTS); // [MR_CAP] clipped rows
+  int* cc = cj + MR_CAP;               // [MR_CAP] clipped slots
+  float* cd = (float*)(cc + MR_CAP);   // [MR_CAP] deltas
+  float* colf = cd + MR_CAP;           // per-slot floats [8][16]
+  int* coli = (int*)(colf + 8 * MR_SLOTS);  // per-slot ints [8][16]
+  float* red = (float*)(coli + 8 * MR_SLOTS);  // [4 waves][16 slots][4]
+  int* redI = (int*)(red + 4 * MR_SLOTS * 4);  // [4]
+
+  // per-slot state in LDS
+  float* s_num = colf + 0 * MR_SLOTS;
+  float* s_res = colf + 1 * MR_SLOTS;
+  float* s_alpha = colf + 2 * MR_SLOTS;
+  float* s_qn = colf + 3 * MR_SLOTS;      // ||q_c|| (1 if 0)
+  float* s_den = colf + 4 * MR_SLOTS;
+  float* s_cnt = colf + 5 * MR_SLOTS;     // passive count
+  float* s_bad = colf + 6 * MR_SLOTS;
+  int* s_col = coli + 0 * MR_SLOTS;       // column id or -1
+  int* s_it = coli + 1 * MR_SLOTS;        // updates done
+  int* s_fresh = coli + 2 * MR_SLOTS;     // gradient exact since last update
+  int* s_act = coli + 3 * MR_SLOTS;       // take an update this pass
+  int* s_ref = coli + 4 * MR_SLOTS;       // needs an exact gradient
+  int* s_rows = coli + 5 * MR_SLOTS;      // rows of Q read (low bits)
+  int* s_rowsh = coli + 6 * MR_SLOTS;     // rows of Q read (high bits)
+  int* s_done = coli + 7 * MR_SLOTS;      // outputs written; slot waits for a new column
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int slot = tid & 15;              // elementwise mapping: slot = tid % 16,
+  const int row0 = tid >> 4;              // rows row0 + 16 m
+
+  // -- load a column into a slot: y = max(Y0, 0) or 0, gradient = q (exact for a cold start)
+  auto load_slot = [&](int sl, int col) {
+    // called by the 16 threads of slot sl (tid % 16 == sl)
+    for (int i = row0; i < np; i += MR_NT / MR_SLOTS) {
+      float qi = 0.f, yi = 0.f;
+      if (col >= 0 && i < n) {
+        qi = A.q[(int64_t)i * A.k + col];
+        if (A.Y0) {
+          yi = A.Y0[(int64_t)i * A.k + col];
+          yi = yi > 0.f ? yi : 0.f;
+        }
+      }
+      Y[i * MR_SLOTS + sl] = yi;
+      Gr[i * MR_SLOTS + sl] = qi;
+    }
+  };
+
+  if (tid < MR_SLOTS) {
+    const int col = blockIdx.x * MR_SLOTS + tid;
+    s_col[tid] = col < A.k ? col : -1;
+    s_it[tid] = 0;
+    s_fresh[tid] = A.Y0 ? 0 : 1;
+    s_ref[tid] = A.Y0 ? 1 : 0;
+    s_rows[tid] = 0;
+    s_rowsh[tid] = 0;
+    s_done[tid] = 0;
+  }
+  __syncthreads();
+  load_slot(slot, s_col[slot]);
+  __syncthreads();
+
+  // per-slot reduction of four per-thread values over the 16 threads sharing a slot
+  auto slot_reduce4 = [&](float v0, float v1, float v2, float v3, float* o0, float* o1,
+                          float* o2, float* o3) {
+    // lanes with equal (lane & 15) share a slot within a wave: xor 16, 32
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1) {
+      v0 += __shfl_xor(v0, off, 64);
+      v1 += __shfl_xor(v1, off, 64);
+      v2 += __shfl_xor(v2, off, 64);
+      v3 += __shfl_xor(v3, off, 64);
+    }
+    if (lane < 16) {
+      float* r = red + (wave * MR_SLOTS + lane) * 4;
+      r[0] = v0;
+      r[1] = v1;
+      r[2] = v2;
+      r[3] = v3;
+    }
+    __syncthreads();
+    if (tid < MR_SLOTS) {
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+      for (int w = 0; w < MR_NT / kWave; ++w) {
+        const float* r = red + (w * MR_SLOTS + tid) * 4;
+        a0 += r[0];
+        a1 += r[1];
+        a2 += r[2];
+        a3 += r[3];
+      }
+      if (o0) o0[tid] = a0;
+      if (o1) o1[tid] = a1;
+      if (o2) o2[tid] = a2;
+      if (o3) o3[tid] = a3;
+    }
+    __syncthreads();
+  };
+
+  // ||q_c|| of every slot
+  auto slot_qnorm = [&]() {
+    float acc = 0.f;
+    const int col = s_col[slot];
+    if (col >= 0)
+      for (int i = row0; i < n; i += MR_NT / MR_SLOTS) {
+        const float qi = A.q[(int64_t)i * A.k + col];
+        acc += qi * qi;
+      }
+    slot_reduce4(acc, 0.f, 0.f, 0.f, s_qn, nullptr, nullptr, nullptr);
+    if (tid < MR_SLOTS) s_qn[tid] = s_qn[tid] > 0.f ? sqrtf(s_qn[tid]) : 1.f;
+    __syncthreads();
+  };
+  slot_qnorm();
+
+  for (;;) {
+    // ---- exact gradient for slots that asked for it: W = Q Y, grad = W + q
+    int any_ref = 0;
+    if (tid < MR_SLOTS) any_ref = s_ref[tid] && s_col[tid] >= 0;
+    any_ref = __syncthreads_or(any_ref);
+    if (any_ref) {
+      for (int e = tid; e < np * MR_SLOTS; e += MR_NT) P[e] = Y[e];
+      __syncthreads();
+      mfma_product(A, P, W);
+      __syncthreads();
+      if (s_ref[slot] && s_col[slot] >= 0) {
+        const int col = s_col[slot];
+        for (int i = row0; i < n; i += MR_NT / MR_SLOTS)
+          Gr[i * MR_SLOTS + slot] = W[i * MR_SLOTS + slot] + A.q[(int64_t)i * A.k + col];
+      }
+      __syncthreads();
+      if (tid < MR_SLOTS && s_ref[tid] && s_col[tid] >= 0) {
+        s_ref[tid] = 0;
+        s_fresh[tid] = 1;
+        const unsigned r = (unsigned)s_rows[tid] + (unsigned)n;
+        if (r < (unsigned)s_rows[tid]) s_rowsh[tid] += 1;
+        s_rows[tid] = (int)r;
+      }
+      __syncthreads();
+    }
+
+    // ---- passive set, masked gradient, statistics
+    {
+      float num = 0.f, res = 0.f, cnt = 0.f, bad = 0.f;
+      const bool live = s_col[slot] >= 0;
+      for (int i = row0; i < np; i += MR_NT / MR_SLOTS) {
+        const int e = i * MR_SLOTS + slot;
+        const float yi = Y[e], gi = Gr[e];
+        const bool valid = live && i < n;
+        const bool pas = valid && ((yi > 0.f) || (gi < 0.f));
+        const float pi = pas ? gi : 0.f;
+        P[e] = pi;
+        num += pi * pi;
+        const float m = yi < gi ? yi : gi;
+        res += valid ? m * m : 0.f;
+        cnt += pas ? 1.f : 0.f;
+        bad += (valid && (!__builtin_isfinite(yi) || !__builtin_isfinite(gi))) ? 1.f : 0.f;
+      }
+      slot_reduce4(num, res, cnt, bad, s_num, s_res, s_cnt, s_bad);
+    }
+
+    // ---- per-slot decisions (threads 0..15): finish, refresh, or update
+    int flag_done = 0, flag_work = 0, flag_act = 0;
+    if (tid < MR_SLOTS) {
+      s_act[tid] = 0;
+      const int col = s_col[tid];
+      if (col >= 0 && !s_done[tid]) {
+        const double r = sqrt((double)s_res[tid]) / (double)s_qn[tid];
+        int st = -1;
+        if (s_bad[tid] > 0.f) {
+          st = NNLS_NONFINITE_DEV;
+        } else if (s_cnt[tid] == 0.f || r <= A.tol) {
+          if (s_fresh[tid]) st = NNLS_CONVERGED_DEV;
+          else s_ref[tid] = 1;
+        } else if (s_it[tid] >= A.max_iter) {
+          if (s_fresh[tid]) st = NNLS_MAXITER_DEV;
+          else s_ref[tid] = 1;
+        } else {
+          s_act[tid] = 1;
+        }
+        if (st >= 0) {
+          A.iters[col] = s_it[tid];
+          A.kkt[col] = st == NNLS_NONFINITE_DEV ? __builtin_nan("") : r;
+          A.status[col] = st;
+          if (A.rows_read)
+            A.rows_read[col] = ((int64_t)s_rowsh[tid] << 32) | (int64_t)(unsigned)s_rows[tid];
+          s_done[tid] = 1;
+        }
+      }
+      flag_done = (col >= 0 && s_done[tid]) ? 1 : 0;
+      flag_work = (col >= 0) ? 1 : 0;
+      flag_act = s_act[tid];
+    }
+    flag_done = __syncthreads_or(flag_done);
+    if (flag_done) {
+      // write x = y / s of finished slots, then give each a new column from the queue
+      const bool fin = s_col[slot] >= 0 && s_done[slot];
+      if (fin) {
+        const int col = s_col[slot];
+        for (int i = row0; i < n; i += MR_NT / MR_SLOTS) {
+          const float yi = Y[i * MR_SLOTS + slot];
+          A.X[(int64_t)i * A.k + col] = A.s ? (float)((double)yi / A.s[i]) : yi;
+        }
+      }
+      __syncthreads();
+      if (tid < MR_SLOTS && fin) {
+        const int next = atomicAdd(A.queue, 1);
+        s_col[tid] = next < A.k ? next : -1;
+        s_it[tid] = 0;
+        s_done[tid] = 0;
+        s_fresh[tid] = A.Y0 ? 0 : 1;
+        s_ref[tid] = (A.Y0 && next < A.k) ? 1 : 0;
+        s_rows[tid] = 0;
+        s_rowsh[tid] = 0;
+      }
+      __syncthreads();
+      if (fin) load_slot(slot, s_col[slot]);
+      __syncthreads();
+      slot_qnorm();
+      continue;  // evaluate the new columns before any update
+    }
+    flag_work = __syncthreads_or(flag_work);
+    if (!flag_work) break;  // every slot empty: the queue is exhausted
+    flag_act = __syncthreads_or(flag_act);
+    if (!flag_act) continue;  // only exact-gradient refreshes are pending
+
+    // ---- W = Q Gbar on the matrix cores (inactive slots have gbar = 0)
+    if (!s_act[slot])
+      for (int i = row0; i < np; i += MR_NT / MR_SLOTS) P[i * MR_SLOTS + slot] = 0.f;
+    __syncthreads();
+    mfma_product(A, P, W);
+    __syncthreads();
+    {
+      float den = 0.f;
+      for (int i = row0; i < np; i += MR_NT / MR_SLOTS) {
+        const int e = i * MR_SLOTS + slot;
+        den += P[e] * W[e];
+      }
+      slot_reduce4(den, 0.f, 0.f, 0.f, s_den, nullptr, nullptr, nullptr);
+    }
+    if (tid < MR_SLOTS && s_act[tid]) {
+      const float den = s_den[tid];
+      if (!(den > 0.f) || !__builtin_isfinite(den)) {
+        // breakdown: retire the column with its current iterate
+        const int col = s_col[tid];
+        A.iters[col] = s_it[tid];
+        A.kkt[col] = sqrt((double)s_res[tid]) / (double)s_qn[tid];
+        A.status[col] = NNLS_BREAKDOWN_DEV;
+        if (A.rows_read)
+          A.rows_read[col] = ((int64_t)s_rowsh[tid] << 32) | (int64_t)(unsigned)s_rows[tid];
+        s_act[tid] = 0;
+        s_done[tid] = 1;
+        s_ref[tid] = 0;
+      } else {
+        s_alpha[tid] = s_num[tid] / den;
+      }
+    }
+    __syncthreads();
+
+    // ---- projected update; clipped pairs (row, slot, delta) into the list, in passes
+    int total_clip;
+    int clip_mine = 0;
+    {
+      const bool act = s_act[slot];
+      const float alpha = act ? s_alpha[slot] : 0.f;
+      int cnt = 0;
+      for (int i = row0; i < n; i += MR_NT / MR_SLOTS) {
+        const int e = i * MR_SLOTS + slot;
+        cnt += (act && (Y[e] - alpha * P[e] < 0.f)) ? 1 : 0;
+      }
+      clip_mine = cnt;
+      int base = block_exclusive_scan<MR_NT>(cnt, redI, total_clip);
+      for (int pass = 0; pass * MR_CAP < total_clip; ++pass) {
+        const int lo = pass * MR_CAP, hi = lo + MR_CAP;
+        int pos = base;
+        for (int i = row0; i < n; i += MR_NT / MR_SLOTS) {
+          const int e = i * MR_SLOTS + slot;
+          if (act && (Y[e] - alpha * P[e] < 0.f)) {
+            if (pos >= lo && pos < hi) {
+              cj[pos - lo] = i;
+              cc[pos - lo] = slot;
+              cd[pos - lo] = alpha * P[e] - Y[e];
+            }
+            ++pos;
+          }
+        }
+        __syncthreads();
+        const int npairs = (total_clip - lo) < MR_CAP ? (total_clip - lo) : MR_CAP;
+        // grad[i][c_m] += delta_m * Q[j_m][i]: thread owns rows i = tid, tid + 256, ...
+        for (int i = tid; i < n; i += MR_NT) {
+          int m = 0;
+          for (; m + 3 < npairs; m += 4) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = A.Q[(int64_t)cj[m + u] * n + i];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) Gr[i * MR_SLOTS + cc[m + u]] += cd[m + u] * v[u];
+          }
+          for (; m < npairs; ++m) Gr[i * MR_SLOTS + cc[m]] += cd[m] * A.Q[(int64_t)cj[m] * n + i];
+        }
+        __syncthreads();
+      }
+      // y' = [y - alpha gbar]_+, grad' = grad - alpha W (+ correction above)
+      if (act) {
+        for (int i = row0; i < n; i += MR_NT / MR_SLOTS) {
+          const int e = i * MR_SLOTS + slot;
+          const float v = Y[e] - alpha * P[e];
+          Y[e] = v > 0.f ? v : 0.f;
+          Gr[e] -= alpha * W[e];
+        }
+      }
+      __syncthreads();
+    }
+    slot_reduce4((float)clip_mine, 0.f, 0.f, 0.f, s_den, nullptr, nullptr, nullptr);
+    if (tid < MR_SLOTS && s_act[tid]) {
+      s_it[tid] += 1;
+      s_fresh[tid] = 0;
+      // rows of Q: the passive rows of the line-search product and the clipped rows
+      const unsigned add = (unsigned)s_cnt[tid] + (unsigned)s_den[tid];
+      const unsigned r = (unsigned)s_rows[tid] + add;
+      if (r < (unsigned)s_rows[tid]) s_rowsh[tid] += 1;
+      s_rows[tid] = (int)r;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void solve_mrhs_queue_init(int* queue, int first_free) {
+  if (threadIdx.x == 0) queue[0] = first_free;
+}
+
+// ---- host side ------------------------------------------------------------------------------
+static int mr_np(int64_t n) { return (int)((n + 15) / 16 * 16); }
+
+size_t solve_mrhs_lds_bytes(int64_t n) {
+  const size_t np = (size_t)mr_np(n);
+  return sizeof(float) * 4 * np * MR_SLOTS + (sizeof(int) * 2 + sizeof(float)) * MR_CAP +
+         sizeof(float) * 8 * MR_SLOTS + sizeof(int) * 8 * MR_SLOTS +
+         sizeof(float) * 4 * MR_SLOTS * 4 + sizeof(int) * 8 + 64;
+}
+
+bool solve_mrhs_supported(int64_t n, int64_t k) {
+  return k >= 2 && n >= 1 && (n % 4) == 0 && solve_mrhs_lds_bytes(n) <= 160 * 1024;
+}
+
+size_t solve_mrhs_ws_bytes() { return 256; }
+
+hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* q,
+                             const double* s, double tol, int max_iter, const float* Y0,
+                             float* X, int32_t* iters, double* kkt, int32_t* status,
+                             int64_t* rows_read, void* ws, hipStream_t st) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const size_t lds = solve_mrhs_lds_bytes(n);
+  int per_cu = 1;
+  hipError_t e = hipFuncSetAttribute((const void*)solve_mrhs_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)solve_mrhs_kernel,
+                                                   MR_NT, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  int64_t groups = (k + MR_SLOTS - 1) / MR_SLOTS;
+  const int64_t resident = (int64_t)cus * per_cu;
+  if (groups > resident) groups = resident;
+  MrArgs A;
+  A.n = (int)n;
+  A.np = mr_np(n);
+  A.k = (int)k;
+  A.Q = Q;
+  A.q = q;
+  A.s = s;
+  A.Y0 = Y0;
+  A.X = X;
+  A.tol = tol;
+  A.max_iter = max_iter;
+  A.iters = iters;
+  A.kkt = kkt;
+  A.status = status;
+  A.rows_read = rows_read;
+  A.queue = (int*)ws;
+  hipLaunchKernelGGL(solve_mrhs_queue_init, dim3(1), dim3(64), 0, st, A.queue,
+                     (int)(groups * MR_SLOTS));
+  hipLaunchKernelGGL(solve_mrhs_kernel, dim3((unsigned)groups), dim3(MR_NT), lds, st, A);
+  return hipGetLastError();
+}
+
+}  // namespace nnls

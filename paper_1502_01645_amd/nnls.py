@@ -35,6 +35,11 @@ class NNLSError(RuntimeError):
     pass
 
 
+class ProblemDesc(ctypes.Structure):
+    """nnls_problem_desc of nnls.h (element offsets into the pools)."""
+    _fields_ = [(f, ctypes.c_int64) for f in ("d", "n", "offA", "offB", "offQ", "offq", "offX")]
+
+
 def lib():
     """The loaded libnnls.so (raises if it is not built)."""
     global _lib
@@ -58,6 +63,16 @@ def lib():
         L.nnls_refine.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _vp, _vp, _vp,
                                   _vp, _sz, _vp]
         L.nnls_refine.restype = ctypes.c_int
+        L.nnls_batched_workspace_bytes.argtypes = [ctypes.POINTER(ProblemDesc), _i64]
+        L.nnls_batched_workspace_bytes.restype = _sz
+        L.nnls_batched_plan_create.argtypes = [ctypes.POINTER(ProblemDesc), _i64, ctypes.c_double,
+                                               _i32] + [_vp] * 11 + [_sz, _vp,
+                                               ctypes.POINTER(ctypes.c_void_p)]
+        L.nnls_batched_plan_create.restype = ctypes.c_int
+        L.nnls_batched_plan_launch.argtypes = [_vp, _vp]
+        L.nnls_batched_plan_launch.restype = ctypes.c_int
+        L.nnls_batched_plan_destroy.argtypes = [_vp]
+        L.nnls_batched_plan_destroy.restype = None
         L.nnls_last_hip_error.argtypes = []
         L.nnls_last_hip_error.restype = ctypes.c_char_p
         L.nnls_version.argtypes = []
@@ -231,3 +246,76 @@ def nnls(A: torch.Tensor, B: torch.Tensor, tol: float = 1e-5, max_iter: int = 0,
         kkt64, obj64 = refine(A, B, X)
         res.update(kkt64=kkt64, obj64=obj64)
     return res
+
+
+def pack_problems(problems, device):
+    """Lay out a list of (A_i [d_i, n_i], b_i [d_i]) host FP32 arrays as the A / B pools of a
+    batched plan.  Returns (A_pool, B_pool, descriptors)."""
+    import numpy as np
+    descs = (ProblemDesc * len(problems))()
+    offA = offB = offQ = offq = 0
+    a_parts, b_parts = [], []
+    for i, (A, b) in enumerate(problems):
+        d, n = A.shape
+        descs[i] = ProblemDesc(d, n, offA, offB, offQ, offq, offq)
+        a_parts.append(np.ascontiguousarray(A, dtype=np.float32).reshape(-1))
+        b_parts.append(np.ascontiguousarray(b, dtype=np.float32).reshape(-1))
+        offA += d * n
+        offB += d
+        offQ += n * n
+        offq += n
+    A_pool = torch.from_numpy(np.concatenate(a_parts)).to(device)
+    B_pool = torch.from_numpy(np.concatenate(b_parts)).to(device)
+    return A_pool, B_pool, descs
+
+
+class BatchedPlan:
+    """An uneven batch captured as one graph (nnls_batched_plan_*).  Outputs: Q, q, s, X pools
+    and per-problem iters, kkt, status, rows_read."""
+
+    def __init__(self, A_pool, B_pool, descs, tol=1e-5, max_iter=0):
+        dev = A_pool.device
+        count = len(descs)
+        sum_n = sum(int(descs[i].n) for i in range(count))
+        sum_nn = sum(int(descs[i].n) ** 2 for i in range(count))
+        self.descs = descs
+        self.A_pool, self.B_pool = A_pool, B_pool
+        self.Q_pool = torch.empty(sum_nn, dtype=torch.float32, device=dev)
+        self.q_pool = torch.empty(sum_n, dtype=torch.float32, device=dev)
+        self.s_pool = torch.empty(sum_n, dtype=torch.float64, device=dev)
+        self.X_pool = torch.empty(sum_n, dtype=torch.float32, device=dev)
+        self.iters = torch.empty(count, dtype=torch.int32, device=dev)
+        self.kkt = torch.empty(count, dtype=torch.float64, device=dev)
+        self.status = torch.empty(count, dtype=torch.int32, device=dev)
+        self.rows_read = torch.zeros(count, dtype=torch.int64, device=dev)
+        wsb = int(lib().nnls_batched_workspace_bytes(descs, count))
+        self.ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        self._capture = torch.cuda.Stream(device=dev)
+        torch.cuda.synchronize(dev)
+        handle = ctypes.c_void_p()
+        rc = lib().nnls_batched_plan_create(
+            descs, count, float(tol), int(max_iter), _ptr(A_pool), _ptr(B_pool),
+            _ptr(self.Q_pool), _ptr(self.q_pool), _ptr(self.s_pool), _ptr(self.X_pool),
+            _ptr(self.iters), _ptr(self.kkt), _ptr(self.status), _ptr(self.rows_read),
+            _ptr(self.ws), wsb, ctypes.c_void_p(self._capture.cuda_stream), ctypes.byref(handle))
+        _check(rc, "nnls_batched_plan_create")
+        self.handle = handle
+
+    def launch(self):
+        rc = lib().nnls_batched_plan_launch(self.handle, _stream(self.A_pool.device))
+        _check(rc, "nnls_batched_plan_launch")
+
+    def x(self, i):
+        d = self.descs[i]
+        return self.X_pool[d.offX:d.offX + d.n]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().nnls_batched_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -38,10 +38,16 @@ def test_exports_every_declared_symbol(L):
         assert hasattr(L, name), name
 
 
-def test_workspace_sizes(L):
+def test_workspace_sizes(L, monkeypatch):
     from paper_1502_01645_amd import nnls as N
-    assert N.workspace_bytes(N.OP_SOLVE, 0, 100, 3, 0, N.F32) >= 3 * 100 * 3 * 4
+    # FP32 with several right-hand sides: matrix-core solver, only a queue counter
+    assert N.workspace_bytes(N.OP_SOLVE, 0, 100, 3, 0, N.F32) >= 4
+    # FP64, or the per-column solver forced: three vectors per column
     assert N.workspace_bytes(N.OP_SOLVE, 0, 100, 3, 0, N.F64) >= 3 * 100 * 3 * 8
+    monkeypatch.setenv("NNLS_SOLVER", "wg")
+    assert N.workspace_bytes(N.OP_SOLVE, 0, 100, 3, 0, N.F32) >= 3 * 100 * 3 * 4
+    monkeypatch.delenv("NNLS_SOLVER")
+    assert N.workspace_bytes(N.OP_SCALES, 1000, 100, 0, 0, N.F32) > 0
     assert N.workspace_bytes(N.OP_PREPARE, 1000, 100, 1, N.GRAM_BF16X3, N.F32) > 0
     assert N.workspace_bytes(N.OP_REFINE, 1000, 100, 1, 0, N.F32) > 0
     # invalid shapes size to 0
@@ -137,3 +143,34 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(N, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(N.NNLSError):
         N.lib()
+
+
+def test_batched_plan_rejects_bad_arguments(L):
+    from paper_1502_01645_amd import nnls as N
+    descs = (N.ProblemDesc * 2)(N.ProblemDesc(30, 10, 0, 0, 0, 0, 0),
+                                N.ProblemDesc(30, 10, 300, 30, 100, 10, 10))
+    assert L.nnls_batched_workspace_bytes(descs, 2) > 0
+    assert L.nnls_batched_workspace_bytes(None, 2) == 0
+    pools = [FAKE] * 6 + [FAKE, FAKE, FAKE, None]  # A B Q q s X pools, iters kkt status rows
+    big = 1 << 40
+
+    def create(d=descs, count=2, tol=1e-5, mi=0, p=pools, ws=FAKE, wsb=big, stream=FAKE):
+        out = ctypes.c_void_p()
+        return L.nnls_batched_plan_create(d, count, tol, mi, *p, ws, wsb, stream,
+                                          ctypes.byref(out))
+
+    assert create(count=0) == N.E_ARG
+    assert create(d=None) == N.E_ARG
+    assert create(tol=-1.0) == N.E_ARG
+    assert create(mi=-3) == N.E_ARG
+    assert create(stream=None) == N.E_ARG          # the null stream cannot be captured
+    for j in range(9):
+        p = list(pools)
+        p[j] = None
+        assert create(p=p) == N.E_ARG, j
+    bad = (N.ProblemDesc * 1)(N.ProblemDesc(0, 10, 0, 0, 0, 0, 0))
+    assert create(d=bad, count=1) == N.E_ARG
+    big_n = (N.ProblemDesc * 1)(N.ProblemDesc(3000, 2000, 0, 0, 0, 0, 0))
+    assert create(d=big_n, count=1) == N.E_UNSUPPORTED
+    assert create(ws=None) == N.E_WORKSPACE
+    assert create(wsb=16) == N.E_WORKSPACE

@@ -1,0 +1,104 @@
+"""Uneven batch (one captured graph over many independent problems) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import DEV, gram_abs_tol, host, orc, say
+from oracle import oracle as O
+from paper_1502_01645_amd import nnls as N
+from paper_1502_01645_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _problems():
+    """Edge sizes around the 128-wide tiles and the 64-entry ownership chunks, plus problems
+    of the batched workload recipe (n ~ U{16..512}, d = 3n)."""
+    rng = np.random.default_rng(51)
+    probs = []
+    for n, d in [(1, 3), (2, 6), (7, 21), (16, 48), (63, 189), (64, 64), (65, 195), (127, 381),
+                 (128, 128), (129, 387), (255, 300), (256, 768), (257, 771), (384, 1152)]:
+        A = rng.random((d, n)).astype(np.float32)
+        x = np.where(rng.random(n) < 0.6, 0.0, rng.random(n))
+        b = (A.astype(np.float64) @ x + 0.01 * rng.standard_normal(d)).astype(np.float32)
+        probs.append((A, b))
+    for i in range(10):
+        A, b, _ = W.make_batched_problem(i)
+        probs.append((A, b[:, 0]))
+    return probs
+
+
+@pytest.fixture(scope="module")
+def solved():
+    probs = _problems()
+    say(f"batched plan over {len(probs)} problems")
+    A_pool, B_pool, descs = N.pack_problems(probs, DEV)
+    plan = N.BatchedPlan(A_pool, B_pool, descs, tol=3e-6, max_iter=100000)
+    plan.launch()
+    torch.cuda.synchronize()
+    return probs, plan
+
+
+def test_batched_rescaled_problem(solved):
+    probs, plan = solved
+    Qp = host(plan.Q_pool)
+    qp = host(plan.q_pool)
+    for i, (A, b) in enumerate(probs):
+        dsc = plan.descs[i]
+        n, d = dsc.n, dsc.d
+        Q = Qp[dsc.offQ:dsc.offQ + n * n].reshape(n, n).astype(np.float64)
+        s_o, Q_o, q_o = orc().prepare(A, b.reshape(-1, 1))
+        # the batch takes its scales from the computed Gram diagonal: any positive scaling is
+        # an exact rescale, so Q still matches the cosine matrix within the Gram error (x2 for
+        # the scale error)
+        tol = 2 * gram_abs_tol(d, "bf16x3")
+        assert np.abs(Q - Q_o).max() <= tol, (i, np.abs(Q - Q_o).max())
+        assert np.array_equal(Q, Q.T)
+        assert np.all(np.diag(Q) == 1.0)
+        q = qp[dsc.offq:dsc.offq + n].astype(np.float64)
+        assert np.abs(q - q_o[:, 0]).max() <= tol * np.linalg.norm(b), i
+
+
+def test_batched_solutions_meet_tolerances(solved):
+    probs, plan = solved
+    st = host(plan.status)
+    assert np.all(st == N.CONVERGED), st
+    X = host(plan.X_pool)
+    worst_r, worst_gap = 0.0, 0.0
+    for i, (A, b) in enumerate(probs):
+        dsc = plan.descs[i]
+        x = X[dsc.offX:dsc.offX + dsc.n].reshape(-1, 1)
+        assert np.all(x >= 0)
+        r, F = orc().kkt_x(A, b.reshape(-1, 1), x)
+        ref = O.reference_solution(A, b.reshape(-1, 1))
+        gap = O.relative_gap(F, ref)
+        worst_r, worst_gap = max(worst_r, r[0]), max(worst_gap, gap[0])
+        assert r[0] <= 1e-5, (i, dsc.n, r[0])
+        assert gap[0] <= 1e-6, (i, dsc.n, gap[0])
+    say(f"batched: worst r={worst_r:.3e} worst gap={worst_gap:.3e}")
+
+
+def test_batched_graph_replays_identical(solved):
+    """Relaunching the captured graph (with eager work in between) reproduces every output."""
+    probs, plan = solved
+    X0, it0 = host(plan.X_pool).copy(), host(plan.iters).copy()
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device=DEV)
+        junk.mul_(2.0).sum()
+        torch.cuda.synchronize()
+        plan.X_pool.fill_(-1.0)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(plan.X_pool), X0), rep
+        assert np.array_equal(host(plan.iters), it0), rep
+
+
+def test_batched_matches_per_problem_launches(solved):
+    """The batch gives the same quality as solving each problem with its own C-ABI calls."""
+    probs, plan = solved
+    for i in [0, 5, 9, 13, 20]:
+        A, b = probs[i]
+        res = N.nnls(torch.from_numpy(A).to(DEV), torch.from_numpy(b.reshape(-1, 1)).to(DEV),
+                     tol=1e-5, max_iter=100000, inner_tol=3e-6, refine_step=False)
+        r1, _ = orc().kkt_x(A, b.reshape(-1, 1), host(res["X"]))
+        assert r1[0] <= 1e-5

@@ -288,3 +288,57 @@ def test_persistent_statuses(force_persistent):
     qp = q.abs()
     X, it, kkt, st = N.solve(Q, qp, s, tol=1e-6, max_iter=50)
     assert host(st)[0] == N.CONVERGED and host(it)[0] == 0 and np.all(host(X) == 0)
+
+
+# ---------------------------------------------------------------------------- many-RHS solver
+@pytest.mark.parametrize("solver", ["mrhs", "wg"])
+@pytest.mark.parametrize("n,k", [(96, 20), (100, 33)])
+def test_multi_rhs_steps_match_oracle(solver, n, k, monkeypatch):
+    """Matrix-core many-RHS solver (and the per-column solver) against the oracle, one update
+    from the oracle's state per column, for several column slots and a padded n."""
+    monkeypatch.setenv("NNLS_SOLVER", solver)
+    say(f"{solver} single steps n={n} k={k}")
+    A, B = _uniform_case(31 + n, 3 * n, n, k)
+    Q, q, s = N.prepare(dev(A), dev(B))
+    Qh, qh = host(Q).astype(np.float64), host(q).astype(np.float64)
+    eps = 2.0 ** -23
+    for m in [0, 1, 3, 10]:
+        Ym = np.zeros((n, k))
+        if m:
+            for c in range(k):
+                Ym[:, c] = orc().nqp(Qh, qh[:, c], 0.0, m)[0]
+        Ystart = Ym.astype(np.float32).astype(np.float64)
+        Y, iters, kkt, st = N.solve(Q, q, None, tol=0.0, max_iter=1,
+                                    Y0=dev(Ym.astype(np.float32)) if m else None)
+        Yh = host(Y).astype(np.float64)
+        assert np.all(host(iters) == 1)
+        for c in range(k):
+            yn = orc().nqp(Qh, qh[:, c], 0.0, 1, y0=Ystart[:, c])[0]
+            err = np.abs(Yh[:, c] - yn).max()
+            scale = np.abs(Ystart[:, c]).max() + np.abs(yn).max()
+            assert err <= 8 * n * eps * scale, (m, c, err / scale)
+
+
+def test_multi_rhs_end_to_end():
+    """Many-RHS workload recipe at reduced size; every column meets the tolerances."""
+    A, B, _ = W.make_manyrhs(seed=6, d=3000, n=128, k=300)
+    say("mrhs e2e 3000x128 k=300")
+    res = N.nnls(dev(A), dev(B), tol=1e-5, max_iter=100000, inner_tol=3e-6)
+    assert np.all(host(res["status"]) == N.CONVERGED)
+    ref = O.reference_solution(A, B)
+    _check_solution(A, B, host(res["X"]), 1e-5, ref, "mrhs")
+
+
+def test_multi_rhs_queue_refill():
+    """More columns than resident slots: finished slots take new columns from the queue."""
+    rng = np.random.default_rng(41)
+    d, n, k = 40, 8, 12000
+    A = rng.random((d, n)).astype(np.float32)
+    X = np.where(rng.random((n, k)) < 0.5, 0.0, rng.random((n, k)))
+    B = (A.astype(np.float64) @ X + 0.01 * rng.standard_normal((d, k))).astype(np.float32)
+    say("mrhs queue refill k=12000")
+    res = N.nnls(dev(A), dev(B), tol=1e-5, max_iter=100000, inner_tol=3e-6)
+    assert np.all(host(res["status"]) == N.CONVERGED)
+    r, F = orc().kkt_x(A, B, host(res["X"]))
+    assert r.max() <= 1e-5
+    assert np.all(host(res["iters"]) >= 0)
