@@ -198,6 +198,67 @@ int nnls_batched_plan_launch(nnls_plan* plan, void* stream);
 /* Releases the plan's graph (not the pools or the workspace). */
 void nnls_batched_plan_destroy(nnls_plan* plan);
 
+/* ---- Learned warm start --------------------------------------------------------------------
+ * Algorithm 2 may start from any y0 >= 0 (the worked example of Section 3 starts from a nonzero
+ * point).  This addition, which the paper does not have, predicts y0 for the fixed-size case
+ * n = 256 with a 256 -> 1024 -> 1024 -> 256 network (GELU hidden layers, exact x * Phi(x)) that
+ * reads u = q / ||q|| (one column of q) and returns one head z per column:
+ *     y0 = ||q|| * ReLU(z)      (Problem (5) is positively homogeneous in q, so this is exact)
+ *     logit of "y*_i > 0" = z_i.
+ * Training minimises, averaged over the batch,
+ *     1/2 ||ReLU(z) - t||^2 + lambda * BCE(z, 1[t > 0]),   t = y* / ||q||,
+ * with Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on FP32 master weights; the
+ * products run on a BF16 copy with FP32 accumulation.
+ *
+ * Parameters live in one device blob of nnls_mlp_blob_bytes() bytes, owned by the caller:
+ *     float master[P] | float adam_m[P] | float adam_v[P] | bf16 copy[P],  P = nnls_mlp_param_count()
+ * with master laid out as W1 [256, 1024] | b1 [1024] | W2 [1024, 1024] | b2 [1024] |
+ * W3 [1024, 256] | b3 [256] (row-major, input index first: h = u W1 + b1).  The caller writes the
+ * master weights and calls nnls_mlp_reset_state() to clear the Adam moments and make the BF16
+ * copy; nnls_mlp_train_step() keeps the copy in step with the master.
+ *
+ * batch must be a positive multiple of 64 (at most 2^24).  u, target and z are FP32 [batch, 256]
+ * row-major.  Workspaces are sized by nnls_mlp_workspace_bytes(batch, train) with train = 0 for
+ * the forward pass and 1 for gradients and training steps. */
+int64_t nnls_mlp_param_count(void);
+size_t nnls_mlp_blob_bytes(void);
+size_t nnls_mlp_workspace_bytes(int64_t batch, int train);
+
+/* Clears the Adam moments and rounds the master weights to the BF16 copy. */
+int nnls_mlp_reset_state(void* blob, void* stream);
+
+/* z = network(u) for `batch` rows. */
+int nnls_mlp_forward(int64_t batch, const void* blob, const float* u, float* z, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Loss (FP32 scalar, device) and the gradient of every parameter (FP32 [P], the master layout)
+ * for one batch, without changing the blob.  grad_out and loss_out may each be NULL. */
+int nnls_mlp_gradients(int64_t batch, const void* blob, const float* u, const float* target,
+                       float lambda, float* grad_out, float* loss_out, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* One Adam step with learning rate lr; step counts from 1 (bias correction).  loss_out (device,
+ * may be NULL) receives the batch loss before the step. */
+int nnls_mlp_train_step(int64_t batch, void* blob, const float* u, const float* target, float lr,
+                        int64_t step, float lambda, float* loss_out, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* Network inputs and training targets from a rescaled problem with n = 256: for each column c
+ * of q [256, k], U[c, :] = q[:, c] / ||q_c|| and, if Y [256, k] (a solution of Problem (5), e.g.
+ * from nnls_solve with s = NULL) is given, T[c, :] = Y[:, c] / ||q_c||.  U and T are FP32
+ * [k, 256]; T may be NULL when Y is.  A zero column of q is divided by 1. */
+int nnls_mlp_inputs(int64_t n, int64_t k, const float* q, const float* Y, float* U, float* T,
+                    void* stream);
+
+/* Warm start for k right-hand sides of a rescaled problem with n = 256 (other n return
+ * NNLS_E_UNSUPPORTED).  Q [256, 256] and q [256, k] FP32 as produced by nnls_prepare; writes
+ * Y0 [256, k] FP32 for nnls_solve and fell_back[k] (int32, device): 1 where the predicted point
+ * had f(y0) = 1/2 y0^T Q y0 + q^T y0 > 0 = f(0) (or was not finite), in which case that column of
+ * Y0 is 0, the cold start.  Workspace: nnls_warm_start_workspace_bytes(n, k). */
+size_t nnls_warm_start_workspace_bytes(int64_t n, int64_t k);
+int nnls_warm_start(int64_t n, int64_t k, const float* Q, const float* q, const void* blob,
+                    float* Y0, int32_t* fell_back, void* ws, size_t ws_bytes, void* stream);
+
 /* Text of the last HIP error seen by this thread (empty if none). */
 const char* nnls_last_hip_error(void);
 

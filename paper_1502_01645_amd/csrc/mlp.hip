@@ -1,0 +1,564 @@
+// Learned warm start for Algorithm 2: a 256 -> 1024 -> 1024 -> 256 GELU network mapping the
+// normalised rescaled right-hand side u = q / ||q|| to one 256-wide head z, read two ways: the
+// start point y0 = ||q|| * ReLU(z) (Problem (5) is positively homogeneous in q) and the
+// passive-set logit z.  Training minimises
+//     1/2 ||ReLU(z) - y* / ||q|| ||^2 + lambda * BCE(z, 1[y* > 0])        (mean over the batch)
+// with Adam on FP32 master weights; products run on BF16 copies with FP32 accumulation.
+//
+// Kernels: one BF16 GEMM on the matrix cores (v_mfma_f32_16x16x32_bf16, 64 x 64 tiles, operands
+// transposed as needed while staged into LDS) with fused epilogues (bias + GELU keeping the
+// pre-activation, bias, plain FP32, GELU backward); the loss and its gradient; column sums for
+// bias gradients; Adam; and the warm-start assembly with the objective check that falls back to
+// y = 0 when f(y0) = 1/2 y0^T Q y0 + q^T y0 > 0.
+#include "../../include/nnls.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace nnls {
+
+constexpr int ML_IN = 256, ML_H = 1024, ML_OUT = 256;
+// parameter layout (elements): W1 [IN, H], b1 [H], W2 [H, H], b2 [H], W3 [H, OUT], b3 [OUT]
+constexpr int64_t ML_W1 = 0;
+constexpr int64_t ML_B1 = ML_W1 + (int64_t)ML_IN * ML_H;
+constexpr int64_t ML_W2 = ML_B1 + ML_H;
+constexpr int64_t ML_B2 = ML_W2 + (int64_t)ML_H * ML_H;
+constexpr int64_t ML_W3 = ML_B2 + ML_H;
+constexpr int64_t ML_B3 = ML_W3 + (int64_t)ML_H * ML_OUT;
+constexpr int64_t ML_P = ML_B3 + ML_OUT;
+// blob: FP32 master [P], Adam m [P], Adam v [P], BF16 copy [P]
+constexpr size_t ML_BLOB = sizeof(float) * 3 * ML_P + sizeof(uint16_t) * ML_P;
+
+typedef uint16_t bf16_t;
+
+__device__ __forceinline__ bf16_t to_bf16(float x) { return (bf16_t)bf16_bits_rne(x); }
+__device__ __forceinline__ float from_bf16(bf16_t b) { return bf16_bits_to_f32(b); }
+
+__device__ __forceinline__ float gelu(float x) {
+  return 0.5f * x * (1.f + erff(x * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad(float x) {
+  const float cdf = 0.5f * (1.f + erff(x * 0.70710678118654752f));
+  const float pdf = 0.39894228040143268f * expf(-0.5f * x * x);
+  return cdf + x * pdf;
+}
+
+enum { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_GELU = 2, EPI_GELU_BWD = 3 };
+
+struct GemmEpi {
+  float* out_f32;        // EPI_F32, EPI_BIAS_F32, EPI_BIAS_GELU (pre-activation)
+  bf16_t* out_bf16;      // EPI_BIAS_GELU (activation), EPI_GELU_BWD (gradient)
+  const float* bias;     // EPI_BIAS_*
+  const float* pre;      // EPI_GELU_BWD: pre-activation of the layer
+  int64_t ldc;
+};
+
+constexpr int MG_T = 64;   // tile
+constexpr int MG_BK = 32;
+constexpr int MG_LDK = 40;
+
+// C[M, N] = op(A)[M, K] op(B)[K, N], bf16 inputs, FP32 accumulation.
+// op(A)(m, k) = TA ? A[k * lda + m] : A[m * lda + k];  op(B)(k, n) = TB ? B[n * ldb + k] : B[k * ldb + n].
+// Requires M, N multiples of 64 and K a multiple of 32 (checked on the host).
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void mlp_gemm_kernel(int M, int N, int K,
+                                                       const bf16_t* __restrict__ A, int64_t lda,
+                                                       const bf16_t* __restrict__ B, int64_t ldb,
+                                                       GemmEpi E) {
+  __shared__ __attribute__((aligned(16))) bf16_t sA[MG_T * MG_LDK];
+  __shared__ __attribute__((aligned(16))) bf16_t sB[MG_T * MG_LDK];
+  const int m0 = blockIdx.x * MG_T, n0 = blockIdx.y * MG_T;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = 0; k0 < K; k0 += MG_BK) {
+    // A tile: 64 rows (m) x 32 k
+    if (!TA) {  // k contiguous: 8 bf16 per thread
+      const int mm = tid >> 2, kk = (tid & 3) * 8;
+      const u32x4 v = *(const u32x4*)(A + (int64_t)(m0 + mm) * lda + k0 + kk);
+      *(u32x4*)&sA[mm * MG_LDK + kk] = v;
+    } else {    // m contiguous: 8 consecutive m of one k
+      const int kk = tid >> 3, mm = (tid & 7) * 8;
+      const u32x4 v = *(const u32x4*)(A + (int64_t)(k0 + kk) * lda + m0 + mm);
+      const bf16_t* e = (const bf16_t*)&v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sA[(mm + j) * MG_LDK + kk] = e[j];
+    }
+    if (TB) {   // k contiguous along a row of B (n fixed)
+      const int nn = tid >> 2, kk = (tid & 3) * 8;
+      const u32x4 v = *(const u32x4*)(B + (int64_t)(n0 + nn) * ldb + k0 + kk);
+      *(u32x4*)&sB[nn * MG_LDK + kk] = v;
+    } else {    // n contiguous
+      const int kk = tid >> 3, nn = (tid & 7) * 8;
+      const u32x4 v = *(const u32x4*)(B + (int64_t)(k0 + kk) * ldb + n0 + nn);
+      const bf16_t* e = (const bf16_t*)&v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sB[(nn + j) * MG_LDK + kk] = e[j];
+    }
+    __syncthreads();
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    bf16x8 af[2], bf[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      af[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&sA[(wm + t * 16 + fr) * MG_LDK + fk]);
+      bf[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&sB[(wn + t * 16 + fr) * MG_LDK + fk]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+    __syncthreads();
+  }
+  const int oc = lane & 15, orow = (lane >> 4) * 4;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t m = m0 + wm + a * 16 + orow + e;
+        const int64_t n = n0 + wn + b * 16 + oc;
+        const float v = acc[a][b][e];
+        const int64_t o = m * E.ldc + n;
+        if (EPI == EPI_F32) {
+          E.out_f32[o] = v;
+        } else if (EPI == EPI_BIAS_F32) {
+          E.out_f32[o] = v + E.bias[n];
+        } else if (EPI == EPI_BIAS_GELU) {
+          const float pre = v + E.bias[n];
+          E.out_f32[o] = pre;
+          E.out_bf16[o] = to_bf16(gelu(pre));
+        } else {
+          E.out_bf16[o] = to_bf16(v * gelu_grad(E.pre[o]));
+        }
+      }
+}
+
+template <bool TA, bool TB, int EPI>
+static void gemm(int M, int N, int K, const bf16_t* A, int64_t lda, const bf16_t* B, int64_t ldb,
+                 GemmEpi E, hipStream_t st) {
+  dim3 grid((unsigned)(M / MG_T), (unsigned)(N / MG_T));  // N / 64 <= 16
+  hipLaunchKernelGGL((mlp_gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B,
+                     ldb, E);
+}
+
+// X[b, :] = bf16(u_b) for the batch input (FP32 [batch, 256] -> BF16).
+__global__ void to_bf16_kernel(int64_t count, const float* __restrict__ x, bf16_t* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) y[i] = to_bf16(x[i]);
+}
+
+// Loss and its gradient w.r.t. z (scaled by 1 / batch), per row block; loss partial per block.
+__global__ __launch_bounds__(256) void mlp_loss_kernel(int64_t batch, const float* __restrict__ Z,
+                                                       const float* __restrict__ T, float lambda,
+                                                       bf16_t* __restrict__ dZ,
+                                                       float* __restrict__ loss_part) {
+  __shared__ float red[4];
+  const int64_t r = blockIdx.x;  // one row per block, 256 outputs per row
+  const int j = threadIdx.x;
+  const int64_t o = r * ML_OUT + j;
+  const float z = Z[o], t = T[o];
+  const float relu = z > 0.f ? z : 0.f;
+  const float lab = t > 0.f ? 1.f : 0.f;
+  const float diff = relu - t;
+  // BCE with logits, stable form: max(z,0) - z*lab + log(1 + exp(-|z|))
+  const float bce = relu - z * lab + log1pf(expf(-fabsf(z)));
+  const float sig = 1.f / (1.f + expf(-z));
+  const float g = (diff * (z > 0.f ? 1.f : 0.f) + lambda * (sig - lab)) / (float)batch;
+  dZ[o] = to_bf16(g);
+  float l = 0.5f * diff * diff + lambda * bce;
+  l = block_sum<float, 256>(l, red);
+  if (j == 0) loss_part[r] = l / (float)batch;
+}
+
+// out[j] = sum_r in[r, j] (FP32 or BF16 rows), one thread per column.
+template <typename TI>
+__global__ void colsum_kernel(int64_t rows, int64_t cols, const TI* __restrict__ in,
+                              float* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= cols) return;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  int64_t r = 0;
+  for (; r + 3 < rows; r += 4) {
+    if constexpr (sizeof(TI) == 2) {
+      a0 += from_bf16(in[(r + 0) * cols + j]);
+      a1 += from_bf16(in[(r + 1) * cols + j]);
+      a2 += from_bf16(in[(r + 2) * cols + j]);
+      a3 += from_bf16(in[(r + 3) * cols + j]);
+    } else {
+      a0 += in[(r + 0) * cols + j];
+      a1 += in[(r + 1) * cols + j];
+      a2 += in[(r + 2) * cols + j];
+      a3 += in[(r + 3) * cols + j];
+    }
+  }
+  for (; r < rows; ++r) {
+    if constexpr (sizeof(TI) == 2) a0 += from_bf16(in[r * cols + j]);
+    else a0 += in[r * cols + j];
+  }
+  out[j] = (a0 + a1) + (a2 + a3);
+}
+
+__global__ void sum_kernel(int64_t count, const float* __restrict__ in, float* __restrict__ out) {
+  __shared__ float red[4];
+  float a = 0.f;
+  for (int64_t i = threadIdx.x; i < count; i += 256) a += in[i];
+  a = block_sum<float, 256>(a, red);
+  if (threadIdx.x == 0) out[0] = a;
+}
+
+// Adam (bias-corrected) on the FP32 master weights, then the BF16 copy.
+__global__ void adam_kernel(int64_t count, float* __restrict__ w, float* __restrict__ m,
+                            float* __restrict__ v, bf16_t* __restrict__ wb,
+                            const float* __restrict__ g, float lr, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  wb[i] = to_bf16(wi);
+}
+
+__global__ void reset_state_kernel(int64_t count, const float* __restrict__ w,
+                                   float* __restrict__ m, float* __restrict__ v,
+                                   bf16_t* __restrict__ wb) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  m[i] = 0.f;
+  v[i] = 0.f;
+  wb[i] = to_bf16(w[i]);
+}
+
+// ---- workspace layout ------------------------------------------------------------------------
+struct MlpWs {
+  bf16_t *X, *A1, *A2, *dZ, *dH2, *dH1;
+  float *H1, *H2, *Z, *grad, *loss_part, *loss;
+};
+
+static size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+static MlpWs mlp_layout(void* ws, int64_t batch, bool train, size_t* total) {
+  MlpWs W{};
+  char* p = (char*)ws;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    void* r = p ? (void*)(p + off) : nullptr;
+    off += al(bytes);
+    return r;
+  };
+  W.X = (bf16_t*)take(2 * batch * ML_IN);
+  W.H1 = (float*)take(4 * batch * ML_H);
+  W.A1 = (bf16_t*)take(2 * batch * ML_H);
+  W.H2 = (float*)take(4 * batch * ML_H);
+  W.A2 = (bf16_t*)take(2 * batch * ML_H);
+  W.Z = (float*)take(4 * batch * ML_OUT);
+  if (train) {
+    W.dZ = (bf16_t*)take(2 * batch * ML_OUT);
+    W.dH2 = (bf16_t*)take(2 * batch * ML_H);
+    W.dH1 = (bf16_t*)take(2 * batch * ML_H);
+    W.grad = (float*)take(4 * ML_P);
+    W.loss_part = (float*)take(4 * batch);
+    W.loss = (float*)take(4);
+  }
+  if (total) *total = off;
+  return W;
+}
+
+size_t mlp_ws_bytes(int64_t batch, bool train) {
+  size_t t = 0;
+  mlp_layout(nullptr, batch, train, &t);
+  return t;
+}
+
+static const bf16_t* wcopy(const void* blob) {
+  return (const bf16_t*)((const char*)blob + sizeof(float) * 3 * ML_P);
+}
+
+// forward pass; leaves H1, A1, H2, A2 and Z in the workspace
+static void forward(int64_t batch, const void* blob, const float* u, const MlpWs& W,
+                    hipStream_t st) {
+  const bf16_t* Wb = wcopy(blob);
+  const float* master = (const float*)blob;
+  const int M = (int)batch;
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((batch * ML_IN + 255) / 256)), dim3(256), 0,
+                     st, batch * ML_IN, u, W.X);
+  GemmEpi e1{W.H1, W.A1, master + ML_B1, nullptr, ML_H};
+  gemm<false, false, EPI_BIAS_GELU>(M, ML_H, ML_IN, W.X, ML_IN, Wb + ML_W1, ML_H, e1, st);
+  GemmEpi e2{W.H2, W.A2, master + ML_B2, nullptr, ML_H};
+  gemm<false, false, EPI_BIAS_GELU>(M, ML_H, ML_H, W.A1, ML_H, Wb + ML_W2, ML_H, e2, st);
+  GemmEpi e3{W.Z, nullptr, master + ML_B3, nullptr, ML_OUT};
+  gemm<false, false, EPI_BIAS_F32>(M, ML_OUT, ML_H, W.A2, ML_H, Wb + ML_W3, ML_OUT, e3, st);
+}
+
+// loss, then gradients of every parameter into W.grad (same layout as the parameters)
+static void backward(int64_t batch, const void* blob, const float* target, float lambda,
+                     const MlpWs& W, hipStream_t st) {
+  const bf16_t* Wb = wcopy(blob);
+  const int M = (int)batch;
+  hipLaunchKernelGGL(mlp_loss_kernel, dim3((unsigned)batch), dim3(256), 0, st, batch, W.Z, target,
+                     lambda, W.dZ, W.loss_part);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, batch, (const float*)W.loss_part,
+                     W.loss);
+  // layer 3: dW3 = A2^T dZ, db3 = colsum dZ, dA2 = dZ W3^T -> dH2 = dA2 * gelu'(H2)
+  GemmEpi g3{W.grad + ML_W3, nullptr, nullptr, nullptr, ML_OUT};
+  gemm<true, false, EPI_F32>(ML_H, ML_OUT, M, W.A2, ML_H, W.dZ, ML_OUT, g3, st);
+  hipLaunchKernelGGL(colsum_kernel<bf16_t>, dim3((ML_OUT + 255) / 256), dim3(256), 0, st, batch,
+                     (int64_t)ML_OUT, (const bf16_t*)W.dZ, W.grad + ML_B3);
+  GemmEpi d2{nullptr, W.dH2, nullptr, W.H2, ML_H};
+  gemm<false, true, EPI_GELU_BWD>(M, ML_H, ML_OUT, W.dZ, ML_OUT, Wb + ML_W3, ML_OUT, d2, st);
+  // layer 2
+  GemmEpi g2{W.grad + ML_W2, nullptr, nullptr, nullptr, ML_H};
+  gemm<true, false, EPI_F32>(ML_H, ML_H, M, W.A1, ML_H, W.dH2, ML_H, g2, st);
+  hipLaunchKernelGGL(colsum_kernel<bf16_t>, dim3((ML_H + 255) / 256), dim3(256), 0, st, batch,
+                     (int64_t)ML_H, (const bf16_t*)W.dH2, W.grad + ML_B2);
+  GemmEpi d1{nullptr, W.dH1, nullptr, W.H1, ML_H};
+  gemm<false, true, EPI_GELU_BWD>(M, ML_H, ML_H, W.dH2, ML_H, Wb + ML_W2, ML_H, d1, st);
+  // layer 1
+  GemmEpi g1{W.grad + ML_W1, nullptr, nullptr, nullptr, ML_H};
+  gemm<true, false, EPI_F32>(ML_IN, ML_H, M, W.X, ML_IN, W.dH1, ML_H, g1, st);
+  hipLaunchKernelGGL(colsum_kernel<bf16_t>, dim3((ML_H + 255) / 256), dim3(256), 0, st, batch,
+                     (int64_t)ML_H, (const bf16_t*)W.dH1, W.grad + ML_B1);
+}
+
+// ---- warm start ------------------------------------------------------------------------------
+constexpr int WS_C = 16;  // columns per block: q and Y0 rows are read and written 16 floats wide
+
+// For columns c0..c0+15 of q [n = 256, k]: ||q_c|| and u_c = q_c / ||q_c|| as row c of U [rows, n]
+// (rows >= k: rows c >= k, the batch padding, are zero).  With Y [n, k] given, also
+// T[c, :] = Y[:, c] / ||q_c||.  qn may be null.  Thread i owns row i of q and Y.
+__global__ __launch_bounds__(256) void ws_normalise_kernel(int64_t k, int64_t rows,
+                                                           const float* __restrict__ q,
+                                                           const float* __restrict__ Y,
+                                                           float* __restrict__ U,
+                                                           float* __restrict__ T,
+                                                           float* __restrict__ qn) {
+  __shared__ float red[WS_C][4];
+  const int i = threadIdx.x, lane = i & 63, wave = i >> 6;
+  const int64_t c0 = (int64_t)blockIdx.x * WS_C;
+  float v[WS_C];
+#pragma unroll
+  for (int c = 0; c < WS_C; ++c) v[c] = c0 + c < k ? q[(int64_t)i * k + c0 + c] : 0.f;
+#pragma unroll
+  for (int c = 0; c < WS_C; ++c) {
+    const float t = wave_sum(v[c] * v[c]);
+    if (lane == 0) red[c][wave] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < WS_C; ++c) {
+    if (c0 + c >= rows) break;
+    const float a = (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]);
+    const float nrm = a > 0.f ? sqrtf(a) : 1.f;
+    U[(c0 + c) * ML_IN + i] = v[c] / nrm;
+    if (Y) T[(c0 + c) * ML_IN + i] = c0 + c < k ? Y[(int64_t)i * k + c0 + c] / nrm : 0.f;
+    if (qn && i == 0 && c0 + c < k) qn[c0 + c] = nrm;
+  }
+}
+
+// Columns c0..c0+15: y_c = ||q_c|| ReLU(Z[c, :]); f_c = 1/2 y_c^T Q y_c + q_c^T y_c with Q read by
+// columns (Q is symmetric, so thread i accumulates (Q y_c)_i from coalesced rows of Q, each row
+// reused for the 16 columns).  A column whose f_c is not <= 0 (this includes NaN and inf) falls
+// back to the cold start y0 = 0.
+__global__ __launch_bounds__(256) void ws_assemble_kernel(int64_t k, const float* __restrict__ Q,
+                                                          const float* __restrict__ q,
+                                                          const float* __restrict__ Z,
+                                                          const float* __restrict__ qn,
+                                                          float* __restrict__ Y0,
+                                                          int32_t* __restrict__ fell_back) {
+  __shared__ float ys[WS_C][ML_IN];
+  __shared__ float red[WS_C][4];
+  const int i = threadIdx.x, lane = i & 63, wave = i >> 6;
+  const int64_t c0 = (int64_t)blockIdx.x * WS_C;
+  const int cols = (int)(k - c0 < WS_C ? k - c0 : WS_C);
+#pragma unroll
+  for (int c = 0; c < WS_C; ++c) {
+    float y = 0.f;
+    if (c < cols) {
+      const float z = Z[(c0 + c) * ML_IN + i];
+      y = qn[c0 + c] * (z > 0.f ? z : 0.f);
+      if (z != z) y = z;  // keep a NaN prediction visible to the objective check
+    }
+    ys[c][i] = y;
+  }
+  __syncthreads();
+  float qy[WS_C];
+#pragma unroll
+  for (int c = 0; c < WS_C; ++c) qy[c] = 0.f;
+  for (int j = 0; j < ML_IN; ++j) {
+    const float qji = Q[j * ML_IN + i];
+#pragma unroll
+    for (int c = 0; c < WS_C; ++c) qy[c] += qji * ys[c][j];
+  }
+#pragma unroll
+  for (int c = 0; c < WS_C; ++c) {
+    const float qi = c < cols ? q[(int64_t)i * k + c0 + c] : 0.f;
+    const float t = wave_sum(ys[c][i] * (0.5f * qy[c] + qi));
+    if (lane == 0) red[c][wave] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < WS_C; ++c) {
+    if (c >= cols) continue;
+    const float f = (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]);
+    const bool back = !(f <= 0.f);
+    Y0[(int64_t)i * k + c0 + c] = back ? 0.f : ys[c][i];
+    if (i == 0) fell_back[c0 + c] = back ? 1 : 0;
+  }
+}
+
+}  // namespace nnls
+
+// ---- C ABI -------------------------------------------------------------------------------------
+extern "C" {
+
+int64_t nnls_mlp_param_count(void) { return nnls::ML_P; }
+
+size_t nnls_mlp_blob_bytes(void) { return nnls::ML_BLOB; }
+
+size_t nnls_mlp_workspace_bytes(int64_t batch, int train) {
+  if (batch < 1) return 0;
+  return nnls::mlp_ws_bytes(batch, train != 0);
+}
+
+static int mlp_check_batch(int64_t batch) {
+  return (batch >= 64 && batch % 64 == 0 && batch <= (1 << 24)) ? NNLS_OK : NNLS_E_ARG;
+}
+
+int nnls_mlp_reset_state(void* blob, void* stream) {
+  if (!blob) return NNLS_E_ARG;
+  float* w = (float*)blob;
+  hipLaunchKernelGGL(nnls::reset_state_kernel, dim3((unsigned)((nnls::ML_P + 255) / 256)),
+                     dim3(256), 0, (hipStream_t)stream, nnls::ML_P, (const float*)w,
+                     w + nnls::ML_P, w + 2 * nnls::ML_P,
+                     (nnls::bf16_t*)(w + 3 * nnls::ML_P));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    nnls::record_hip_error(e);
+    return NNLS_E_HIP;
+  }
+  return NNLS_OK;
+}
+
+int nnls_mlp_forward(int64_t batch, const void* blob, const float* u, float* z, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (mlp_check_batch(batch) != NNLS_OK || !blob || !u || !z) return NNLS_E_ARG;
+  size_t need = 0;
+  nnls::mlp_layout(nullptr, batch, false, &need);
+  if (!ws || ws_bytes < need) return NNLS_E_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  nnls::MlpWs W = nnls::mlp_layout(ws, batch, false, nullptr);
+  nnls::forward(batch, blob, u, W, st);
+  hipError_t e = hipMemcpyAsync(z, W.Z, sizeof(float) * batch * nnls::ML_OUT,
+                                hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    nnls::record_hip_error(e);
+    return NNLS_E_HIP;
+  }
+  return NNLS_OK;
+}
+
+int nnls_mlp_gradients(int64_t batch, const void* blob, const float* u, const float* target,
+                       float lambda, float* grad_out, float* loss_out, void* ws, size_t ws_bytes,
+                       void* stream) {
+  if (mlp_check_batch(batch) != NNLS_OK || !blob || !u || !target) return NNLS_E_ARG;
+  size_t need = 0;
+  nnls::mlp_layout(nullptr, batch, true, &need);
+  if (!ws || ws_bytes < need) return NNLS_E_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  nnls::MlpWs W = nnls::mlp_layout(ws, batch, true, nullptr);
+  nnls::forward(batch, blob, u, W, st);
+  nnls::backward(batch, blob, target, lambda, W, st);
+  hipError_t e = hipSuccess;
+  if (grad_out)
+    e = hipMemcpyAsync(grad_out, W.grad, sizeof(float) * nnls::ML_P, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && loss_out)
+    e = hipMemcpyAsync(loss_out, W.loss, sizeof(float), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    nnls::record_hip_error(e);
+    return NNLS_E_HIP;
+  }
+  return NNLS_OK;
+}
+
+int nnls_mlp_train_step(int64_t batch, void* blob, const float* u, const float* target,
+                        float lr, int64_t step, float lambda, float* loss_out, void* ws,
+                        size_t ws_bytes, void* stream) {
+  if (step < 1 || !(lr > 0.f)) return NNLS_E_ARG;
+  int rc = nnls_mlp_gradients(batch, blob, u, target, lambda, nullptr, loss_out, ws, ws_bytes,
+                              stream);
+  if (rc != NNLS_OK) return rc;
+  nnls::MlpWs W = nnls::mlp_layout(ws, batch, true, nullptr);
+  float* w = (float*)blob;
+  const float c1 = 1.f - powf(0.9f, (float)step), c2 = 1.f - powf(0.999f, (float)step);
+  hipLaunchKernelGGL(nnls::adam_kernel, dim3((unsigned)((nnls::ML_P + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, nnls::ML_P, w, w + nnls::ML_P, w + 2 * nnls::ML_P,
+                     (nnls::bf16_t*)(w + 3 * nnls::ML_P), (const float*)W.grad, lr, c1, c2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    nnls::record_hip_error(e);
+    return NNLS_E_HIP;
+  }
+  return NNLS_OK;
+}
+
+int nnls_mlp_inputs(int64_t n, int64_t k, const float* q, const float* Y, float* U, float* T,
+                    void* stream) {
+  if (n != nnls::ML_IN) return n < 1 ? NNLS_E_ARG : NNLS_E_UNSUPPORTED;
+  if (k < 1 || k > (int64_t(1) << 30) || !q || !U || (Y && !T)) return NNLS_E_ARG;
+  hipLaunchKernelGGL(nnls::ws_normalise_kernel, dim3((unsigned)((k + nnls::WS_C - 1) / nnls::WS_C)),
+                     dim3(256), 0, (hipStream_t)stream, k, k, q, Y, U, T, (float*)nullptr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    nnls::record_hip_error(e);
+    return NNLS_E_HIP;
+  }
+  return NNLS_OK;
+}
+
+size_t nnls_warm_start_workspace_bytes(int64_t n, int64_t k) {
+  if (n != nnls::ML_IN || k < 1) return 0;
+  const int64_t kb = (k + 63) / 64 * 64;
+  return nnls::mlp_ws_bytes(kb, false) + nnls::al(sizeof(float) * kb * n) +
+         nnls::al(sizeof(float) * kb);
+}
+
+int nnls_warm_start(int64_t n, int64_t k, const float* Q, const float* q, const void* blob,
+                    float* Y0, int32_t* fell_back, void* ws, size_t ws_bytes, void* stream) {
+  if (n != nnls::ML_IN) return n < 1 ? NNLS_E_ARG : NNLS_E_UNSUPPORTED;
+  if (k < 1 || !Q || !q || !blob || !Y0 || !fell_back) return NNLS_E_ARG;
+  const size_t need = nnls_warm_start_workspace_bytes(n, k);
+  if (!ws || ws_bytes < need) return NNLS_E_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t kb = (k + 63) / 64 * 64;
+  char* p = (char*)ws;
+  nnls::MlpWs W = nnls::mlp_layout(p, kb, false, nullptr);
+  const size_t m = nnls::mlp_ws_bytes(kb, false);
+  float* U = (float*)(p + m);
+  float* qn = (float*)(p + m + nnls::al(sizeof(float) * kb * n));
+  hipLaunchKernelGGL(nnls::ws_normalise_kernel, dim3((unsigned)(kb / nnls::WS_C)), dim3(256), 0,
+                     st, k, kb, q, (const float*)nullptr, U, (float*)nullptr, qn);
+  nnls::forward(kb, blob, U, W, st);
+  hipLaunchKernelGGL(nnls::ws_assemble_kernel, dim3((unsigned)((k + nnls::WS_C - 1) / nnls::WS_C)),
+                     dim3(256), 0, st, k, Q, q, (const float*)W.Z, (const float*)qn, Y0,
+                     fell_back);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    nnls::record_hip_error(e);
+    return NNLS_E_HIP;
+  }
+  return NNLS_OK;
+}
+
+}  // extern "C"

@@ -73,6 +73,28 @@ def lib():
         L.nnls_batched_plan_launch.restype = ctypes.c_int
         L.nnls_batched_plan_destroy.argtypes = [_vp]
         L.nnls_batched_plan_destroy.restype = None
+        L.nnls_mlp_param_count.argtypes = []
+        L.nnls_mlp_param_count.restype = _i64
+        L.nnls_mlp_blob_bytes.argtypes = []
+        L.nnls_mlp_blob_bytes.restype = _sz
+        L.nnls_mlp_workspace_bytes.argtypes = [_i64, ctypes.c_int]
+        L.nnls_mlp_workspace_bytes.restype = _sz
+        L.nnls_mlp_reset_state.argtypes = [_vp, _vp]
+        L.nnls_mlp_reset_state.restype = ctypes.c_int
+        L.nnls_mlp_forward.argtypes = [_i64, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.nnls_mlp_forward.restype = ctypes.c_int
+        L.nnls_mlp_gradients.argtypes = [_i64, _vp, _vp, _vp, ctypes.c_float, _vp, _vp, _vp, _sz,
+                                         _vp]
+        L.nnls_mlp_gradients.restype = ctypes.c_int
+        L.nnls_mlp_train_step.argtypes = [_i64, _vp, _vp, _vp, ctypes.c_float, _i64,
+                                          ctypes.c_float, _vp, _vp, _sz, _vp]
+        L.nnls_mlp_train_step.restype = ctypes.c_int
+        L.nnls_mlp_inputs.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _vp]
+        L.nnls_mlp_inputs.restype = ctypes.c_int
+        L.nnls_warm_start_workspace_bytes.argtypes = [_i64, _i64]
+        L.nnls_warm_start_workspace_bytes.restype = _sz
+        L.nnls_warm_start.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.nnls_warm_start.restype = ctypes.c_int
         L.nnls_last_hip_error.argtypes = []
         L.nnls_last_hip_error.restype = ctypes.c_char_p
         L.nnls_version.argtypes = []
@@ -319,3 +341,97 @@ class BatchedPlan:
             self.close()
         except Exception:
             pass
+
+
+MLP_IN = 256
+
+
+def mlp_inputs(q, Y=None):
+    """(U, T): network inputs q / ||q|| and targets Y / ||q||, one row per column of q."""
+    n, k = q.shape
+    assert q.is_contiguous() and q.dtype == torch.float32
+    U = torch.empty((k, n), dtype=torch.float32, device=q.device)
+    T = None
+    if Y is not None:
+        assert Y.shape == q.shape and Y.is_contiguous() and Y.dtype == torch.float32
+        T = torch.empty((k, n), dtype=torch.float32, device=q.device)
+    _check(lib().nnls_mlp_inputs(n, k, _ptr(q), _ptr(Y), _ptr(U), _ptr(T), _stream(q.device)),
+           "nnls_mlp_inputs")
+    return U, T
+
+
+class WarmStartNet:
+    """The warm-start network's parameter blob (nnls_mlp_* / nnls_warm_start of nnls.h).
+    `params` are the initial FP32 master weights in the library's layout."""
+
+    def __init__(self, params, device):
+        L = lib()
+        self.P = int(L.nnls_mlp_param_count())
+        self.device = torch.device(device)
+        self.blob = torch.empty(int(L.nnls_mlp_blob_bytes()), dtype=torch.uint8, device=device)
+        self.master = self.blob[:4 * self.P].view(torch.float32)
+        p = torch.as_tensor(params, dtype=torch.float32).reshape(-1)
+        if p.numel() != self.P:
+            raise NNLSError(f"expected {self.P} parameters, got {p.numel()}")
+        self.master.copy_(p.to(device))
+        self.step = 0
+        self._ws = {}
+        _check(L.nnls_mlp_reset_state(_ptr(self.blob), _stream(self.device)), "nnls_mlp_reset_state")
+
+    def _wsb(self, key, nbytes):
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    def forward(self, u):
+        b = u.shape[0]
+        z = torch.empty((b, MLP_IN), dtype=torch.float32, device=self.device)
+        nb = int(lib().nnls_mlp_workspace_bytes(b, 0))
+        ws = self._wsb(("f", b), nb)
+        _check(lib().nnls_mlp_forward(b, _ptr(self.blob), _ptr(u), _ptr(z), _ptr(ws), nb,
+                                      _stream(self.device)), "nnls_mlp_forward")
+        return z
+
+    def gradients(self, u, target, lam):
+        b = u.shape[0]
+        grad = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        nb = int(lib().nnls_mlp_workspace_bytes(b, 1))
+        ws = self._wsb(("t", b), nb)
+        _check(lib().nnls_mlp_gradients(b, _ptr(self.blob), _ptr(u), _ptr(target), float(lam),
+                                        _ptr(grad), _ptr(loss), _ptr(ws), nb, _stream(self.device)),
+               "nnls_mlp_gradients")
+        return loss, grad
+
+    def train_step(self, u, target, lr, lam, loss=None):
+        """One Adam step; returns the device loss tensor (the batch loss before the step)."""
+        b = u.shape[0]
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        nb = int(lib().nnls_mlp_workspace_bytes(b, 1))
+        ws = self._wsb(("t", b), nb)
+        self.step += 1
+        _check(lib().nnls_mlp_train_step(b, _ptr(self.blob), _ptr(u), _ptr(target), float(lr),
+                                         self.step, float(lam), _ptr(loss), _ptr(ws), nb,
+                                         _stream(self.device)), "nnls_mlp_train_step")
+        return loss
+
+    def warm_start(self, Q, q, out=None):
+        """(Y0 [256, k], fell_back [k] int32) for the rescaled problem (Q, q)."""
+        n = Q.shape[0]
+        if q.dim() == 1:
+            q = q.reshape(n, 1)
+        k = q.shape[1]
+        assert Q.is_contiguous() and q.is_contiguous() and Q.dtype == torch.float32
+        if out is None:
+            Y0 = torch.empty((n, k), dtype=torch.float32, device=self.device)
+            fb = torch.empty(k, dtype=torch.int32, device=self.device)
+        else:
+            Y0, fb = out
+        nb = int(lib().nnls_warm_start_workspace_bytes(n, k))
+        ws = self._wsb(("w", k), max(nb, 1))
+        _check(lib().nnls_warm_start(n, k, _ptr(Q), _ptr(q), _ptr(self.blob), _ptr(Y0), _ptr(fb),
+                                     _ptr(ws), nb, _stream(self.device)), "nnls_warm_start")
+        return Y0, fb

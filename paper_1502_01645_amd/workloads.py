@@ -112,3 +112,21 @@ def make_warm_rhs(A: np.ndarray, count: int, split: int, start: int = 0, dtype=n
         X[:, j] = _zero_pattern(rng, n, n_zero, lambda m: rng.gamma(1.5, 1.0, m))
     B = A.astype(np.float64) @ X
     return B.astype(dtype), X
+
+
+MLP_SHAPES = [((256, 1024), True), ((1024,), False), ((1024, 1024), True), ((1024,), False),
+              ((1024, 256), True), ((256,), False)]
+
+
+def make_mlp_params(seed: int = 0) -> np.ndarray:
+    """Initial FP32 parameters of the warm-start network in the library's flat layout
+    (W1, b1, W2, b2, W3, b3): weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)), biases zero."""
+    rng = np.random.default_rng(np.random.SeedSequence([7, seed]))
+    parts = []
+    for shape, is_weight in MLP_SHAPES:
+        if is_weight:
+            lim = 1.0 / np.sqrt(shape[0])
+            parts.append(rng.uniform(-lim, lim, size=shape).reshape(-1))
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(np.float32)

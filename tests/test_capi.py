@@ -174,3 +174,41 @@ def test_batched_plan_rejects_bad_arguments(L):
     assert create(d=big_n, count=1) == N.E_UNSUPPORTED
     assert create(ws=None) == N.E_WORKSPACE
     assert create(wsb=16) == N.E_WORKSPACE
+
+
+def test_mlp_sizes_and_argument_errors(L):
+    from paper_1502_01645_amd import nnls as N
+    P = 256 * 1024 + 1024 + 1024 * 1024 + 1024 + 1024 * 256 + 256
+    assert L.nnls_mlp_param_count() == P
+    assert L.nnls_mlp_blob_bytes() == 14 * P
+    assert L.nnls_mlp_workspace_bytes(0, 0) == 0
+    assert L.nnls_mlp_workspace_bytes(64, 1) > L.nnls_mlp_workspace_bytes(64, 0) > 0
+    big = 1 << 40
+    # batch not a multiple of 64, null pointers, workspace too small
+    assert L.nnls_mlp_forward(65, FAKE, FAKE, FAKE, FAKE, big, None) == N.E_ARG
+    assert L.nnls_mlp_forward(0, FAKE, FAKE, FAKE, FAKE, big, None) == N.E_ARG
+    assert L.nnls_mlp_forward(64, None, FAKE, FAKE, FAKE, big, None) == N.E_ARG
+    assert L.nnls_mlp_forward(64, FAKE, FAKE, FAKE, FAKE, 16, None) == N.E_WORKSPACE
+    assert L.nnls_mlp_gradients(64, FAKE, FAKE, None, 0.01, None, None, FAKE, big,
+                                None) == N.E_ARG
+    assert L.nnls_mlp_gradients(64, FAKE, FAKE, FAKE, 0.01, None, None, FAKE, 16,
+                                None) == N.E_WORKSPACE
+    # Adam steps count from 1; the learning rate must be positive
+    assert L.nnls_mlp_train_step(64, FAKE, FAKE, FAKE, 1e-3, 0, 0.01, None, FAKE, big,
+                                 None) == N.E_ARG
+    assert L.nnls_mlp_train_step(64, FAKE, FAKE, FAKE, 0.0, 1, 0.01, None, FAKE, big,
+                                 None) == N.E_ARG
+    assert L.nnls_mlp_reset_state(None, None) == N.E_ARG
+    # warm start: only n = 256
+    assert L.nnls_warm_start_workspace_bytes(128, 4) == 0
+    assert L.nnls_warm_start_workspace_bytes(256, 4) > 0
+    assert L.nnls_warm_start(128, 4, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, big,
+                             None) == N.E_UNSUPPORTED
+    assert L.nnls_warm_start(0, 4, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, big, None) == N.E_ARG
+    assert L.nnls_warm_start(256, 0, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, big, None) == N.E_ARG
+    assert L.nnls_warm_start(256, 4, FAKE, FAKE, FAKE, FAKE, None, FAKE, big, None) == N.E_ARG
+    assert L.nnls_warm_start(256, 4, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 16,
+                             None) == N.E_WORKSPACE
+    assert L.nnls_mlp_inputs(128, 4, FAKE, None, FAKE, None, None) == N.E_UNSUPPORTED
+    assert L.nnls_mlp_inputs(256, 4, FAKE, FAKE, FAKE, None, None) == N.E_ARG
+    assert L.nnls_mlp_inputs(256, 0, FAKE, None, FAKE, None, None) == N.E_ARG
