@@ -33,6 +33,17 @@ TOL = 1e-5
 INNER_TOL = 8e-6
 BATCH_INNER_TOL = 5e-6
 BATCH_MAX_ITER = 20000
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
+# learned warm start: training recipe (the method's own solves of 200k seeded b = A x)
+WARM_TRAIN = 200000
+WARM_EVAL = 32768
+WARM_TARGET_TOL = 3e-6
+WARM_EPOCHS = 60
+WARM_BATCH = 512
+WARM_LR = 1e-3
+WARM_LAMBDA = 1e-4
+MLP_FWD_FLOP = 2.0 * (256 * 1024 + 1024 * 1024 + 1024 * 256)   # per sample
 
 
 def _src_sha(path):
@@ -90,7 +101,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample-cols", type=int, default=1400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="large", choices=["large", "manyrhs", "batched"])
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "manyrhs", "batched", "warm"])
+    ap.add_argument("--epochs", type=int, default=WARM_EPOCHS)
     ap.add_argument("--batch", type=int, default=8192)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -101,6 +114,8 @@ def main():
         return bench_manyrhs(args)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "warm":
+        return bench_warm(args)
 
     import torch
     from paper_1502_01645_amd import nnls as N
@@ -393,6 +408,215 @@ def bench_batched(args):
         "kkt64_sample": {"count": len(sample), "max": float(r64.max())},
         "gen_s": round(t_gen, 1),
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_warm(args):
+    """Learned warm start (A 4096 x 256 |N(0,1)|, noiseless b = A x, x 85 % zeros Gamma(1.5,1)).
+    Training (untimed, reported): the method's own cold solves of 200k seeded right-hand sides,
+    then the network trained on them with the library's kernels.  One step = scales + BF16x3
+    Gram with A^T B for the 32768 held-out right-hand sides + warm start + many-RHS solve + FP64
+    refine; the same step from the cold start is timed beside it."""
+    import torch
+    from paper_1502_01645_amd import nnls as N
+    from paper_1502_01645_amd import workloads as W
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    A_h = W.make_warm_matrix()
+    d, n = A_h.shape
+    A = torch.from_numpy(A_h).to(dev)
+    t0 = time.perf_counter()
+    parts = []
+    for st in range(0, WARM_TRAIN, 20000):
+        Bc, _ = W.make_warm_rhs(A_h, min(20000, WARM_TRAIN - st), split=0, start=st)
+        parts.append(torch.from_numpy(Bc).to(dev))
+    Btr = torch.cat(parts, 1).contiguous()
+    del parts
+    Bev_h, _ = W.make_warm_rhs(A_h, WARM_EVAL, split=1, start=0)
+    Bev = torch.from_numpy(Bev_h).to(dev)
+    log(f"warm: generated {WARM_TRAIN} + {WARM_EVAL} right-hand sides in "
+        f"{time.perf_counter() - t0:.1f} s")
+
+    # ---- training set: the method's own solutions, then the network
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    e = [ev() for _ in range(4)]
+    e[0].record()
+    Qt, qt, _ = N.prepare(A, Btr)
+    Ytr, it_tr, _, st_tr = N.solve(Qt, qt, None, WARM_TARGET_TOL, 20000)
+    U, T = N.mlp_inputs(qt, Ytr)
+    e[1].record()
+    del Btr, qt, Ytr
+    net = N.WarmStartNet(W.make_mlp_params(0), dev)
+    net.fit_input(U)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    steps_per = WARM_TRAIN // WARM_BATCH
+    total = args.epochs * steps_per
+    loss = torch.zeros(1, device=dev)
+    loss_sum = torch.zeros(1, device=dev)
+    step = 0
+    e[2].record()
+    for ep in range(args.epochs):
+        perm = torch.randperm(WARM_TRAIN, device=dev, generator=gen)
+        if ep == args.epochs - 1:
+            loss_sum.zero_()
+        for b in range(steps_per):
+            idx = perm[b * WARM_BATCH:(b + 1) * WARM_BATCH]
+            lr = WARM_LR * 0.5 * (1.0 + np.cos(np.pi * step / total))
+            net.train_step(U[idx].contiguous(), T[idx].contiguous(), lr, WARM_LAMBDA, loss)
+            if ep == args.epochs - 1:
+                loss_sum += loss
+            step += 1
+    e[3].record()
+    torch.cuda.synchronize()
+    train_ms = e[2].elapsed_time(e[3])
+    targets_ms = e[0].elapsed_time(e[1])
+    train_flop = 3.0 * MLP_FWD_FLOP * WARM_BATCH * total
+    log(f"warm: targets {targets_ms:.0f} ms, training {train_ms / 1e3:.1f} s")
+    del U, T
+
+    # ---- evaluation: cold and warm steps over the held-out set
+    k = WARM_EVAL
+    s = torch.empty(n, dtype=torch.float64, device=dev)
+    Q = torch.empty((n, n), dtype=torch.float32, device=dev)
+    q = torch.empty((n, k), dtype=torch.float32, device=dev)
+    X = torch.empty((n, k), dtype=torch.float32, device=dev)
+    Y0 = torch.empty((n, k), dtype=torch.float32, device=dev)
+    fb = torch.empty(k, dtype=torch.int32, device=dev)
+    iters = torch.empty(k, dtype=torch.int32, device=dev)
+    kkt = torch.empty(k, dtype=torch.float64, device=dev)
+    status = torch.empty(k, dtype=torch.int32, device=dev)
+    rows = torch.zeros(k, dtype=torch.int64, device=dev)
+    kkt64 = torch.empty(k, dtype=torch.float64, device=dev)
+    obj64 = torch.empty(k, dtype=torch.float64, device=dev)
+    mk = lambda op, mode=0: torch.empty(max(N.workspace_bytes(op, d, n, k, mode, N.F32), 1),  # noqa
+                                        dtype=torch.uint8, device=dev)
+    ws_s, ws_g, ws_v, ws_r = mk(N.OP_SCALES), mk(N.OP_GRAM, N.GRAM_BF16X3), mk(N.OP_SOLVE), \
+        mk(N.OP_REFINE)
+    total_steps = args.warmup + args.steps
+    names = ["scales", "gram", "warm_start", "solve", "refine"]
+
+    def run(warm):
+        marks = [[ev() for _ in range(6)] for _ in range(total_steps)]
+
+        def one(i):
+            m = marks[i]
+            m[0].record()
+            N.column_scales(A, out=s, ws=ws_s)
+            m[1].record()
+            N.gram_rescaled(A, Bev, s, N.GRAM_BF16X3, out=(Q, q), ws=ws_g)
+            m[2].record()
+            if warm:
+                net.warm_start(Q, q, out=(Y0, fb))
+            m[3].record()
+            N.solve(Q, q, s, tol=INNER_TOL, max_iter=5 * n, Y0=Y0 if warm else None,
+                    out=(X, iters, kkt, status), ws=ws_v, rows_read=rows)
+            m[4].record()
+            N.refine(A, Bev, X, out=(kkt64, obj64), ws=ws_r)
+            m[5].record()
+
+        for i in range(args.warmup):
+            one(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.warmup, total_steps):
+            one(i)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        timed = marks[args.warmup:]
+        ms = {nm: float(np.mean([m[j].elapsed_time(m[j + 1]) for m in timed]))
+              for j, nm in enumerate(names)}
+        it = iters.cpu().numpy()
+        r64 = kkt64.cpu().numpy()
+        res = {"wall": wall, "ms": ms, "iters": it, "r64": r64,
+               "status": status.cpu().numpy(), "rows": int(rows.sum().item()),
+               "fell_back": float(fb.float().mean().item()) if warm else None}
+        return res
+
+    cold = run(False)
+    warm = run(True)
+    log(f"warm: cold {cold['ms']} warm {warm['ms']}")
+
+    def rate(r):
+        return k * args.steps / r["wall"] if bool(np.all(r["r64"] <= TOL)) else 0.0
+
+    v_warm, v_cold = rate(warm), rate(cold)
+    ms = warm["ms"]
+    # roofline of the dominant kernel of the warm step
+    gram_flop = d * n * (n + 1) + 2.0 * d * n * k
+    solve_flop = 2.0 * n * warm["rows"]       # algorithmic: rows of Q the products read
+    kb = (k + 63) // 64 * 64
+    mlp_flop = MLP_FWD_FLOP * kb
+    refine_flop = 2.0 * d * n * (n + k) + 3 * 2.0 * n * n * k
+    cand = {
+        "solve": {"kernel": "solve_mrhs_kernel", "bound": "mfma", "flop": solve_flop,
+                  "peak": PEAK_FP32_MFMA_TFLOPS},
+        "gram": {"kernel": "gram_bf16x3_kernel", "bound": "mfma", "flop": gram_flop,
+                 "peak": PEAK_BF16X3_TFLOPS},
+        "warm_start": {"kernel": "mlp_gemm_kernel", "bound": "mfma", "flop": mlp_flop,
+                       "peak": PEAK_BF16_TFLOPS},
+        "refine": {"kernel": "gemm_tn_f64_kernel", "bound": "mfma", "flop": refine_flop,
+                   "peak": PEAK_FP64_TFLOPS},
+    }
+    rl = {}
+    for nm, c in cand.items():
+        ach = c["flop"] / (ms[nm] * 1e-3) / 1e12
+        rl[nm] = {"kernel": c["kernel"], "bound": c["bound"], "achieved": round(ach, 2),
+                  "peak": round(c["peak"], 1), "unit": "TFLOP/s",
+                  "frac": round(ach / c["peak"], 4), "traffic": None}
+    dom = max(cand, key=lambda nm: ms[nm])
+
+    def stats(r):
+        it = r["iters"]
+        return {"solves_per_s": round(rate(r), 1), "ms_per_step": round(r["wall"] * 1e3 / args.steps, 3),
+                "ms": {kk: round(v, 4) for kk, v in r["ms"].items()},
+                "iters_mean": round(float(it.mean()), 2), "iters_p99": float(np.percentile(it, 99)),
+                "iters_max": int(it.max()), "kkt64_max": float(r["r64"].max()),
+                "all_meet_tol": bool(np.all(r["r64"] <= TOL)),
+                "status_counts": {str(int(v)): int(c) for v, c in
+                                  zip(*np.unique(r["status"], return_counts=True))}}
+
+    out = {
+        "metric": "NNLS solves/sec at rel KKT<=1e-5 (learned warm start, including the network)",
+        "value": round(v_warm, 1), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(warm["wall"] * 1e3 / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16-mlp/bf16x3-gram/f32-mfma-iter/f64-check", "data": "synthetic",
+        "config": {"workload": f"learned warm start: A {d}x{n} |N(0,1)|, noiseless b = A x, "
+                               "x 85% zeros Gamma(1.5,1); trained on 200k method solves, "
+                               f"evaluated on {k} held-out", "d": d, "n": n, "k": k, "tol": TOL},
+        "roofline": rl[dom],
+        "roofline_all": rl,
+        "warm": stats(warm),
+        "cold": stats(cold),
+        "speedup_vs_cold": round(v_warm / v_cold, 3) if v_cold > 0 else None,
+        "fallback_rate": warm["fell_back"],
+        "training": {"samples": WARM_TRAIN, "epochs": args.epochs, "batch": WARM_BATCH,
+                     "lr": WARM_LR, "lambda": WARM_LAMBDA, "target_tol": WARM_TARGET_TOL,
+                     "target_solve_ms": round(targets_ms, 1),
+                     "target_iters_mean": round(float(it_tr.float().mean().item()), 2),
+                     "target_status_nonzero": int((st_tr != 0).sum().item()),
+                     "train_s": round(train_ms / 1e3, 2),
+                     "train_tflops": round(train_flop / (train_ms * 1e-3) / 1e12, 2),
+                     "final_epoch_loss": round(loss_sum.item() / steps_per, 6)},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        orc = O.load()
+        m = min(4096, k)
+        Bs = np.ascontiguousarray(Bev_h[:, :m], dtype=np.float64)
+        t0 = time.perf_counter()
+        ito = orc.nnls(A_h.astype(np.float64), Bs, TOL, 0)["iters"]
+        t_o = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(m / t_o, 2), "unit": "solves/s", "cores": orc.num_threads(),
+            "kind": "oracle",
+            "sample": (f"oracle (FP64 Gram, rescale, Algorithm 2 from y = 0) on the first {m} of "
+                       f"the {k} held-out right-hand sides: {t_o:.1f} s, mean "
+                       f"{float(np.mean(ito)):.1f} iterations; rate = {m} / time")}
     print(json.dumps(out), flush=True)
 
 

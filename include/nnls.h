@@ -203,19 +203,25 @@ void nnls_batched_plan_destroy(nnls_plan* plan);
  * point).  This addition, which the paper does not have, predicts y0 for the fixed-size case
  * n = 256 with a 256 -> 1024 -> 1024 -> 256 network (GELU hidden layers, exact x * Phi(x)) that
  * reads u = q / ||q|| (one column of q) and returns one head z per column:
- *     y0 = ||q|| * ReLU(z)      (Problem (5) is positively homogeneous in q, so this is exact)
+ *     direction of y0:  v = ReLU(z)  (Problem (5) is positively homogeneous in q, so the
+ *                       direction of y* depends on q / ||q|| only)
  *     logit of "y*_i > 0" = z_i.
  * Training minimises, averaged over the batch,
- *     1/2 ||ReLU(z) - t||^2 + lambda * BCE(z, 1[t > 0]),   t = y* / ||q||,
+ *     1/2 ||ReLU(z) - t||^2 + lambda * BCE(z, 1[t > 0]),   t = y* / ||y*||,
  * with Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on FP32 master weights; the
  * products run on a BF16 copy with FP32 accumulation.
  *
+ * The input is standardised first, in FP32: x = (u - shift) * scale per feature, then rounded to
+ * BF16 (for a fixed A the informative part of u is a small fraction of its size).
+ *
  * Parameters live in one device blob of nnls_mlp_blob_bytes() bytes, owned by the caller:
- *     float master[P] | float adam_m[P] | float adam_v[P] | bf16 copy[P],  P = nnls_mlp_param_count()
+ *     float master[P] | float adam_m[P] | float adam_v[P] | bf16 copy[P] |
+ *     float shift[256] | float scale[256],              P = nnls_mlp_param_count()
  * with master laid out as W1 [256, 1024] | b1 [1024] | W2 [1024, 1024] | b2 [1024] |
- * W3 [1024, 256] | b3 [256] (row-major, input index first: h = u W1 + b1).  The caller writes the
- * master weights and calls nnls_mlp_reset_state() to clear the Adam moments and make the BF16
- * copy; nnls_mlp_train_step() keeps the copy in step with the master.
+ * W3 [1024, 256] | b3 [256] (row-major, input index first: h = x W1 + b1).  The caller writes the
+ * master weights and shift/scale (or fits them with nnls_mlp_fit_input) and calls
+ * nnls_mlp_reset_state() to clear the Adam moments and make the BF16 copy;
+ * nnls_mlp_train_step() keeps the copy in step with the master.
  *
  * batch must be a positive multiple of 64 (at most 2^24).  u, target and z are FP32 [batch, 256]
  * row-major.  Workspaces are sized by nnls_mlp_workspace_bytes(batch, train) with train = 0 for
@@ -224,7 +230,15 @@ int64_t nnls_mlp_param_count(void);
 size_t nnls_mlp_blob_bytes(void);
 size_t nnls_mlp_workspace_bytes(int64_t batch, int train);
 
-/* Clears the Adam moments and rounds the master weights to the BF16 copy. */
+/* Sets shift = per-feature mean and scale = 1 / per-feature standard deviation (population; 1
+ * where it is 0) of the `count` rows of U [count, 256] FP32 (device), accumulated in FP64.
+ * Workspace: nnls_mlp_fit_input_workspace_bytes() bytes. */
+size_t nnls_mlp_fit_input_workspace_bytes(void);
+int nnls_mlp_fit_input(int64_t count, void* blob, const float* U, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* Clears the Adam moments and rounds the master weights to the BF16 copy (shift and scale are
+ * left as they are). */
 int nnls_mlp_reset_state(void* blob, void* stream);
 
 /* z = network(u) for `batch` rows. */
@@ -245,16 +259,19 @@ int nnls_mlp_train_step(int64_t batch, void* blob, const float* u, const float* 
 
 /* Network inputs and training targets from a rescaled problem with n = 256: for each column c
  * of q [256, k], U[c, :] = q[:, c] / ||q_c|| and, if Y [256, k] (a solution of Problem (5), e.g.
- * from nnls_solve with s = NULL) is given, T[c, :] = Y[:, c] / ||q_c||.  U and T are FP32
- * [k, 256]; T may be NULL when Y is.  A zero column of q is divided by 1. */
+ * from nnls_solve with s = NULL) is given, T[c, :] = Y[:, c] / ||Y_c||.  U and T are FP32
+ * [k, 256]; T may be NULL when Y is.  A zero column is divided by 1. */
 int nnls_mlp_inputs(int64_t n, int64_t k, const float* q, const float* Y, float* U, float* T,
                     void* stream);
 
-/* Warm start for k right-hand sides of a rescaled problem with n = 256 (other n return
- * NNLS_E_UNSUPPORTED).  Q [256, 256] and q [256, k] FP32 as produced by nnls_prepare; writes
- * Y0 [256, k] FP32 for nnls_solve and fell_back[k] (int32, device): 1 where the predicted point
- * had f(y0) = 1/2 y0^T Q y0 + q^T y0 > 0 = f(0) (or was not finite), in which case that column of
- * Y0 is 0, the cold start.  Workspace: nnls_warm_start_workspace_bytes(n, k). */
+/* Warm start for k (1 <= k <= 2^24) right-hand sides of a rescaled problem with n = 256 (other
+ * n return NNLS_E_UNSUPPORTED).  Q [256, 256] (symmetric) and q [256, k] FP32 as produced by
+ * nnls_prepare.  Per column, with v = ReLU(z) from the network, a = v^T Q v and b = q^T v:
+ *     y0 = c* v,  c* = -b / a  (the exact minimiser of f along v),  f(y0) = -b^2 / (2a) < f(0),
+ * written to Y0 [256, k] FP32 for nnls_solve.  Where b >= 0 or a <= 0 (v = 0, or no descent
+ * along v) or anything is not finite, that column of Y0 is 0, the cold start, and
+ * fell_back[k] (int32, device) is 1 there, else 0.
+ * Workspace: nnls_warm_start_workspace_bytes(n, k). */
 size_t nnls_warm_start_workspace_bytes(int64_t n, int64_t k);
 int nnls_warm_start(int64_t n, int64_t k, const float* Q, const float* q, const void* blob,
                     float* Y0, int32_t* fell_back, void* ws, size_t ws_bytes, void* stream);

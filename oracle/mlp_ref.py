@@ -1,8 +1,8 @@
 """Plain FP64 numpy reference of the warm-start network (test infrastructure only).
 
-The network maps u = q / ||q|| (256) through 1024 -> 1024 GELU hidden layers to a 256-wide head z;
-y0 = ||q|| ReLU(z).  Loss per sample: 1/2 ||ReLU(z) - t||^2 + lambda * BCE(z, 1[t > 0]) with
-t = y* / ||q||, averaged over the batch.  Everything here is written from those definitions:
+The network maps u = q / ||q|| (256) through 1024 -> 1024 GELU hidden layers to a 256-wide head z
+whose ReLU is the direction of the start point.  Loss per sample:
+1/2 ||ReLU(z) - t||^2 + lambda * BCE(z, 1[t > 0]) with t = y* / ||y*||, averaged over the batch.  Everything here is written from those definitions:
 exact GELU x * Phi(x) via erf, hand-derived backward pass.  `emulate` rounds the same tensors to
 bfloat16 that the GPU kernels store in bfloat16 (weights, inputs, hidden activations and the
 backward signals), so kernel logic can be compared tightly; without it the reference is exact
@@ -55,12 +55,22 @@ def gelu_grad(x):
     return cdf + x * pdf
 
 
-def forward(flat, u, emulate=False):
+def standardise(u, shift=None, scale=None):
+    """x = (u - shift) * scale per feature (identity when not given), in FP32 as the kernels
+    compute it before rounding x to bfloat16."""
+    u = np.asarray(u, dtype=np.float32)
+    if shift is None:
+        return u.astype(np.float64)
+    x = (u - np.asarray(shift, np.float32)) * np.asarray(scale, np.float32)
+    return x.astype(np.float32).astype(np.float64)
+
+
+def forward(flat, u, emulate=False, shift=None, scale=None):
     """z and the intermediates of the forward pass for inputs u [batch, 256]."""
     p = unpack(flat)
     r = bf16 if emulate else (lambda a: np.asarray(a, dtype=np.float64))
     W1, W2, W3 = r(p["W1"]), r(p["W2"]), r(p["W3"])
-    x = r(u)
+    x = r(standardise(u, shift, scale))
     h1 = x @ W1 + p["b1"]
     a1 = r(gelu(h1))
     h2 = a1 @ W2 + p["b2"]
@@ -82,9 +92,9 @@ def loss_and_grad_z(z, t, lam):
     return loss, dz
 
 
-def gradients(flat, u, t, lam, emulate=False):
+def gradients(flat, u, t, lam, emulate=False, shift=None, scale=None):
     """(loss, flat gradient) for a batch."""
-    z, c = forward(flat, u, emulate)
+    z, c = forward(flat, u, emulate, shift, scale)
     loss, dz = loss_and_grad_z(z, t, lam)
     r = bf16 if emulate else (lambda a: a)
     dz = r(dz)

@@ -164,6 +164,30 @@ class Oracle:
         return r, F
 
 
+def refine_candidate(A, B, X, out_dtype=np.float64) -> np.ndarray:
+    """One step of Algorithm 2 taken from x in FP64 against the original data (the refinement
+    step of the FP64 check): y = s x, gradient of Problem (5) g_y = A^T (A x - b) / s, masked
+    gradient p on the passive set, exact step alpha = ||p||^2 / ||A (p / s)||^2, projection
+    x' = [x - alpha p / s]_+, rounded to the output type.  Plain numpy, one column at a time."""
+    A = np.asarray(A, dtype=np.float64)
+    d, n = A.shape
+    B = np.asarray(B, dtype=np.float64).reshape(d, -1)
+    X = np.asarray(X, dtype=np.float64).reshape(n, -1)
+    s = np.sqrt(np.sum(A * A, axis=0))
+    s = np.where(s > 0, s, 1.0)
+    out = np.zeros_like(X)
+    for c in range(X.shape[1]):
+        x = X[:, c]
+        gy = (A.T @ (A @ x - B[:, c])) / s
+        y = s * x
+        p = np.where((y > 0) | (gy < 0), gy, 0.0)
+        D = p / s
+        den = np.sum((A @ D) ** 2)
+        alpha = np.sum(p * p) / den if den > 0 else 0.0
+        out[:, c] = np.maximum(x - alpha * D, 0.0)
+    return out.astype(out_dtype).astype(np.float64)
+
+
 _default: Oracle | None = None
 
 

@@ -1,15 +1,16 @@
 // Learned warm start for Algorithm 2: a 256 -> 1024 -> 1024 -> 256 GELU network mapping the
 // normalised rescaled right-hand side u = q / ||q|| to one 256-wide head z, read two ways: the
-// start point y0 = ||q|| * ReLU(z) (Problem (5) is positively homogeneous in q) and the
-// passive-set logit z.  Training minimises
-//     1/2 ||ReLU(z) - y* / ||q|| ||^2 + lambda * BCE(z, 1[y* > 0])        (mean over the batch)
+// direction v = ReLU(z) of the start point and the passive-set logit z.  The start itself is
+// y0 = c* v with c* the exact line-search step of f along v (the same kind of step Algorithm 2
+// takes), so only the direction has to be learned.  Training minimises
+//     1/2 ||ReLU(z) - y* / ||y*|| ||^2 + lambda * BCE(z, 1[y* > 0])        (mean over the batch)
 // with Adam on FP32 master weights; products run on BF16 copies with FP32 accumulation.
 //
 // Kernels: one BF16 GEMM on the matrix cores (v_mfma_f32_16x16x32_bf16, 64 x 64 tiles, operands
 // transposed as needed while staged into LDS) with fused epilogues (bias + GELU keeping the
 // pre-activation, bias, plain FP32, GELU backward); the loss and its gradient; column sums for
-// bias gradients; Adam; and the warm-start assembly with the objective check that falls back to
-// y = 0 when f(y0) = 1/2 y0^T Q y0 + q^T y0 > 0.
+// bias gradients; Adam; and the warm-start assembly (line-search scale, and the fallback to y = 0
+// when v gives no descent).
 #include "../../include/nnls.h"
 #include "common.hpp"
 #include "kernels.hpp"
@@ -25,8 +26,9 @@ constexpr int64_t ML_B2 = ML_W2 + (int64_t)ML_H * ML_H;
 constexpr int64_t ML_W3 = ML_B2 + ML_H;
 constexpr int64_t ML_B3 = ML_W3 + (int64_t)ML_H * ML_OUT;
 constexpr int64_t ML_P = ML_B3 + ML_OUT;
-// blob: FP32 master [P], Adam m [P], Adam v [P], BF16 copy [P]
-constexpr size_t ML_BLOB = sizeof(float) * 3 * ML_P + sizeof(uint16_t) * ML_P;
+// blob: FP32 master [P], Adam m [P], Adam v [P], BF16 copy [P], input shift [IN], input scale [IN]
+constexpr size_t ML_NORM = sizeof(float) * 3 * ML_P + sizeof(uint16_t) * ML_P;
+constexpr size_t ML_BLOB = ML_NORM + sizeof(float) * 2 * ML_IN;
 
 typedef uint16_t bf16_t;
 
@@ -147,10 +149,54 @@ static void gemm(int M, int N, int K, const bf16_t* A, int64_t lda, const bf16_t
                      ldb, E);
 }
 
-// X[b, :] = bf16(u_b) for the batch input (FP32 [batch, 256] -> BF16).
-__global__ void to_bf16_kernel(int64_t count, const float* __restrict__ x, bf16_t* __restrict__ y) {
+// X[b, j] = bf16((u[b, j] - shift[j]) * scale[j]): the input standardisation, applied in FP32
+// before the BF16 rounding (the informative part of u can be a small fraction of its size).
+__global__ void input_kernel(int64_t count, const float* __restrict__ u,
+                             const float* __restrict__ shift, const float* __restrict__ scale,
+                             bf16_t* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < count) y[i] = to_bf16(x[i]);
+  if (i < count) {
+    const int j = (int)(i & (ML_IN - 1));
+    y[i] = to_bf16((u[i] - shift[j]) * scale[j]);
+  }
+}
+
+// Input statistics over `count` rows of U [count, 256], first pass: block b sums rows
+// b, b + FI_CHUNKS, ... of (u - u[0]) and its square in FP64 (thread j = feature j, so each row
+// is one coalesced read).  Shifting by the first row keeps the variance free of cancellation.
+constexpr int FI_CHUNKS = 256;
+__global__ __launch_bounds__(256) void fit_input_partial_kernel(int64_t count,
+                                                                const float* __restrict__ U,
+                                                                double* __restrict__ part) {
+  const int j = threadIdx.x;
+  const double ref = U[j];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t r = blockIdx.x; r < count; r += FI_CHUNKS) {
+    const double d = (double)U[r * ML_IN + j] - ref;
+    s1 += d;
+    s2 += d * d;
+  }
+  part[(int64_t)blockIdx.x * 2 * ML_IN + j] = s1;
+  part[(int64_t)blockIdx.x * 2 * ML_IN + ML_IN + j] = s2;
+}
+
+// Second pass: shift = mean, scale = 1 / standard deviation (population), 1 where it is 0.
+__global__ __launch_bounds__(256) void fit_input_final_kernel(int64_t count,
+                                                              const float* __restrict__ U,
+                                                              const double* __restrict__ part,
+                                                              float* __restrict__ shift,
+                                                              float* __restrict__ scale) {
+  const int j = threadIdx.x;
+  double s1 = 0.0, s2 = 0.0;
+  for (int c = 0; c < FI_CHUNKS; ++c) {
+    s1 += part[(int64_t)c * 2 * ML_IN + j];
+    s2 += part[(int64_t)c * 2 * ML_IN + ML_IN + j];
+  }
+  const double m = s1 / (double)count;
+  double var = s2 / (double)count - m * m;
+  var = var > 0.0 ? var : 0.0;
+  shift[j] = (float)((double)U[j] + m);
+  scale[j] = var > 0.0 ? (float)(1.0 / sqrt(var)) : 1.f;
 }
 
 // Loss and its gradient w.r.t. z (scaled by 1 / batch), per row block; loss partial per block.
@@ -283,6 +329,10 @@ size_t mlp_ws_bytes(int64_t batch, bool train) {
 static const bf16_t* wcopy(const void* blob) {
   return (const bf16_t*)((const char*)blob + sizeof(float) * 3 * ML_P);
 }
+static const float* norm_shift(const void* blob) {
+  return (const float*)((const char*)blob + ML_NORM);
+}
+static const float* norm_scale(const void* blob) { return norm_shift(blob) + ML_IN; }
 
 // forward pass; leaves H1, A1, H2, A2 and Z in the workspace
 static void forward(int64_t batch, const void* blob, const float* u, const MlpWs& W,
@@ -290,8 +340,8 @@ static void forward(int64_t batch, const void* blob, const float* u, const MlpWs
   const bf16_t* Wb = wcopy(blob);
   const float* master = (const float*)blob;
   const int M = (int)batch;
-  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((batch * ML_IN + 255) / 256)), dim3(256), 0,
-                     st, batch * ML_IN, u, W.X);
+  hipLaunchKernelGGL(input_kernel, dim3((unsigned)((batch * ML_IN + 255) / 256)), dim3(256), 0,
+                     st, batch * ML_IN, u, norm_shift(blob), norm_scale(blob), W.X);
   GemmEpi e1{W.H1, W.A1, master + ML_B1, nullptr, ML_H};
   gemm<false, false, EPI_BIAS_GELU>(M, ML_H, ML_IN, W.X, ML_IN, Wb + ML_W1, ML_H, e1, st);
   GemmEpi e2{W.H2, W.A2, master + ML_B2, nullptr, ML_H};
@@ -333,86 +383,102 @@ static void backward(int64_t batch, const void* blob, const float* target, float
 // ---- warm start ------------------------------------------------------------------------------
 constexpr int WS_C = 16;  // columns per block: q and Y0 rows are read and written 16 floats wide
 
-// For columns c0..c0+15 of q [n = 256, k]: ||q_c|| and u_c = q_c / ||q_c|| as row c of U [rows, n]
-// (rows >= k: rows c >= k, the batch padding, are zero).  With Y [n, k] given, also
-// T[c, :] = Y[:, c] / ||q_c||.  qn may be null.  Thread i owns row i of q and Y.
+// For columns c0..c0+15 of q [n = 256, k]: u_c = q_c / ||q_c|| as row c of U [rows, n]
+// (rows >= k: rows c >= k, the batch padding, are zero).  With Y [n, k] given, also the unit
+// target T[c, :] = Y[:, c] / ||Y_c|| (zero for a zero column).  Thread i owns row i of q and Y.
 __global__ __launch_bounds__(256) void ws_normalise_kernel(int64_t k, int64_t rows,
                                                            const float* __restrict__ q,
                                                            const float* __restrict__ Y,
                                                            float* __restrict__ U,
-                                                           float* __restrict__ T,
-                                                           float* __restrict__ qn) {
-  __shared__ float red[WS_C][4];
+                                                           float* __restrict__ T) {
+  __shared__ float red[2][WS_C][4];
   const int i = threadIdx.x, lane = i & 63, wave = i >> 6;
   const int64_t c0 = (int64_t)blockIdx.x * WS_C;
-  float v[WS_C];
-#pragma unroll
-  for (int c = 0; c < WS_C; ++c) v[c] = c0 + c < k ? q[(int64_t)i * k + c0 + c] : 0.f;
+  float v[WS_C], w[WS_C];
 #pragma unroll
   for (int c = 0; c < WS_C; ++c) {
-    const float t = wave_sum(v[c] * v[c]);
-    if (lane == 0) red[c][wave] = t;
+    const bool in = c0 + c < k;
+    v[c] = in ? q[(int64_t)i * k + c0 + c] : 0.f;
+    w[c] = (in && Y) ? Y[(int64_t)i * k + c0 + c] : 0.f;
+  }
+#pragma unroll
+  for (int c = 0; c < WS_C; ++c) {
+    const float t0 = wave_sum(v[c] * v[c]);
+    const float t1 = wave_sum(w[c] * w[c]);
+    if (lane == 0) {
+      red[0][c][wave] = t0;
+      red[1][c][wave] = t1;
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < WS_C; ++c) {
     if (c0 + c >= rows) break;
-    const float a = (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]);
-    const float nrm = a > 0.f ? sqrtf(a) : 1.f;
-    U[(c0 + c) * ML_IN + i] = v[c] / nrm;
-    if (Y) T[(c0 + c) * ML_IN + i] = c0 + c < k ? Y[(int64_t)i * k + c0 + c] / nrm : 0.f;
-    if (qn && i == 0 && c0 + c < k) qn[c0 + c] = nrm;
+    const float a = (red[0][c][0] + red[0][c][1]) + (red[0][c][2] + red[0][c][3]);
+    U[(c0 + c) * ML_IN + i] = v[c] / (a > 0.f ? sqrtf(a) : 1.f);
+    if (Y) {
+      const float b = (red[1][c][0] + red[1][c][1]) + (red[1][c][2] + red[1][c][3]);
+      T[(c0 + c) * ML_IN + i] = w[c] / (b > 0.f ? sqrtf(b) : 1.f);
+    }
   }
 }
 
-// Columns c0..c0+15: y_c = ||q_c|| ReLU(Z[c, :]); f_c = 1/2 y_c^T Q y_c + q_c^T y_c with Q read by
-// columns (Q is symmetric, so thread i accumulates (Q y_c)_i from coalesced rows of Q, each row
-// reused for the 16 columns).  A column whose f_c is not <= 0 (this includes NaN and inf) falls
-// back to the cold start y0 = 0.
+// Columns c0..c0+15: direction v_c = ReLU(Z[c, :]); then a = v^T Q v and b = q_c^T v with Q read by
+// columns (Q is symmetric, so thread i accumulates (Q v)_i from coalesced rows of Q, each row
+// reused for the 16 columns).  The start is the exact minimiser of f along v,
+//     y0 = c* v,  c* = -b / a,  f(y0) = -b^2 / (2 a) < 0 = f(0),
+// taken only when b < 0 and a > 0 with c* finite; otherwise (v = 0, v an ascent direction, NaN
+// or inf) the column falls back to the cold start y0 = 0.
 __global__ __launch_bounds__(256) void ws_assemble_kernel(int64_t k, const float* __restrict__ Q,
                                                           const float* __restrict__ q,
                                                           const float* __restrict__ Z,
-                                                          const float* __restrict__ qn,
                                                           float* __restrict__ Y0,
                                                           int32_t* __restrict__ fell_back) {
-  __shared__ float ys[WS_C][ML_IN];
-  __shared__ float red[WS_C][4];
+  __shared__ float vs[WS_C][ML_IN];
+  __shared__ float red[2][WS_C][4];
   const int i = threadIdx.x, lane = i & 63, wave = i >> 6;
   const int64_t c0 = (int64_t)blockIdx.x * WS_C;
   const int cols = (int)(k - c0 < WS_C ? k - c0 : WS_C);
 #pragma unroll
   for (int c = 0; c < WS_C; ++c) {
-    float y = 0.f;
+    float v = 0.f;
     if (c < cols) {
       const float z = Z[(c0 + c) * ML_IN + i];
-      y = qn[c0 + c] * (z > 0.f ? z : 0.f);
-      if (z != z) y = z;  // keep a NaN prediction visible to the objective check
+      v = z > 0.f ? z : 0.f;
+      if (z != z) v = z;  // keep a NaN prediction visible to the checks
     }
-    ys[c][i] = y;
+    vs[c][i] = v;
   }
   __syncthreads();
-  float qy[WS_C];
+  float qv[WS_C];
 #pragma unroll
-  for (int c = 0; c < WS_C; ++c) qy[c] = 0.f;
+  for (int c = 0; c < WS_C; ++c) qv[c] = 0.f;
   for (int j = 0; j < ML_IN; ++j) {
     const float qji = Q[j * ML_IN + i];
 #pragma unroll
-    for (int c = 0; c < WS_C; ++c) qy[c] += qji * ys[c][j];
+    for (int c = 0; c < WS_C; ++c) qv[c] += qji * vs[c][j];
   }
 #pragma unroll
   for (int c = 0; c < WS_C; ++c) {
+    const float vi = vs[c][i];
     const float qi = c < cols ? q[(int64_t)i * k + c0 + c] : 0.f;
-    const float t = wave_sum(ys[c][i] * (0.5f * qy[c] + qi));
-    if (lane == 0) red[c][wave] = t;
+    const float ta = wave_sum(vi * qv[c]);
+    const float tb = wave_sum(vi * qi);
+    if (lane == 0) {
+      red[0][c][wave] = ta;
+      red[1][c][wave] = tb;
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < WS_C; ++c) {
     if (c >= cols) continue;
-    const float f = (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]);
-    const bool back = !(f <= 0.f);
-    Y0[(int64_t)i * k + c0 + c] = back ? 0.f : ys[c][i];
-    if (i == 0) fell_back[c0 + c] = back ? 1 : 0;
+    const float a = (red[0][c][0] + red[0][c][1]) + (red[0][c][2] + red[0][c][3]);
+    const float b = (red[1][c][0] + red[1][c][1]) + (red[1][c][2] + red[1][c][3]);
+    const float cs = -b / a;
+    const bool take = b < 0.f && a > 0.f && is_finite_val(cs) && is_finite_val(a);
+    Y0[(int64_t)i * k + c0 + c] = take ? cs * vs[c][i] : 0.f;
+    if (i == 0) fell_back[c0 + c] = take ? 0 : 1;
   }
 }
 
@@ -441,6 +507,28 @@ int nnls_mlp_reset_state(void* blob, void* stream) {
                      dim3(256), 0, (hipStream_t)stream, nnls::ML_P, (const float*)w,
                      w + nnls::ML_P, w + 2 * nnls::ML_P,
                      (nnls::bf16_t*)(w + 3 * nnls::ML_P));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    nnls::record_hip_error(e);
+    return NNLS_E_HIP;
+  }
+  return NNLS_OK;
+}
+
+size_t nnls_mlp_fit_input_workspace_bytes(void) {
+  return sizeof(double) * 2 * nnls::ML_IN * nnls::FI_CHUNKS;
+}
+
+int nnls_mlp_fit_input(int64_t count, void* blob, const float* U, void* ws, size_t ws_bytes,
+                       void* stream) {
+  if (count < 1 || !blob || !U) return NNLS_E_ARG;
+  if (!ws || ws_bytes < nnls_mlp_fit_input_workspace_bytes()) return NNLS_E_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  float* shift = (float*)((char*)blob + nnls::ML_NORM);
+  hipLaunchKernelGGL(nnls::fit_input_partial_kernel, dim3(nnls::FI_CHUNKS), dim3(256), 0, st,
+                     count, U, (double*)ws);
+  hipLaunchKernelGGL(nnls::fit_input_final_kernel, dim3(1), dim3(256), 0, st, count, U,
+                     (const double*)ws, shift, shift + nnls::ML_IN);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     nnls::record_hip_error(e);
@@ -518,7 +606,7 @@ int nnls_mlp_inputs(int64_t n, int64_t k, const float* q, const float* Y, float*
   if (n != nnls::ML_IN) return n < 1 ? NNLS_E_ARG : NNLS_E_UNSUPPORTED;
   if (k < 1 || k > (int64_t(1) << 30) || !q || !U || (Y && !T)) return NNLS_E_ARG;
   hipLaunchKernelGGL(nnls::ws_normalise_kernel, dim3((unsigned)((k + nnls::WS_C - 1) / nnls::WS_C)),
-                     dim3(256), 0, (hipStream_t)stream, k, k, q, Y, U, T, (float*)nullptr);
+                     dim3(256), 0, (hipStream_t)stream, k, k, q, Y, U, T);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     nnls::record_hip_error(e);
@@ -528,31 +616,27 @@ int nnls_mlp_inputs(int64_t n, int64_t k, const float* q, const float* Y, float*
 }
 
 size_t nnls_warm_start_workspace_bytes(int64_t n, int64_t k) {
-  if (n != nnls::ML_IN || k < 1) return 0;
+  if (n != nnls::ML_IN || k < 1 || k > (int64_t(1) << 24)) return 0;
   const int64_t kb = (k + 63) / 64 * 64;
-  return nnls::mlp_ws_bytes(kb, false) + nnls::al(sizeof(float) * kb * n) +
-         nnls::al(sizeof(float) * kb);
+  return nnls::mlp_ws_bytes(kb, false) + nnls::al(sizeof(float) * kb * n);
 }
 
 int nnls_warm_start(int64_t n, int64_t k, const float* Q, const float* q, const void* blob,
                     float* Y0, int32_t* fell_back, void* ws, size_t ws_bytes, void* stream) {
   if (n != nnls::ML_IN) return n < 1 ? NNLS_E_ARG : NNLS_E_UNSUPPORTED;
-  if (k < 1 || !Q || !q || !blob || !Y0 || !fell_back) return NNLS_E_ARG;
+  if (k < 1 || k > (int64_t(1) << 24) || !Q || !q || !blob || !Y0 || !fell_back) return NNLS_E_ARG;
   const size_t need = nnls_warm_start_workspace_bytes(n, k);
   if (!ws || ws_bytes < need) return NNLS_E_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   const int64_t kb = (k + 63) / 64 * 64;
   char* p = (char*)ws;
   nnls::MlpWs W = nnls::mlp_layout(p, kb, false, nullptr);
-  const size_t m = nnls::mlp_ws_bytes(kb, false);
-  float* U = (float*)(p + m);
-  float* qn = (float*)(p + m + nnls::al(sizeof(float) * kb * n));
+  float* U = (float*)(p + nnls::mlp_ws_bytes(kb, false));
   hipLaunchKernelGGL(nnls::ws_normalise_kernel, dim3((unsigned)(kb / nnls::WS_C)), dim3(256), 0,
-                     st, k, kb, q, (const float*)nullptr, U, (float*)nullptr, qn);
+                     st, k, kb, q, (const float*)nullptr, U, (float*)nullptr);
   nnls::forward(kb, blob, U, W, st);
   hipLaunchKernelGGL(nnls::ws_assemble_kernel, dim3((unsigned)((k + nnls::WS_C - 1) / nnls::WS_C)),
-                     dim3(256), 0, st, k, Q, q, (const float*)W.Z, (const float*)qn, Y0,
-                     fell_back);
+                     dim3(256), 0, st, k, Q, q, (const float*)W.Z, Y0, fell_back);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     nnls::record_hip_error(e);

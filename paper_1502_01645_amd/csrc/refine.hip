@@ -1,15 +1,17 @@
 // FP64 check and one refinement step against the original data (A, B).
 //
-// Products with A are done in FP64 arithmetic on the stored entries of A (FP32 or FP64):
-//   R = A X - B,  G = A^T R,  a = A^T B,  s_i^2 = sum_r A_ri^2           (passes 1 and 2)
-//   in the rescaled variables y = s .* x, grad_y = G ./ s: passive set, masked gradient p,
-//   relative KKT residual ||min(y, grad_y)|| / ||a ./ s||                 (per column)
-//   V = A (p ./ s), alpha = ||p||^2 / ||V||^2  (= p^T Q p in exact arithmetic) (pass 3)
-//   x' = [x - alpha p ./ s]_+, R' = A x' - B, G' = A^T R'                   (passes 4 and 5)
-//   keep x' when it lowers the residual without raising 1/2||A x - b||^2, and report the
-//   residual and objective of the x that is returned.
-// Few right-hand sides use matrix-vector kernels that stream A once per pass; many use a
-// tiled FP64 product.
+// In the rescaled variables y = s .* x (s_i = ||A_i||), with g = A^T (A x - B) = H x - A^T B:
+//   grad_y = g ./ s, passive set, masked gradient p, relative KKT residual
+//   ||min(y, grad_y)|| / ||A^T b ./ s||; direction D = p ./ s, exact step
+//   alpha = ||p||^2 / (D^T H D) (= p^T Q p), candidate x' = [x - alpha D]_+; keep x' when it lowers
+//   the residual without raising F(x) = 1/2 ||A x - b||^2, and report the residual and objective
+//   of the x that is returned.
+// Few right-hand sides (k <= 4) stream A once per pass with matrix-vector kernels:
+//   R = A X - B, g = A^T R, V = A D (D^T H D = ||V||^2), R' = A x' - B, g' = A^T R'.
+// Many right-hand sides form the FP64 Gram matrix once, on the FP64 matrix cores:
+//   H = A^T A, a = A^T B, ||b||^2;  g = H X - a,  D^T H D from H D,  g' = H X' - a,
+//   F(x) = 1/2 (x^T (H x - 2 a) + ||b||^2) and F(x') - F(x) = 1/2 (x' - x)^T (g + g'),
+// so the work over the d rows of A is one product instead of five.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -233,85 +235,217 @@ __global__ __launch_bounds__(256) void cols_finalize_kernel(int64_t n, int64_t k
 // ---- many right-hand sides: tiled FP64 products -----------------------------------------------
 // TRANS = false: C[M, N] = A[M, K] * Bm[K, N] - Cin      (A row-major [d, n], M = d, K = n)
 // TRANS = true:  C[M, N] = A^T[M, K] * Bm[K, N]           (A row-major [d, n], M = n, K = d)
-// Bm is FP64 [K, N] with leading dimension ldbm; Cin (optional, element type TA) is subtracted.
-// When with_sq, column sums of squares of A are also produced (TRANS only, tile column 0).
-constexpr int RG_BM = 64;
-constexpr int RG_BK = 16;
+// ---- many right-hand sides: FP64 Gram path ---------------------------------------------------
+// C[i, j] = sum_r A[r, i] M[r, j] for i < N, j < Mc, r < K (A [K, N] and M [K, Mc] row-major), in
+// FP64 on the matrix cores (v_mfma_f64_16x16x4f64): 64 x 64 output tiles, four waves of 32 x 32,
+// K staged through LDS 32 rows at a time (zero-filled past the edges).
+constexpr int TN_T = 64, TN_BK = 32, TN_LD = TN_T + 2;
 
-template <typename TA, typename TB, bool TRANS>
-__global__ __launch_bounds__(256) void gemm64_kernel(int64_t M, int64_t N, int64_t K,
-                                                     const TA* __restrict__ A, int64_t lda,
-                                                     const TB* __restrict__ Bm, int64_t ldbm,
-                                                     const TA* __restrict__ Cin, int64_t ldcin,
-                                                     double* __restrict__ C, int64_t ldc) {
-  __shared__ double sa[RG_BK][RG_BM + 1];
-  __shared__ double sb[RG_BK][RG_BM + 1];
-  const int64_t m0 = (int64_t)blockIdx.y * RG_BM, n0 = (int64_t)blockIdx.x * RG_BM;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4];
+template <typename TA, typename TM>
+__global__ __launch_bounds__(256) void gemm_tn_f64_kernel(int64_t K, int64_t N, int64_t Mc,
+                                                          const TA* __restrict__ A, int64_t lda,
+                                                          const TM* __restrict__ Mm, int64_t ldm,
+                                                          double* __restrict__ C, int64_t ldc) {
+  __shared__ double sa[TN_BK][TN_LD];
+  __shared__ double sm[TN_BK][TN_LD];
+  const int64_t i0 = (int64_t)blockIdx.y * TN_T, j0 = (int64_t)blockIdx.x * TN_T;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  f64x4 acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int64_t k0 = 0; k0 < K; k0 += RG_BK) {
-    for (int e = threadIdx.x; e < RG_BK * RG_BM; e += 256) {
-      int kk, mm;
-      if (TRANS) {  // A^T[m, k] = A[k, m]: consecutive threads along m (contiguous in A)
-        kk = e / RG_BM;
-        mm = e % RG_BM;
-      } else {      // A[m, k]: consecutive threads along k
-        mm = e / RG_BK;
-        kk = e % RG_BK;
-      }
-      const int64_t gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < M && gk < K) v = TRANS ? (double)A[gk * lda + gm] : (double)A[gm * lda + gk];
-      sa[kk][mm] = v;
-      const int bk = e / RG_BM, bn = e % RG_BM;
-      const int64_t gbk = k0 + bk, gbn = n0 + bn;
-      sb[bk][bn] = (gbk < K && gbn < N) ? (double)Bm[gbk * ldbm + gbn] : 0.0;
+    for (int b = 0; b < 2; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  const int col = lane & 15, kq = lane >> 4;
+  for (int64_t k0 = 0; k0 < K; k0 += TN_BK) {
+#pragma unroll
+    for (int e = tid; e < TN_BK * TN_T; e += 256) {
+      const int r = e >> 6, c = e & 63;
+      const int64_t gr = k0 + r;
+      sa[r][c] = (gr < K && i0 + c < N) ? (double)A[gr * lda + i0 + c] : 0.0;
+      sm[r][c] = (gr < K && j0 + c < Mc) ? (double)Mm[gr * ldm + j0 + c] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < RG_BK; ++kk) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = sa[kk][ty + 16 * a];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = sb[kk][tx + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+    for (int kk = 0; kk < TN_BK; kk += 4) {
+      const int kr = kk + kq;
+      const double a0 = sa[kr][wi + col], a1 = sa[kr][wi + 16 + col];
+      const double b0 = sm[kr][wj + col], b1 = sm[kr][wj + 16 + col];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
     __syncthreads();
   }
+  // lane l holds column l % 16 and rows l / 16 + 4 e of each 16 x 16 block (the FP64 layout;
+  // the FP32 16 x 16 instructions place rows 4 (l / 16) + e instead)
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t gm = m0 + ty + 16 * a, gn = n0 + tx + 16 * b;
-      if (gm < M && gn < N) {
-        double v = acc[a][b];
-        if (Cin) v -= (double)Cin[gm * ldcin + gn];
-        C[gm * ldc + gn] = v;
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = i0 + wi + a * 16 + kq + 4 * e;
+        const int64_t j = j0 + wj + b * 16 + col;
+        if (i < N && j < Mc) C[i * ldc + j] = acc[a][b][e];
       }
-    }
 }
 
-// Column sums of squares of A (FP64), for the many-RHS path.
-template <typename TA>
-__global__ __launch_bounds__(256) void sumsq_cols_kernel(int64_t d, int64_t n,
-                                                         const TA* __restrict__ A, int64_t lda,
-                                                         double* __restrict__ s) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
+// Partial column sums of squares of B [d, k] (FP64), row chunk blockIdx.y of BB_CH.
+constexpr int BB_CH = 16;
+template <typename T>
+__global__ __launch_bounds__(256) void colsq_partial_kernel(int64_t d, int64_t k,
+                                                            const T* __restrict__ B, int64_t ldb,
+                                                            double* __restrict__ out) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= k) return;
+  const int64_t rows = (d + BB_CH - 1) / BB_CH;
+  const int64_t r0 = (int64_t)blockIdx.y * rows;
+  const int64_t r1 = r0 + rows < d ? r0 + rows : d;
   double acc = 0.0;
-  for (int64_t r = 0; r < d; ++r) {
-    const double a = (double)A[r * lda + i];
-    acc += a * a;
+  for (int64_t r = r0; r < r1; ++r) {
+    const double v = (double)B[r * ldb + c];
+    acc += v * v;
   }
-  s[i] = acc > 0.0 ? sqrt(acc) : 1.0;
+  out[(int64_t)blockIdx.y * k + c] = acc;
+}
+
+// s_i = sqrt(H_ii), 1 where H_ii = 0.
+__global__ void diag_scale_kernel(int64_t n, const double* __restrict__ H, double* __restrict__ s) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    const double h = H[i * n + i];
+    s[i] = h > 0.0 ? sqrt(h) : 1.0;
+  }
+}
+
+// Per-column stages of the Gram path: 64 columns per block, thread t on column t % 64 and rows
+// t / 64, t / 64 + 4, ... (a wave reads 64 consecutive columns of one row).
+constexpr int GS_C = 64;
+
+__device__ __forceinline__ double gs_reduce(double v, double (*red)[GS_C], int rg, int cl) {
+  red[rg][cl] = v;
+  __syncthreads();
+  const double t = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+  __syncthreads();
+  return t;
+}
+
+// Stage 1: residual and objective at x, direction D = p ./ s, ||p||^2.
+template <typename TX>
+__global__ __launch_bounds__(256) void gref_stage1_kernel(int64_t n, int64_t k,
+                                                          const TX* __restrict__ X,
+                                                          const double* __restrict__ GX,
+                                                          const double* __restrict__ Atb,
+                                                          const double* __restrict__ s,
+                                                          const double* __restrict__ bbp,
+                                                          double* __restrict__ D,
+                                                          double* __restrict__ colstat) {
+  __shared__ double red[4][GS_C];
+  const int cl = threadIdx.x & (GS_C - 1), rg = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * GS_C + cl;
+  const bool in = c < k;
+  double kk = 0.0, aa = 0.0, num = 0.0, fx = 0.0;
+  if (in) {
+    for (int64_t i = rg; i < n; i += 4) {
+      const int64_t o = i * k + c;
+      const double x = (double)X[o], a = Atb[o], hx = GX[o], si = s[i];
+      const double y = si * x, gy = (hx - a) / si;
+      const double p = (y > 0.0 || gy < 0.0) ? gy : 0.0;
+      num += p * p;
+      D[o] = p / si;
+      const double m = y < gy ? y : gy;
+      kk += m * m;
+      const double ai = a / si;
+      aa += ai * ai;
+      fx += x * (hx - 2.0 * a);
+    }
+  }
+  kk = gs_reduce(kk, red, rg, cl);
+  aa = gs_reduce(aa, red, rg, cl);
+  num = gs_reduce(num, red, rg, cl);
+  fx = gs_reduce(fx, red, rg, cl);
+  if (in && rg == 0) {
+    double bb = 0.0;
+    for (int ch = 0; ch < BB_CH; ++ch) bb += bbp[(int64_t)ch * k + c];
+    colstat[c * 8 + 0] = aa > 0.0 ? sqrt(kk) / sqrt(aa) : sqrt(kk);
+    colstat[c * 8 + 1] = 0.5 * (fx + bb);
+    colstat[c * 8 + 2] = num;
+    colstat[c * 8 + 3] = aa;
+  }
+}
+
+// Stage 2 (after HD = H D): alpha = ||p||^2 / D^T H D and the candidate x' (rounded to TX).
+template <typename TX>
+__global__ __launch_bounds__(256) void gref_stage2_kernel(int64_t n, int64_t k,
+                                                          const TX* __restrict__ X,
+                                                          const double* __restrict__ D,
+                                                          const double* __restrict__ HD,
+                                                          double* __restrict__ Xn,
+                                                          const double* __restrict__ colstat) {
+  __shared__ double red[4][GS_C];
+  const int cl = threadIdx.x & (GS_C - 1), rg = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * GS_C + cl;
+  const bool in = c < k;
+  double den = 0.0;
+  if (in)
+    for (int64_t i = rg; i < n; i += 4) den += D[i * k + c] * HD[i * k + c];
+  den = gs_reduce(den, red, rg, cl);
+  if (!in) return;
+  const double num = colstat[c * 8 + 2];
+  const double alpha = (den > 0.0 && __builtin_isfinite(den)) ? num / den : 0.0;
+  for (int64_t i = rg; i < n; i += 4) {
+    const int64_t o = i * k + c;
+    const double v = (double)X[o] - alpha * D[o];
+    Xn[o] = (double)(TX)(v > 0.0 ? v : 0.0);
+  }
+}
+
+// Stage 3 (after HXn = H x'): residual at x', objective change, accept or reject, results.
+template <typename TX>
+__global__ __launch_bounds__(256) void gref_stage3_kernel(int64_t n, int64_t k,
+                                                          TX* __restrict__ X,
+                                                          const double* __restrict__ Xn,
+                                                          const double* __restrict__ HXn,
+                                                          const double* __restrict__ GX,
+                                                          const double* __restrict__ Atb,
+                                                          const double* __restrict__ s,
+                                                          const double* __restrict__ colstat,
+                                                          double* __restrict__ kkt64,
+                                                          double* __restrict__ obj64) {
+  __shared__ double red[4][GS_C];
+  __shared__ int acc_s[GS_C];
+  const int cl = threadIdx.x & (GS_C - 1), rg = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * GS_C + cl;
+  const bool in = c < k;
+  double kk = 0.0, df = 0.0;
+  if (in) {
+    for (int64_t i = rg; i < n; i += 4) {
+      const int64_t o = i * k + c;
+      const double a = Atb[o], si = s[i];
+      const double xn = Xn[o];
+      const double g1 = HXn[o] - a, g0 = GX[o] - a;
+      const double y = si * xn, gy = g1 / si;
+      const double m = y < gy ? y : gy;
+      kk += m * m;
+      df += (xn - (double)X[o]) * (g0 + g1);
+    }
+  }
+  kk = gs_reduce(kk, red, rg, cl);
+  df = 0.5 * gs_reduce(df, red, rg, cl);
+  if (in && rg == 0) {
+    const double aa = colstat[c * 8 + 3];
+    const double r1 = aa > 0.0 ? sqrt(kk) / sqrt(aa) : sqrt(kk);
+    const double r0 = colstat[c * 8 + 0];
+    const bool accept = (r1 < r0) && (df <= 0.0);
+    acc_s[cl] = accept ? 1 : 0;
+    kkt64[c] = accept ? r1 : r0;
+    obj64[c] = colstat[c * 8 + 1] + (accept ? df : 0.0);
+  }
+  __syncthreads();
+  if (in && acc_s[cl])
+    for (int64_t i = rg; i < n; i += 4) X[i * k + c] = (TX)Xn[i * k + c];
 }
 
 // ---- per-column steps ---------------------------------------------------------------------
@@ -456,9 +590,33 @@ static RefineWs refine_layout(void* ws, int64_t d, int64_t n, int64_t k) {
   return w;
 }
 
+// Gram path workspace: H [n, n], a, HX, D, HD (reused for H X'), X' [n, k], s [n],
+// colstat [8 k], ||b||^2 partials [BB_CH k].
+struct GramRefineWs {
+  double *H, *a, *HX, *D, *HD, *Xn, *s, *colstat, *bbp;
+};
+
+static GramRefineWs gram_refine_layout(void* ws, int64_t n, int64_t k) {
+  GramRefineWs w;
+  double* p = (double*)ws;
+  w.H = p; p += n * n;
+  w.a = p; p += n * k;
+  w.HX = p; p += n * k;
+  w.D = p; p += n * k;
+  w.HD = p; p += n * k;
+  w.Xn = p; p += n * k;
+  w.s = p; p += n;
+  w.colstat = p; p += 8 * k;
+  w.bbp = p;
+  return w;
+}
+
 size_t refine_ws_bytes(int64_t d, int64_t n, int64_t k) {
-  size_t el = (size_t)(2 * d * k + 4 * n * k + n + 8 * k);
-  if (k <= RF_SMALL_K) el += (size_t)refine_chunks(d, n) * (2 * k + 1) * n;
+  size_t el;
+  if (k <= RF_SMALL_K)
+    el = (size_t)(2 * d * k + 4 * n * k + n + 8 * k) + (size_t)refine_chunks(d, n) * (2 * k + 1) * n;
+  else
+    el = (size_t)(n * n + 5 * n * k + n + 8 * k + BB_CH * k);
   return el * sizeof(double) + 256;
 }
 
@@ -470,7 +628,7 @@ template <typename T>
 static void launch_resid(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda,
                          const void* X, bool x_is_double, const T* B, int64_t ldb, double* R,
                          hipStream_t st) {
-  if (k <= RF_SMALL_K && vec_ok(A, lda, n, sizeof(T))) {
+  if (vec_ok(A, lda, n, sizeof(T))) {
     dim3 grid((unsigned)((d + 4 * RF_RPW - 1) / (4 * RF_RPW)));
     if (x_is_double)
       hipLaunchKernelGGL(rows_residual_vec_kernel<double>, grid, dim3(256), 0, st, d, n, k,
@@ -478,7 +636,7 @@ static void launch_resid(int64_t d, int64_t n, int64_t k, const T* A, int64_t ld
     else
       hipLaunchKernelGGL(rows_residual_vec_kernel<float>, grid, dim3(256), 0, st, d, n, k,
                          (const float*)A, lda, (const float*)X, (const float*)B, ldb, R);
-  } else if (k <= RF_SMALL_K) {
+  } else {
     dim3 grid((unsigned)((d + 3) / 4));
     if (x_is_double)
       hipLaunchKernelGGL((rows_residual_kernel<T, double>), grid, dim3(256), 0, st, d, n, k, A, lda,
@@ -486,14 +644,6 @@ static void launch_resid(int64_t d, int64_t n, int64_t k, const T* A, int64_t ld
     else
       hipLaunchKernelGGL((rows_residual_kernel<T, T>), grid, dim3(256), 0, st, d, n, k, A, lda,
                          (const T*)X, B, ldb, R);
-  } else {
-    dim3 grid((unsigned)((k + RG_BM - 1) / RG_BM), (unsigned)((d + RG_BM - 1) / RG_BM));
-    if (x_is_double)
-      hipLaunchKernelGGL((gemm64_kernel<T, double, false>), grid, dim3(256), 0, st, d, k, n, A, lda,
-                         (const double*)X, k, B, ldb, R, k);
-    else
-      hipLaunchKernelGGL((gemm64_kernel<T, T, false>), grid, dim3(256), 0, st, d, k, n, A, lda,
-                         (const T*)X, k, B, ldb, R, k);
   }
 }
 
@@ -501,45 +651,70 @@ template <typename T>
 static void launch_atr(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda, const double* R,
                        const T* B, int64_t ldb, bool with_b, RefineWs& w, double* G,
                        hipStream_t st) {
-  if (k <= RF_SMALL_K && vec_ok(A, lda, n, sizeof(T))) {
-    const int64_t rows = (d + w.chunks - 1) / w.chunks;
+  const int64_t rows = (d + w.chunks - 1) / w.chunks;
+  const int wb = with_b ? 1 : 0;
+  if (vec_ok(A, lda, n, sizeof(T))) {
     dim3 g1((unsigned)((n + 1023) / 1024), (unsigned)w.chunks);
     const float* Af = (const float*)A;
     const float* Bf = (const float*)B;
-    const int wb = with_b ? 1 : 0;
     switch (k) {
       case 1: hipLaunchKernelGGL(cols_partial_vec_kernel<1>, g1, dim3(256), 0, st, d, n, Af, lda, R, Bf, ldb, wb, rows, w.partial); break;
       case 2: hipLaunchKernelGGL(cols_partial_vec_kernel<2>, g1, dim3(256), 0, st, d, n, Af, lda, R, Bf, ldb, wb, rows, w.partial); break;
       case 3: hipLaunchKernelGGL(cols_partial_vec_kernel<3>, g1, dim3(256), 0, st, d, n, Af, lda, R, Bf, ldb, wb, rows, w.partial); break;
       default: hipLaunchKernelGGL(cols_partial_vec_kernel<4>, g1, dim3(256), 0, st, d, n, Af, lda, R, Bf, ldb, wb, rows, w.partial); break;
     }
-    hipLaunchKernelGGL(cols_finalize_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
-                       k, wb, w.chunks, (const double*)w.partial, G, w.Atb, w.s);
-  } else if (k <= RF_SMALL_K) {
-    const int64_t rows = (d + w.chunks - 1) / w.chunks;
+  } else {
     dim3 g1((unsigned)((n + 255) / 256), (unsigned)w.chunks);
     hipLaunchKernelGGL(cols_partial_kernel<T>, g1, dim3(256), 0, st, d, n, k, A, lda, R, B, ldb,
-                       with_b ? 1 : 0, rows, w.partial);
-    hipLaunchKernelGGL(cols_finalize_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
-                       k, with_b ? 1 : 0, w.chunks, (const double*)w.partial, G, w.Atb, w.s);
-  } else {
-    dim3 grid((unsigned)((k + RG_BM - 1) / RG_BM), (unsigned)((n + RG_BM - 1) / RG_BM));
-    hipLaunchKernelGGL((gemm64_kernel<T, double, true>), grid, dim3(256), 0, st, n, k, d, A, lda, R,
-                       k, (const T*)nullptr, 0, G, k);
-    if (with_b) {
-      // a = A^T B: the same product with B (element type T) as the right operand.
-      hipLaunchKernelGGL((gemm64_kernel<T, T, true>), grid, dim3(256), 0, st, n, k, d, A, lda, B,
-                         ldb, (const T*)nullptr, 0, w.Atb, k);
-      hipLaunchKernelGGL(sumsq_cols_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                         d, n, A, lda, w.s);
-    }
+                       wb, rows, w.partial);
   }
+  hipLaunchKernelGGL(cols_finalize_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+                     k, wb, w.chunks, (const double*)w.partial, G, w.Atb, w.s);
+}
+
+template <typename TA, typename TM>
+static void gemm_tn(int64_t K, int64_t N, int64_t Mc, const TA* A, int64_t lda, const TM* M,
+                    int64_t ldm, double* C, int64_t ldc, hipStream_t st) {
+  dim3 grid((unsigned)((Mc + TN_T - 1) / TN_T), (unsigned)((N + TN_T - 1) / TN_T));
+  hipLaunchKernelGGL((gemm_tn_f64_kernel<TA, TM>), grid, dim3(256), 0, st, K, N, Mc, A, lda, M,
+                     ldm, C, ldc);
+}
+
+template <typename T>
+static void launch_refine_gram(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda,
+                               const T* B, int64_t ldb, T* X, double* kkt64, double* obj64,
+                               void* ws, hipStream_t st) {
+  GramRefineWs w = gram_refine_layout(ws, n, k);
+  const unsigned cb = (unsigned)((k + GS_C - 1) / GS_C);
+  gemm_tn<T, T>(d, n, n, A, lda, A, lda, w.H, n, st);      // H = A^T A
+  gemm_tn<T, T>(d, n, k, A, lda, B, ldb, w.a, k, st);      // a = A^T B
+  hipLaunchKernelGGL(colsq_partial_kernel<T>, dim3((unsigned)((k + 255) / 256), BB_CH), dim3(256),
+                     0, st, d, k, B, ldb, w.bbp);
+  hipLaunchKernelGGL(diag_scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+                     (const double*)w.H, w.s);
+  // H is symmetric, so H^T M = H M: the same transposed product with K = n
+  gemm_tn<double, T>(n, n, k, w.H, n, X, k, w.HX, k, st);
+  hipLaunchKernelGGL(gref_stage1_kernel<T>, dim3(cb), dim3(256), 0, st, n, k, (const T*)X,
+                     (const double*)w.HX, (const double*)w.a, (const double*)w.s,
+                     (const double*)w.bbp, w.D, w.colstat);
+  gemm_tn<double, double>(n, n, k, w.H, n, w.D, k, w.HD, k, st);
+  hipLaunchKernelGGL(gref_stage2_kernel<T>, dim3(cb), dim3(256), 0, st, n, k, (const T*)X,
+                     (const double*)w.D, (const double*)w.HD, w.Xn, (const double*)w.colstat);
+  gemm_tn<double, double>(n, n, k, w.H, n, w.Xn, k, w.HD, k, st);  // H x' (reuses HD)
+  hipLaunchKernelGGL(gref_stage3_kernel<T>, dim3(cb), dim3(256), 0, st, n, k, X,
+                     (const double*)w.Xn, (const double*)w.HD, (const double*)w.HX,
+                     (const double*)w.a, (const double*)w.s, (const double*)w.colstat, kkt64,
+                     obj64);
 }
 
 template <typename T>
 hipError_t launch_refine(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda, const T* B,
                          int64_t ldb, T* X, double* kkt64, double* obj64, void* ws,
                          hipStream_t st) {
+  if (k > RF_SMALL_K) {
+    launch_refine_gram<T>(d, n, k, A, lda, B, ldb, X, kkt64, obj64, ws, st);
+    return hipGetLastError();
+  }
   RefineWs w = refine_layout(ws, d, n, k);
   launch_resid<T>(d, n, k, A, lda, X, false, B, ldb, w.R, st);
   launch_atr<T>(d, n, k, A, lda, w.R, B, ldb, true, w, w.G, st);

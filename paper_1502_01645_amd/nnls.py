@@ -81,6 +81,10 @@ def lib():
         L.nnls_mlp_workspace_bytes.restype = _sz
         L.nnls_mlp_reset_state.argtypes = [_vp, _vp]
         L.nnls_mlp_reset_state.restype = ctypes.c_int
+        L.nnls_mlp_fit_input_workspace_bytes.argtypes = []
+        L.nnls_mlp_fit_input_workspace_bytes.restype = _sz
+        L.nnls_mlp_fit_input.argtypes = [_i64, _vp, _vp, _vp, _sz, _vp]
+        L.nnls_mlp_fit_input.restype = ctypes.c_int
         L.nnls_mlp_forward.argtypes = [_i64, _vp, _vp, _vp, _vp, _sz, _vp]
         L.nnls_mlp_forward.restype = ctypes.c_int
         L.nnls_mlp_gradients.argtypes = [_i64, _vp, _vp, _vp, ctypes.c_float, _vp, _vp, _vp, _sz,
@@ -362,18 +366,25 @@ def mlp_inputs(q, Y=None):
 
 class WarmStartNet:
     """The warm-start network's parameter blob (nnls_mlp_* / nnls_warm_start of nnls.h).
-    `params` are the initial FP32 master weights in the library's layout."""
+    `params` are the initial FP32 master weights in the library's layout; shift and scale the
+    input standardisation (default 0 and 1; nnls_mlp_fit_input fits them with fit_input)."""
 
-    def __init__(self, params, device):
+    def __init__(self, params, device, shift=None, scale=None):
         L = lib()
         self.P = int(L.nnls_mlp_param_count())
         self.device = torch.device(device)
         self.blob = torch.empty(int(L.nnls_mlp_blob_bytes()), dtype=torch.uint8, device=device)
         self.master = self.blob[:4 * self.P].view(torch.float32)
+        norm = self.blob[14 * self.P:14 * self.P + 8 * MLP_IN].view(torch.float32)
+        self.shift, self.scale = norm[:MLP_IN], norm[MLP_IN:]
         p = torch.as_tensor(params, dtype=torch.float32).reshape(-1)
         if p.numel() != self.P:
             raise NNLSError(f"expected {self.P} parameters, got {p.numel()}")
         self.master.copy_(p.to(device))
+        self.shift.copy_(torch.as_tensor(0.0 if shift is None else shift, dtype=torch.float32)
+                         .expand(MLP_IN).to(device))
+        self.scale.copy_(torch.as_tensor(1.0 if scale is None else scale, dtype=torch.float32)
+                         .expand(MLP_IN).to(device))
         self.step = 0
         self._ws = {}
         _check(L.nnls_mlp_reset_state(_ptr(self.blob), _stream(self.device)), "nnls_mlp_reset_state")
@@ -384,6 +395,13 @@ class WarmStartNet:
             ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             self._ws[key] = ws
         return ws
+
+    def fit_input(self, U):
+        """shift, scale = per-feature mean and 1 / std of the rows of U [count, 256]."""
+        nb = int(lib().nnls_mlp_fit_input_workspace_bytes())
+        ws = self._wsb("fit", nb)
+        _check(lib().nnls_mlp_fit_input(U.shape[0], _ptr(self.blob), _ptr(U), _ptr(ws), nb,
+                                        _stream(self.device)), "nnls_mlp_fit_input")
 
     def forward(self, u):
         b = u.shape[0]

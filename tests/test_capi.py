@@ -180,7 +180,7 @@ def test_mlp_sizes_and_argument_errors(L):
     from paper_1502_01645_amd import nnls as N
     P = 256 * 1024 + 1024 + 1024 * 1024 + 1024 + 1024 * 256 + 256
     assert L.nnls_mlp_param_count() == P
-    assert L.nnls_mlp_blob_bytes() == 14 * P
+    assert L.nnls_mlp_blob_bytes() == 14 * P + 8 * 256
     assert L.nnls_mlp_workspace_bytes(0, 0) == 0
     assert L.nnls_mlp_workspace_bytes(64, 1) > L.nnls_mlp_workspace_bytes(64, 0) > 0
     big = 1 << 40
@@ -199,6 +199,9 @@ def test_mlp_sizes_and_argument_errors(L):
     assert L.nnls_mlp_train_step(64, FAKE, FAKE, FAKE, 0.0, 1, 0.01, None, FAKE, big,
                                  None) == N.E_ARG
     assert L.nnls_mlp_reset_state(None, None) == N.E_ARG
+    assert L.nnls_mlp_fit_input_workspace_bytes() > 0
+    assert L.nnls_mlp_fit_input(0, FAKE, FAKE, FAKE, big, None) == N.E_ARG
+    assert L.nnls_mlp_fit_input(10, FAKE, FAKE, FAKE, 8, None) == N.E_WORKSPACE
     # warm start: only n = 256
     assert L.nnls_warm_start_workspace_bytes(128, 4) == 0
     assert L.nnls_warm_start_workspace_bytes(256, 4) > 0

@@ -164,6 +164,43 @@ def test_many_rhs_small():
     _check_solution(A, B, host(res["X"]), 1e-5, ref, "many-rhs")
 
 
+@pytest.mark.parametrize("dtype,d,n,k", [(np.float32, 700, 130, 70), (np.float64, 500, 67, 9),
+                                         (np.float32, 300, 256, 5)])
+@pytest.mark.parametrize("start", ["loose", "zero"])
+def test_refine_many_rhs_matches_oracle(dtype, d, n, k, start):
+    """FP64 check and refinement step for more than four right-hand sides (the FP64 Gram path):
+    reported residual and objective are the oracle's for the returned X, and a column's step is
+    kept exactly where the FP64 step lowers the residual without raising the objective."""
+    say(f"refine many rhs {np.dtype(dtype).name} d={d} n={n} k={k} start={start}")
+    A, B = _uniform_case(31 + k, d, n, k, dtype)
+    Q, q, s = N.prepare(dev(A), dev(B))
+    if start == "loose":
+        X, it, kkt, st = N.solve(Q, q, s, tol=1e-3, max_iter=0)
+    else:
+        X = torch.zeros_like(q)
+    X0 = host(X).copy()
+    kkt64, obj64 = N.refine(dev(A), dev(B), X)
+    X1 = host(X)
+    r0, F0 = orc().kkt_x(A, B, X0)
+    r1, F1 = orc().kkt_x(A, B, X1)
+    np.testing.assert_allclose(host(kkt64), r1, rtol=1e-6, atol=1e-14)
+    bb = 0.5 * (B.astype(np.float64) ** 2).sum(0)
+    assert np.all(np.abs(host(obj64) - F1) <= 1e-10 * bb)
+    Xc = O.refine_candidate(A, B, X0, dtype)
+    rc, Fc = orc().kkt_x(A, B, Xc)
+    want = (rc < r0) & (Fc <= F0)
+    clear = (np.abs(rc - r0) > 1e-6 * r0) & (np.abs(Fc - F0) > 1e-12 * bb)
+    changed = np.any(X1 != X0, axis=0)
+    say(f"  steps kept {int(changed.sum())} of {k}; expected {int(want.sum())}")
+    assert np.array_equal(changed[clear], want[clear])
+    if start == "zero":
+        assert changed.any()
+    np.testing.assert_allclose(X1[:, changed], Xc[:, changed], rtol=1e-6,
+                               atol=1e-6 * max(np.abs(Xc).max(), 1e-30))
+    assert np.all(r1 <= r0 * (1 + 1e-6))
+    assert np.all(X1 >= 0)
+
+
 # ---------------------------------------------------------------------------- edge cases ------
 def test_n_equals_one():
     say("n = 1")

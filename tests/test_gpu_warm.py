@@ -48,26 +48,35 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
 
 
-@pytest.mark.parametrize("batch", [64, 192])
-def test_forward_matches_reference(params, batch):
-    say(f"mlp forward batch={batch}")
+def _norm(seed):
+    rng = np.random.default_rng(seed)
+    shift = (0.05 * rng.standard_normal(256)).astype(np.float32)
+    scale = rng.uniform(0.5, 3.0, 256).astype(np.float32)
+    return shift, scale
+
+
+@pytest.mark.parametrize("batch,standardise", [(64, False), (192, True)])
+def test_forward_matches_reference(params, batch, standardise):
+    say(f"mlp forward batch={batch} standardise={standardise}")
     u, _ = _batch(batch, batch)
-    net = N.WarmStartNet(params, DEV)
+    shift, scale = _norm(batch) if standardise else (None, None)
+    net = N.WarmStartNet(params, DEV, shift, scale)
     z = host(net.forward(dev(u)))
-    z_em, _ = M.forward(params, u, emulate=True)
+    z_em, _ = M.forward(params, u, True, shift, scale)
     assert _rel(z, z_em) <= 1e-3, _rel(z, z_em)
     # against exact FP64 arithmetic on the FP32 parameters: BF16 operands cost ~2^-8 relative
-    z_ex, _ = M.forward(params, u)
+    z_ex, _ = M.forward(params, u, False, shift, scale)
     assert _rel(z, z_ex) <= 3e-2, _rel(z, z_ex)
 
 
 def test_gradients_match_reference(params):
     say("mlp gradients batch=128")
     u, t = _batch(128, 3)
-    net = N.WarmStartNet(params, DEV)
+    shift, scale = _norm(3)
+    net = N.WarmStartNet(params, DEV, shift, scale)
     loss, g = net.gradients(dev(u), dev(t), LAM)
     loss, g = float(host(loss)[0]), host(g).astype(np.float64)
-    loss_ref, g_ref = M.gradients(params, u, t, LAM, emulate=True)
+    loss_ref, g_ref = M.gradients(params, u, t, LAM, True, shift, scale)
     assert abs(loss - loss_ref) <= 1e-4 * abs(loss_ref), (loss, loss_ref)
     for name, (a, b) in OFF.items():
         r = _rel(g[a:b], g_ref[a:b])
@@ -96,6 +105,23 @@ def test_adam_first_step_and_bf16_copy(params):
     assert np.array_equal(copy, want.astype(np.uint16))
 
 
+def test_fit_input_statistics(params):
+    """shift and scale are the FP64 mean and 1 / std of each feature; a constant feature gets
+    scale 1.  Rows that differ by a tiny fraction of their size keep their spread."""
+    rng = np.random.default_rng(8)
+    U = (0.0625 + 5e-4 * rng.standard_normal((5000, 256))).astype(np.float32)
+    U[:, 7] = 0.25
+    net = N.WarmStartNet(params, DEV)
+    net.fit_input(dev(U))
+    U64 = U.astype(np.float64)
+    mu, sd = U64.mean(0), U64.std(0)
+    np.testing.assert_allclose(host(net.shift), mu.astype(np.float32), rtol=1e-6)
+    sc = host(net.scale)
+    assert sc[7] == 1.0
+    keep = np.arange(256) != 7
+    np.testing.assert_allclose(sc[keep], 1.0 / sd[keep], rtol=1e-5)
+
+
 def test_reset_state_clears_moments(params):
     net = N.WarmStartNet(params, DEV)
     u, t = _batch(64, 6)
@@ -112,6 +138,14 @@ def _warm_problem(k, seed):
     return A, B
 
 
+def _mixed_problem(k, seed):
+    """A general problem whose q has entries of both signs (A, B ~ N(0, 1))."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((600, 256)).astype(np.float32)
+    B = rng.standard_normal((600, k)).astype(np.float32)
+    return A, B
+
+
 def _net_with_head(params, z_head):
     """A network whose output is z_head for every input: W3 = 0, b3 = z_head."""
     p = params.copy()
@@ -122,67 +156,65 @@ def _net_with_head(params, z_head):
     return N.WarmStartNet(p, DEV)
 
 
-@pytest.mark.parametrize("factor,expect_fallback", [(3.0, 1), (1.0, 0)])
-def test_warm_start_objective_check(params, factor, expect_fallback):
-    """y0 = c u with u = max(-q, 0): f(c u) = c^2 u'Qu / 2 - c ||u||^2 is positive for
-    c > 2 ||u||^2 / u'Qu (forced fallback) and negative at c = ||u||^2 / u'Qu."""
-    say(f"warm start objective check factor={factor}")
-    A, B = _warm_problem(1, 0)
+@pytest.mark.parametrize("case", ["descent", "ascent", "zero"])
+def test_warm_start_line_search_and_fallback(params, case):
+    """Direction v: y0 = c* v with c* = -q'v / v'Qv when q'v < 0; v = max(-q, 0) gives
+    c* = ||v||^2 / v'Qv.  v = max(q, 0) has q'v = ||v||^2 > 0 and v = 0 has nothing to scale:
+    both fall back to the cold start, which then solves exactly as a cold solve."""
+    say(f"warm start {case}")
+    A, B = _mixed_problem(1, 21)
     Q, q, s = N.prepare(dev(A), dev(B))
     Qh, qh = host(Q).astype(np.float64), host(q)[:, 0].astype(np.float64)
-    uu = np.maximum(-qh, 0.0)
-    c = factor * (uu @ uu) / (uu @ Qh @ uu)
-    qn = np.linalg.norm(qh)
-    net = _net_with_head(params, (c * uu / qn).astype(np.float32))
+    v = {"descent": np.maximum(-qh, 0.0), "ascent": np.maximum(qh, 0.0),
+         "zero": np.zeros_like(qh)}[case]
+    head = v if case != "zero" else -np.ones_like(qh)
+    v = v.astype(np.float32).astype(np.float64)  # the head is stored in FP32
+    net = _net_with_head(params, head.astype(np.float32))
     Y0, fb = net.warm_start(Q, q)
     Y0, fb = host(Y0)[:, 0], host(fb)
-    assert fb[0] == expect_fallback
-    if expect_fallback:
+    if case == "descent":
+        assert fb[0] == 0
+        c = -(qh @ v) / (v @ Qh @ v)
+        np.testing.assert_allclose(Y0, c * v, rtol=1e-5, atol=1e-6 * np.abs(c * v).max())
+        f0 = 0.5 * Y0 @ Qh @ Y0 + qh @ Y0
+        assert f0 < 0
+    else:
+        assert fb[0] == 1
         assert np.all(Y0 == 0)
-        X_w, it_w, _, st_w = N.solve(Q, q, s, 1e-5, 0, Y0=torch.zeros_like(q))
-        X_c, it_c, _, st_c = N.solve(Q, q, s, 1e-5, 0)
+        X_w, it_w, _, _ = N.solve(Q, q, s, 1e-5, 0, Y0=torch.zeros_like(q))
+        X_c, it_c, _, _ = N.solve(Q, q, s, 1e-5, 0)
         assert np.array_equal(host(X_w), host(X_c))
         assert np.array_equal(host(it_w), host(it_c))
-    else:
-        np.testing.assert_allclose(Y0, c * uu, rtol=1e-5, atol=1e-6 * np.abs(c * uu).max())
 
 
-def test_fallback_flags_follow_objective_sign(params):
-    """Across many right-hand sides, the flag is set exactly where the FP64 objective of the
-    predicted point is positive (columns with |f| within rounding of 0 may go either way)."""
+def test_warm_start_many_columns(params):
+    """Across many right-hand sides with q of both signs, a column falls back exactly where
+    q'v >= 0 for the network's direction v (columns with q'v within rounding of 0 may go either
+    way), and elsewhere y0 = c* v."""
     k = 320
-    say(f"warm start flags k={k}")
-    A, B = _warm_problem(k, 100)
+    say(f"warm start k={k}")
+    A, B = _mixed_problem(k, 22)
     Q, q, s = N.prepare(dev(A), dev(B))
-    # scale the head (W3, b3) by gamma: z, and so y0, scale by gamma, and f(gamma y) =
-    # gamma^2 y'Qy / 2 + gamma q'y changes sign at gamma = -2 q'y / y'Qy.  The median of that
-    # threshold over the columns (from the FP64 reference network) splits them about evenly.
-    Qh, qh = host(Q).astype(np.float64), host(q).astype(np.float64)
-    qn = np.linalg.norm(qh, axis=0)
-    z0, _ = M.forward(params, (qh / qn).T, emulate=True)
-    y0 = (qn[:, None] * np.maximum(z0, 0.0)).T
-    thr = -2 * np.einsum("ik,ik->k", qh, y0) / np.einsum("ik,ij,jk->k", y0, Qh, y0)
-    gamma = float(np.nanmedian(thr))
-    p = params.astype(np.float64)
-    for name in ("W3", "b3"):
-        a, b = OFF[name]
-        p[a:b] *= gamma
-    net = N.WarmStartNet(p.astype(np.float32), DEV)
+    net = N.WarmStartNet(params, DEV)
     Y0, fb = net.warm_start(Q, q)
+    Qh, qh = host(Q).astype(np.float64), host(q).astype(np.float64)
     U, _ = N.mlp_inputs(q)
     z = host(net.forward(U)).astype(np.float64)
-    y = (qn[:, None] * np.maximum(z, 0.0)).T
-    f = 0.5 * np.einsum("ik,ij,jk->k", y, Qh, y) + np.einsum("ik,ik->k", qh, y)
-    scale = np.einsum("ik,ij,jk->k", np.abs(y), np.abs(Qh), np.abs(y)) + np.abs(qh * y).sum(0)
+    v = np.maximum(z, 0.0).T                       # [256, k]
+    a = np.einsum("ik,ij,jk->k", v, Qh, v)
+    b = np.einsum("ik,ik->k", qh, v)
+    scale = np.abs(qh * v).sum(0)
     fb = host(fb)
-    sure = np.abs(f) > 1e-4 * scale
+    sure = np.abs(b) > 1e-4 * scale
     say(f"  fallbacks {int(fb.sum())} of {k}; undecided {int((~sure).sum())}")
     assert 0 < fb.sum() < k
-    assert np.array_equal(fb[sure], (f[sure] > 0).astype(np.int32))
+    assert np.array_equal(fb[sure], (b[sure] >= 0).astype(np.int32))
     Y0 = host(Y0)
     assert np.all(Y0[:, fb == 1] == 0)
     keep = fb == 0
-    np.testing.assert_allclose(Y0[:, keep], y[:, keep], rtol=1e-4, atol=1e-6 * np.abs(y).max())
+    c = -b[keep] / a[keep]
+    np.testing.assert_allclose(Y0[:, keep], c * v[:, keep], rtol=1e-4,
+                               atol=1e-6 * np.abs(c * v[:, keep]).max())
 
 
 def test_mlp_inputs(params):
@@ -193,4 +225,5 @@ def test_mlp_inputs(params):
     qh, Yh = host(q).astype(np.float64), host(X).astype(np.float64)
     qn = np.linalg.norm(qh, axis=0)
     np.testing.assert_allclose(host(U), (qh / qn).T, rtol=1e-6, atol=1e-7)
-    np.testing.assert_allclose(host(T), (Yh / qn).T, rtol=1e-6, atol=1e-7)
+    yn = np.linalg.norm(Yh, axis=0)
+    np.testing.assert_allclose(host(T), (Yh / yn).T, rtol=1e-6, atol=1e-7)

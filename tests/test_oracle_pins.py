@@ -2,6 +2,7 @@
 import os
 import subprocess
 
+import numpy as np
 import pytest
 
 import oracle_pins as P
@@ -41,3 +42,38 @@ def test_pins_catch_planted_mistake(plant, tmp_path):
                 __import__("numpy").linalg.LinAlgError):
             failed.append(pin.__name__)
     assert failed, f"planted mistake '{PLANTS[plant]}' passed every pin"
+
+
+# ---- the FP64 refinement step (one step of Algorithm 2 from a given x) ----------------------
+def test_refine_candidate_n1_closed_form():
+    """n = 1 from x = 0: the exact step lands on max(0, a^T b) / ||a||^2."""
+    rng = P._rng(31)
+    for _ in range(10):
+        a = rng.random((7, 1)) + 0.1
+        b = rng.standard_normal((7, 3))
+        xc = O.refine_candidate(a, b, np.zeros((1, 3)))
+        x_cf = np.maximum(0.0, a[:, 0] @ b) / (a[:, 0] @ a[:, 0])
+        assert np.allclose(xc[0], x_cf, rtol=1e-13, atol=1e-15)
+
+
+def test_refine_candidate_orthogonal_columns():
+    """Q = I: one step from x = 0 is the clipped least-squares solution."""
+    rng = P._rng(32)
+    U, _ = np.linalg.qr(rng.standard_normal((30, 8)))
+    A = U * (rng.random(8) * 4 + 0.5)[None, :]
+    B = rng.standard_normal((30, 4))
+    xc = O.refine_candidate(A, B, np.zeros((8, 4)))
+    x_ls = np.maximum(0.0, A.T @ B) / np.sum(A * A, axis=0)[:, None]
+    assert np.allclose(xc, x_ls, rtol=1e-10, atol=1e-12)
+
+
+def test_refine_candidate_fixed_point_and_rounding():
+    """At the solution the masked gradient vanishes and x stays; FP32 output is rounded."""
+    rng = P._rng(33)
+    A = rng.random((50, 6))
+    x = np.array([0.5, 0.0, 1.5, 0.0, 0.25, 2.0])
+    b = A @ x                                   # noiseless, full rank: x is the solution
+    xc = O.refine_candidate(A, b, x)
+    assert np.allclose(xc[:, 0], x, rtol=0, atol=1e-12)
+    x32 = O.refine_candidate(A, b + 0.1, x, np.float32)
+    assert np.array_equal(x32, x32.astype(np.float32).astype(np.float64))
