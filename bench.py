@@ -46,14 +46,22 @@ WARM_LAMBDA = 1e-4
 MLP_FWD_FLOP = 2.0 * (256 * 1024 + 1024 * 1024 + 1024 * 256)   # per sample
 
 
-def _src_sha(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+CSRC = os.path.join(ROOT, "paper_1502_01645_amd", "csrc")
+
+
+def _src_sha(src):
+    """Hash of a kernel's source file together with the shared headers it is built with."""
+    h = hashlib.sha256()
+    for name in (src, "common.hpp", "kernels.hpp"):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_record(kernel_key, src):
-    """Measured HBM traffic of a kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated with a copy
-    kernel) if it was taken on the current source of that kernel; otherwise None."""
+    """Measured HBM traffic per launch of a kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE, each
+    scaled by what the counter reads for a copy kernel of known size) if it was taken on the
+    current source of that kernel; otherwise None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -190,16 +198,14 @@ def main():
     gram_tf = gram_flops / (ms["gram"] * 1e-3) / 1e12
     solve_bytes = 4.0 * n * rows_last
     solve_gbs = solve_bytes / (ms["solve"] * 1e-3) / 1e9
-    src = os.path.join(ROOT, "paper_1502_01645_amd", "csrc")
     roof_gram = {"kernel": "gram_bf16x3_kernel", "bound": "mfma", "achieved": round(gram_tf, 2),
                  "peak": round(PEAK_BF16X3_TFLOPS, 1), "unit": "TFLOP/s",
                  "frac": round(gram_tf / PEAK_BF16X3_TFLOPS, 4),
-                 "traffic": traffic_record("gram_bf16x3_kernel", os.path.join(src, "gram.hip"))}
+                 "traffic": traffic_record("gram_bf16x3_kernel", "gram.hip")}
     roof_solve = {"kernel": "solve_persistent_kernel", "bound": "hbm",
                   "achieved": round(solve_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                   "frac": round(solve_gbs / PEAK_HBM_GBS, 4),
-                  "traffic": traffic_record("solve_persistent_kernel",
-                                            os.path.join(src, "solve_persistent.hip"))}
+                  "traffic": traffic_record("solve_persistent_kernel", "solve_persistent.hip")}
     dominant, other = (roof_gram, roof_solve) if ms["gram"] >= ms["solve"] else (roof_solve, roof_gram)
 
     out = {
