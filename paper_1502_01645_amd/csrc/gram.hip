@@ -1,16 +1,19 @@
 // Gram product and rescale of Algorithm 1 (Problem (2) -> Problem (5)) for gfx950.
 //
 //   colnorm     s_i = ||A_i||_2 in FP64 from the stored entries (1 for a zero column)
-//   gram_bf16x3 upper-triangle tiles of [A | B]^T [A | B] restricted to rows of A, so one launch
-//               gives H = A^T A and A^T B.  FP32 inputs are split into hi + lo bfloat16 while
-//               they are staged into LDS; each tile accumulates hi*hi + hi*lo + lo*hi on the
+//   presplit +  upper-triangle tiles of [A | B]^T [A | B] restricted to rows of A, so one launch
+//   gram_dma    gives H = A^T A and A^T B.  FP32 inputs are split once into hi + lo bfloat16
+//               (presplit, stored by column); each 256 x 256 tile streams both parts through
+//               LDS with direct global-to-LDS loads and accumulates hi*hi + hi*lo + lo*hi on the
 //               matrix cores (v_mfma_f32_16x16x32_bf16) in FP32.  The epilogue applies the
-//               rescale of Problem (5) directly: Q_ij = H_ij / (s_i s_j), Q_ii = 1, q = -A^T B / s,
-//               and mirrors the tile into the lower triangle.
+//               rescale of Problem (5) directly: Q_ij = H_ij / (s_i s_j), Q_ii = 1,
+//               q = -A^T B / s, and mirrors the tile into the lower triangle.  Split-K over the
+//               rows of A fills the GPU when there are few tiles; the partial tiles then go
+//               through gram_splitk_epilogue.
+//   batched     one workgroup per problem of an uneven batch, 128 x 128 tiles split while they
+//               are staged (gram_tile_bf16x3).
 //   gram_fma    the same product with plain FMAs in FP32 or FP64 (FP64 problems and the FP32
 //               accuracy cross-check).
-// Split-K over the rows of A is available for shapes with few output tiles; the partial tiles
-// then go through gram_splitk_epilogue.
 #include <algorithm>
 
 #include "common.hpp"
@@ -145,76 +148,70 @@ __device__ __forceinline__ GramPanelPtr panel_column(int64_t col, int64_t n, int
 }
 
 // Number of tiles (ti, tj), ti <= tj, in group (band, chunk).
-__device__ __forceinline__ int group_size(int band, int chunk, int tiles_a, int tiles_aug) {
+__host__ __device__ inline int group_size(int band, int chunk, int tiles_a, int tiles_aug) {
   const int r0 = band * GB_GROUP_ROWS;
-  const int r1 = min(r0 + GB_GROUP_ROWS, tiles_a);
+  const int r1 = r0 + GB_GROUP_ROWS < tiles_a ? r0 + GB_GROUP_ROWS : tiles_a;
   const int c0 = r0 + chunk * GB_GROUP_COLS;
-  const int c1 = min(c0 + GB_GROUP_COLS, tiles_aug);
+  const int c1 = c0 + GB_GROUP_COLS < tiles_aug ? c0 + GB_GROUP_COLS : tiles_aug;
   int cnt = 0;
   for (int ti = r0; ti < r1; ++ti) {
-    const int lo = max(c0, ti);
+    const int lo = c0 > ti ? c0 : ti;
     cnt += c1 > lo ? c1 - lo : 0;
   }
   return cnt;
 }
 
-// Tile of workgroup b under the XCD-grouped schedule; false if b has no tile.
-__device__ bool schedule_tile(int b, int tiles_a, int tiles_aug, int& ti, int& tj) {
-  const int xcd = b % GB_XCDS;
-  int slot = b / GB_XCDS;
+// Tile t of the grouped order: groups of 4 tile rows x 8 tile columns (band by band, chunk by
+// chunk), row-major inside a group, so neighbours in the order share panels.
+__device__ void grouped_tile(int t, int tiles_a, int tiles_aug, int& ti, int& tj) {
   const int bands = (tiles_a + GB_GROUP_ROWS - 1) / GB_GROUP_ROWS;
-  int g = 0;
   for (int band = 0; band < bands; ++band) {
     const int r0 = band * GB_GROUP_ROWS;
     const int chunks = (tiles_aug - r0 + GB_GROUP_COLS - 1) / GB_GROUP_COLS;
-    for (int chunk = 0; chunk < chunks; ++chunk, ++g) {
-      if (g % GB_XCDS != xcd) continue;
+    for (int chunk = 0; chunk < chunks; ++chunk) {
       const int sz = group_size(band, chunk, tiles_a, tiles_aug);
-      if (slot >= sz) {
-        slot -= sz;
+      if (t >= sz) {
+        t -= sz;
         continue;
       }
       const int c0 = r0 + chunk * GB_GROUP_COLS;
       const int c1 = min(c0 + GB_GROUP_COLS, tiles_aug);
       const int r1 = min(r0 + GB_GROUP_ROWS, tiles_a);
-      for (int t = r0; t < r1; ++t) {
-        const int lo = max(c0, t);
+      for (int r = r0; r < r1; ++r) {
+        const int lo = max(c0, r);
         const int w = c1 > lo ? c1 - lo : 0;
-        if (slot < w) {
-          ti = t;
-          tj = lo + slot;
-          return true;
+        if (t < w) {
+          ti = r;
+          tj = lo + t;
+          return;
         }
-        slot -= w;
+        t -= w;
       }
     }
   }
-  return false;
+  ti = tj = 0;  // not reached for t < ntiles
 }
 
-// Host mirror of the schedule: workgroups needed = 8 x the largest per-XCD tile count.
-static int schedule_blocks(int tiles_a, int tiles_aug) {
-  int per[GB_XCDS] = {0};
-  const int bands = (tiles_a + GB_GROUP_ROWS - 1) / GB_GROUP_ROWS;
-  int g = 0;
-  for (int band = 0; band < bands; ++band) {
-    const int r0 = band * GB_GROUP_ROWS;
-    const int chunks = (tiles_aug - r0 + GB_GROUP_COLS - 1) / GB_GROUP_COLS;
-    for (int chunk = 0; chunk < chunks; ++chunk, ++g) {
-      const int c0 = r0 + chunk * GB_GROUP_COLS;
-      const int c1 = std::min(c0 + GB_GROUP_COLS, tiles_aug);
-      const int r1 = std::min(r0 + GB_GROUP_ROWS, tiles_a);
-      int cnt = 0;
-      for (int ti = r0; ti < r1; ++ti) {
-        const int lo = std::max(c0, ti);
-        cnt += c1 > lo ? c1 - lo : 0;
-      }
-      per[g % GB_XCDS] += cnt;
-    }
-  }
-  int mx = 0;
-  for (int x = 0; x < GB_XCDS; ++x) mx = std::max(mx, per[x]);
-  return mx * GB_XCDS;
+// Work item of workgroup b: items are (split, tile) pairs, split-major over the grouped tile
+// order.  Workgroup b runs on XCD b % 8 (round-robin dispatch); XCD x takes the x-th contiguous
+// eighth of the item list, so each XCD holds a balanced share of neighbouring tiles and the
+// panels they share stay in its own L2.  False if b has no item.
+__device__ bool schedule_item(int b, int ntiles, int splits, int tiles_a, int tiles_aug, int& ti,
+                              int& tj, int& split) {
+  const int items = ntiles * splits;
+  const int per = (items + GB_XCDS - 1) / GB_XCDS;
+  const int slot = b / GB_XCDS;
+  if (slot >= per) return false;
+  const int idx = (b % GB_XCDS) * per + slot;
+  if (idx >= items) return false;
+  split = idx / ntiles;
+  grouped_tile(idx % ntiles, tiles_a, tiles_aug, ti, tj);
+  return true;
+}
+
+static int schedule_blocks(int ntiles, int splits) {
+  const int items = ntiles * splits;
+  return (items + GB_XCDS - 1) / GB_XCDS * GB_XCDS;
 }
 
 // One 128 x 128 tile of [A | B]^T [A | B] over rows [r_begin, r_end): px / py locate the two
@@ -328,39 +325,199 @@ __device__ __forceinline__ void gram_tile_bf16x3(f32x4 (&acc)[4][4], int64_t r_b
 
 }
 
-__global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
-    int64_t d, int64_t n, int64_t k, const float* __restrict__ A, int64_t lda,
-    const float* __restrict__ B, int64_t ldb, const double* __restrict__ s, float* __restrict__ Q,
-    float* __restrict__ q, float* __restrict__ partial, int tiles_a, int tiles_aug,
+// ---------------------------------------------------------------------------------------------
+// BF16x3 Gram with pre-split operands and direct-to-LDS loads (the single-problem path).
+//
+// presplit_kernel writes [A | B] once as two BF16 matrices (hi and lo of the split), stored by
+// column: column c is dpad consecutive values (zero past d, zero columns up to the padded width),
+// so the K direction of the Gram is contiguous and the main loop needs no bounds checks.
+//
+// gram_dma_kernel: 256 x 256 output tile per workgroup of 8 waves (2 x 4 waves of 128 x 64), K
+// staged 32 rows at a time in two LDS stages of 64 KB (Xh, Xl, Yh, Yl parts of 256 columns x 32
+// values).  Each stage is filled by global_load_lds_dwordx4 (16 bytes per lane straight into
+// LDS): the loads of step s+1 are issued right after the barrier of step s and land while the
+// waves run the 3 x 32 MFMAs (hi*hi + hi*lo + lo*hi, v_mfma_f32_16x16x32_bf16) of step s.
+// Inside a stage, the four 16-byte k-groups of a column are stored XOR-swizzled by bits 2..3 of
+// the column, so the fragment reads of 16 consecutive columns hit 16 distinct bank quads.  The
+// swizzle is applied on the global side: lane i of a load instruction fetches the k-group that
+// belongs at LDS position i.  One barrier per step: waits are explicit (vmcnt for this wave's
+// own loads of the step, lgkmcnt for its last LDS reads) and the barrier is a bare s_barrier,
+// so the loads of the next step stay in flight across it.
+// ---------------------------------------------------------------------------------------------
+constexpr int PS_T = 64;
+constexpr int GD_T = 256;
+constexpr int GD_BK = 32;
+constexpr int GD_NT = 512;
+constexpr int GD_PART = GD_T * GD_BK;        // bf16 per part
+constexpr int GD_STAGE = 4 * GD_PART;
+constexpr int GD_LDS_BYTES = 2 * GD_STAGE * 2;
+constexpr int GD_CPI = 512 / GD_BK;          // columns per load instruction (1 KB)
+constexpr int GD_IPP = GD_T / GD_CPI;        // instructions per part
+constexpr int GD_IPW = 4 * GD_IPP / (GD_NT / 64);
+constexpr int GD_MT = 8, GD_NTL = 4;         // 16 x 16 blocks per wave (rows, columns)
+
+typedef __attribute__((address_space(1))) void gd_gvoid;
+typedef __attribute__((address_space(3))) void gd_lvoid;
+
+__device__ __forceinline__ void gb_split_pair(float v0, float v1, uint32_t& h, uint32_t& l) {
+  const f32x2 x = {v0, v1};
+  const bf16x2 hb = __builtin_convertvector(x, bf16x2);
+  const f32x2 hf = __builtin_convertvector(hb, f32x2);
+  const bf16x2 lb = __builtin_convertvector(x - hf, bf16x2);
+  h = __builtin_bit_cast(uint32_t, hb);
+  l = __builtin_bit_cast(uint32_t, lb);
+}
+
+// Grid (ncols_pad / 64, dpad / 64): a 64 x 64 block through LDS, transposed on the way out.
+__global__ __launch_bounds__(256) void presplit_kernel(int64_t d, int64_t n, int64_t k,
+                                                       const float* __restrict__ A, int64_t lda,
+                                                       const float* __restrict__ B, int64_t ldb,
+                                                       int64_t dpad, uint16_t* __restrict__ Ph,
+                                                       uint16_t* __restrict__ Pl) {
+  __shared__ float t[PS_T][PS_T + 1];
+  const int tid = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * PS_T, r0 = (int64_t)blockIdx.y * PS_T;
+  // a block inside A (or inside B) with 16-byte aligned rows loads 4 columns per lane
+  const float* vbase = nullptr;
+  int64_t vld = 0;
+  if (c0 + PS_T <= n) {
+    vbase = A + c0;
+    vld = lda;
+  } else if (c0 >= n && c0 + PS_T <= n + k) {
+    vbase = B + (c0 - n);
+    vld = ldb;
+  }
+  if (vbase != nullptr && ((vld & 3) != 0 || (((uintptr_t)vbase) & 15) != 0)) vbase = nullptr;
+  if (vbase != nullptr) {
+    const int cq = tid & 15;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int rr = (tid >> 4) + 16 * u;
+      const int64_t r = r0 + rr;
+      f32x4 v = (f32x4){0.f, 0.f, 0.f, 0.f};
+      if (r < d) v = *(const f32x4*)(vbase + r * vld + 4 * cq);
+      t[rr][4 * cq + 0] = v[0];
+      t[rr][4 * cq + 1] = v[1];
+      t[rr][4 * cq + 2] = v[2];
+      t[rr][4 * cq + 3] = v[3];
+    }
+  } else {
+    const int tc = tid & (PS_T - 1);
+    const int64_t c = c0 + tc;
+    const float* colp = nullptr;
+    int64_t ld = 0;
+    if (c < n) {
+      colp = A + c;
+      ld = lda;
+    } else if (c < n + k) {
+      colp = B + (c - n);
+      ld = ldb;
+    }
+    for (int rr = tid >> 6; rr < PS_T; rr += 4) {
+      const int64_t r = r0 + rr;
+      t[rr][tc] = (colp != nullptr && r < d) ? colp[r * ld] : 0.f;
+    }
+  }
+  __syncthreads();
+  // 8 lanes per column, each 8 consecutive rows: every group of 8 lanes writes 128 contiguous
+  // bytes of Ph and of Pl
+  const int oct = tid & 7;
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    const int cl = pass * 32 + (tid >> 3);
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      gb_split_pair(t[oct * 8 + 2 * u][cl], t[oct * 8 + 2 * u + 1][cl], h[u], l[u]);
+    const int64_t o = (c0 + cl) * dpad + r0 + oct * 8;
+    *(u32x4*)(Ph + o) = (u32x4){h[0], h[1], h[2], h[3]};
+    *(u32x4*)(Pl + o) = (u32x4){l[0], l[1], l[2], l[3]};
+  }
+}
+
+__global__ __launch_bounds__(GD_NT, 1) void gram_dma_kernel(
+    int64_t n, int64_t k, const uint16_t* __restrict__ Ph, const uint16_t* __restrict__ Pl,
+    int64_t dpad, const double* __restrict__ s, float* __restrict__ Q, float* __restrict__ q,
+    float* __restrict__ partial, int tiles_a, int tiles_aug, int ntiles, int nsplit,
     int64_t rows_per_split) {
   extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
-
-  int ti, tj;
-  if (!schedule_tile(blockIdx.x, tiles_a, tiles_aug, ti, tj)) return;
+  int ti, tj, split;
+  if (!schedule_item(blockIdx.x, ntiles, nsplit, tiles_a, tiles_aug, ti, tj, split)) return;
   const bool diag = (ti == tj);
-  const int64_t i0 = (int64_t)ti * GB_BM, j0 = (int64_t)tj * GB_BM;
-  const int64_t r_begin = (int64_t)blockIdx.y * rows_per_split;
-  const int64_t r_end = r_begin + rows_per_split < d ? r_begin + rows_per_split : d;
+  const int64_t i0 = (int64_t)ti * GD_T, j0 = (int64_t)tj * GD_T;
+  const int64_t r_begin = (int64_t)split * rows_per_split;
+  const int64_t r_end = r_begin + rows_per_split < dpad ? r_begin + rows_per_split : dpad;
+  const int nsteps = r_end > r_begin ? (int)((r_end - r_begin) / GD_BK) : 0;
 
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int lc = tid & 127;
-  const GramPanelPtr px = panel_column(i0 + lc, n, k, A, lda, B, ldb);
-  const GramPanelPtr py = panel_column(j0 + lc, n, k, A, lda, B, ldb);
-  f32x4 acc[4][4];
-  gram_tile_bf16x3(acc, r_begin, r_end, px, py, diag, lds);
-  const int wm = (wave >> 1) * 64;
-  const int wn = (wave & 1) * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // this lane's part of each load instruction: column (lane / 4) of the instruction's 16, the
+  // k-group that belongs at LDS position lane % 4
+  const int lcol = lane >> 2;
+  const int lg = (lane & 3) ^ ((lcol >> 2) & 3);
+  auto issue = [&](int step, int stage) {
+#pragma unroll
+    for (int u = 0; u < GD_IPW; ++u) {
+      const int inst = wave * GD_IPW + u;
+      const int part = inst / GD_IPP;
+      const int icol0 = (inst % GD_IPP) * GD_CPI;
+      const uint16_t* base = (part & 1) ? Pl : Ph;
+      const int64_t gc = ((part < 2) ? i0 : j0) + icol0 + lcol;
+      const uint16_t* src = base + gc * dpad + r_begin + (int64_t)step * GD_BK + 8 * lg;
+      uint16_t* dst = lds + stage * GD_STAGE + part * GD_PART + icol0 * GD_BK;
+      __builtin_amdgcn_global_load_lds((gd_gvoid*)src, (gd_lvoid*)dst, 16, 0, 0);
+    }
+  };
 
-  // D fragment layout of the 16x16 MFMA: lane holds column (lane & 15), rows 4*(lane>>4)+e.
+  f32x4 acc[GD_MT][GD_NTL];
+#pragma unroll
+  for (int a = 0; a < GD_MT; ++a)
+#pragma unroll
+    for (int b = 0; b < GD_NTL; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
+  const int fr = lane & 15;
+  const int fp = (lane >> 4) ^ ((fr >> 2) & 3);  // physical k-group of this lane's fragment
+
+  if (nsteps > 0) issue(0, 0);
+  for (int step = 0; step < nsteps; ++step) {
+    // own loads of this step done (vmcnt 0), own LDS reads of the previous step done
+    // (lgkmcnt 0), then the bare barrier: every wave's part of the stage has landed and the
+    // other stage is free for the next step's loads.
+    __builtin_amdgcn_s_waitcnt(0x0070);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (step + 1 < nsteps) issue(step + 1, (step + 1) & 1);
+    const uint16_t* st = lds + (step & 1) * GD_STAGE;
+    bf16x8 bh[GD_NTL], bl[GD_NTL];
+#pragma unroll
+    for (int t = 0; t < GD_NTL; ++t) {
+      const int yo = (wn + t * 16 + fr) * GD_BK + 8 * fp;
+      bh[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&st[2 * GD_PART + yo]);
+      bl[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&st[3 * GD_PART + yo]);
+    }
+#pragma unroll
+    for (int a = 0; a < GD_MT; ++a) {
+      const int xo = (wm + a * 16 + fr) * GD_BK + 8 * fp;
+      const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u32x4*)&st[xo]);
+      const bf16x8 al = __builtin_bit_cast(bf16x8, *(const u32x4*)&st[GD_PART + xo]);
+#pragma unroll
+      for (int b = 0; b < GD_NTL; ++b) {
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
+      }
+    }
+  }
+
+  // D fragment layout of the 16x16 FP32 MFMA: lane holds column (lane & 15), rows
+  // 4 (lane >> 4) + e.
   const int out_col = lane & 15;
   const int out_row = (lane >> 4) * 4;
   if (partial == nullptr) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < GD_MT; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < GD_NTL; ++b)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int64_t i = i0 + wm + a * 16 + out_row + e;
@@ -368,21 +525,19 @@ __global__ __launch_bounds__(256, 2) void gram_bf16x3_kernel(
           gram_emit<float, float>(i, j, acc[a][b][e], n, k, s, Q, q, diag);
         }
   } else {
-    // partial tiles are indexed by (ti, tj) in the plain row-major tile order
     int tile = 0;
     for (int t = 0; t < ti; ++t) tile += tiles_aug - t;
     tile += tj - ti;
-    const int ntiles = tiles_a * tiles_aug - tiles_a * (tiles_a - 1) / 2;
-    float* dst = partial + ((int64_t)blockIdx.y * ntiles + tile) * (GB_BM * GB_BM);
+    float* dst = partial + ((int64_t)split * ntiles + tile) * (GD_T * GD_T);
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < GD_MT; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < GD_NTL; ++b)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int li = wm + a * 16 + out_row + e;
           const int lj = wn + b * 16 + out_col;
-          dst[li * GB_BM + lj] = acc[a][b][e];
+          dst[li * GD_T + lj] = acc[a][b][e];
         }
   }
 }
@@ -500,20 +655,22 @@ hipError_t launch_batched_gram(const BatchDesc* desc, int64_t count, const float
 }
 
 // Sum of split-K partial tiles in fixed split order, then the rescale epilogue.
-__global__ __launch_bounds__(256) void gram_splitk_epilogue_kernel(
+// Sum of the split-K partial tiles and the rescale epilogue: block (tile, row of the tile), one
+// thread per column (TILE = 256 threads), so every partial row is one coalesced read.
+template <int TILE>
+__global__ __launch_bounds__(TILE) void gram_splitk_epilogue_kernel(
     int64_t n, int64_t k, const float* __restrict__ partial, int nsplit, int ntiles,
     int tiles_aug, const double* __restrict__ s, float* __restrict__ Q, float* __restrict__ q) {
   int ti, tj;
   decode_tile(blockIdx.x, tiles_aug, ti, tj);
   const bool diag = (ti == tj);
-  const int64_t i0 = (int64_t)ti * GB_BM, j0 = (int64_t)tj * GB_BM;
-  for (int e = threadIdx.x; e < GB_BM * GB_BM; e += 256) {
-    float acc = 0.f;
-    for (int sp = 0; sp < nsplit; ++sp)
-      acc += partial[((int64_t)sp * ntiles + blockIdx.x) * (GB_BM * GB_BM) + e];
-    const int li = e / GB_BM, lj = e % GB_BM;
-    gram_emit<float, float>(i0 + li, j0 + lj, acc, n, k, s, Q, q, diag);
-  }
+  const int li = blockIdx.y, lj = threadIdx.x;
+  const int64_t e = (int64_t)li * TILE + lj;
+  float acc = 0.f;
+  for (int sp = 0; sp < nsplit; ++sp)
+    acc += partial[((int64_t)sp * ntiles + blockIdx.x) * (TILE * TILE) + e];
+  gram_emit<float, float>((int64_t)ti * TILE + li, (int64_t)tj * TILE + lj, acc, n, k, s, Q, q,
+                          diag);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -617,40 +774,72 @@ static void gram_tiles(int64_t n, int64_t k, int bm, int& tiles_a, int& tiles_au
   ntiles = tiles_a * tiles_aug - tiles_a * (tiles_a - 1) / 2;
 }
 
-int gram_bf16x3_splits(int64_t d, int64_t n, int64_t k) {
-  int ta, taug, nt;
-  gram_tiles(n, k, GB_BM, ta, taug, nt);
+// Layout of the single-problem BF16x3 workspace: Ph, Pl (pre-split [A | B]) and, with split-K,
+// the partial tiles.
+struct GramDmaPlan {
+  int tiles_a, tiles_aug, ntiles, splits;
+  int64_t dpad, ncols_pad, rows_per_split;
+  size_t split_bytes, partial_bytes;
+};
+
+static GramDmaPlan gram_dma_plan(int64_t d, int64_t n, int64_t k) {
+  GramDmaPlan p;
+  gram_tiles(n, k, GD_T, p.tiles_a, p.tiles_aug, p.ntiles);
+  p.dpad = (d + PS_T - 1) / PS_T * PS_T;
+  p.ncols_pad = (int64_t)p.tiles_aug * GD_T;
+  // One workgroup per compute unit, 256 at a time: split the rows of A into s parts where
+  // that shortens the critical path, rounds(s) / s with rounds = ceil(tiles * s / 256), with a
+  // small charge per split for the partial tiles; each part keeps at least 8 K steps.
+  int64_t max_splits = p.dpad / (8 * GD_BK);
+  if (max_splits > 16) max_splits = 16;
   int splits = 1;
-  // Fewer tiles than about two per compute unit: split the K loop (rows of A).
-  while (nt * splits < 512 && d / (splits * 2) >= 4 * GB_BK && splits < 32) splits *= 2;
-  return splits;
+  double best = 1e30;
+  for (int sp = 1; sp <= (max_splits > 1 ? max_splits : 1); ++sp) {
+    const double rounds = (double)(((int64_t)p.ntiles * sp + 255) / 256);
+    const double cost = rounds / sp * (1.0 + 0.05 * sp);
+    if (cost < best) {
+      best = cost;
+      splits = sp;
+    }
+  }
+  int64_t rows = (p.dpad + splits - 1) / splits;
+  rows = (rows + GD_BK - 1) / GD_BK * GD_BK;
+  p.splits = (int)((p.dpad + rows - 1) / rows);
+  p.rows_per_split = rows;
+  p.split_bytes = sizeof(uint16_t) * (size_t)p.ncols_pad * (size_t)p.dpad;
+  p.partial_bytes = p.splits > 1 ? sizeof(float) * (size_t)p.splits * p.ntiles * GD_T * GD_T : 0;
+  return p;
 }
 
+int gram_bf16x3_splits(int64_t d, int64_t n, int64_t k) { return gram_dma_plan(d, n, k).splits; }
+
 size_t gram_bf16x3_ws_bytes(int64_t d, int64_t n, int64_t k) {
-  int ta, taug, nt;
-  gram_tiles(n, k, GB_BM, ta, taug, nt);
-  const int splits = gram_bf16x3_splits(d, n, k);
-  return splits > 1 ? sizeof(float) * (size_t)splits * nt * GB_BM * GB_BM : 0;
+  const GramDmaPlan p = gram_dma_plan(d, n, k);
+  return 2 * p.split_bytes + p.partial_bytes;
 }
 
 hipError_t launch_gram_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
                               const float* B, int64_t ldb, const double* s, float* Q, float* q,
                               float* ws, hipStream_t st) {
-  int ta, taug, nt;
-  gram_tiles(n, k, GB_BM, ta, taug, nt);
-  const int splits = gram_bf16x3_splits(d, n, k);
-  int64_t rows = (d + splits - 1) / splits;
-  rows = (rows + GB_BK - 1) / GB_BK * GB_BK;
-  const int blocks = schedule_blocks(ta, taug);
-  dim3 grid((unsigned)blocks, (unsigned)splits);
-  hipError_t e = hipFuncSetAttribute((const void*)gram_bf16x3_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, GB_LDS_BYTES);
+  const GramDmaPlan p = gram_dma_plan(d, n, k);
+  uint16_t* Ph = (uint16_t*)ws;
+  uint16_t* Pl = (uint16_t*)((char*)ws + p.split_bytes);
+  float* partial = p.splits > 1 ? (float*)((char*)ws + 2 * p.split_bytes) : nullptr;
+  dim3 g0((unsigned)(p.ncols_pad / PS_T), (unsigned)(p.dpad / PS_T));
+  hipLaunchKernelGGL(presplit_kernel, g0, dim3(256), 0, st, d, n, k, A, lda, B, ldb, p.dpad, Ph,
+                     Pl);
+  const int blocks = schedule_blocks(p.ntiles, p.splits);
+  dim3 grid((unsigned)blocks);
+  hipError_t e = hipFuncSetAttribute((const void*)gram_dma_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, GD_LDS_BYTES);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gram_bf16x3_kernel, grid, dim3(256), GB_LDS_BYTES, st, d, n, k, A, lda, B,
-                     ldb, s, Q, q, splits > 1 ? ws : (float*)nullptr, ta, taug, rows);
-  if (splits > 1)
-    hipLaunchKernelGGL(gram_splitk_epilogue_kernel, dim3((unsigned)nt), dim3(256), 0, st, n, k,
-                       (const float*)ws, splits, nt, taug, s, Q, q);
+  hipLaunchKernelGGL(gram_dma_kernel, grid, dim3(GD_NT), GD_LDS_BYTES, st, n, k,
+                     (const uint16_t*)Ph, (const uint16_t*)Pl, p.dpad, s, Q, q, partial, p.tiles_a,
+                     p.tiles_aug, p.ntiles, p.splits, p.rows_per_split);
+  if (p.splits > 1)
+    hipLaunchKernelGGL(gram_splitk_epilogue_kernel<GD_T>, dim3((unsigned)p.ntiles, GD_T),
+                       dim3(GD_T), 0, st, n, k, (const float*)partial, p.splits, p.ntiles,
+                       p.tiles_aug, s, Q, q);
   return hipGetLastError();
 }
 
