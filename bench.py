@@ -2,7 +2,7 @@
 
 One step = the whole path of Algorithm 1 on one resident instance of the large single
 right-hand-side workload (A 20000 x 5000 FP32, U[0,1] entries, 70 % zeros in x, 1 % noise):
-column scales -> BF16x3 Gram with fused rescale -> Algorithm 2 (whole-GPU persistent solver) ->
+column scales -> BF16x3 Gram with fused rescale -> Algorithm 2 (whole-GPU solver, Q held in registers) ->
 FP64 KKT check and refinement step.  The inputs are generated on the host, copied to HBM before
 the timed region, and every step writes into preallocated buffers (no allocation while timed).
 
@@ -202,10 +202,14 @@ def main():
                  "peak": round(PEAK_BF16X3_TFLOPS, 1), "unit": "TFLOP/s",
                  "frac": round(gram_tf / PEAK_BF16X3_TFLOPS, 4),
                  "traffic": traffic_record("gram_bf16x3_kernel", "gram.hip")}
-    roof_solve = {"kernel": "solve_persistent_kernel", "bound": "hbm",
+    solver = N.solver_name(n, k, N.F32)
+    solve_kernel = {"regq": "solve_regq_kernel", "persistent": "solve_persistent_kernel"}.get(
+        solver, "solve_" + solver + "_kernel")
+    roof_solve = {"kernel": solve_kernel, "bound": "hbm",
                   "achieved": round(solve_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                   "frac": round(solve_gbs / PEAK_HBM_GBS, 4),
-                  "traffic": traffic_record("solve_persistent_kernel", "solve_persistent.hip")}
+                  "traffic": traffic_record(solve_kernel, {"solve_regq_kernel": "solve_regq.hip"}
+                                            .get(solve_kernel, "solve_persistent.hip"))}
     dominant, other = (roof_gram, roof_solve) if ms["gram"] >= ms["solve"] else (roof_solve, roof_gram)
 
     out = {

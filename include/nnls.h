@@ -133,8 +133,10 @@ int nnls_gram_rescaled(int64_t d, int64_t n, int64_t k, const void* A, int64_t l
  *             of exact gradient recomputations); 4 n bytes each for FP32 Q.  This is the
  *             S(n)-weighted work of the complexity lemma of Section 4.
  * The workspace size depends on the solver chosen for the shape; NNLS_OP_SOLVE sizes it for
- * the current device.  The environment variable NNLS_SOLVER=wg|persistent forces the
- * one-workgroup-per-column or the whole-GPU single-right-hand-side solver where valid.
+ * the current device.  The environment variable NNLS_SOLVER=wg|regq|persistent|mrhs forces
+ * the one-workgroup-per-column solver, the whole-GPU single-right-hand-side solver with Q held
+ * in registers (n <= 5120) or streamed from memory, or the matrix-core many-right-hand-side
+ * solver, where valid.
  */
 int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, const double* s,
                double tol, int32_t max_iter, const void* Y0, void* X, int32_t* iters,
@@ -275,6 +277,13 @@ int nnls_mlp_inputs(int64_t n, int64_t k, const float* q, const float* Y, float*
 size_t nnls_warm_start_workspace_bytes(int64_t n, int64_t k);
 int nnls_warm_start(int64_t n, int64_t k, const float* Q, const float* q, const void* blob,
                     float* Y0, int32_t* fell_back, void* ws, size_t ws_bytes, void* stream);
+
+/* Which solver nnls_solve uses for this shape on the current device: "regq" (one right-hand
+ * side, Q held in the register file of the whole GPU), "persistent" (one right-hand side, Q
+ * streamed from memory), "mrhs" (many right-hand sides on the matrix cores) or "wg" (one
+ * workgroup per column); "" if the shape is not supported.  Host function; the string is
+ * static. */
+const char* nnls_solver_name(int64_t n, int64_t k, int dtype);
 
 /* Text of the last HIP error seen by this thread (empty if none). */
 const char* nnls_last_hip_error(void);

@@ -46,13 +46,14 @@ size_t prepare_ws(int64_t d, int64_t n, int64_t k, int mode) {
 }
 
 // Solver choice (FP32):
-//   one right-hand side with n >= kPersistentMinN  -> persistent whole-GPU kernel
+//   one right-hand side with n >= kPersistentMinN  -> whole-GPU kernel, Q held in registers
+//                                                     (n <= 5120) or streamed (larger n)
 //   several right-hand sides, n small enough for LDS -> matrix-core many-RHS kernel
 //   otherwise (and FP64)                             -> one workgroup per column
-// NNLS_SOLVER=wg|persistent|mrhs in the environment forces a choice where it is valid.
+// NNLS_SOLVER=wg|persistent|regq|mrhs in the environment forces a choice where it is valid.
 constexpr int64_t kPersistentMinN = 1536;
 
-enum SolverKind { SOLVER_WG = 0, SOLVER_PERSISTENT = 1, SOLVER_MRHS = 2 };
+enum SolverKind { SOLVER_WG = 0, SOLVER_PERSISTENT = 1, SOLVER_MRHS = 2, SOLVER_REGQ = 3 };
 
 int solver_override() {
   const char* v = getenv("NNLS_SOLVER");
@@ -60,17 +61,21 @@ int solver_override() {
   if (strcmp(v, "wg") == 0) return SOLVER_WG;
   if (strcmp(v, "persistent") == 0) return SOLVER_PERSISTENT;
   if (strcmp(v, "mrhs") == 0) return SOLVER_MRHS;
+  if (strcmp(v, "regq") == 0) return SOLVER_REGQ;
   return -1;
 }
 
 SolverKind pick_solver(int64_t n, int64_t k, int dt) {
   const bool can_p = dt == NNLS_F32 && nnls::solve_persistent_supported(n, k);
+  const bool can_r = dt == NNLS_F32 && nnls::solve_regq_supported(n, k);
   const bool can_m = dt == NNLS_F32 && nnls::solve_mrhs_supported(n, k);
   const bool can_w = nnls::solve_wg_lds_bytes(n, (int)elem_size(dt)) <= kMaxLds;
   const int o = solver_override();
   if (o == SOLVER_PERSISTENT && can_p) return SOLVER_PERSISTENT;
+  if (o == SOLVER_REGQ && can_r) return SOLVER_REGQ;
   if (o == SOLVER_MRHS && can_m) return SOLVER_MRHS;
   if (o == SOLVER_WG && can_w) return SOLVER_WG;
+  if (can_r && (n >= kPersistentMinN || !can_w)) return SOLVER_REGQ;
   if (can_p && (n >= kPersistentMinN || !can_w)) return SOLVER_PERSISTENT;
   if (can_m) return SOLVER_MRHS;
   return SOLVER_WG;
@@ -78,6 +83,7 @@ SolverKind pick_solver(int64_t n, int64_t k, int dt) {
 
 bool solver_supported(int64_t n, int64_t k, int dt) {
   return (dt == NNLS_F32 && nnls::solve_persistent_supported(n, k)) ||
+         (dt == NNLS_F32 && nnls::solve_regq_supported(n, k)) ||
          (dt == NNLS_F32 && nnls::solve_mrhs_supported(n, k)) ||
          nnls::solve_wg_lds_bytes(n, (int)elem_size(dt)) <= kMaxLds;
 }
@@ -86,6 +92,8 @@ size_t solve_ws(int64_t n, int64_t k, int dt) {
   switch (pick_solver(n, k, dt)) {
     case SOLVER_PERSISTENT:
       return align_up(nnls::solve_persistent_ws_bytes(n));
+    case SOLVER_REGQ:
+      return align_up(nnls::solve_regq_ws_bytes(n));
     case SOLVER_MRHS:
       return align_up(nnls::solve_mrhs_ws_bytes());
     default:
@@ -98,6 +106,16 @@ size_t solve_ws(int64_t n, int64_t k, int dt) {
 extern "C" {
 
 const char* nnls_last_hip_error(void) { return g_last_hip_error.c_str(); }
+
+const char* nnls_solver_name(int64_t n, int64_t k, int dtype) {
+  if (n < 1 || k < 1 || !valid_dtype(dtype) || !solver_supported(n, k, dtype)) return "";
+  switch (pick_solver(n, k, dtype)) {
+    case SOLVER_REGQ: return "regq";
+    case SOLVER_PERSISTENT: return "persistent";
+    case SOLVER_MRHS: return "mrhs";
+    default: return "wg";
+  }
+}
 
 const char* nnls_version(void) { return "nnls-mi355x 0.1 (gfx950)"; }
 
@@ -216,6 +234,10 @@ int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, co
   if (kind == SOLVER_MRHS) {
     if (((uintptr_t)Q & 15) != 0) return NNLS_E_ARG;  // rows are read as 16-byte vectors
     e = nnls::launch_solve_mrhs(n, k, (const float*)Q, (const float*)q, s, tol, mi,
+                                (const float*)Y0, (float*)X, iters, kkt, status, rows_read, ws,
+                                st);
+  } else if (kind == SOLVER_REGQ) {
+    e = nnls::launch_solve_regq(n, (const float*)Q, (const float*)q, s, tol, mi,
                                 (const float*)Y0, (float*)X, iters, kkt, status, rows_read, ws,
                                 st);
   } else if (kind == SOLVER_PERSISTENT) {

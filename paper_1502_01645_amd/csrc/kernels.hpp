@@ -52,6 +52,14 @@ hipError_t launch_solve_wg(int64_t n, int64_t k, const T* Q, const T* q, const d
                            double* kkt, int32_t* status, int64_t* rows_read, T* ws,
                            hipStream_t st);
 
+// solve_regq.hip (one right-hand side, Q held in the register file of the whole GPU)
+bool solve_regq_supported(int64_t n, int64_t k);
+size_t solve_regq_ws_bytes(int64_t n);
+hipError_t launch_solve_regq(int64_t n, const float* Q, const float* q, const double* s,
+                             double tol, int max_iter, const float* Y0, float* X, int32_t* iters,
+                             double* kkt, int32_t* status, int64_t* rows_read, void* ws,
+                             hipStream_t st);
+
 // solve_persistent.hip
 bool solve_persistent_supported(int64_t n, int64_t k);
 size_t solve_persistent_ws_bytes(int64_t n);

@@ -25,6 +25,7 @@
 // is double-buffered by iteration parity: phase 2 reads the current copy (every workgroup needs
 // it for the clipped set) while owners write the next one.
 #include "common.hpp"
+#include "grid_sync.hpp"
 #include "kernels.hpp"
 
 namespace nnls {
@@ -33,25 +34,10 @@ constexpr int SP_NT = 512;     // threads per workgroup (8 waves)
 constexpr int SP_NW = SP_NT / kWave;
 constexpr int SP_CB = 1024;    // columns per block in phase 1 (4 per thread, two row halves)
 constexpr int SP_CHUNK = 64;   // entries per owner chunk (one wave, one 64-bit mask word)
-constexpr int SP_GROUPS = 8;   // barrier arrival groups
-constexpr int SP_BAR_WORDS = 1024;
 constexpr int SP_TPT = 32;     // clip thresholds held per thread: n <= SP_NT * SP_TPT
 constexpr int64_t SP_MAX_N = (int64_t)SP_NT * SP_TPT;
 constexpr size_t SP_MAX_LDS = 160 * 1024;
 constexpr int SP_RPT = 4;      // row-range entries per thread in phase 1: n / R <= SP_NT * SP_RPT
-
-__device__ __forceinline__ float ld_sc(const float* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_sc(float* p, float v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t ld_sc(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_sc(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 struct SpArgs {
   int n, G, nb, R, nw, rows_max;
@@ -72,36 +58,6 @@ struct SpArgs {
   float *part, *scal;
   unsigned* bar;
 };
-
-// Grid barrier.  Every wave first waits for its own sc1 stores, so once all workgroups have
-// arrived their published data is visible at the coherence point.  Counters only grow, so no
-// reset can race with a later arrival; epoch is this workgroup's count of barriers passed.
-__device__ __forceinline__ void grid_barrier(unsigned* bar, int G, unsigned& epoch) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int ngroups = G < SP_GROUPS ? G : SP_GROUPS;
-    const int grp = blockIdx.x % ngroups;
-    const unsigned gsize = (unsigned)(G / ngroups + (grp < G % ngroups ? 1 : 0));
-    unsigned* gen = bar;
-    unsigned* top = bar + 32;
-    unsigned* gc = bar + 64 + 32 * grp;
-    const unsigned target = epoch + 1;
-    const unsigned a = __hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (a == gsize * target - 1) {
-      const unsigned b =
-          __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (b == (unsigned)ngroups * target - 1)
-        __hip_atomic_store(gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
-      __builtin_amdgcn_s_sleep(1);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  }
-  epoch += 1;
-  __syncthreads();
-}
 
 __device__ __forceinline__ float sp_block_sum(float v, float* red) {
   return block_sum<float, SP_NT>(v, red);
@@ -518,8 +474,8 @@ __global__ __launch_bounds__(SP_NT) void solve_persistent_kernel(SpArgs A) {
   }
 }
 
-__global__ void solve_persistent_init_kernel(unsigned* bar) {
-  for (int i = threadIdx.x; i < SP_BAR_WORDS; i += blockDim.x) bar[i] = 0u;
+__global__ void grid_barrier_init_kernel(unsigned* bar) {
+  for (int i = threadIdx.x; i < GS_BAR_WORDS; i += blockDim.x) bar[i] = 0u;
 }
 
 // ---- host side ------------------------------------------------------------------------------
@@ -567,7 +523,7 @@ size_t solve_persistent_ws_bytes(int64_t n) {
   b += 2 * (2 * (sizeof(uint64_t) * P.nw + 256)); // masks (two copies)
   b += sizeof(float) * (size_t)P.R * n + 256;     // partials
   b += sizeof(float) * 8 * P.G + 256;             // per-workgroup scalars
-  b += sizeof(unsigned) * SP_BAR_WORDS + 256;     // barrier words
+  b += sizeof(unsigned) * GS_BAR_WORDS + 256;     // barrier words
   return b + 1024;
 }
 
@@ -600,7 +556,7 @@ hipError_t launch_solve_persistent(int64_t n, const float* Q, const float* q, co
     p += (bytes + 255) / 256 * 256;
     return (void*)r;
   };
-  A.bar = (unsigned*)take(sizeof(unsigned) * SP_BAR_WORDS);
+  A.bar = (unsigned*)take(sizeof(unsigned) * GS_BAR_WORDS);
   for (int b = 0; b < 2; ++b) {
     A.y[b] = (float*)take(sizeof(float) * n);
     A.g[b] = (float*)take(sizeof(float) * n);
@@ -620,7 +576,7 @@ hipError_t launch_solve_persistent(int64_t n, const float* Q, const float* q, co
                                                    SP_NT, P.lds);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL(solve_persistent_init_kernel, dim3(1), dim3(256), 0, st, A.bar);
+  hipLaunchKernelGGL(grid_barrier_init_kernel, dim3(1), dim3(256), 0, st, A.bar);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   void* args[] = {&A};

@@ -99,6 +99,8 @@ def lib():
         L.nnls_warm_start_workspace_bytes.restype = _sz
         L.nnls_warm_start.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
         L.nnls_warm_start.restype = ctypes.c_int
+        L.nnls_solver_name.argtypes = [_i64, _i64, ctypes.c_int]
+        L.nnls_solver_name.restype = ctypes.c_char_p
         L.nnls_last_hip_error.argtypes = []
         L.nnls_last_hip_error.restype = ctypes.c_char_p
         L.nnls_version.argtypes = []
@@ -129,6 +131,11 @@ def _dtype_code(t: torch.Tensor) -> int:
     if t.dtype == torch.float64:
         return F64
     raise NNLSError(f"unsupported dtype {t.dtype}")
+
+
+def solver_name(n: int, k: int, dtype: int = F32) -> str:
+    """The solver nnls_solve picks for this shape on the current device."""
+    return lib().nnls_solver_name(n, k, dtype).decode()
 
 
 def workspace_bytes(op: int, d: int, n: int, k: int, mode: int, dtype: int) -> int:

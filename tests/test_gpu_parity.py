@@ -258,18 +258,19 @@ def test_warm_start_at_solution():
     assert np.array_equal(host(Y2), host(Y))
 
 
-# ---------------------------------------------------------------------------- persistent solver
-@pytest.fixture
-def force_persistent(monkeypatch):
-    monkeypatch.setenv("NNLS_SOLVER", "persistent")
-    yield
+# ---------------------------------------------------------------------------- whole-GPU solvers
+# "regq" keeps Q in the register file of the whole GPU (n <= 5120), "persistent" streams it.
+@pytest.fixture(params=["regq", "persistent"])
+def whole_gpu(request, monkeypatch):
+    monkeypatch.setenv("NNLS_SOLVER", request.param)
+    yield request.param
     monkeypatch.delenv("NNLS_SOLVER", raising=False)
 
 
-@pytest.mark.parametrize("n", [512, 1024, 2000])
-def test_persistent_steps_match_oracle(n, force_persistent):
-    """Whole-GPU solver, one update from the oracle's state (as for the per-column solver)."""
-    say(f"persistent single steps n={n}")
+@pytest.mark.parametrize("n", [512, 1024, 2000, 5000])
+def test_persistent_steps_match_oracle(n, whole_gpu):
+    """Whole-GPU solvers, one update from the oracle's state (as for the per-column solver)."""
+    say(f"{whole_gpu} single steps n={n}")
     A, B = _uniform_case(21, 2 * n, n, 1)
     Q, q, s = N.prepare(dev(A), dev(B))
     Qh, qh = host(Q).astype(np.float64), host(q).astype(np.float64)[:, 0]
@@ -287,28 +288,20 @@ def test_persistent_steps_match_oracle(n, force_persistent):
         assert err <= 8 * n * eps * scale, (m, err / scale)
 
 
-@pytest.mark.parametrize("d,n,seed", [(1500, 512, 4), (6000, 2000, 5), (9000, 3072, 6)])
-def test_persistent_end_to_end(d, n, seed):
-    """Large single right-hand sides (n >= 1536 takes the whole-GPU solver by default)."""
-    say(f"persistent e2e d={d} n={n}")
+@pytest.mark.parametrize("d,n,seed", [(1500, 512, 4), (6000, 2000, 5), (9000, 3072, 6),
+                                      (12000, 4100, 7)])
+def test_persistent_end_to_end(d, n, seed, whole_gpu):
+    """Large single right-hand sides (n >= 1536 takes a whole-GPU solver by default)."""
+    say(f"{whole_gpu} e2e d={d} n={n}")
     A, b, _ = W.make_large(seed=seed, d=d, n=n)
-    import os
-    old = os.environ.get("NNLS_SOLVER")
-    os.environ["NNLS_SOLVER"] = "persistent"
-    try:
-        res = N.nnls(dev(A), dev(b), tol=1e-5, max_iter=100000, inner_tol=3e-6)
-    finally:
-        if old is None:
-            del os.environ["NNLS_SOLVER"]
-        else:
-            os.environ["NNLS_SOLVER"] = old
+    res = N.nnls(dev(A), dev(b), tol=1e-5, max_iter=100000, inner_tol=3e-6)
     assert host(res["status"])[0] == N.CONVERGED
     ref = O.reference_solution(A, b)
-    _check_solution(A, b, host(res["X"]), 1e-5, ref, f"persistent n={n}")
+    _check_solution(A, b, host(res["X"]), 1e-5, ref, f"{whole_gpu} n={n}")
 
 
-def test_persistent_statuses(force_persistent):
-    say("persistent statuses")
+def test_persistent_statuses(whole_gpu):
+    say(f"{whole_gpu} statuses")
     A, B = _uniform_case(22, 3000, 1024, 1)
     Q, q, s = N.prepare(dev(A), dev(B))
     X, it, kkt, st = N.solve(Q, q, s, tol=1e-12, max_iter=4)
@@ -325,6 +318,23 @@ def test_persistent_statuses(force_persistent):
     qp = q.abs()
     X, it, kkt, st = N.solve(Q, qp, s, tol=1e-6, max_iter=50)
     assert host(st)[0] == N.CONVERGED and host(it)[0] == 0 and np.all(host(X) == 0)
+
+
+def test_regq_rows_read_counts_passive_and_clipped(monkeypatch):
+    """The register solver reports the rows a streaming solver reads (|P| + |C| per update plus
+    n per exact refresh): the same count as the streaming solver on the same problem."""
+    A, b, _ = W.make_large(seed=8, d=3000, n=1600)
+    Q, q, s = N.prepare(dev(A), dev(b))
+    counts = {}
+    for solver in ["regq", "persistent"]:
+        monkeypatch.setenv("NNLS_SOLVER", solver)
+        rows = torch.zeros(1, dtype=torch.int64, device=DEV)
+        X, it, kkt, st = N.solve(Q, q, s, tol=1e-5, max_iter=5, rows_read=rows)
+        counts[solver] = (int(host(rows)[0]), int(host(it)[0]))
+    monkeypatch.delenv("NNLS_SOLVER", raising=False)
+    say(f"rows read {counts}")
+    assert counts["regq"][1] == counts["persistent"][1] == 5
+    assert abs(counts["regq"][0] - counts["persistent"][0]) <= 0.02 * counts["persistent"][0]
 
 
 # ---------------------------------------------------------------------------- many-RHS solver
