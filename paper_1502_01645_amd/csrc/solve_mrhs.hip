@@ -2,11 +2,12 @@
 //
 // A workgroup owns 16 column slots.  Per update, for all its active columns at once:
 //   gbar = masked gradient (passive set per column), num_c = ||gbar_c||^2, residual r_c;
-//   W = Q * Gbar on the FP32 matrix cores (v_mfma_f32_16x16x4f32): 16 output columns, Q read
+//   W = Q * Gbar on the FP32 matrix cores (v_mfma_f32_16x16x4f32): 16 output columns; for
+//   n <= 256 Q is held in the registers of each workgroup (256 per lane), otherwise it is read
 //   from L2 (every workgroup streams the same n x n matrix);
 //   den_c = gbar_c^T W_c, alpha_c = num_c / den_c;  y' = [y - alpha gbar]_+;
-//   grad' = grad - alpha W + Q[:, C] delta_C, the clip correction applied with vector FMAs over
-//   the clipped entries only (delta = (y' - y) + alpha gbar is nonzero just there).
+//   grad' = grad + Q (y' - y), the second product of Algorithm 2, again on the matrix cores
+//   (with 16 columns per product the dense form beats gathering the clipped rows of Q).
 // A column whose residual meets tol has its gradient recomputed exactly (Q y + q, one more
 // matrix-core product over all slots) before it retires; it then writes x = y / s, its
 // iteration count, residual and status, and the slot takes the next column from a queue.
@@ -18,7 +19,6 @@ namespace nnls {
 
 constexpr int MR_NT = 256;
 constexpr int MR_SLOTS = 16;
-constexpr int MR_CAP = 1024;  // clipped (row, slot) pairs applied per pass
 
 struct MrArgs {
   int n, np, k;
@@ -76,17 +76,43 @@ __device__ void mfma_product(const MrArgs& A, const float* V, float* W) {
   }
 }
 
-__global__ __launch_bounds__(MR_NT) void solve_mrhs_kernel(MrArgs A) {
+// W = Q * V with Q held in registers (n <= 256): wave w owns the row tiles t = w + 4 tt
+// (tt < TPW, np = 64 TPW); lane l holds Q[16 t + l % 16][4 ks + l / 16] for every k step ks,
+// the A operand of MFMA ks, so a product reads only V from LDS (lane l: row 4 ks + l / 16, slot
+// l % 16; 16 consecutive lanes hit 16 consecutive banks) and one V value feeds TPW MFMAs.
+template <int TPW>
+__device__ __forceinline__ void mfma_product_reg(const float (&qa)[TPW][16 * TPW],
+                                                 const float* V, float* W) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  f32x4 acc[TPW];
+#pragma unroll
+  for (int tt = 0; tt < TPW; ++tt) acc[tt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < 16 * TPW; ++ks) {
+    const float b = V[(4 * ks + lg) * MR_SLOTS + lr];
+#pragma unroll
+    for (int tt = 0; tt < TPW; ++tt)
+      acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[tt][ks], b, acc[tt], 0, 0, 0);
+  }
+#pragma unroll
+  for (int tt = 0; tt < TPW; ++tt) {
+    const int t = wave + 4 * tt;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) W[(t * 16 + 4 * lg + e) * MR_SLOTS + lr] = acc[tt][e];
+  }
+}
+
+// TPW > 0: Q in registers (n <= 64 TPW); TPW == 0: Q read from L2 by mfma_product.
+template <int TPW>
+__global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrArgs A) {
   extern __shared__ __attribute__((aligned(16))) float sm[];
   const int np = A.np, n = A.n;
   float* Y = sm;                       // [np][16]
   float* Gr = Y + np * MR_SLOTS;       // [np][16] gradient
   float* P = Gr + np * MR_SLOTS;       // [np][16] masked gradient / product operand
   float* W = P + np * MR_SLOTS;        // [np][16] product result
-  int* cj = (int*)(W + np * MR_SLOTS); // [MR_CAP] clipped rows
-  int* cc = cj + MR_CAP;               // [MR_CAP] clipped slots
-  float* cd = (float*)(cc + MR_CAP);   // [MR_CAP] deltas
-  float* colf = cd + MR_CAP;           // per-slot floats [8][16]
+  float* colf = W + np * MR_SLOTS;     // per-slot floats [8][16]
   int* coli = (int*)(colf + 8 * MR_SLOTS);  // per-slot ints [8][16]
   float* red = (float*)(coli + 8 * MR_SLOTS);  // [4 waves][16 slots][4]
   int* redI = (int*)(red + 4 * MR_SLOTS * 4);  // [4]
@@ -112,6 +138,26 @@ __global__ __launch_bounds__(MR_NT) void solve_mrhs_kernel(MrArgs A) {
   const int lane = tid & 63, wave = tid >> 6;
   const int slot = tid & 15;              // elementwise mapping: slot = tid % 16,
   const int row0 = tid >> 4;              // rows row0 + 16 m
+
+  // Q in registers for the matrix-core products (TPW > 0)
+  constexpr int QT = TPW > 0 ? TPW : 1;
+  float qa[QT][16 * QT];
+  if (TPW > 0) {
+    const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int tt = 0; tt < QT; ++tt) {
+      const int m = (wave + 4 * tt) * 16 + lr;
+#pragma unroll
+      for (int ks = 0; ks < 16 * QT; ++ks) {
+        const int kk = 4 * ks + lg;
+        qa[tt][ks] = (m < n && kk < n) ? A.Q[(int64_t)m * n + kk] : 0.f;
+      }
+    }
+  }
+  auto product = [&](const float* V, float* Wout) {
+    if constexpr (TPW > 0) mfma_product_reg<QT>(qa, V, Wout);
+    else mfma_product(A, V, Wout);
+  };
 
   // -- load a column into a slot: y = max(Y0, 0) or 0, gradient = q (exact for a cold start)
   auto load_slot = [&](int sl, int col) {
@@ -204,7 +250,7 @@ __global__ __launch_bounds__(MR_NT) void solve_mrhs_kernel(MrArgs A) {
     if (any_ref) {
       for (int e = tid; e < np * MR_SLOTS; e += MR_NT) P[e] = Y[e];
       __syncthreads();
-      mfma_product(A, P, W);
+      product(P, W);
       __syncthreads();
       if (s_ref[slot] && s_col[slot] >= 0) {
         const int col = s_col[slot];
@@ -311,7 +357,7 @@ __global__ __launch_bounds__(MR_NT) void solve_mrhs_kernel(MrArgs A) {
     if (!s_act[slot])
       for (int i = row0; i < np; i += MR_NT / MR_SLOTS) P[i * MR_SLOTS + slot] = 0.f;
     __syncthreads();
-    mfma_product(A, P, W);
+    product(P, W);
     __syncthreads();
     {
       float den = 0.f;
@@ -340,58 +386,30 @@ __global__ __launch_bounds__(MR_NT) void solve_mrhs_kernel(MrArgs A) {
     }
     __syncthreads();
 
-    // ---- projected update; clipped pairs (row, slot, delta) into the list, in passes
-    int total_clip;
+    // ---- projected update y' = [y - alpha gbar]_+; P becomes d = y' - y
     int clip_mine = 0;
     {
       const bool act = s_act[slot];
       const float alpha = act ? s_alpha[slot] : 0.f;
-      int cnt = 0;
-      for (int i = row0; i < n; i += MR_NT / MR_SLOTS) {
+      for (int i = row0; i < np; i += MR_NT / MR_SLOTS) {
         const int e = i * MR_SLOTS + slot;
-        cnt += (act && (Y[e] - alpha * P[e] < 0.f)) ? 1 : 0;
-      }
-      clip_mine = cnt;
-      int base = block_exclusive_scan<MR_NT>(cnt, redI, total_clip);
-      for (int pass = 0; pass * MR_CAP < total_clip; ++pass) {
-        const int lo = pass * MR_CAP, hi = lo + MR_CAP;
-        int pos = base;
-        for (int i = row0; i < n; i += MR_NT / MR_SLOTS) {
-          const int e = i * MR_SLOTS + slot;
-          if (act && (Y[e] - alpha * P[e] < 0.f)) {
-            if (pos >= lo && pos < hi) {
-              cj[pos - lo] = i;
-              cc[pos - lo] = slot;
-              cd[pos - lo] = alpha * P[e] - Y[e];
-            }
-            ++pos;
-          }
+        float d = 0.f;
+        if (act && i < n) {
+          const float yo = Y[e];
+          const float v = yo - alpha * P[e];
+          const float yn = v > 0.f ? v : 0.f;
+          clip_mine += (v < 0.f) ? 1 : 0;
+          Y[e] = yn;
+          d = yn - yo;
         }
-        __syncthreads();
-        const int npairs = (total_clip - lo) < MR_CAP ? (total_clip - lo) : MR_CAP;
-        // grad[i][c_m] += delta_m * Q[j_m][i]: thread owns rows i = tid, tid + 256, ...
-        for (int i = tid; i < n; i += MR_NT) {
-          int m = 0;
-          for (; m + 3 < npairs; m += 4) {
-            float v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = A.Q[(int64_t)cj[m + u] * n + i];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) Gr[i * MR_SLOTS + cc[m + u]] += cd[m + u] * v[u];
-          }
-          for (; m < npairs; ++m) Gr[i * MR_SLOTS + cc[m]] += cd[m] * A.Q[(int64_t)cj[m] * n + i];
-        }
-        __syncthreads();
+        P[e] = d;
       }
-      // y' = [y - alpha gbar]_+, grad' = grad - alpha W (+ correction above)
-      if (act) {
-        for (int i = row0; i < n; i += MR_NT / MR_SLOTS) {
-          const int e = i * MR_SLOTS + slot;
-          const float v = Y[e] - alpha * P[e];
-          Y[e] = v > 0.f ? v : 0.f;
-          Gr[e] -= alpha * W[e];
-        }
-      }
+      __syncthreads();
+      // grad' = grad + Q d, the second product of Algorithm 2, on the matrix cores
+      product(P, W);
+      __syncthreads();
+      if (act)
+        for (int i = row0; i < n; i += MR_NT / MR_SLOTS) Gr[i * MR_SLOTS + slot] += W[i * MR_SLOTS + slot];
       __syncthreads();
     }
     slot_reduce4((float)clip_mine, 0.f, 0.f, 0.f, s_den, nullptr, nullptr, nullptr);
@@ -413,11 +431,15 @@ __global__ void solve_mrhs_queue_init(int* queue, int first_free) {
 }
 
 // ---- host side ------------------------------------------------------------------------------
-static int mr_np(int64_t n) { return (int)((n + 15) / 16 * 16); }
+static int mr_tpw(int64_t n) { return n <= 256 ? (int)((n + 63) / 64) : 0; }
+static int mr_np(int64_t n) {
+  const int tpw = mr_tpw(n);
+  return tpw > 0 ? 64 * tpw : (int)((n + 15) / 16 * 16);
+}
 
 size_t solve_mrhs_lds_bytes(int64_t n) {
   const size_t np = (size_t)mr_np(n);
-  return sizeof(float) * 4 * np * MR_SLOTS + (sizeof(int) * 2 + sizeof(float)) * MR_CAP +
+  return sizeof(float) * 4 * np * MR_SLOTS +
          sizeof(float) * 8 * MR_SLOTS + sizeof(int) * 8 * MR_SLOTS +
          sizeof(float) * 4 * MR_SLOTS * 4 + sizeof(int) * 8 + 64;
 }
@@ -436,12 +458,18 @@ hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* 
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const size_t lds = solve_mrhs_lds_bytes(n);
+  const void* kern = nullptr;
+  switch (mr_tpw(n)) {
+    case 1: kern = (const void*)solve_mrhs_kernel<1>; break;
+    case 2: kern = (const void*)solve_mrhs_kernel<2>; break;
+    case 3: kern = (const void*)solve_mrhs_kernel<3>; break;
+    case 4: kern = (const void*)solve_mrhs_kernel<4>; break;
+    default: kern = (const void*)solve_mrhs_kernel<0>; break;
+  }
   int per_cu = 1;
-  hipError_t e = hipFuncSetAttribute((const void*)solve_mrhs_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)solve_mrhs_kernel,
-                                                   MR_NT, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, MR_NT, lds);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   int64_t groups = (k + MR_SLOTS - 1) / MR_SLOTS;
@@ -465,7 +493,9 @@ hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* 
   A.queue = (int*)ws;
   hipLaunchKernelGGL(solve_mrhs_queue_init, dim3(1), dim3(64), 0, st, A.queue,
                      (int)(groups * MR_SLOTS));
-  hipLaunchKernelGGL(solve_mrhs_kernel, dim3((unsigned)groups), dim3(MR_NT), lds, st, A);
+  void* args[] = {&A};
+  e = hipLaunchKernel(kern, dim3((unsigned)groups), dim3(MR_NT), args, lds, st);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
