@@ -236,36 +236,72 @@ __global__ __launch_bounds__(256) void cols_finalize_kernel(int64_t n, int64_t k
 // TRANS = false: C[M, N] = A[M, K] * Bm[K, N] - Cin      (A row-major [d, n], M = d, K = n)
 // TRANS = true:  C[M, N] = A^T[M, K] * Bm[K, N]           (A row-major [d, n], M = n, K = d)
 // ---- many right-hand sides: FP64 Gram path ---------------------------------------------------
-// C[i, j] = sum_r A[r, i] M[r, j] for i < N, j < Mc, r < K (A [K, N] and M [K, Mc] row-major), in
-// FP64 on the matrix cores (v_mfma_f64_16x16x4f64): 64 x 64 output tiles, four waves of 32 x 32,
-// K staged through LDS 32 rows at a time (zero-filled past the edges).
+// C[i, j] = sum_r A[r, i] M[r, j] for i < N, r < K, with M = [M1 | M2] (columns j < n1 from M1,
+// the next n2 from M2; all row-major with r as the row), written to C1 (j < n1) and C2 (the rest)
+// in FP64 on the matrix cores (v_mfma_f64_16x16x4f64): 64 x 64 output tiles, four waves of
+// 32 x 32, K staged through LDS 32 rows at a time (zero-filled past the edges) with the next
+// chunk loaded into registers while the current one is multiplied.  With sq != nullptr the
+// workgroups of row tile 0 also write sq[j] = sum_r M2[r, j]^2 for their M2 columns.
 constexpr int TN_T = 64, TN_BK = 32, TN_LD = TN_T + 2;
 
 template <typename TA, typename TM>
-__global__ __launch_bounds__(256) void gemm_tn_f64_kernel(int64_t K, int64_t N, int64_t Mc,
-                                                          const TA* __restrict__ A, int64_t lda,
-                                                          const TM* __restrict__ Mm, int64_t ldm,
-                                                          double* __restrict__ C, int64_t ldc) {
+__global__ __launch_bounds__(256) void gemm_tn_f64_kernel(
+    int64_t K, int64_t N, int64_t n1, int64_t n2, const TA* __restrict__ A, int64_t lda,
+    const TM* __restrict__ M1, int64_t ld1, const TM* __restrict__ M2, int64_t ld2,
+    double* __restrict__ C1, int64_t ldc1, double* __restrict__ C2, int64_t ldc2,
+    double* __restrict__ sq) {
   __shared__ double sa[TN_BK][TN_LD];
   __shared__ double sm[TN_BK][TN_LD];
+  __shared__ double sqred[4][TN_T];
   const int64_t i0 = (int64_t)blockIdx.y * TN_T, j0 = (int64_t)blockIdx.x * TN_T;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  // staging: this thread's column c = tid % 64, rows (tid / 64) + 4 u of each chunk
+  const int c = tid & 63, r0 = tid >> 6;
+  const int64_t ia = i0 + c, jm = j0 + c;
+  const bool a_ok = ia < N;
+  const TM* mp = nullptr;
+  int64_t mld = 0;
+  if (jm < n1) {
+    mp = M1 + jm;
+    mld = ld1;
+  } else if (jm < n1 + n2) {
+    mp = M2 + (jm - n1);
+    mld = ld2;
+  }
+  const bool want_sq = sq != nullptr && blockIdx.y == 0 && jm >= n1 && jm < n1 + n2;
+  double sqacc = 0.0;
+  TA ra[TN_BK / 4];
+  TM rm[TN_BK / 4];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < TN_BK / 4; ++u) {
+      const int64_t gr = k0 + r0 + 4 * u;
+      ra[u] = (a_ok && gr < K) ? A[gr * lda + ia] : (TA)0;
+      rm[u] = (mp != nullptr && gr < K) ? mp[gr * mld] : (TM)0;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < TN_BK / 4; ++u) {
+      sa[r0 + 4 * u][c] = (double)ra[u];
+      const double mv = (double)rm[u];
+      sm[r0 + 4 * u][c] = mv;
+      if (want_sq) sqacc += mv * mv;
+    }
+  };
+
   f64x4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
   const int col = lane & 15, kq = lane >> 4;
+  if (K > 0) load(0);
   for (int64_t k0 = 0; k0 < K; k0 += TN_BK) {
-#pragma unroll
-    for (int e = tid; e < TN_BK * TN_T; e += 256) {
-      const int r = e >> 6, c = e & 63;
-      const int64_t gr = k0 + r;
-      sa[r][c] = (gr < K && i0 + c < N) ? (double)A[gr * lda + i0 + c] : 0.0;
-      sm[r][c] = (gr < K && j0 + c < Mc) ? (double)Mm[gr * ldm + j0 + c] : 0.0;
-    }
+    store();
     __syncthreads();
+    if (k0 + TN_BK < K) load(k0 + TN_BK);  // in flight during the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < TN_BK; kk += 4) {
       const int kr = kk + kq;
@@ -288,27 +324,16 @@ __global__ __launch_bounds__(256) void gemm_tn_f64_kernel(int64_t K, int64_t N, 
       for (int e = 0; e < 4; ++e) {
         const int64_t i = i0 + wi + a * 16 + kq + 4 * e;
         const int64_t j = j0 + wj + b * 16 + col;
-        if (i < N && j < Mc) C[i * ldc + j] = acc[a][b][e];
+        if (i >= N) continue;
+        if (j < n1) C1[i * ldc1 + j] = acc[a][b][e];
+        else if (j < n1 + n2) C2[i * ldc2 + (j - n1)] = acc[a][b][e];
       }
-}
-
-// Partial column sums of squares of B [d, k] (FP64), row chunk blockIdx.y of BB_CH.
-constexpr int BB_CH = 16;
-template <typename T>
-__global__ __launch_bounds__(256) void colsq_partial_kernel(int64_t d, int64_t k,
-                                                            const T* __restrict__ B, int64_t ldb,
-                                                            double* __restrict__ out) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (c >= k) return;
-  const int64_t rows = (d + BB_CH - 1) / BB_CH;
-  const int64_t r0 = (int64_t)blockIdx.y * rows;
-  const int64_t r1 = r0 + rows < d ? r0 + rows : d;
-  double acc = 0.0;
-  for (int64_t r = r0; r < r1; ++r) {
-    const double v = (double)B[r * ldb + c];
-    acc += v * v;
+  if (sq != nullptr && blockIdx.y == 0) {
+    sqred[r0][c] = sqacc;
+    __syncthreads();
+    if (tid < TN_T && want_sq)
+      sq[jm - n1] = (sqred[0][tid] + sqred[1][tid]) + (sqred[2][tid] + sqred[3][tid]);
   }
-  out[(int64_t)blockIdx.y * k + c] = acc;
 }
 
 // s_i = sqrt(H_ii), 1 where H_ii = 0.
@@ -339,7 +364,7 @@ __global__ __launch_bounds__(256) void gref_stage1_kernel(int64_t n, int64_t k,
                                                           const double* __restrict__ GX,
                                                           const double* __restrict__ Atb,
                                                           const double* __restrict__ s,
-                                                          const double* __restrict__ bbp,
+                                                          const double* __restrict__ bb,
                                                           double* __restrict__ D,
                                                           double* __restrict__ colstat) {
   __shared__ double red[4][GS_C];
@@ -367,10 +392,8 @@ __global__ __launch_bounds__(256) void gref_stage1_kernel(int64_t n, int64_t k,
   num = gs_reduce(num, red, rg, cl);
   fx = gs_reduce(fx, red, rg, cl);
   if (in && rg == 0) {
-    double bb = 0.0;
-    for (int ch = 0; ch < BB_CH; ++ch) bb += bbp[(int64_t)ch * k + c];
     colstat[c * 8 + 0] = aa > 0.0 ? sqrt(kk) / sqrt(aa) : sqrt(kk);
-    colstat[c * 8 + 1] = 0.5 * (fx + bb);
+    colstat[c * 8 + 1] = 0.5 * (fx + bb[c]);
     colstat[c * 8 + 2] = num;
     colstat[c * 8 + 3] = aa;
   }
@@ -591,9 +614,9 @@ static RefineWs refine_layout(void* ws, int64_t d, int64_t n, int64_t k) {
 }
 
 // Gram path workspace: H [n, n], a, HX, D, HD (reused for H X'), X' [n, k], s [n],
-// colstat [8 k], ||b||^2 partials [BB_CH k].
+// colstat [8 k], ||b||^2 [k].
 struct GramRefineWs {
-  double *H, *a, *HX, *D, *HD, *Xn, *s, *colstat, *bbp;
+  double *H, *a, *HX, *D, *HD, *Xn, *s, *colstat, *bb;
 };
 
 static GramRefineWs gram_refine_layout(void* ws, int64_t n, int64_t k) {
@@ -607,7 +630,7 @@ static GramRefineWs gram_refine_layout(void* ws, int64_t n, int64_t k) {
   w.Xn = p; p += n * k;
   w.s = p; p += n;
   w.colstat = p; p += 8 * k;
-  w.bbp = p;
+  w.bb = p;
   return w;
 }
 
@@ -616,7 +639,7 @@ size_t refine_ws_bytes(int64_t d, int64_t n, int64_t k) {
   if (k <= RF_SMALL_K)
     el = (size_t)(2 * d * k + 4 * n * k + n + 8 * k) + (size_t)refine_chunks(d, n) * (2 * k + 1) * n;
   else
-    el = (size_t)(n * n + 5 * n * k + n + 8 * k + BB_CH * k);
+    el = (size_t)(n * n + 5 * n * k + n + 9 * k);
   return el * sizeof(double) + 256;
 }
 
@@ -672,12 +695,14 @@ static void launch_atr(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda,
                      k, wb, w.chunks, (const double*)w.partial, G, w.Atb, w.s);
 }
 
+// C = A^T [M1 | M2] (see gemm_tn_f64_kernel); sq optional.
 template <typename TA, typename TM>
-static void gemm_tn(int64_t K, int64_t N, int64_t Mc, const TA* A, int64_t lda, const TM* M,
-                    int64_t ldm, double* C, int64_t ldc, hipStream_t st) {
-  dim3 grid((unsigned)((Mc + TN_T - 1) / TN_T), (unsigned)((N + TN_T - 1) / TN_T));
-  hipLaunchKernelGGL((gemm_tn_f64_kernel<TA, TM>), grid, dim3(256), 0, st, K, N, Mc, A, lda, M,
-                     ldm, C, ldc);
+static void gemm_tn(int64_t K, int64_t N, const TA* A, int64_t lda, int64_t n1, const TM* M1,
+                    int64_t ld1, double* C1, int64_t ldc1, int64_t n2, const TM* M2, int64_t ld2,
+                    double* C2, int64_t ldc2, double* sq, hipStream_t st) {
+  dim3 grid((unsigned)((n1 + n2 + TN_T - 1) / TN_T), (unsigned)((N + TN_T - 1) / TN_T));
+  hipLaunchKernelGGL((gemm_tn_f64_kernel<TA, TM>), grid, dim3(256), 0, st, K, N, n1, n2, A, lda,
+                     M1, ld1, M2, ld2, C1, ldc1, C2, ldc2, sq);
 }
 
 template <typename T>
@@ -686,21 +711,22 @@ static void launch_refine_gram(int64_t d, int64_t n, int64_t k, const T* A, int6
                                void* ws, hipStream_t st) {
   GramRefineWs w = gram_refine_layout(ws, n, k);
   const unsigned cb = (unsigned)((k + GS_C - 1) / GS_C);
-  gemm_tn<T, T>(d, n, n, A, lda, A, lda, w.H, n, st);      // H = A^T A
-  gemm_tn<T, T>(d, n, k, A, lda, B, ldb, w.a, k, st);      // a = A^T B
-  hipLaunchKernelGGL(colsq_partial_kernel<T>, dim3((unsigned)((k + 255) / 256), BB_CH), dim3(256),
-                     0, st, d, k, B, ldb, w.bbp);
+  // H = A^T A and a = A^T B in one launch over the columns of [A | B], with ||b||^2
+  gemm_tn<T, T>(d, n, A, lda, n, A, lda, w.H, n, k, B, ldb, w.a, k, w.bb, st);
   hipLaunchKernelGGL(diag_scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
                      (const double*)w.H, w.s);
   // H is symmetric, so H^T M = H M: the same transposed product with K = n
-  gemm_tn<double, T>(n, n, k, w.H, n, X, k, w.HX, k, st);
+  gemm_tn<double, T>(n, n, w.H, n, k, X, k, w.HX, k, 0, (const T*)nullptr, 0, nullptr, 0,
+                     nullptr, st);
   hipLaunchKernelGGL(gref_stage1_kernel<T>, dim3(cb), dim3(256), 0, st, n, k, (const T*)X,
                      (const double*)w.HX, (const double*)w.a, (const double*)w.s,
-                     (const double*)w.bbp, w.D, w.colstat);
-  gemm_tn<double, double>(n, n, k, w.H, n, w.D, k, w.HD, k, st);
+                     (const double*)w.bb, w.D, w.colstat);
+  gemm_tn<double, double>(n, n, w.H, n, k, w.D, k, w.HD, k, 0, (const double*)nullptr, 0,
+                          nullptr, 0, nullptr, st);
   hipLaunchKernelGGL(gref_stage2_kernel<T>, dim3(cb), dim3(256), 0, st, n, k, (const T*)X,
                      (const double*)w.D, (const double*)w.HD, w.Xn, (const double*)w.colstat);
-  gemm_tn<double, double>(n, n, k, w.H, n, w.Xn, k, w.HD, k, st);  // H x' (reuses HD)
+  gemm_tn<double, double>(n, n, w.H, n, k, w.Xn, k, w.HD, k, 0, (const double*)nullptr, 0,
+                          nullptr, 0, nullptr, st);  // H x' (reuses HD)
   hipLaunchKernelGGL(gref_stage3_kernel<T>, dim3(cb), dim3(256), 0, st, n, k, X,
                      (const double*)w.Xn, (const double*)w.HD, (const double*)w.HX,
                      (const double*)w.a, (const double*)w.s, (const double*)w.colstat, kkt64,
