@@ -44,13 +44,18 @@ struct RqArgs {
   double* kkt;
   int32_t* status;
   int64_t* rows_read;
-  float* gf;     // [n] masked gradient of the current iterate, written by the row owners
+  float* gf;     // [CS NT] masked gradient of the current iterate, written by the row owners
+                 // (entries past n stay zero)
   float* sf;     // [8 G] statistics partials
   uint64_t* fl;  // [G] publish flags: update number of the last gbar / statistics written
   uint64_t* dw;  // [G] line-search denominator partials, tagged with the update number
   unsigned* bar;
   int spin_limit;  // polls before a workgroup gives up waiting (a guard that never fires)
 };
+
+typedef __attribute__((address_space(1))) void rq_gvoid;
+typedef __attribute__((address_space(3))) void rq_lvoid;
+constexpr int RQ_SC1 = 16;  // cache-policy bit of an agent-coherent (sc1) load
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_shr(float v) {
@@ -136,6 +141,7 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
   __shared__ float redF[NT / 64];
   __shared__ float ys[CS * NT];
   __shared__ float vs[CS * NT];
+  __shared__ float stl[5 * NT];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int n = A.n, G = A.G;
@@ -217,24 +223,35 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
   __shared__ float red5[5][NT / 64];
   auto read_gbar = [&]() -> bool {
     for (int poll = 0;; ++poll) {
-      bool ok = true;
-      for (int c = t; c < G; c += NT) ok = ok && tag_ok(ld_sc(A.fl + c), ep);
+      const bool ok = t >= G || tag_ok(ld_sc(A.fl + t), ep);
       if (__syncthreads_and(ok)) break;
       if (poll >= A.spin_limit) return false;
       __builtin_amdgcn_s_sleep(1);
     }
+    // gbar at the own columns straight into vs, and the statistics of every workgroup into
+    // stl, by global-to-LDS loads with the agent-coherent cache policy (sc1, the policy of the
+    // agent-scope loads): a thread's CS + 5 loads are all in flight at once and never pass
+    // through registers (agent-scope atomic loads would each wait for the previous one).
+    // gf is zero-padded to CS x NT entries; rows of stl past G read workgroup 0's words and are
+    // ignored.
+    // (the lane offsets are made opaque here so that the addresses are formed at each read as
+    // uniform base + lane offset instead of being kept in registers through the whole solve)
+    const int wl = wave * 64;
+    int tg = t, tc = t < G ? 8 * t : 0;
+    asm volatile("" : "+v"(tg), "+v"(tc));
 #pragma unroll
-    for (int s = 0; s < CS; ++s) {
-      const int j = t + NT * s;
-      vs[s * NT + t] = (j < n) ? ld_sc(A.gf + j) : 0.f;
-    }
-    float sv[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int c = t; c < G; c += NT) {
+    for (int s = 0; s < CS; ++s)
+      __builtin_amdgcn_global_load_lds((rq_gvoid*)(A.gf + NT * s + tg),
+                                       (rq_lvoid*)(vs + s * NT + wl), 4, 0, RQ_SC1);
 #pragma unroll
-      for (int u = 0; u < 5; ++u) sv[u] += ld_sc(A.sf + (int64_t)c * 8 + u);
-    }
+    for (int u = 0; u < 5; ++u)
+      __builtin_amdgcn_global_load_lds((rq_gvoid*)(A.sf + u + tc), (rq_lvoid*)(stl + u * NT + wl),
+                                       4, 0, RQ_SC1);
+    __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0), lgkmcnt(0)
+    __syncthreads();
+    float sv[5];
 #pragma unroll
-    for (int u = 0; u < 5; ++u) sv[u] = wave_sum(sv[u]);
+    for (int u = 0; u < 5; ++u) sv[u] = wave_sum(t < G ? stl[u * NT + t] : 0.f);
     if (lane == 0) {
 #pragma unroll
       for (int u = 0; u < 5; ++u) red5[u][wave] = sv[u];
@@ -367,12 +384,17 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
   }
 }
 
-// Zeroes the barrier words and the tagged exchange words (tag 0 never matches a read).
-__global__ void regq_init_kernel(unsigned* bar, uint64_t* words, int64_t nwords) {
+// Zeroes the barrier words, the tagged exchange words (tag 0 never matches a read) and the
+// gradient exchange vector (its entries past n are read as padding).
+__global__ void regq_init_kernel(unsigned* bar, uint64_t* words, int64_t nwords, float* gf,
+                                 int64_t ngf) {
   for (int i = threadIdx.x; i < GS_BAR_WORDS; i += blockDim.x) bar[i] = 0u;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
        i += (int64_t)gridDim.x * blockDim.x)
     words[i] = 0ull;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ngf;
+       i += (int64_t)gridDim.x * blockDim.x)
+    gf[i] = 0.f;
 }
 
 // ---- host side ------------------------------------------------------------------------------
@@ -382,6 +404,9 @@ struct RqShape {
   int rpc, cs, nt;
 };
 constexpr RqShape kRqShapes[] = {{8, 4, 512}, {12, 6, 512}, {16, 8, 512}, {20, 20, 256}};
+constexpr int RQ_GF = 5120;  // entries of the gradient exchange vector: CS x NT of every shape
+static_assert(4 * 512 <= RQ_GF && 6 * 512 <= RQ_GF && 8 * 512 <= RQ_GF && 20 * 256 <= RQ_GF,
+              "exchange vector too short for a shape");
 
 int rq_cus() {
   int dev = 0, cus = 0;
@@ -393,7 +418,8 @@ int rq_cus() {
 
 int rq_pick(int64_t n, int G) {
   for (int i = 0; i < (int)(sizeof(kRqShapes) / sizeof(kRqShapes[0])); ++i)
-    if ((int64_t)kRqShapes[i].rpc * G >= n && (int64_t)kRqShapes[i].cs * kRqShapes[i].nt >= n)
+    if ((int64_t)kRqShapes[i].rpc * G >= n && (int64_t)kRqShapes[i].cs * kRqShapes[i].nt >= n &&
+        kRqShapes[i].nt >= G)
       return i;
   return -1;
 }
@@ -420,8 +446,9 @@ bool solve_regq_supported(int64_t n, int64_t k) {
 
 size_t solve_regq_ws_bytes(int64_t n) {
   const int G = rq_cus() > 0 ? rq_cus() : 1;
+  (void)n;
   return sizeof(unsigned) * GS_BAR_WORDS + 256 + sizeof(uint64_t) * 2 * (size_t)G + 256 +
-         sizeof(float) * (n + 8 * (size_t)G) + 512;
+         sizeof(float) * (RQ_GF + 8 * (size_t)G) + 512;
 }
 
 hipError_t launch_solve_regq(int64_t n, const float* Q, const float* q, const double* s,
@@ -455,11 +482,11 @@ hipError_t launch_solve_regq(int64_t n, const float* Q, const float* q, const do
   uint64_t* words = (uint64_t*)take(sizeof(uint64_t) * 2 * (size_t)G);
   A.fl = words;
   A.dw = words + G;
-  A.gf = (float*)take(sizeof(float) * n);
+  A.gf = (float*)take(sizeof(float) * RQ_GF);
   A.sf = (float*)take(sizeof(float) * 8 * (size_t)G);
   A.spin_limit = 1 << 24;
   hipLaunchKernelGGL(regq_init_kernel, dim3(1), dim3(256), 0, st, A.bar, words,
-                     (int64_t)(2 * (size_t)G));
+                     (int64_t)(2 * (size_t)G), A.gf, (int64_t)RQ_GF);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (pick) {
