@@ -48,10 +48,17 @@ struct RqArgs {
                  // (entries past n stay zero)
   float* sf;     // [8 G] statistics partials
   uint64_t* fl;  // [G] publish flags: update number of the last gbar / statistics written
-  uint64_t* dw;  // [G] line-search denominator partials, tagged with the update number
+  uint64_t* dw;  // [G] line-search denominator partials, tagged with the update number, in
+                 // RQ_DREP copies RQ_DREP_WORDS apart
   unsigned* bar;
   int spin_limit;  // polls before a workgroup gives up waiting (a guard that never fires)
 };
+
+// The denominator partials are polled by every workgroup at once; each is written to RQ_DREP
+// copies far apart in memory and workgroup b polls copy b % RQ_DREP, which spreads the polling
+// over several memory channels.
+constexpr int RQ_DREP = 8;
+constexpr int64_t RQ_DREP_WORDS = 33280;  // 260 KiB between copies
 
 typedef __attribute__((address_space(1))) void rq_gvoid;
 typedef __attribute__((address_space(3))) void rq_lvoid;
@@ -212,6 +219,8 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
 
   int it = 0;
   int64_t rows = 0;  // rows of Q an implementation streaming Q would read (|P| + |C| per update)
+  int clipped = 0;   // this thread's share of the |C| terms, summed over the block at the end
+  const uint64_t* dwr = A.dw + (blockIdx.x % RQ_DREP) * RQ_DREP_WORDS;
   bool fresh = (A.Y0 == nullptr);
   bool need_refresh = (A.Y0 != nullptr);
   int status = NNLS_MAXITER_DEV;
@@ -314,7 +323,10 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
     if (wave == 0) {
       const bool pas = own && ((y_own > 0.f) || (g_own < 0.f));
       const float v = wave_sum(pas ? g_own * prod[t] : 0.f);
-      if (lane == 0) st_sc(A.dw + blockIdx.x, tag(ed, v));
+      if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < RQ_DREP; ++r) st_sc(A.dw + r * RQ_DREP_WORDS + blockIdx.x, tag(ed, v));
+      }
     }
 
     // ---- C: den (the same in every workgroup: fixed-order sums of the same partials)
@@ -325,7 +337,7 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
         bool ok = true;
         float v = 0.f;
         for (int c = t; c < G; c += NT) {
-          const uint64_t w = ld_sc(A.dw + c);
+          const uint64_t w = ld_sc(dwr + c);
           ok = ok && tag_ok(w, ed);
           v += tag_val(w);
         }
@@ -349,18 +361,17 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
     }
     const float alpha = num / den;
 
-    // projection on the own columns; vs becomes d = y' - y
-    float cc = 0.f;
+    // projection on the own columns (a thread reads and writes only its own entries of ys and
+    // vs, so no barrier is needed); vs becomes d = y' - y
 #pragma unroll
     for (int s = 0; s < CS; ++s) {
       const float yo = ys[s * NT + t];
       const float v = yo - alpha * vs[s * NT + t];
       const float yn = v > 0.f ? v : 0.f;
-      cc += (v < 0.f) ? 1.f : 0.f;
+      clipped += (v < 0.f) ? 1 : 0;
       vs[s * NT + t] = yn - yo;
       ys[s * NT + t] = yn;
     }
-    rows += (int64_t)block_sum<float, NT>(cc, redF);  // also orders the LDS writes above
 
     // ---- D: g'_I = g_I + Q[I, :] d, publish gbar(e + 1)
     reg_product<RPC, CS, NT>(qr, vs, red, prod);
@@ -375,6 +386,7 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
   }
 
   // ---- outputs
+  rows += (int64_t)block_sum<float, NT>((float)clipped, redF);
   if (own) A.X[i0 + t] = A.s ? (float)((double)y_own / A.s[i0 + t]) : y_own;
   if (blockIdx.x == 0 && t == 0) {
     A.iters[0] = timed_out ? -1 : it;
@@ -384,14 +396,17 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
   }
 }
 
-// Zeroes the barrier words, the tagged exchange words (tag 0 never matches a read) and the
-// gradient exchange vector (its entries past n are read as padding).
-__global__ void regq_init_kernel(unsigned* bar, uint64_t* words, int64_t nwords, float* gf,
+// Zeroes the barrier words, the flags and every copy of the denominator partials (tag 0 never
+// matches a read), and the gradient exchange vector (its entries past n are read as padding).
+__global__ void regq_init_kernel(unsigned* bar, uint64_t* fl, uint64_t* dw, int G, float* gf,
                                  int64_t ngf) {
   for (int i = threadIdx.x; i < GS_BAR_WORDS; i += blockDim.x) bar[i] = 0u;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
-       i += (int64_t)gridDim.x * blockDim.x)
-    words[i] = 0ull;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)G * (RQ_DREP + 1);
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / G, c = i % G;
+    if (r == 0) fl[c] = 0ull;
+    else dw[(r - 1) * RQ_DREP_WORDS + c] = 0ull;
+  }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ngf;
        i += (int64_t)gridDim.x * blockDim.x)
     gf[i] = 0.f;
@@ -419,7 +434,7 @@ int rq_cus() {
 int rq_pick(int64_t n, int G) {
   for (int i = 0; i < (int)(sizeof(kRqShapes) / sizeof(kRqShapes[0])); ++i)
     if ((int64_t)kRqShapes[i].rpc * G >= n && (int64_t)kRqShapes[i].cs * kRqShapes[i].nt >= n &&
-        kRqShapes[i].nt >= G)
+        kRqShapes[i].nt >= G && G <= RQ_DREP_WORDS)
       return i;
   return -1;
 }
@@ -447,7 +462,8 @@ bool solve_regq_supported(int64_t n, int64_t k) {
 size_t solve_regq_ws_bytes(int64_t n) {
   const int G = rq_cus() > 0 ? rq_cus() : 1;
   (void)n;
-  return sizeof(unsigned) * GS_BAR_WORDS + 256 + sizeof(uint64_t) * 2 * (size_t)G + 256 +
+  return sizeof(unsigned) * GS_BAR_WORDS + 256 + sizeof(uint64_t) * (size_t)G + 256 +
+         sizeof(uint64_t) * RQ_DREP * (size_t)RQ_DREP_WORDS + 256 +
          sizeof(float) * (RQ_GF + 8 * (size_t)G) + 512;
 }
 
@@ -479,14 +495,13 @@ hipError_t launch_solve_regq(int64_t n, const float* Q, const float* q, const do
     return (void*)r;
   };
   A.bar = (unsigned*)take(sizeof(unsigned) * GS_BAR_WORDS);
-  uint64_t* words = (uint64_t*)take(sizeof(uint64_t) * 2 * (size_t)G);
-  A.fl = words;
-  A.dw = words + G;
+  A.fl = (uint64_t*)take(sizeof(uint64_t) * (size_t)G);
+  A.dw = (uint64_t*)take(sizeof(uint64_t) * RQ_DREP * (size_t)RQ_DREP_WORDS);
   A.gf = (float*)take(sizeof(float) * RQ_GF);
   A.sf = (float*)take(sizeof(float) * 8 * (size_t)G);
   A.spin_limit = 1 << 24;
-  hipLaunchKernelGGL(regq_init_kernel, dim3(1), dim3(256), 0, st, A.bar, words,
-                     (int64_t)(2 * (size_t)G), A.gf, (int64_t)RQ_GF);
+  hipLaunchKernelGGL(regq_init_kernel, dim3(8), dim3(256), 0, st, A.bar, A.fl, A.dw, G, A.gf,
+                     (int64_t)RQ_GF);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   switch (pick) {
