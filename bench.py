@@ -151,9 +151,7 @@ def main():
     steps_total = args.warmup + args.steps
     kkt64 = torch.empty((steps_total, k), dtype=torch.float64, device=dev)
     obj64 = torch.empty((steps_total, k), dtype=torch.float64, device=dev)
-    ws_s = torch.empty(max(N.workspace_bytes(N.OP_SCALES, d, n, k, 0, N.F32), 1), dtype=torch.uint8,
-                       device=dev)
-    ws_g = torch.empty(max(N.workspace_bytes(N.OP_GRAM, d, n, k, N.GRAM_BF16X3, N.F32), 1),
+    ws_p = torch.empty(max(N.workspace_bytes(N.OP_PREPARE, d, n, k, N.GRAM_BF16X3, N.F32), 1),
                        dtype=torch.uint8, device=dev)
     ws_v = torch.empty(max(N.workspace_bytes(N.OP_SOLVE, d, n, k, 0, N.F32), 1), dtype=torch.uint8,
                        device=dev)
@@ -162,20 +160,18 @@ def main():
     torch.cuda.synchronize()
 
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    marks = [[ev() for _ in range(5)] for _ in range(steps_total)]
+    marks = [[ev() for _ in range(4)] for _ in range(steps_total)]
 
     def step(i):
         e = marks[i]
         e[0].record()
-        N.column_scales(A, out=s, ws=ws_s)
+        N.prepare(A, b, N.GRAM_BF16X3, out=(Q, q, s), ws=ws_p)
         e[1].record()
-        N.gram_rescaled(A, b, s, N.GRAM_BF16X3, out=(Q, q), ws=ws_g)
-        e[2].record()
         N.solve(Q, q, s, tol=INNER_TOL, max_iter=5 * n, out=(X, iters, kkt, status), ws=ws_v,
                 rows_read=rows)
-        e[3].record()
+        e[2].record()
         N.refine(A, b, X, out=(kkt64[i], obj64[i]), ws=ws_r)
-        e[4].record()
+        e[3].record()
 
     for i in range(args.warmup):
         step(i)
@@ -188,7 +184,7 @@ def main():
 
     timed = marks[args.warmup:]
     ms = {name: float(np.mean([m[j].elapsed_time(m[j + 1]) for m in timed]))
-          for j, name in enumerate(["scales", "gram", "solve", "refine"])}
+          for j, name in enumerate(["prepare", "solve", "refine"])}
     ms_step = wall * 1e3 / args.steps
     r64 = kkt64[args.warmup:].cpu().numpy()[:, 0]
     ok = bool(np.all(r64 <= TOL))
@@ -198,12 +194,15 @@ def main():
 
     # roofline of the two heavy kernels
     gram_flops = d * n * (n + 1) + 2.0 * d * n * k
-    gram_tf = gram_flops / (ms["gram"] * 1e-3) / 1e12
+    gram_tf = gram_flops / (ms["prepare"] * 1e-3) / 1e12
     solve_bytes = 4.0 * n * rows_last
     solve_gbs = solve_bytes / (ms["solve"] * 1e-3) / 1e9
-    # the Gram call is three launches (operand split, main product, split-K epilogue); the
-    # figure is for the whole call, the traffic record for the main product kernel
-    roof_gram = {"kernel": "gram_dma_kernel", "bound": "mfma", "achieved": round(gram_tf, 2),
+    # the prepare call is the operand split (which also forms the column norms), their
+    # finalisation and the main product; the figure is for the whole call, the traffic record
+    # for the main product kernel
+    roof_gram = {"kernel": "gram_dma_kernel", "timed": "nnls_prepare call (presplit_kernel + "
+                 "colnorm_finalize_kernel + gram_dma_kernel)", "bound": "mfma",
+                 "achieved": round(gram_tf, 2),
                  "peak": round(PEAK_BF16X3_TFLOPS, 1), "unit": "TFLOP/s",
                  "frac": round(gram_tf / PEAK_BF16X3_TFLOPS, 4),
                  "traffic": traffic_record("gram_dma_kernel", "gram.hip")}
@@ -215,7 +214,7 @@ def main():
                   "frac": round(solve_gbs / PEAK_HBM_GBS, 4),
                   "traffic": traffic_record(solve_kernel, {"solve_regq_kernel": "solve_regq.hip"}
                                             .get(solve_kernel, "solve_persistent.hip"))}
-    dominant, other = ((roof_gram, roof_solve) if ms["gram"] >= ms["solve"]
+    dominant, other = ((roof_gram, roof_solve) if ms["prepare"] >= ms["solve"]
                        else (roof_solve, roof_gram))
 
     out = {
@@ -273,24 +272,21 @@ def bench_manyrhs(args):
     obj64 = torch.empty(k, dtype=torch.float64, device=dev)
     mk = lambda op, mode=0: torch.empty(max(N.workspace_bytes(op, d, n, k, mode, N.F32), 1),  # noqa
                                         dtype=torch.uint8, device=dev)
-    ws_s, ws_g, ws_v, ws_r = mk(N.OP_SCALES), mk(N.OP_GRAM, N.GRAM_BF16X3), mk(N.OP_SOLVE), \
-        mk(N.OP_REFINE)
+    ws_p, ws_v, ws_r = mk(N.OP_PREPARE, N.GRAM_BF16X3), mk(N.OP_SOLVE), mk(N.OP_REFINE)
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     total = args.warmup + args.steps
-    marks = [[ev() for _ in range(5)] for _ in range(total)]
+    marks = [[ev() for _ in range(4)] for _ in range(total)]
 
     def step(i):
         e = marks[i]
         e[0].record()
-        N.column_scales(A, out=s, ws=ws_s)
+        N.prepare(A, B, N.GRAM_BF16X3, out=(Q, q, s), ws=ws_p)
         e[1].record()
-        N.gram_rescaled(A, B, s, N.GRAM_BF16X3, out=(Q, q), ws=ws_g)
-        e[2].record()
         N.solve(Q, q, s, tol=INNER_TOL, max_iter=5 * n, out=(X, iters, kkt, status), ws=ws_v,
                 rows_read=rows)
-        e[3].record()
+        e[2].record()
         N.refine(A, B, X, out=(kkt64, obj64), ws=ws_r)
-        e[4].record()
+        e[3].record()
 
     for i in range(args.warmup):
         step(i)
@@ -302,7 +298,7 @@ def bench_manyrhs(args):
     wall = time.perf_counter() - t0
     timed = marks[args.warmup:]
     ms = {name: float(np.mean([m[j].elapsed_time(m[j + 1]) for m in timed]))
-          for j, name in enumerate(["scales", "gram", "solve", "refine"])}
+          for j, name in enumerate(["prepare", "solve", "refine"])}
     r64 = kkt64.cpu().numpy()
     it = iters.cpu().numpy()
     ok = bool(np.all(r64 <= TOL))
@@ -318,7 +314,7 @@ def bench_manyrhs(args):
                                "B = AX + 1% noise, k=4096, seed 0", "d": d, "n": n, "k": k,
                    "tol": TOL},
         "ms": {kk: round(v, 4) for kk, v in ms.items()},
-        "gram_tflops": round(gram_flops / (ms["gram"] * 1e-3) / 1e12, 2),
+        "gram_tflops": round(gram_flops / (ms["prepare"] * 1e-3) / 1e12, 2),
         "iters": {"mean": float(it.mean()), "p99": float(np.percentile(it, 99)),
                   "max": int(it.max())},
         "kkt64": {"max": float(r64.max()), "p50": float(np.median(r64)),
@@ -510,29 +506,26 @@ def bench_warm(args):
     obj64 = torch.empty(k, dtype=torch.float64, device=dev)
     mk = lambda op, mode=0: torch.empty(max(N.workspace_bytes(op, d, n, k, mode, N.F32), 1),  # noqa
                                         dtype=torch.uint8, device=dev)
-    ws_s, ws_g, ws_v, ws_r = mk(N.OP_SCALES), mk(N.OP_GRAM, N.GRAM_BF16X3), mk(N.OP_SOLVE), \
-        mk(N.OP_REFINE)
+    ws_p, ws_v, ws_r = mk(N.OP_PREPARE, N.GRAM_BF16X3), mk(N.OP_SOLVE), mk(N.OP_REFINE)
     total_steps = args.warmup + args.steps
-    names = ["scales", "gram", "warm_start", "solve", "refine"]
+    names = ["prepare", "warm_start", "solve", "refine"]
 
     def run(warm):
-        marks = [[ev() for _ in range(6)] for _ in range(total_steps)]
+        marks = [[ev() for _ in range(5)] for _ in range(total_steps)]
 
         def one(i):
             m = marks[i]
             m[0].record()
-            N.column_scales(A, out=s, ws=ws_s)
+            N.prepare(A, Bev, N.GRAM_BF16X3, out=(Q, q, s), ws=ws_p)
             m[1].record()
-            N.gram_rescaled(A, Bev, s, N.GRAM_BF16X3, out=(Q, q), ws=ws_g)
-            m[2].record()
             if warm:
                 net.warm_start(Q, q, out=(Y0, fb))
-            m[3].record()
+            m[2].record()
             N.solve(Q, q, s, tol=INNER_TOL, max_iter=5 * n, Y0=Y0 if warm else None,
                     out=(X, iters, kkt, status), ws=ws_v, rows_read=rows)
-            m[4].record()
+            m[3].record()
             N.refine(A, Bev, X, out=(kkt64, obj64), ws=ws_r)
-            m[5].record()
+            m[4].record()
 
         for i in range(args.warmup):
             one(i)
@@ -570,8 +563,8 @@ def bench_warm(args):
     cand = {
         "solve": {"kernel": "solve_mrhs_kernel", "bound": "mfma", "flop": solve_flop,
                   "peak": PEAK_FP32_MFMA_TFLOPS},
-        "gram": {"kernel": "gram_dma_kernel", "bound": "mfma", "flop": gram_flop,
-                 "peak": PEAK_BF16X3_TFLOPS},
+        "prepare": {"kernel": "gram_dma_kernel", "bound": "mfma", "flop": gram_flop,
+                    "peak": PEAK_BF16X3_TFLOPS},
         "warm_start": {"kernel": "mlp_gemm_kernel", "bound": "mfma", "flop": mlp_flop,
                        "peak": PEAK_BF16_TFLOPS},
         "refine": {"kernel": "gemm_tn_f64_kernel", "bound": "mfma", "flop": refine_flop,

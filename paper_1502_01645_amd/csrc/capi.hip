@@ -40,6 +40,7 @@ size_t gram_ws(int64_t d, int64_t n, int64_t k, int mode) {
 
 // The scale pass and the Gram run one after the other on the stream, so they share the buffer.
 size_t prepare_ws(int64_t d, int64_t n, int64_t k, int mode) {
+  if (mode == NNLS_GRAM_BF16X3) return align_up(nnls::prepare_bf16x3_ws_bytes(d, n, k));
   size_t a = align_up(nnls::colnorm_ws_bytes(d, n));
   size_t b = gram_ws(d, n, k, mode);
   return a > b ? a : b;
@@ -210,7 +211,13 @@ int nnls_prepare(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, co
   const size_t need = prepare_ws(d, n, k, mode);
   if (ws_bytes < need || (need > 0 && !ws)) return NNLS_E_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = run_scales(d, n, A, lda, dtype, s, ws, st);
+  hipError_t e;
+  if (dtype == NNLS_F32 && mode == NNLS_GRAM_BF16X3) {
+    e = nnls::launch_prepare_bf16x3(d, n, k, (const float*)A, lda, (const float*)B, ldb, s,
+                                    (float*)Q, (float*)q, ws, st);
+    return e == hipSuccess ? NNLS_OK : hip_fail(e);
+  }
+  e = run_scales(d, n, A, lda, dtype, s, ws, st);
   if (e != hipSuccess) return hip_fail(e);
   e = run_gram(d, n, k, A, lda, B, ldb, mode, dtype, s, Q, q, ws, st);
   return e == hipSuccess ? NNLS_OK : hip_fail(e);

@@ -48,19 +48,28 @@ __global__ __launch_bounds__(256) void colnorm_partial_kernel(int64_t d, int64_t
   partial[chunk * n + col] = acc0 + acc1;
 }
 
+// Block: 64 columns; thread (column tid % 64, group tid / 64) sums the chunks g, g + 4, ... with
+// four accumulators, then the four group sums are added in fixed order.
 __global__ __launch_bounds__(256) void colnorm_finalize_kernel(int64_t n, int64_t nchunks,
                                                                const double* partial, double* s) {
-  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (col >= n) return;
+  __shared__ double red[4][64];
+  const int cl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t col = (int64_t)blockIdx.x * 64 + cl;
   double a[4] = {0.0, 0.0, 0.0, 0.0};
-  int64_t c = 0;
-  for (; c + 3 < nchunks; c += 4) {
+  if (col < n) {
+    int64_t c = grp;
+    for (; c + 12 < nchunks; c += 16) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] += partial[(c + u) * n + col];
+      for (int u = 0; u < 4; ++u) a[u] += partial[(c + 4 * u) * n + col];
+    }
+    for (; c < nchunks; c += 4) a[0] += partial[c * n + col];
   }
-  for (; c < nchunks; ++c) a[0] += partial[c * n + col];
-  const double acc = (a[0] + a[1]) + (a[2] + a[3]);
-  s[col] = acc > 0.0 ? sqrt(acc) : 1.0;
+  red[grp][cl] = (a[0] + a[1]) + (a[2] + a[3]);
+  __syncthreads();
+  if (grp == 0 && col < n) {
+    const double acc = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+    s[col] = acc > 0.0 ? sqrt(acc) : 1.0;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -369,11 +378,14 @@ __device__ __forceinline__ void gb_split_pair(float v0, float v1, uint32_t& h, u
 }
 
 // Grid (ncols_pad / 64, dpad / 64): a 64 x 64 block through LDS, transposed on the way out.
+// With colsq != nullptr the block also writes, for its columns of A, the FP64 sum of squares of
+// its 64 rows: colsq[row block][column], the partial sums of the column norms.
 __global__ __launch_bounds__(256) void presplit_kernel(int64_t d, int64_t n, int64_t k,
                                                        const float* __restrict__ A, int64_t lda,
                                                        const float* __restrict__ B, int64_t ldb,
                                                        int64_t dpad, uint16_t* __restrict__ Ph,
-                                                       uint16_t* __restrict__ Pl) {
+                                                       uint16_t* __restrict__ Pl,
+                                                       double* __restrict__ colsq) {
   __shared__ float t[PS_T][PS_T + 1];
   const int tid = threadIdx.x;
   const int64_t c0 = (int64_t)blockIdx.x * PS_T, r0 = (int64_t)blockIdx.y * PS_T;
@@ -426,12 +438,23 @@ __global__ __launch_bounds__(256) void presplit_kernel(int64_t d, int64_t n, int
   for (int pass = 0; pass < 2; ++pass) {
     const int cl = pass * 32 + (tid >> 3);
     uint32_t h[4], l[4];
+    double sq = 0.0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      gb_split_pair(t[oct * 8 + 2 * u][cl], t[oct * 8 + 2 * u + 1][cl], h[u], l[u]);
+    for (int u = 0; u < 4; ++u) {
+      const float v0 = t[oct * 8 + 2 * u][cl], v1 = t[oct * 8 + 2 * u + 1][cl];
+      gb_split_pair(v0, v1, h[u], l[u]);
+      sq += (double)v0 * (double)v0 + (double)v1 * (double)v1;
+    }
     const int64_t o = (c0 + cl) * dpad + r0 + oct * 8;
     *(u32x4*)(Ph + o) = (u32x4){h[0], h[1], h[2], h[3]};
     *(u32x4*)(Pl + o) = (u32x4){l[0], l[1], l[2], l[3]};
+    if (colsq != nullptr) {
+      // the 8 lanes of a column are consecutive: sum over them in fixed order
+      sq += __shfl_xor(sq, 1, 64);
+      sq += __shfl_xor(sq, 2, 64);
+      sq += __shfl_xor(sq, 4, 64);
+      if (oct == 0 && c0 + cl < n) colsq[(int64_t)blockIdx.y * n + c0 + cl] = sq;
+    }
   }
 }
 
@@ -759,7 +782,7 @@ hipError_t launch_colnorm(int64_t d, int64_t n, const T* A, int64_t lda, double*
   const int64_t rows = (d + chunks - 1) / chunks;
   dim3 g1((unsigned)((n + 255) / 256), (unsigned)chunks);
   hipLaunchKernelGGL(colnorm_partial_kernel<T>, g1, dim3(256), 0, st, d, n, A, lda, rows, ws);
-  hipLaunchKernelGGL(colnorm_finalize_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+  hipLaunchKernelGGL(colnorm_finalize_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st,
                      n, chunks, (const double*)ws, s);
   return hipGetLastError();
 }
@@ -818,16 +841,21 @@ size_t gram_bf16x3_ws_bytes(int64_t d, int64_t n, int64_t k) {
   return 2 * p.split_bytes + p.partial_bytes;
 }
 
-hipError_t launch_gram_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
-                              const float* B, int64_t ldb, const double* s, float* Q, float* q,
-                              float* ws, hipStream_t st) {
+// s_out != nullptr: the operand split also forms the column norms (partials in colsq) and
+// writes them to s_out = s before the main kernel reads them; otherwise s is an input.
+static hipError_t gram_bf16x3_run(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
+                                  const float* B, int64_t ldb, const double* s, float* Q, float* q,
+                                  float* ws, double* colsq, double* s_out, hipStream_t st) {
   const GramDmaPlan p = gram_dma_plan(d, n, k);
   uint16_t* Ph = (uint16_t*)ws;
   uint16_t* Pl = (uint16_t*)((char*)ws + p.split_bytes);
   float* partial = p.splits > 1 ? (float*)((char*)ws + 2 * p.split_bytes) : nullptr;
   dim3 g0((unsigned)(p.ncols_pad / PS_T), (unsigned)(p.dpad / PS_T));
   hipLaunchKernelGGL(presplit_kernel, g0, dim3(256), 0, st, d, n, k, A, lda, B, ldb, p.dpad, Ph,
-                     Pl);
+                     Pl, s_out != nullptr ? colsq : nullptr);
+  if (s_out != nullptr)
+    hipLaunchKernelGGL(colnorm_finalize_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0,
+                       st, n, p.dpad / PS_T, (const double*)colsq, s_out);
   const int blocks = schedule_blocks(p.ntiles, p.splits);
   dim3 grid((unsigned)blocks);
   hipError_t e = hipFuncSetAttribute((const void*)gram_dma_kernel,
@@ -841,6 +869,27 @@ hipError_t launch_gram_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, i
                        dim3(GD_T), 0, st, n, k, (const float*)partial, p.splits, p.ntiles,
                        p.tiles_aug, s, Q, q);
   return hipGetLastError();
+}
+
+hipError_t launch_gram_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
+                              const float* B, int64_t ldb, const double* s, float* Q, float* q,
+                              float* ws, hipStream_t st) {
+  return gram_bf16x3_run(d, n, k, A, lda, B, ldb, s, Q, q, ws, nullptr, nullptr, st);
+}
+
+size_t prepare_bf16x3_ws_bytes(int64_t d, int64_t n, int64_t k) {
+  const GramDmaPlan p = gram_dma_plan(d, n, k);
+  const size_t gram = (2 * p.split_bytes + p.partial_bytes + 255) / 256 * 256;
+  return gram + sizeof(double) * (size_t)(p.dpad / PS_T) * (size_t)n;
+}
+
+hipError_t launch_prepare_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
+                                 const float* B, int64_t ldb, double* s, float* Q, float* q,
+                                 void* ws, hipStream_t st) {
+  const GramDmaPlan p = gram_dma_plan(d, n, k);
+  const size_t gram = (2 * p.split_bytes + p.partial_bytes + 255) / 256 * 256;
+  double* colsq = (double*)((char*)ws + gram);
+  return gram_bf16x3_run(d, n, k, A, lda, B, ldb, s, Q, q, (float*)ws, colsq, s, st);
 }
 
 template <typename T>

@@ -30,6 +30,11 @@ hipError_t launch_colnorm(int64_t d, int64_t n, const T* A, int64_t lda, double*
                           hipStream_t st);
 int gram_bf16x3_splits(int64_t d, int64_t n, int64_t k);
 size_t gram_bf16x3_ws_bytes(int64_t d, int64_t n, int64_t k);
+// Column norms and the BF16x3 Gram in one pass over A (the norms come from the operand split).
+size_t prepare_bf16x3_ws_bytes(int64_t d, int64_t n, int64_t k);
+hipError_t launch_prepare_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
+                                 const float* B, int64_t ldb, double* s, float* Q, float* q,
+                                 void* ws, hipStream_t st);
 hipError_t launch_gram_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
                               const float* B, int64_t ldb, const double* s, float* Q, float* q,
                               float* ws, hipStream_t st);

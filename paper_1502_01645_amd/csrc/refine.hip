@@ -208,27 +208,38 @@ __global__ __launch_bounds__(256) void cols_partial_kernel(int64_t d, int64_t n,
   for (int m = 0; m < nvec; ++m) partial[(chunk * nvec + m) * n + i] = acc[m];
 }
 
+// Block: 64 columns x all nvec vectors; thread (column tid % 64, group tid / 64) sums the chunks
+// g, g + 4, ... with four accumulators (16 loads of a column in flight across the groups), then
+// the four group sums are added in fixed order.
 __global__ __launch_bounds__(256) void cols_finalize_kernel(int64_t n, int64_t k, int with_b,
                                                             int64_t nchunks,
                                                             const double* __restrict__ partial,
                                                             double* __restrict__ G,
                                                             double* __restrict__ Atb,
                                                             double* __restrict__ s) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
+  __shared__ double red[4][64];
+  const int cl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + cl;
   const int nvec = with_b ? (int)(2 * k + 1) : (int)k;
   for (int m = 0; m < nvec; ++m) {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    int64_t c = 0;
-    for (; c + 3 < nchunks; c += 4) {
+    if (i < n) {
+      int64_t c = grp;
+      for (; c + 12 < nchunks; c += 16) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] += partial[((c + u) * nvec + m) * n + i];
+        for (int u = 0; u < 4; ++u) a[u] += partial[((c + 4 * u) * nvec + m) * n + i];
+      }
+      for (; c < nchunks; c += 4) a[0] += partial[(c * nvec + m) * n + i];
     }
-    for (; c < nchunks; ++c) a[0] += partial[(c * nvec + m) * n + i];
-    const double acc = (a[0] + a[1]) + (a[2] + a[3]);
-    if (m < k) G[i * k + m] = acc;
-    else if (m < 2 * k) Atb[i * k + (m - k)] = acc;
-    else s[i] = acc > 0.0 ? sqrt(acc) : 1.0;
+    red[grp][cl] = (a[0] + a[1]) + (a[2] + a[3]);
+    __syncthreads();
+    if (grp == 0 && i < n) {
+      const double acc = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+      if (m < k) G[i * k + m] = acc;
+      else if (m < 2 * k) Atb[i * k + (m - k)] = acc;
+      else s[i] = acc > 0.0 ? sqrt(acc) : 1.0;
+    }
+    __syncthreads();
   }
 }
 
@@ -472,6 +483,26 @@ __global__ __launch_bounds__(256) void gref_stage3_kernel(int64_t n, int64_t k,
 }
 
 // ---- per-column steps ---------------------------------------------------------------------
+// sum over r < len of V[r * k + c]^2 by one thread, stride 256 from threadIdx.x, with eight loads
+// in flight (the sums run in eight fixed lanes of accumulation, added in a fixed order).
+__device__ __forceinline__ double strided_sumsq(const double* __restrict__ V, int64_t len,
+                                                int64_t k, int64_t c) {
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t r = threadIdx.x;
+  for (; r + 7 * 256 < len; r += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = V[(r + u * 256) * k + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += v[u] * v[u];
+  }
+  for (; r < len; r += 256) {
+    const double v = V[r * k + c];
+    a[0] += v * v;
+  }
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 // Stage 1 (after R, G, Atb, s): residual and objective at x, direction D = p ./ s, ||p||^2.
 template <typename TX>
 __global__ __launch_bounds__(256) void refine_stage1_kernel(int64_t d, int64_t n, int64_t k,
@@ -497,10 +528,7 @@ __global__ __launch_bounds__(256) void refine_stage1_kernel(int64_t d, int64_t n
     const double ai = Atb[i * k + c] / s[i];
     aa += ai * ai;
   }
-  for (int64_t r = threadIdx.x; r < d; r += 256) {
-    const double v = R[r * k + c];
-    ff += v * v;
-  }
+  ff = strided_sumsq(R, d, k, c);
   kk = block_sum<double, 256>(kk, red);
   aa = block_sum<double, 256>(aa, red);
   num = block_sum<double, 256>(num, red);
@@ -523,11 +551,7 @@ __global__ __launch_bounds__(256) void refine_stage2_kernel(int64_t d, int64_t n
                                                             double* __restrict__ colstat) {
   __shared__ double red[4];
   const int64_t c = blockIdx.x;
-  double vv = 0.0;
-  for (int64_t r = threadIdx.x; r < d; r += 256) {
-    const double v = V[r * k + c];
-    vv += v * v;
-  }
+  double vv = strided_sumsq(V, d, k, c);
   vv = block_sum<double, 256>(vv, red);
   const double num = colstat[c * 8 + 2];
   const double alpha = (vv > 0.0 && __builtin_isfinite(vv)) ? num / vv : 0.0;
@@ -552,11 +576,7 @@ __global__ __launch_bounds__(256) void refine_stage3_kernel(int64_t d, int64_t n
                                                             double* __restrict__ obj64) {
   __shared__ double red[4];
   const int64_t c = blockIdx.x;
-  double ff = 0.0, kk = 0.0;
-  for (int64_t r = threadIdx.x; r < d; r += 256) {
-    const double v = R2[r * k + c];
-    ff += v * v;
-  }
+  double ff = strided_sumsq(R2, d, k, c), kk = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += 256) {
     const double y = s[i] * Xn[i * k + c];
     const double gy = G2[i * k + c] / s[i];
@@ -691,7 +711,7 @@ static void launch_atr(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda,
     hipLaunchKernelGGL(cols_partial_kernel<T>, g1, dim3(256), 0, st, d, n, k, A, lda, R, B, ldb,
                        wb, rows, w.partial);
   }
-  hipLaunchKernelGGL(cols_finalize_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
+  hipLaunchKernelGGL(cols_finalize_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, n,
                      k, wb, w.chunks, (const double*)w.partial, G, w.Atb, w.s);
 }
 

@@ -63,6 +63,28 @@ def test_prepare_splitk_parity():
     assert (np.abs(host(q) - q_o) / bn[None, :]).max() <= tol
 
 
+@pytest.mark.parametrize("d,n,k", [(1000, 130, 1), (513, 384, 130)])
+def test_split_calls_match_prepare(d, n, k):
+    """nnls_column_scales + nnls_gram_rescaled (s computed by its own pass, then given to the
+    Gram) against the one-call nnls_prepare (s formed inside the operand split): the same s to
+    rounding, and Q, q within the BF16x3 bound of the oracle."""
+    say(f"split calls d={d} n={n} k={k}")
+    A, B = _uniform_case(d + n, d, n, k)
+    Q1, q1, s1 = N.prepare(dev(A), dev(B))
+    s2 = N.column_scales(dev(A))
+    Q2, q2 = N.gram_rescaled(dev(A), dev(B), s2)
+    s_o, Q_o, q_o = orc().prepare(A, B)
+    assert np.allclose(host(s1), s_o, rtol=1e-13, atol=0)
+    assert np.allclose(host(s2), s_o, rtol=1e-13, atol=0)
+    tol = gram_abs_tol(d, "bf16x3")
+    for Q, q in ((Q1, q1), (Q2, q2)):
+        Qh = host(Q).astype(np.float64)
+        assert np.abs(Qh - Q_o).max() <= tol
+        assert np.array_equal(Qh, Qh.T)
+        bn = np.linalg.norm(B.astype(np.float64), axis=0)
+        assert (np.abs(host(q).astype(np.float64) - q_o) / bn[None, :]).max() <= tol
+
+
 def test_prepare_fp64_parity():
     A, b, _ = W.make_small()
     say("prepare fp64 200x50")
