@@ -110,6 +110,18 @@ int nnls_prepare(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, co
  */
 int nnls_column_scales(int64_t d, int64_t n, const void* A, int64_t lda, int dtype, double* s,
                        void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * nnls_gram -- the Gram product of Problem (2) without the rescale: H = A^T A [n, n] (exactly
+ * symmetric, its diagonal as computed) and h = -A^T B [n, k] (h may be NULL when k = 0).  Solving
+ * (H, h) with nnls_solve and s = NULL runs Algorithm 2 on the unscaled problem, the method
+ * without the anti-lopsided transformation (the contrast of Figure 1 against Figure 2).
+ * Arguments, modes, layouts and errors as for nnls_gram_rescaled; workspace
+ * nnls_workspace_bytes(NNLS_OP_GRAM, ...).
+ */
+int nnls_gram(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
+              int64_t ldb, int mode, int dtype, void* H, void* h, void* ws, size_t ws_bytes,
+              void* stream);
 int nnls_gram_rescaled(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda,
                        const void* B, int64_t ldb, int mode, int dtype, const double* s, void* Q,
                        void* q, void* ws, size_t ws_bytes, void* stream);

@@ -202,6 +202,18 @@ int nnls_gram_rescaled(int64_t d, int64_t n, int64_t k, const void* A, int64_t l
   return e == hipSuccess ? NNLS_OK : hip_fail(e);
 }
 
+int nnls_gram(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
+              int64_t ldb, int mode, int dtype, void* H, void* h, void* ws, size_t ws_bytes,
+              void* stream) {
+  int rc = validate_gram(d, n, k, A, lda, B, ldb, mode, dtype, H, h);
+  if (rc != NNLS_OK) return rc;
+  const size_t need = gram_ws(d, n, k, mode);
+  if (ws_bytes < need || (need > 0 && !ws)) return NNLS_E_WORKSPACE;
+  hipError_t e = run_gram(d, n, k, A, lda, B, ldb, mode, dtype, nullptr, H, h, ws,
+                          (hipStream_t)stream);
+  return e == hipSuccess ? NNLS_OK : hip_fail(e);
+}
+
 int nnls_prepare(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
                  int64_t ldb, int mode, int dtype, void* Q, void* q, double* s, void* ws,
                  size_t ws_bytes, void* stream) {

@@ -76,7 +76,8 @@ __global__ __launch_bounds__(256) void colnorm_finalize_kernel(int64_t n, int64_
 // Epilogue shared by all Gram variants: one entry (i, j) of [A | B]^T [A | B] with i < n.
 // ---------------------------------------------------------------------------------------------
 // Q is written from one computed value per unordered pair {i, j}, so it is exactly symmetric:
-// tiles above the diagonal mirror every entry; in diagonal tiles only i <= j is emitted.
+// tiles above the diagonal mirror every entry; in diagonal tiles only i <= j is emitted.  With
+// s == nullptr nothing is rescaled: Q = H (its diagonal included) and q = -A^T B.
 template <typename T, typename Acc>
 __device__ __forceinline__ void gram_emit(int64_t i, int64_t j, Acc val, int64_t n, int64_t k,
                                           const double* __restrict__ s, T* __restrict__ Q,
@@ -85,7 +86,9 @@ __device__ __forceinline__ void gram_emit(int64_t i, int64_t j, Acc val, int64_t
   if (j < n) {
     if (diag_tile && i > j) return;
     T out;
-    if (i == j) {
+    if (s == nullptr) {
+      out = (T)val;
+    } else if (i == j) {
       out = val > (Acc)0 ? (T)1 : (T)0;
     } else {
       out = (T)((double)val / (s[i] * s[j]));
@@ -93,7 +96,7 @@ __device__ __forceinline__ void gram_emit(int64_t i, int64_t j, Acc val, int64_t
     Q[i * n + j] = out;
     if (i != j) Q[j * n + i] = out;
   } else if (j < n + k) {
-    q[i * k + (j - n)] = (T)(-(double)val / s[i]);
+    q[i * k + (j - n)] = s == nullptr ? (T)(-val) : (T)(-(double)val / s[i]);
   }
 }
 

@@ -59,6 +59,9 @@ def lib():
         L.nnls_gram_rescaled.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int,
                                          ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]
         L.nnls_gram_rescaled.restype = ctypes.c_int
+        L.nnls_gram.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, ctypes.c_int,
+                                _vp, _vp, _vp, _sz, _vp]
+        L.nnls_gram.restype = ctypes.c_int
         L.nnls_solve.restype = ctypes.c_int
         L.nnls_refine.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _vp, _vp, _vp,
                                   _vp, _sz, _vp]
@@ -215,6 +218,30 @@ def gram_rescaled(A: torch.Tensor, B: torch.Tensor | None, s: torch.Tensor, mode
                                   _ptr(q) if k > 0 else None, _ptr(ws), wsb, _stream(A.device))
     _check(rc, "nnls_gram_rescaled")
     return Q, q
+
+
+def gram(A: torch.Tensor, B: torch.Tensor | None = None, mode: int | None = None, out=None,
+         ws=None):
+    """H = A^T A and h = -A^T B without the rescale (Problem (2)).  Returns (H, h)."""
+    d, n = A.shape
+    dt = _dtype_code(A)
+    if mode is None:
+        mode = GRAM_FP64 if dt == F64 else GRAM_BF16X3
+    k = 0 if B is None else B.reshape(d, -1).shape[1]
+    if B is not None:
+        B = B.reshape(d, k)
+    if out is None:
+        H = torch.empty((n, n), dtype=A.dtype, device=A.device)
+        h = torch.empty((n, max(k, 1)), dtype=A.dtype, device=A.device)[:, :k]
+    else:
+        H, h = out
+    wsb = workspace_bytes(OP_GRAM, d, n, k, mode, dt)
+    ws = _workspace(wsb, A.device, ws)
+    rc = lib().nnls_gram(d, n, k, _ptr(A), A.stride(0), _ptr(B), B.stride(0) if B is not None else 0,
+                         mode, dt, _ptr(H), _ptr(h) if k > 0 else None, _ptr(ws), wsb,
+                         _stream(A.device))
+    _check(rc, "nnls_gram")
+    return H, h
 
 
 def solve(Q: torch.Tensor, q: torch.Tensor, s: torch.Tensor | None = None, tol: float = 1e-5,

@@ -56,6 +56,17 @@ def make_large(seed: int = 0, d: int = 20000, n: int = 5000, dtype=np.float32):
     return A, b.reshape(d, 1).astype(dtype), x
 
 
+def make_lopsided(seed: int = 0, d: int = 20000, n: int = 5000, decades: float = 2.0,
+                  dtype=np.float32):
+    """The large single right-hand side recipe with lopsided columns: column j of A is multiplied
+    by c_j = 10^u, u ~ U(-decades / 2, decades / 2) (drawn from SeedSequence([9, seed]) after the
+    base instance), b unchanged, so the solution is x / c.  Returns (A c, b, x / c, c)."""
+    A, b, x = make_large(seed, d, n, dtype=np.float64)
+    rng = np.random.default_rng(np.random.SeedSequence([9, seed]))
+    c = 10.0 ** rng.uniform(-decades / 2.0, decades / 2.0, n)
+    return (A * c[None, :]).astype(dtype), b.astype(dtype), x / c, c
+
+
 def make_manyrhs(seed: int = 0, d: int = 10000, n: int = 256, k: int = 4096, dtype=np.float32):
     """Many right-hand sides sharing A (an NMF-style update): A ~ |N(0,1)|, each column of X has
     round(0.8 n) zeros and Gamma(2,1) nonzeros, per-column noise 0.01 * RMS(b0)."""

@@ -120,6 +120,17 @@ def test_split_prepare_rejects_bad_arguments(L):
                                 FAKE, FAKE, big, None) == N.E_ARG
     assert L.nnls_gram_rescaled(10, 10, 1, FAKE, 10, FAKE, 1, N.GRAM_FP64, N.F32, FAKE, FAKE,
                                 FAKE, FAKE, big, None) == N.E_ARG
+    # the unscaled Gram: same checks, no s
+    assert L.nnls_gram(10, 10, 1, None, 10, FAKE, 1, N.GRAM_BF16X3, N.F32, FAKE, FAKE, FAKE, big,
+                       None) == N.E_ARG
+    assert L.nnls_gram(10, 10, 1, FAKE, 10, None, 1, N.GRAM_BF16X3, N.F32, FAKE, FAKE, FAKE, big,
+                       None) == N.E_ARG
+    assert L.nnls_gram(10, 10, 1, FAKE, 10, FAKE, 1, N.GRAM_BF16X3, N.F32, None, FAKE, FAKE, big,
+                       None) == N.E_ARG
+    assert L.nnls_gram(10, 10, 1, FAKE, 10, FAKE, 1, N.GRAM_FP64, N.F32, FAKE, FAKE, FAKE, big,
+                       None) == N.E_ARG
+    assert L.nnls_gram(10, 10, 1, FAKE, 10, FAKE, 1, N.GRAM_BF16X3, N.F32, FAKE, FAKE, FAKE, 0,
+                       None) == N.E_WORKSPACE
 
 
 def test_refine_rejects_bad_arguments(L):

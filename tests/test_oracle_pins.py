@@ -77,3 +77,28 @@ def test_refine_candidate_fixed_point_and_rounding():
     assert np.allclose(xc[:, 0], x, rtol=0, atol=1e-12)
     x32 = O.refine_candidate(A, b + 0.1, x, np.float32)
     assert np.array_equal(x32, x32.astype(np.float32).astype(np.float64))
+
+
+def test_unscaled_ablation_on_lopsided_columns(orc):
+    """Section 3's contrast at the size of a real problem: with column scales over two decades
+    the anti-lopsided method reaches the scale-invariant KKT residual 1e-5, while Algorithm 2 on
+    the unscaled (H, h), given the same number of updates and then ten times as many, stays
+    orders of magnitude away; its own x-space stop test is no guide (it is not scale
+    invariant)."""
+    from paper_1502_01645_amd import workloads as W
+    A, b, _, _ = W.make_lopsided(seed=0, d=2000, n=500, decades=2.0)
+    H, h = orc.gram(A, b)
+    s, Q, q = orc.rescale(H, h)
+    y, m, _, st = orc.nqp(Q, q[:, 0], 1e-5, 100000)
+    assert st == 0
+    r_s, _ = orc.kkt_x(A, b, (y / s).reshape(-1, 1))
+    assert r_s[0] <= 1e-5
+    for mult in [1, 10]:
+        x_u, it, _, _ = orc.nqp(H, h[:, 0], 0.0, mult * m)
+        assert it == mult * m
+        r_u, _ = orc.kkt_x(A, b, x_u.reshape(-1, 1))
+        assert r_u[0] >= 30 * r_s[0], (mult, r_u, r_s)
+    # stopping on the unscaled problem's own relative residual accepts a poor point
+    x_u, it, r_own, st = orc.nqp(H, h[:, 0], 1e-5, 100000)
+    r_u, _ = orc.kkt_x(A, b, x_u.reshape(-1, 1))
+    assert st == 0 and r_own <= 1e-5 and r_u[0] >= 100 * r_s[0]
