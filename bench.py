@@ -113,7 +113,7 @@ def main():
     ap.add_argument("--cpu-sample-cols", type=int, default=1400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="large",
-                    choices=["large", "manyrhs", "batched", "warm", "ablation"])
+                    choices=["large", "manyrhs", "batched", "warm", "ablation", "paper"])
     ap.add_argument("--epochs", type=int, default=WARM_EPOCHS)
     ap.add_argument("--batch", type=int, default=8192)
     args = ap.parse_args()
@@ -129,6 +129,8 @@ def main():
         return bench_warm(args)
     if args.workload == "ablation":
         return bench_ablation(args)
+    if args.workload == "paper":
+        return bench_paper(args)
 
     import torch
     from paper_1502_01645_amd import nnls as N
@@ -399,6 +401,93 @@ def bench_ablation(args):
                    "d": d, "n": n, "k": 1, "tol": TOL},
         "anti_lopsided": {"updates": m, "kkt64": r_scaled, "ms": round(ms_scaled, 4)},
         "unscaled": runs,
+    }
+    print(json.dumps(out), flush=True)
+
+
+# Mean running time in seconds of the method on each test-case kind, MATLAB on one CPU core
+# (Section 5, Table 3); context for the stand-ins, not a target.
+PAPER_TABLE3_S = {1: 146.8, 2: 11.9, 3: 71.5, 4: 12.5, 5: 154.7, 6: 12.3}
+
+
+def bench_paper(args):
+    """Stand-ins for the 30 test cases of Section 5 (kinds T1-T6, sparsity 0-40 %, n = 4000,
+    d = 6000, b = A x* without noise): each case prepared, solved to the FP32 inner tolerance
+    (at most 5 n updates, the paper's cap) and checked in FP64, timed over the steps."""
+    import torch
+    from paper_1502_01645_amd import nnls as N
+    from paper_1502_01645_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    d, n = 6000, 4000
+    mk = lambda op, mode=0: torch.empty(max(N.workspace_bytes(op, d, n, 1, mode, N.F32), 1),  # noqa
+                                        dtype=torch.uint8, device=dev)
+    ws_p, ws_v, ws_r = mk(N.OP_PREPARE, N.GRAM_BF16X3), mk(N.OP_SOLVE), mk(N.OP_REFINE)
+    Q = torch.empty((n, n), dtype=torch.float32, device=dev)
+    q = torch.empty((n, 1), dtype=torch.float32, device=dev)
+    s = torch.empty(n, dtype=torch.float64, device=dev)
+    X = torch.empty((n, 1), dtype=torch.float32, device=dev)
+    iters = torch.empty(1, dtype=torch.int32, device=dev)
+    kkt = torch.empty(1, dtype=torch.float64, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    kkt64 = torch.empty(1, dtype=torch.float64, device=dev)
+    obj64 = torch.empty(1, dtype=torch.float64, device=dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    cases, total_ms, total_solves = [], 0.0, 0
+    for kind in range(1, 7):
+        for sp in W.PAPER_SPARSITY:
+            A_h, b_h, _ = W.make_paper_case(kind, sp)
+            A = torch.from_numpy(A_h).to(dev)
+            b = torch.from_numpy(b_h).to(dev)
+
+            def one():
+                N.prepare(A, b, N.GRAM_BF16X3, out=(Q, q, s), ws=ws_p)
+                N.solve(Q, q, s, tol=INNER_TOL, max_iter=5 * n, out=(X, iters, kkt, status),
+                        ws=ws_v)
+                N.refine(A, b, X, out=(kkt64, obj64), ws=ws_r)
+
+            for _ in range(args.warmup):
+                one()
+            torch.cuda.synchronize()
+            e0, e1 = ev(), ev()
+            e0.record()
+            for _ in range(args.steps):
+                one()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            total_ms += ms * args.steps
+            total_solves += args.steps
+            cases.append({"kind": kind, "sparsity": sp, "ms": round(ms, 3),
+                          "updates": int(iters.cpu()[0]), "status": int(status.cpu()[0]),
+                          "kkt64": float(kkt64.cpu()[0]), "obj64": float(obj64.cpu()[0])})
+            del A, b
+    ok = all(c["kkt64"] <= TOL for c in cases)
+    per_kind = {}
+    for kind in range(1, 7):
+        cs = [c for c in cases if c["kind"] == kind]
+        mean_ms = float(np.mean([c["ms"] for c in cs]))
+        per_kind[f"T{kind}"] = {
+            "signs_lengths": "/".join(W.PAPER_KINDS[kind]),
+            "mean_ms": round(mean_ms, 3),
+            "mean_updates": float(np.mean([c["updates"] for c in cs])),
+            "max_kkt64": max(c["kkt64"] for c in cs),
+            "cases_meeting_tol": sum(c["kkt64"] <= TOL for c in cs),
+            "paper_table3_s": PAPER_TABLE3_S[kind],
+            "paper_time_over_ours": round(PAPER_TABLE3_S[kind] / (mean_ms * 1e-3), 1),
+        }
+    out = {
+        "metric": "NNLS solves/sec at rel KKT<=1e-5 on stand-ins of the paper's test cases T1-T6",
+        "value": round(total_solves / (total_ms * 1e-3), 3) if ok else 0.0,
+        "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(total_ms / total_solves, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3-gram/f32-iter/f64-check",
+        "data": "synthetic",
+        "config": {"workload": "30 stand-ins of Section 5's test cases: kinds T1-T6 (signs +/+-, "
+                               "column lengths SAM/RAN/VAR), sparsity 0-40 %, A 6000x4000, "
+                               "b = A x* noiseless", "d": d, "n": n, "tol": TOL},
+        "per_kind": per_kind,
+        "cases": cases,
     }
     print(json.dumps(out), flush=True)
 

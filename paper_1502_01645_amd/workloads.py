@@ -67,6 +67,45 @@ def make_lopsided(seed: int = 0, d: int = 20000, n: int = 5000, decades: float =
     return (A * c[None, :]).astype(dtype), b.astype(dtype), x / c, c
 
 
+PAPER_KINDS = {  # kind: (signs of A and x*, column lengths), Section 5, Table 1
+    1: ("+", "SAM"), 2: ("+-", "RAN"), 3: ("+", "VAR"),
+    4: ("+-", "SAM"), 5: ("+", "RAN"), 6: ("+-", "VAR"),
+}
+PAPER_SPARSITY = (0.0, 0.1, 0.2, 0.3, 0.4)
+
+
+def make_paper_case(kind: int, sparsity: float, seed: int = 0, d: int = 6000, n: int = 4000,
+                    dtype=np.float32):
+    """Stand-in for test case T<kind> of Section 5 (the paper's 30 cases were never published):
+    A [d, n] and x* [n] nonnegative (entries U[0, 1]) or mixed-sign (U[-1, 1]); round(sparsity d)
+    zeros in every column of A and round(sparsity n) zeros in x*; the columns of A then scaled to
+    the same length 1 (SAM), to random lengths U(0, 1] (RAN) or to lengths 10^U(-2, 2) spanning
+    four decades (VAR); b = A x* without noise.  Returns (A, b [d, 1], x*)."""
+    signs, lengths = PAPER_KINDS[kind]
+    rng = np.random.default_rng(np.random.SeedSequence([11, kind, int(round(100 * sparsity)),
+                                                        seed]))
+    lo = 0.0 if signs == "+" else -1.0
+    A = rng.uniform(lo, 1.0, (d, n))
+    nz = int(round(sparsity * d))
+    if nz:
+        for j in range(n):
+            A[rng.permutation(d)[:nz], j] = 0.0
+    norms = np.linalg.norm(A, axis=0)
+    norms[norms == 0] = 1.0
+    if lengths == "SAM":
+        target = np.ones(n)
+    elif lengths == "RAN":
+        target = 1.0 - rng.random(n)            # U(0, 1]
+    else:
+        target = 10.0 ** rng.uniform(-2.0, 2.0, n)
+    A *= (target / norms)[None, :]
+    x = rng.uniform(lo, 1.0, n)
+    x[rng.permutation(n)[: int(round(sparsity * n))]] = 0.0
+    A = A.astype(dtype)
+    b = A.astype(np.float64) @ x
+    return A, b.reshape(d, 1).astype(dtype), x
+
+
 def make_manyrhs(seed: int = 0, d: int = 10000, n: int = 256, k: int = 4096, dtype=np.float32):
     """Many right-hand sides sharing A (an NMF-style update): A ~ |N(0,1)|, each column of X has
     round(0.8 n) zeros and Gamma(2,1) nonzeros, per-column noise 0.01 * RMS(b0)."""
