@@ -74,6 +74,23 @@ def traffic_record(kernel_key, src):
     return rec.get("bytes_per_launch")
 
 
+def stage_rooflines(N, d, n, k, ms, rows_read):
+    """Rooflines of the prepare call (BF16x3 Gram flops d n (n + 1) + 2 d n k over the call's
+    time) and of the single-RHS solver (4 n bytes per row of Q a streaming solver reads, over the
+    solve time); returns (dominant, other) by time."""
+    gram_tf = (d * n * (n + 1) + 2.0 * d * n * k) / (ms["prepare"] * 1e-3) / 1e12
+    solve_gbs = 4.0 * n * rows_read / (ms["solve"] * 1e-3) / 1e9
+    solver = N.solver_name(n, k, N.F32)
+    kern = {"regq": "solve_regq_kernel", "persistent": "solve_persistent_kernel"}.get(
+        solver, "solve_" + solver + "_kernel")
+    rg = {"kernel": "gram_dma_kernel", "timed": "nnls_prepare call", "bound": "mfma",
+          "achieved": round(gram_tf, 2), "peak": round(PEAK_BF16X3_TFLOPS, 1),
+          "unit": "TFLOP/s", "frac": round(gram_tf / PEAK_BF16X3_TFLOPS, 4), "traffic": None}
+    rs = {"kernel": kern, "bound": "hbm", "achieved": round(solve_gbs, 1), "peak": PEAK_HBM_GBS,
+          "unit": "GB/s", "frac": round(solve_gbs / PEAK_HBM_GBS, 4), "traffic": None}
+    return (rg, rs) if ms["prepare"] >= ms["solve"] else (rs, rg)
+
+
 def cpu_baseline(A, b, n_full, iters_full, cols):
     """The FP64 oracle on the first `cols` columns of the workload (same b): Gram, rescale and
     Algorithm 2, each timed; a full-size solve is extrapolated with the Gram's d n (n+1) cost and
@@ -359,22 +376,33 @@ def bench_ablation(args):
     obj64 = torch.empty(1, dtype=torch.float64, device=dev)
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
 
-    def scaled():
-        N.prepare(A, b, N.GRAM_BF16X3, out=(Q, q, s), ws=ws_p)
-        N.solve(Q, q, s, tol=INNER_TOL, max_iter=5 * n, out=(X, iters, kkt, status), ws=ws_v)
-        N.refine(A, b, X, out=(kkt64, obj64), ws=ws_r)
+    rows = torch.zeros(1, dtype=torch.int64, device=dev)
+    marks = [[ev() for _ in range(4)] for _ in range(args.warmup + args.steps)]
 
-    for _ in range(args.warmup):
-        scaled()
+    def scaled(i):
+        e = marks[i]
+        e[0].record()
+        N.prepare(A, b, N.GRAM_BF16X3, out=(Q, q, s), ws=ws_p)
+        e[1].record()
+        N.solve(Q, q, s, tol=INNER_TOL, max_iter=5 * n, out=(X, iters, kkt, status), ws=ws_v,
+                rows_read=rows)
+        e[2].record()
+        N.refine(A, b, X, out=(kkt64, obj64), ws=ws_r)
+        e[3].record()
+
+    for i in range(args.warmup):
+        scaled(i)
     torch.cuda.synchronize()
-    e0, e1 = ev(), ev()
-    e0.record()
-    for _ in range(args.steps):
-        scaled()
-    e1.record()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, args.warmup + args.steps):
+        scaled(i)
     torch.cuda.synchronize()
-    ms_scaled = e0.elapsed_time(e1) / args.steps
+    ms_scaled = (time.perf_counter() - t0) * 1e3 / args.steps
+    timed = marks[args.warmup:]
+    ms = {nm: float(np.mean([mk_[j].elapsed_time(mk_[j + 1]) for mk_ in timed]))
+          for j, nm in enumerate(["prepare", "solve", "refine"])}
     m = int(iters.cpu()[0])
+    roof = stage_rooflines(N, d, n, 1, ms, int(rows.cpu()[0]))
     r_scaled = float(kkt64.cpu()[0])
     ok = r_scaled <= TOL and int(status.cpu()[0]) == 0
 
@@ -399,9 +427,13 @@ def bench_ablation(args):
         "config": {"workload": "lopsided large single RHS: A 20000x5000 U[0,1] with column j "
                                "scaled by 10^U(-1,1), x 70% zeros Exp(1), 1% noise, seed 0",
                    "d": d, "n": n, "k": 1, "tol": TOL},
-        "anti_lopsided": {"updates": m, "kkt64": r_scaled, "ms": round(ms_scaled, 4)},
+        "roofline": roof[0], "roofline_other": roof[1],
+        "anti_lopsided": {"updates": m, "kkt64": r_scaled, "ms": round(ms_scaled, 4),
+                          "ms_stages": {kk: round(v, 4) for kk, v in ms.items()}},
         "unscaled": runs,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A_h, b_h, n, m, args.cpu_sample_cols)
     print(json.dumps(out), flush=True)
 
 
@@ -434,28 +466,40 @@ def bench_paper(args):
     obj64 = torch.empty(1, dtype=torch.float64, device=dev)
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     cases, total_ms, total_solves = [], 0.0, 0
+    rows = torch.zeros(1, dtype=torch.int64, device=dev)
+    stage_ms = {"prepare": 0.0, "solve": 0.0, "refine": 0.0}
+    rows_total = 0
     for kind in range(1, 7):
         for sp in W.PAPER_SPARSITY:
             A_h, b_h, _ = W.make_paper_case(kind, sp)
             A = torch.from_numpy(A_h).to(dev)
             b = torch.from_numpy(b_h).to(dev)
 
-            def one():
-                N.prepare(A, b, N.GRAM_BF16X3, out=(Q, q, s), ws=ws_p)
-                N.solve(Q, q, s, tol=INNER_TOL, max_iter=5 * n, out=(X, iters, kkt, status),
-                        ws=ws_v)
-                N.refine(A, b, X, out=(kkt64, obj64), ws=ws_r)
+            marks = [[ev() for _ in range(4)] for _ in range(args.warmup + args.steps)]
 
-            for _ in range(args.warmup):
-                one()
+            def one(i):
+                e = marks[i]
+                e[0].record()
+                N.prepare(A, b, N.GRAM_BF16X3, out=(Q, q, s), ws=ws_p)
+                e[1].record()
+                N.solve(Q, q, s, tol=INNER_TOL, max_iter=5 * n, out=(X, iters, kkt, status),
+                        ws=ws_v, rows_read=rows)
+                e[2].record()
+                N.refine(A, b, X, out=(kkt64, obj64), ws=ws_r)
+                e[3].record()
+
+            for i in range(args.warmup):
+                one(i)
             torch.cuda.synchronize()
-            e0, e1 = ev(), ev()
-            e0.record()
-            for _ in range(args.steps):
-                one()
-            e1.record()
+            t0 = time.perf_counter()
+            for i in range(args.warmup, args.warmup + args.steps):
+                one(i)
             torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / args.steps
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            timed = marks[args.warmup:]
+            for j, nm in enumerate(["prepare", "solve", "refine"]):
+                stage_ms[nm] += float(np.mean([e[j].elapsed_time(e[j + 1]) for e in timed]))
+            rows_total += int(rows.cpu()[0])
             total_ms += ms * args.steps
             total_solves += args.steps
             cases.append({"kind": kind, "sparsity": sp, "ms": round(ms, 3),
@@ -489,6 +533,26 @@ def bench_paper(args):
         "per_kind": per_kind,
         "cases": cases,
     }
+    # rooflines over the whole set: summed flops / bytes over summed per-case times
+    ncase = len(cases)
+    roof = stage_rooflines(N, d, n, 1, {kk: v / ncase for kk, v in stage_ms.items()},
+                           rows_total / ncase)
+    out["roofline"], out["roofline_other"] = roof
+    out["ms_stages_mean"] = {kk: round(v / ncase, 4) for kk, v in stage_ms.items()}
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        orc = O.load()
+        A_h, b_h, _ = W.make_paper_case(3, 0.2)
+        t0 = time.perf_counter()
+        H, h = orc.gram(A_h, b_h)
+        sc, Qo, qo = orc.rescale(H, h)
+        _, it_o, _, _ = orc.nqp(Qo, qo[:, 0], TOL, 5 * n)
+        t_o = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1.0 / t_o, "unit": "solves/s", "cores": orc.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"one full case (T3, 20 % sparsity, 6000 x 4000): Gram, "
+                                         f"rescale and {it_o} updates of Algorithm 2 in FP64, "
+                                         f"{t_o:.1f} s"}
     print(json.dumps(out), flush=True)
 
 
