@@ -290,6 +290,15 @@ size_t nnls_warm_start_workspace_bytes(int64_t n, int64_t k);
 int nnls_warm_start(int64_t n, int64_t k, const float* Q, const float* q, const void* blob,
                     float* Y0, int32_t* fell_back, void* ws, size_t ws_bytes, void* stream);
 
+/* nnls_transpose -- dst[j, i] = src[i, j] for FP32 src [rows, cols] (row-major, leading
+ * dimension ld_src >= cols) into dst [cols, rows] (ld_dst >= rows); device pointers, caller-owned,
+ * not overlapping.  The data movement of the alternating NNLS update of a nonnegative matrix
+ * factorisation V ~ W H (the use the Introduction motivates): the W half solves NNLS with the
+ * matrix H^T and right-hand sides V^T.  NNLS_E_ARG for bad sizes or pointers,
+ * NNLS_E_UNSUPPORTED for more than 65535 x 64 rows. */
+int nnls_transpose(int64_t rows, int64_t cols, const float* src, int64_t ld_src, float* dst,
+                   int64_t ld_dst, void* stream);
+
 /* Which solver nnls_solve uses for this shape on the current device: "regq" (one right-hand
  * side, Q held in the register file of the whole GPU), "persistent" (one right-hand side, Q
  * streamed from memory), "mrhs" (many right-hand sides on the matrix cores) or "wg" (one

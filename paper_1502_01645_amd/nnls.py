@@ -62,6 +62,8 @@ def lib():
         L.nnls_gram.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, ctypes.c_int,
                                 _vp, _vp, _vp, _sz, _vp]
         L.nnls_gram.restype = ctypes.c_int
+        L.nnls_transpose.argtypes = [_i64, _i64, _vp, _i64, _vp, _i64, _vp]
+        L.nnls_transpose.restype = ctypes.c_int
         L.nnls_solve.restype = ctypes.c_int
         L.nnls_refine.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _vp, _vp, _vp,
                                   _vp, _sz, _vp]
@@ -242,6 +244,18 @@ def gram(A: torch.Tensor, B: torch.Tensor | None = None, mode: int | None = None
                          _stream(A.device))
     _check(rc, "nnls_gram")
     return H, h
+
+
+def transpose(src: torch.Tensor, out=None) -> torch.Tensor:
+    """dst = src^T for an FP32 matrix (row-major, unit column stride)."""
+    assert src.dim() == 2 and src.stride(1) == 1 and src.dtype == torch.float32
+    rows, cols = src.shape
+    dst = out if out is not None else torch.empty((cols, rows), dtype=src.dtype, device=src.device)
+    assert dst.shape == (cols, rows) and dst.stride(1) == 1
+    rc = lib().nnls_transpose(rows, cols, _ptr(src), src.stride(0), _ptr(dst), dst.stride(0),
+                              _stream(src.device))
+    _check(rc, "nnls_transpose")
+    return dst
 
 
 def solve(Q: torch.Tensor, q: torch.Tensor, s: torch.Tensor | None = None, tol: float = 1e-5,

@@ -106,6 +106,25 @@ def make_paper_case(kind: int, sparsity: float, seed: int = 0, d: int = 6000, n:
     return A, b.reshape(d, 1).astype(dtype), x
 
 
+def make_nmf(seed: int = 0, m: int = 10000, p: int = 4096, r: int = 256, dtype=np.float32):
+    """Data for a nonnegative factorisation: V = max(W* H* + noise, 0) with W* [m, r] U[0,1] with
+    30 % zeros per column, H* [r, p] with 70 % zeros per column and Exp(1) nonzeros, noise
+    0.01 * RMS(W* H*); the start W0 [m, r] is U[0,1] from its own stream SeedSequence([13, seed]).
+    Returns (V, W0, W*, H*)."""
+    rng = np.random.default_rng(np.random.SeedSequence([12, seed]))
+    Ws = rng.random((m, r))
+    for j in range(r):
+        Ws[rng.permutation(m)[: int(round(0.3 * m))], j] = 0.0
+    Hs = np.zeros((r, p))
+    for c in range(p):
+        Hs[:, c] = _zero_pattern(rng, r, int(round(0.7 * r)), lambda k: rng.exponential(1.0, k))
+    V0 = Ws @ Hs
+    rms = float(np.sqrt(np.mean(V0 * V0)))
+    V = np.maximum(V0 + rng.normal(0.0, 0.01 * rms, V0.shape), 0.0)
+    W0 = np.random.default_rng(np.random.SeedSequence([13, seed])).random((m, r))
+    return V.astype(dtype), W0.astype(dtype), Ws, Hs
+
+
 def make_manyrhs(seed: int = 0, d: int = 10000, n: int = 256, k: int = 4096, dtype=np.float32):
     """Many right-hand sides sharing A (an NMF-style update): A ~ |N(0,1)|, each column of X has
     round(0.8 n) zeros and Gamma(2,1) nonzeros, per-column noise 0.01 * RMS(b0)."""
