@@ -299,6 +299,14 @@ int nnls_warm_start(int64_t n, int64_t k, const float* Q, const float* q, const 
 int nnls_transpose(int64_t rows, int64_t cols, const float* src, int64_t ld_src, float* dst,
                    int64_t ld_dst, void* stream);
 
+/* nnls_rescale_start -- Y0 = s .* X (row i of the FP32 [n, k] X times s[i], FP64 product rounded
+ * to FP32): a start given in the original variables x, such as the previous factor in an
+ * alternating NNLS loop, mapped to the rescaled variables y = D^(1/2) x of rescaling (4) in which
+ * nnls_solve takes its start (the worked example of Section 3 starts the same way).  s as
+ * written by nnls_prepare; device pointers; NNLS_E_ARG for bad sizes or pointers. */
+int nnls_rescale_start(int64_t n, int64_t k, const double* s, const float* X, float* Y0,
+                       void* stream);
+
 /* Which solver nnls_solve uses for this shape on the current device: "regq" (one right-hand
  * side, Q held in the register file of the whole GPU), "persistent" (one right-hand side, Q
  * streamed from memory), "mrhs" (many right-hand sides on the matrix cores) or "wg" (one

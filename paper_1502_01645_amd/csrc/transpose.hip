@@ -52,3 +52,33 @@ extern "C" int nnls_transpose(int64_t rows, int64_t cols, const float* src, int6
   }
   return NNLS_OK;
 }
+
+namespace nnls {
+
+// Y0[i, c] = s[i] * X[i, c]: a start point in the original variables mapped to the rescaled ones
+// (rescaling (4), y = D^(1/2) x), the form in which Algorithm 2 takes a start.
+__global__ __launch_bounds__(256) void rescale_start_kernel(int64_t n, int64_t k,
+                                                            const double* __restrict__ s,
+                                                            const float* __restrict__ X,
+                                                            float* __restrict__ Y0) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * k) return;
+  Y0[e] = (float)(s[e / k] * (double)X[e]);
+}
+
+}  // namespace nnls
+
+extern "C" int nnls_rescale_start(int64_t n, int64_t k, const double* s, const float* X,
+                                  float* Y0, void* stream) {
+  if (n < 1 || k < 1 || !s || !X || !Y0) return NNLS_E_ARG;
+  const int64_t blocks = (n * k + 255) / 256;
+  if (blocks > (int64_t(1) << 31) - 1) return NNLS_E_UNSUPPORTED;
+  hipLaunchKernelGGL(nnls::rescale_start_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     (hipStream_t)stream, n, k, s, X, Y0);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    nnls::record_hip_error(e);
+    return NNLS_E_HIP;
+  }
+  return NNLS_OK;
+}

@@ -6,7 +6,9 @@ Each half of an outer step is one NNLS problem with many right-hand sides sharin
     W <- argmin_{W >= 0} ||V^T - H^T W^T||: matrix H^T [p, r], right-hand sides the m columns of
                                             V^T, the transposes made by nnls_transpose.
 Each half runs nnls_prepare (Gram and rescale, Algorithm 1), nnls_solve (Algorithm 2 on the
-matrix cores) and nnls_refine, whose FP64 objectives give 1/2 ||V - W H||_F^2 exactly.  This
+matrix cores; after the first step started from the half's previous factor, mapped to the
+rescaled variables by nnls_rescale_start) and nnls_refine, whose FP64 objectives give
+1/2 ||V - W H||_F^2 exactly.  This
 module only orders the calls and owns the buffers; every arithmetic step runs in the library.
 """
 from __future__ import annotations
@@ -21,7 +23,7 @@ class AlternatingNNLS:
     max_iter caps the updates per column (the paper's 5 n is far too few at a small rank r)."""
 
     def __init__(self, V: torch.Tensor, W0: torch.Tensor, tol: float = 1e-5,
-                 inner_tol: float = 8e-6, max_iter: int = 100000):
+                 inner_tol: float = 8e-6, max_iter: int = 100000, warm: bool = True):
         assert V.dim() == 2 and V.dtype == torch.float32 and V.stride(1) == 1
         m, p = V.shape
         r = W0.shape[1]
@@ -29,6 +31,8 @@ class AlternatingNNLS:
         dev = V.device
         self.m, self.p, self.r = m, p, r
         self.tol, self.inner_tol, self.max_iter = tol, inner_tol, max_iter
+        self.warm = warm
+        self.steps_done = 0
         self.V = V
         self.Vt = N.transpose(V)
         self.W = W0.contiguous().clone()
@@ -44,6 +48,7 @@ class AlternatingNNLS:
                                    dtype=torch.uint8, device=dev)
             return dict(Q=torch.empty((r, r), dtype=f32, device=dev),
                         q=torch.empty((r, k), dtype=f32, device=dev),
+                        Y0=torch.empty((r, k), dtype=f32, device=dev),
                         s=torch.empty(r, dtype=f64, device=dev),
                         iters=torch.empty(k, dtype=i32, device=dev),
                         kkt=torch.empty(k, dtype=f64, device=dev),
@@ -58,10 +63,15 @@ class AlternatingNNLS:
 
     def _solve(self, h, A, B, X, mark):
         N.prepare(A, B, N.GRAM_BF16X3, out=(h["Q"], h["q"], h["s"]), ws=h["ws_p"])
+        # after the first step, X holds this half's previous factor: start from it
+        warm = self.warm and self.steps_done > 0
+        if warm:
+            N.rescale_start(h["s"], X, out=h["Y0"])
         mark()
         h["rows"].zero_()
         N.solve(h["Q"], h["q"], h["s"], tol=self.inner_tol, max_iter=self.max_iter,
-                out=(X, h["iters"], h["kkt"], h["status"]), ws=h["ws_v"], rows_read=h["rows"])
+                Y0=h["Y0"] if warm else None, out=(X, h["iters"], h["kkt"], h["status"]),
+                ws=h["ws_v"], rows_read=h["rows"])
         mark()
         N.refine(A, B, X, out=(h["kkt64"], h["obj64"]), ws=h["ws_r"])
         mark()
@@ -84,6 +94,7 @@ class AlternatingNNLS:
         self._solve(self.hw, self.Ht, self.Vt, self.Wt, mark)
         N.transpose(self.Wt, out=self.W)
         mark()
+        self.steps_done += 1
 
     def objective(self):
         """(1/2 ||V - W H||^2 after the H half, after the W half), FP64."""

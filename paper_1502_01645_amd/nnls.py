@@ -64,6 +64,8 @@ def lib():
         L.nnls_gram.restype = ctypes.c_int
         L.nnls_transpose.argtypes = [_i64, _i64, _vp, _i64, _vp, _i64, _vp]
         L.nnls_transpose.restype = ctypes.c_int
+        L.nnls_rescale_start.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp]
+        L.nnls_rescale_start.restype = ctypes.c_int
         L.nnls_solve.restype = ctypes.c_int
         L.nnls_refine.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _vp, _vp, _vp,
                                   _vp, _sz, _vp]
@@ -256,6 +258,16 @@ def transpose(src: torch.Tensor, out=None) -> torch.Tensor:
                               _stream(src.device))
     _check(rc, "nnls_transpose")
     return dst
+
+
+def rescale_start(s: torch.Tensor, X: torch.Tensor, out=None) -> torch.Tensor:
+    """Y0 = s .* X: a start in the original variables mapped to the rescaled ones."""
+    assert X.dim() == 2 and X.is_contiguous() and X.dtype == torch.float32
+    n, k = X.shape
+    Y0 = out if out is not None else torch.empty_like(X)
+    rc = lib().nnls_rescale_start(n, k, _ptr(s), _ptr(X), _ptr(Y0), _stream(X.device))
+    _check(rc, "nnls_rescale_start")
+    return Y0
 
 
 def solve(Q: torch.Tensor, q: torch.Tensor, s: torch.Tensor | None = None, tol: float = 1e-5,

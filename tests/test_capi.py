@@ -133,6 +133,18 @@ def test_split_prepare_rejects_bad_arguments(L):
                        None) == N.E_WORKSPACE
 
 
+def test_nmf_helpers_reject_bad_arguments(L):
+    from paper_1502_01645_amd import nnls as N
+    assert L.nnls_transpose(0, 5, FAKE, 5, FAKE, 1, None) == N.E_ARG
+    assert L.nnls_transpose(5, 5, None, 5, FAKE, 5, None) == N.E_ARG
+    assert L.nnls_transpose(5, 6, FAKE, 5, FAKE, 5, None) == N.E_ARG    # ld_src < cols
+    assert L.nnls_transpose(5, 6, FAKE, 6, FAKE, 4, None) == N.E_ARG    # ld_dst < rows
+    assert L.nnls_transpose(64 * 65536, 1, FAKE, 1, FAKE, 64 * 65536, None) == N.E_UNSUPPORTED
+    assert L.nnls_rescale_start(0, 3, FAKE, FAKE, FAKE, None) == N.E_ARG
+    assert L.nnls_rescale_start(3, 3, None, FAKE, FAKE, None) == N.E_ARG
+    assert L.nnls_rescale_start(3, 3, FAKE, FAKE, None, None) == N.E_ARG
+
+
 def test_refine_rejects_bad_arguments(L):
     from paper_1502_01645_amd import nnls as N
     big = 1 << 40

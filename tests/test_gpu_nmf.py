@@ -68,3 +68,33 @@ def test_nmf_objective_decreases():
     for a, b in zip(objs, objs[1:]):
         assert b <= a * (1 + 1e-6)
     assert objs[-1] < 0.9 * objs[0]
+
+
+def test_rescale_start():
+    rng = np.random.default_rng(9)
+    s = rng.random(37) * 10 + 0.1
+    X = rng.random((37, 5)).astype(np.float32)
+    Y = host(N.rescale_start(dev(s), dev(X)))
+    assert np.array_equal(Y, (s[:, None] * X.astype(np.float64)).astype(np.float32))
+
+
+def test_nmf_warm_steps_match_oracle():
+    """From the second step on each half starts from its previous factor: the halves still land
+    on the oracle's solutions of their own problems, with fewer updates than cold starts."""
+    m, p, r = 240, 150, 12
+    V, W0, _, _ = W.make_nmf(seed=5, m=m, p=p, r=r)
+    say(f"nmf warm steps {m} x {p} rank {r}")
+    warm = F.AlternatingNNLS(dev(V), dev(W0), inner_tol=3e-6)
+    cold = F.AlternatingNNLS(dev(V), dev(W0), inner_tol=3e-6, warm=False)
+    for _ in range(3):
+        W_prev = host(warm.W).astype(np.float32)
+        warm.step()
+        cold.step()
+    H3, W3 = host(warm.H).astype(np.float64), host(warm.W).astype(np.float64)
+    _check(W_prev, V, H3, "H half, warm")
+    _check(H3.astype(np.float32).T.copy(), V.T.copy(), W3.T.copy(), "W half, warm")
+    uw, uc = warm.stats(), cold.stats()
+    say(f"  mean updates warm H {uw['H']['updates_mean']:.1f} W {uw['W']['updates_mean']:.1f}; "
+        f"cold H {uc['H']['updates_mean']:.1f} W {uc['W']['updates_mean']:.1f}")
+    assert uw["H"]["updates_mean"] < uc["H"]["updates_mean"]
+    assert uw["W"]["updates_mean"] < uc["W"]["updates_mean"]
