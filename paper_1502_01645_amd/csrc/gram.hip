@@ -680,23 +680,56 @@ hipError_t launch_batched_gram(const BatchDesc* desc, int64_t count, const float
   return hipGetLastError();
 }
 
-// Sum of split-K partial tiles in fixed split order, then the rescale epilogue.
-// Sum of the split-K partial tiles and the rescale epilogue: block (tile, row of the tile), one
-// thread per column (TILE = 256 threads), so every partial row is one coalesced read.
+// Sum of the split-K partial tiles in fixed split order and the rescale epilogue.  Block (tile,
+// 8-row band of the tile), one thread per column: the band's 8 partial rows of a split are read
+// together (coalesced, 8 loads in flight per thread) and the direct write Q[i, j] is coalesced;
+// the rescaled band is staged in LDS so that thread jj writes the mirrored Q[j, i] as 8
+// consecutive floats of row j.  Same values and rules as gram_emit (s == nullptr: no rescale).
+constexpr int GE_BAND = 8;
+
 template <int TILE>
 __global__ __launch_bounds__(TILE) void gram_splitk_epilogue_kernel(
     int64_t n, int64_t k, const float* __restrict__ partial, int nsplit, int ntiles,
     int tiles_aug, const double* __restrict__ s, float* __restrict__ Q, float* __restrict__ q) {
+  __shared__ float band[GE_BAND][TILE + 1];
   int ti, tj;
   decode_tile(blockIdx.x, tiles_aug, ti, tj);
   const bool diag = (ti == tj);
-  const int li = blockIdx.y, lj = threadIdx.x;
-  const int64_t e = (int64_t)li * TILE + lj;
-  float acc = 0.f;
-  for (int sp = 0; sp < nsplit; ++sp)
-    acc += partial[((int64_t)sp * ntiles + blockIdx.x) * (TILE * TILE) + e];
-  gram_emit<float, float>((int64_t)ti * TILE + li, (int64_t)tj * TILE + lj, acc, n, k, s, Q, q,
-                          diag);
+  const int64_t i0 = (int64_t)ti * TILE + (int64_t)blockIdx.y * GE_BAND, j0 = (int64_t)tj * TILE;
+  const int lj = threadIdx.x;
+  const int64_t j = j0 + lj;
+  const float* src = partial + (int64_t)blockIdx.x * (TILE * TILE) +
+                     (int64_t)blockIdx.y * GE_BAND * TILE + lj;
+  float acc[GE_BAND];
+#pragma unroll
+  for (int r = 0; r < GE_BAND; ++r) acc[r] = 0.f;
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const float* sp_src = src + (int64_t)sp * ntiles * (TILE * TILE);
+#pragma unroll
+    for (int r = 0; r < GE_BAND; ++r) acc[r] += sp_src[r * TILE];
+  }
+#pragma unroll
+  for (int r = 0; r < GE_BAND; ++r) {
+    const int64_t i = i0 + r;
+    float out = acc[r];
+    if (i < n && j < n) {
+      if (s != nullptr)
+        out = (i == j) ? (acc[r] > 0.f ? 1.f : 0.f) : (float)((double)acc[r] / (s[i] * s[j]));
+      if (!(diag && i > j)) Q[i * n + j] = out;
+    } else if (i < n && j < n + k) {
+      q[i * k + (j - n)] = s == nullptr ? -acc[r] : (float)(-(double)acc[r] / s[i]);
+    }
+    band[r][lj] = out;
+  }
+  __syncthreads();
+  // mirror: thread jj writes row j0 + jj, columns i0 .. i0 + 7
+  if (j < n) {
+#pragma unroll
+    for (int r = 0; r < GE_BAND; ++r) {
+      const int64_t i = i0 + r;
+      if (i < n && i != j && !(diag && i > j)) Q[j * n + i] = band[r][lj];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -868,9 +901,9 @@ static hipError_t gram_bf16x3_run(int64_t d, int64_t n, int64_t k, const float* 
                      (const uint16_t*)Ph, (const uint16_t*)Pl, p.dpad, s, Q, q, partial, p.tiles_a,
                      p.tiles_aug, p.ntiles, p.splits, p.rows_per_split);
   if (p.splits > 1)
-    hipLaunchKernelGGL(gram_splitk_epilogue_kernel<GD_T>, dim3((unsigned)p.ntiles, GD_T),
-                       dim3(GD_T), 0, st, n, k, (const float*)partial, p.splits, p.ntiles,
-                       p.tiles_aug, s, Q, q);
+    hipLaunchKernelGGL(gram_splitk_epilogue_kernel<GD_T>,
+                       dim3((unsigned)p.ntiles, GD_T / GE_BAND), dim3(GD_T), 0, st, n, k,
+                       (const float*)partial, p.splits, p.ntiles, p.tiles_aug, s, Q, q);
   return hipGetLastError();
 }
 
