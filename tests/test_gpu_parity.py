@@ -289,9 +289,11 @@ def whole_gpu(request, monkeypatch):
     monkeypatch.delenv("NNLS_SOLVER", raising=False)
 
 
-@pytest.mark.parametrize("n", [512, 1024, 2000, 5000])
+@pytest.mark.parametrize("n", [512, 1024, 2000, 2500, 4000, 5000, 5120])
 def test_persistent_steps_match_oracle(n, whole_gpu):
-    """Whole-GPU solvers, one update from the oracle's state (as for the per-column solver)."""
+    """Whole-GPU solvers, one update from the oracle's state (as for the per-column solver).
+    The sizes cover every register shape of the register-resident solver (n <= 2048, 3072,
+    4096, 5120) and its largest n."""
     say(f"{whole_gpu} single steps n={n}")
     A, B = _uniform_case(21, 2 * n, n, 1)
     Q, q, s = N.prepare(dev(A), dev(B))
