@@ -349,8 +349,8 @@ __device__ __forceinline__ void gram_tile_bf16x3(f32x4 (&acc)[4][4], int64_t r_b
 // values).  Each stage is filled by global_load_lds_dwordx4 (16 bytes per lane straight into
 // LDS): the loads of step s+1 are issued right after the barrier of step s and land while the
 // waves run the 3 x 32 MFMAs (hi*hi + hi*lo + lo*hi, v_mfma_f32_16x16x32_bf16) of step s.
-// Inside a stage, the four 16-byte k-groups of a column are stored XOR-swizzled by bits 2..3 of
-// the column, so the fragment reads of 16 consecutive columns hit 16 distinct bank quads.  The
+// Inside a stage, the four 16-byte k-groups of a column are stored XOR-swizzled by gd_swz of the
+// column, so the fragment reads of 8 or 16 consecutive columns hit distinct bank groups.  The
 // swizzle is applied on the global side: lane i of a load instruction fetches the k-group that
 // belongs at LDS position i.  One barrier per step: waits are explicit (vmcnt for this wave's
 // own loads of the step, lgkmcnt for its last LDS reads) and the barrier is a bare s_barrier,
@@ -367,6 +367,11 @@ constexpr int GD_CPI = 512 / GD_BK;          // columns per load instruction (1 
 constexpr int GD_IPP = GD_T / GD_CPI;        // instructions per part
 constexpr int GD_IPW = 4 * GD_IPP / (GD_NT / 64);
 constexpr int GD_MT = 8, GD_NTL = 4;         // 16 x 16 blocks per wave (rows, columns)
+
+// LDS position of k-group g of column c (64 bytes per column, four 16-byte k-groups): g ^ swz(c).
+// Any 8 consecutive columns (and any 16) then put their 16-byte pieces on distinct bank groups
+// whether a fragment read serves 8 lanes per cycle over 128 bytes of banks or 16 lanes over 256.
+__device__ __forceinline__ int gd_swz(int c) { return ((c >> 1) ^ (c >> 2)) & 3; }
 
 typedef __attribute__((address_space(1))) void gd_gvoid;
 typedef __attribute__((address_space(3))) void gd_lvoid;
@@ -479,7 +484,7 @@ __global__ __launch_bounds__(GD_NT, 1) void gram_dma_kernel(
   // this lane's part of each load instruction: column (lane / 4) of the instruction's 16, the
   // k-group that belongs at LDS position lane % 4
   const int lcol = lane >> 2;
-  const int lg = (lane & 3) ^ ((lcol >> 2) & 3);
+  const int lg = (lane & 3) ^ gd_swz(lcol);
   auto issue = [&](int step, int stage) {
 #pragma unroll
     for (int u = 0; u < GD_IPW; ++u) {
@@ -501,7 +506,7 @@ __global__ __launch_bounds__(GD_NT, 1) void gram_dma_kernel(
     for (int b = 0; b < GD_NTL; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
   const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
   const int fr = lane & 15;
-  const int fp = (lane >> 4) ^ ((fr >> 2) & 3);  // physical k-group of this lane's fragment
+  const int fp = (lane >> 4) ^ gd_swz(fr);  // physical k-group of this lane's fragment
 
   if (nsteps > 0) issue(0, 0);
   for (int step = 0; step < nsteps; ++step) {
