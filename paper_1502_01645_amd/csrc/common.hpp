@@ -24,27 +24,10 @@ __device__ __forceinline__ float bf16_bits_to_f32(uint32_t b) {
   return __builtin_bit_cast(float, b << 16);
 }
 
-// Split x = hi + lo + O(2^-16 |x|) with hi, lo bfloat16 (hi = RNE(x), lo = RNE(x - hi)).
-__device__ __forceinline__ void split_bf16(float x, uint32_t& hi, uint32_t& lo) {
-  hi = bf16_bits_rne(x);
-  float r = x - bf16_bits_to_f32(hi);
-  lo = bf16_bits_rne(r);
-}
-
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    T o = __shfl_xor(v, off, kWave);
-    v = o > v ? o : v;
-  }
   return v;
 }
 

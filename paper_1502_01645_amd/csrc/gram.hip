@@ -875,7 +875,6 @@ static GramDmaPlan gram_dma_plan(int64_t d, int64_t n, int64_t k) {
   return p;
 }
 
-int gram_bf16x3_splits(int64_t d, int64_t n, int64_t k) { return gram_dma_plan(d, n, k).splits; }
 
 size_t gram_bf16x3_ws_bytes(int64_t d, int64_t n, int64_t k) {
   const GramDmaPlan p = gram_dma_plan(d, n, k);

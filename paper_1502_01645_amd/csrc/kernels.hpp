@@ -28,7 +28,6 @@ size_t colnorm_ws_bytes(int64_t d, int64_t n);
 template <typename T>
 hipError_t launch_colnorm(int64_t d, int64_t n, const T* A, int64_t lda, double* s, double* ws,
                           hipStream_t st);
-int gram_bf16x3_splits(int64_t d, int64_t n, int64_t k);
 size_t gram_bf16x3_ws_bytes(int64_t d, int64_t n, int64_t k);
 // Column norms and the BF16x3 Gram in one pass over A (the norms come from the operand split).
 size_t prepare_bf16x3_ws_bytes(int64_t d, int64_t n, int64_t k);
