@@ -113,8 +113,8 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
   float* P = Gr + np * MR_SLOTS;       // [np][16] masked gradient / product operand
   float* W = P + np * MR_SLOTS;        // [np][16] product result
   float* colf = W + np * MR_SLOTS;     // per-slot floats [8][16]
-  int* coli = (int*)(colf + 8 * MR_SLOTS);  // per-slot ints [8][16]
-  float* red = (float*)(coli + 8 * MR_SLOTS);  // [4 waves][16 slots][4]
+  int* coli = (int*)(colf + 8 * MR_SLOTS);  // per-slot ints [9][16]
+  float* red = (float*)(coli + 9 * MR_SLOTS);  // [4 waves][16 slots][4]
   int* redI = (int*)(red + 4 * MR_SLOTS * 4);  // [4]
 
   // per-slot state in LDS
@@ -133,6 +133,7 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
   int* s_rows = coli + 5 * MR_SLOTS;      // rows of Q read (low bits)
   int* s_rowsh = coli + 6 * MR_SLOTS;     // rows of Q read (high bits)
   int* s_done = coli + 7 * MR_SLOTS;      // outputs written; slot waits for a new column
+  int* s_clip = coli + 8 * MR_SLOTS;      // clipped rows of the gradient corrections so far
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -185,14 +186,17 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
     s_rows[tid] = 0;
     s_rowsh[tid] = 0;
     s_done[tid] = 0;
+    s_clip[tid] = 0;
   }
   __syncthreads();
   load_slot(slot, s_col[slot]);
   __syncthreads();
 
   // per-slot reduction of four per-thread values over the 16 threads sharing a slot
+  // (sync_after = false leaves out the trailing barrier: only threads 0..15 may then read the
+  // results, each its own slot's)
   auto slot_reduce4 = [&](float v0, float v1, float v2, float v3, float* o0, float* o1,
-                          float* o2, float* o3) {
+                          float* o2, float* o3, bool sync_after = true) {
     // lanes with equal (lane & 15) share a slot within a wave: xor 16, 32
 #pragma unroll
     for (int off = 16; off < 64; off <<= 1) {
@@ -224,7 +228,16 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
       if (o2) o2[tid] = a2;
       if (o3) o3[tid] = a3;
     }
-    __syncthreads();
+    if (sync_after) __syncthreads();
+  };
+
+  // OR over the 16 slots of a per-slot predicate read from LDS by every thread (the slot state
+  // is written by threads 0..15 only, and every read follows a barrier after those writes)
+  auto any_slot = [&](const int* flag, bool need_col) {
+    int r = 0;
+#pragma unroll
+    for (int t2 = 0; t2 < MR_SLOTS; ++t2) r |= (flag[t2] != 0 && (!need_col || s_col[t2] >= 0));
+    return r;
   };
 
   // ||q_c|| of every slot
@@ -244,10 +257,7 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
 
   for (;;) {
     // ---- exact gradient for slots that asked for it: W = Q Y, grad = W + q
-    int any_ref = 0;
-    if (tid < MR_SLOTS) any_ref = s_ref[tid] && s_col[tid] >= 0;
-    any_ref = __syncthreads_or(any_ref);
-    if (any_ref) {
+    if (any_slot(s_ref, true)) {
       for (int e = tid; e < np * MR_SLOTS; e += MR_NT) P[e] = Y[e];
       __syncthreads();
       product(P, W);
@@ -289,7 +299,6 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
     }
 
     // ---- per-slot decisions (threads 0..15): finish, refresh, or update
-    int flag_done = 0, flag_work = 0, flag_act = 0;
     if (tid < MR_SLOTS) {
       s_act[tid] = 0;
       const int col = s_col[tid];
@@ -312,16 +321,14 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
           A.kkt[col] = st == NNLS_NONFINITE_DEV ? __builtin_nan("") : r;
           A.status[col] = st;
           if (A.rows_read)
-            A.rows_read[col] = ((int64_t)s_rowsh[tid] << 32) | (int64_t)(unsigned)s_rows[tid];
+            A.rows_read[col] =
+                (((int64_t)s_rowsh[tid] << 32) | (int64_t)(unsigned)s_rows[tid]) + s_clip[tid];
           s_done[tid] = 1;
         }
       }
-      flag_done = (col >= 0 && s_done[tid]) ? 1 : 0;
-      flag_work = (col >= 0) ? 1 : 0;
-      flag_act = s_act[tid];
     }
-    flag_done = __syncthreads_or(flag_done);
-    if (flag_done) {
+    __syncthreads();
+    if (any_slot(s_done, true)) {
       // write x = y / s of finished slots, then give each a new column from the queue
       const bool fin = s_col[slot] >= 0 && s_done[slot];
       if (fin) {
@@ -341,6 +348,7 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
         s_ref[tid] = (A.Y0 && next < A.k) ? 1 : 0;
         s_rows[tid] = 0;
         s_rowsh[tid] = 0;
+        s_clip[tid] = 0;
       }
       __syncthreads();
       if (fin) load_slot(slot, s_col[slot]);
@@ -348,15 +356,17 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
       slot_qnorm();
       continue;  // evaluate the new columns before any update
     }
-    flag_work = __syncthreads_or(flag_work);
-    if (!flag_work) break;  // every slot empty: the queue is exhausted
-    flag_act = __syncthreads_or(flag_act);
-    if (!flag_act) continue;  // only exact-gradient refreshes are pending
+    {
+      int work = 0;
+#pragma unroll
+      for (int t2 = 0; t2 < MR_SLOTS; ++t2) work |= s_col[t2] >= 0;
+      if (!work) break;  // every slot empty: the queue is exhausted
+    }
+    if (!any_slot(s_act, false)) continue;  // only exact-gradient refreshes are pending
 
-    // ---- W = Q Gbar on the matrix cores (inactive slots have gbar = 0)
-    if (!s_act[slot])
-      for (int i = row0; i < np; i += MR_NT / MR_SLOTS) P[i * MR_SLOTS + slot] = 0.f;
-    __syncthreads();
+    // ---- W = Q Gbar on the matrix cores.  The columns of W are independent, so the columns of
+    // slots that take no update need no clearing: their W is never used.  (P was written before
+    // the barriers of the statistics reduction; W was last read before them.)
     product(P, W);
     __syncthreads();
     {
@@ -365,7 +375,7 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
         const int e = i * MR_SLOTS + slot;
         den += P[e] * W[e];
       }
-      slot_reduce4(den, 0.f, 0.f, 0.f, s_den, nullptr, nullptr, nullptr);
+      slot_reduce4(den, 0.f, 0.f, 0.f, s_den, nullptr, nullptr, nullptr, false);
     }
     if (tid < MR_SLOTS && s_act[tid]) {
       const float den = s_den[tid];
@@ -376,7 +386,8 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
         A.kkt[col] = sqrt((double)s_res[tid]) / (double)s_qn[tid];
         A.status[col] = NNLS_BREAKDOWN_DEV;
         if (A.rows_read)
-          A.rows_read[col] = ((int64_t)s_rowsh[tid] << 32) | (int64_t)(unsigned)s_rows[tid];
+          A.rows_read[col] =
+              (((int64_t)s_rowsh[tid] << 32) | (int64_t)(unsigned)s_rows[tid]) + s_clip[tid];
         s_act[tid] = 0;
         s_done[tid] = 1;
         s_ref[tid] = 0;
@@ -404,25 +415,28 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
         }
         P[e] = d;
       }
+      // the clipped rows of this update, summed per slot in LDS; read only when the column
+      // retires, after many barriers
+      if (clip_mine) atomicAdd(&s_clip[slot], clip_mine);
       __syncthreads();
       // grad' = grad + Q d, the second product of Algorithm 2, on the matrix cores
       product(P, W);
       __syncthreads();
+      // (each thread adds to its own entries of Gr; the next writer of W runs after the
+      // barriers of the next statistics reduction, so no barrier is needed here)
       if (act)
         for (int i = row0; i < n; i += MR_NT / MR_SLOTS) Gr[i * MR_SLOTS + slot] += W[i * MR_SLOTS + slot];
-      __syncthreads();
     }
-    slot_reduce4((float)clip_mine, 0.f, 0.f, 0.f, s_den, nullptr, nullptr, nullptr);
+    // slot bookkeeping by threads 0..15, each for its own slot (read again only by the same
+    // thread in the next decisions)
     if (tid < MR_SLOTS && s_act[tid]) {
       s_it[tid] += 1;
       s_fresh[tid] = 0;
-      // rows of Q: the passive rows of the line-search product and the clipped rows
-      const unsigned add = (unsigned)s_cnt[tid] + (unsigned)s_den[tid];
-      const unsigned r = (unsigned)s_rows[tid] + add;
+      // rows of Q: the passive rows of the line-search product (the clipped rows are in s_clip)
+      const unsigned r = (unsigned)s_rows[tid] + (unsigned)s_cnt[tid];
       if (r < (unsigned)s_rows[tid]) s_rowsh[tid] += 1;
       s_rows[tid] = (int)r;
     }
-    __syncthreads();
   }
 }
 
@@ -440,7 +454,7 @@ static int mr_np(int64_t n) {
 size_t solve_mrhs_lds_bytes(int64_t n) {
   const size_t np = (size_t)mr_np(n);
   return sizeof(float) * 4 * np * MR_SLOTS +
-         sizeof(float) * 8 * MR_SLOTS + sizeof(int) * 8 * MR_SLOTS +
+         sizeof(float) * 8 * MR_SLOTS + sizeof(int) * 9 * MR_SLOTS +
          sizeof(float) * 4 * MR_SLOTS * 4 + sizeof(int) * 8 + 64;
 }
 
