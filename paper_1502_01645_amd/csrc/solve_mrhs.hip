@@ -115,7 +115,7 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
   float* colf = W + np * MR_SLOTS;     // per-slot floats [8][16]
   int* coli = (int*)(colf + 8 * MR_SLOTS);  // per-slot ints [9][16]
   float* red = (float*)(coli + 9 * MR_SLOTS);  // [4 waves][16 slots][4]
-  int* redI = (int*)(red + 4 * MR_SLOTS * 4);  // [4]
+  int* s_anyclip = (int*)(red + 4 * MR_SLOTS * 4);  // some slot clipped in this update
 
   // per-slot state in LDS
   float* s_num = colf + 0 * MR_SLOTS;
@@ -187,6 +187,7 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
     s_rowsh[tid] = 0;
     s_done[tid] = 0;
     s_clip[tid] = 0;
+    if (tid == 0) *s_anyclip = 0;
   }
   __syncthreads();
   load_slot(slot, s_col[slot]);
@@ -301,6 +302,8 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
     // ---- per-slot decisions (threads 0..15): finish, refresh, or update
     if (tid < MR_SLOTS) {
       s_act[tid] = 0;
+      // the clip flag was last read before the barriers of the statistics reduction
+      if (tid == 0) *s_anyclip = 0;
       const int col = s_col[tid];
       if (col >= 0 && !s_done[tid]) {
         const double r = sqrt((double)s_res[tid]) / (double)s_qn[tid];
@@ -417,15 +420,27 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
       }
       // the clipped rows of this update, summed per slot in LDS; read only when the column
       // retires, after many barriers
-      if (clip_mine) atomicAdd(&s_clip[slot], clip_mine);
-      __syncthreads();
-      // grad' = grad + Q d, the second product of Algorithm 2, on the matrix cores
-      product(P, W);
+      if (clip_mine) {
+        atomicAdd(&s_clip[slot], clip_mine);
+        *s_anyclip = 1;
+      }
       __syncthreads();
       // (each thread adds to its own entries of Gr; the next writer of W runs after the
-      // barriers of the next statistics reduction, so no barrier is needed here)
-      if (act)
-        for (int i = row0; i < n; i += MR_NT / MR_SLOTS) Gr[i * MR_SLOTS + slot] += W[i * MR_SLOTS + slot];
+      // barriers of the next statistics reduction, so no barrier is needed after the adds)
+      if (*s_anyclip) {
+        // grad' = grad + Q d, the second product of Algorithm 2, on the matrix cores
+        product(P, W);
+        __syncthreads();
+        if (act)
+          for (int i = row0; i < n; i += MR_NT / MR_SLOTS)
+            Gr[i * MR_SLOTS + slot] += W[i * MR_SLOTS + slot];
+      } else if (act) {
+        // no slot clipped: d = -alpha gbar in every slot, so Q d = -alpha W with the
+        // line-search product W = Q gbar, still intact
+        const float alpha = s_alpha[slot];
+        for (int i = row0; i < n; i += MR_NT / MR_SLOTS)
+          Gr[i * MR_SLOTS + slot] -= alpha * W[i * MR_SLOTS + slot];
+      }
     }
     // slot bookkeeping by threads 0..15, each for its own slot (read again only by the same
     // thread in the next decisions)
