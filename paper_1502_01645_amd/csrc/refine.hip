@@ -8,6 +8,9 @@
 //   of the x that is returned.
 // Few right-hand sides (k <= 4) stream A once per pass with matrix-vector kernels:
 //   R = A X - B, g = A^T R, V = A D (D^T H D = ||V||^2), R' = A x' - B, g' = A^T R'.
+// For one right-hand side and n <= 6144 (FP32 A, aligned rows) a workgroup holds a few full rows
+// of A in registers, forms their residuals and adds their share of A^T R before it moves on, so
+// (R, g) and (R', g') each cost one read of A: three reads instead of five.
 // Many right-hand sides form the FP64 Gram matrix once, on the FP64 matrix cores:
 //   H = A^T A, a = A^T B, ||b||^2;  g = H X - a,  D^T H D from H D,  g' = H X' - a,
 //   F(x) = 1/2 (x^T (H x - 2 a) + ||b||^2) and F(x') - F(x) = 1/2 (x' - x)^T (g + g'),
@@ -173,6 +176,120 @@ __global__ __launch_bounds__(256) void cols_partial_vec_kernel(int64_t d, int64_
   for (int m = 0; m < nvec; ++m)
 #pragma unroll
     for (int e = 0; e < 4; ++e) partial[(chunk * nvec + m) * n + i + e] = acc[m][e];
+}
+
+// One right-hand side, fused: R[r] = sum_i A[r, i] x_i - b_r for the rows of this workgroup's
+// range, and partial[wg, m, i] = sum over those rows of A[r, i] v_m[r] with v_0 = R, and with WB
+// v_1 = b and v_2 = A[r, i] (the squared column norm), in the layout of cols_partial_vec_kernel
+// with one chunk per workgroup.  Thread t owns columns 2048 j + 4 t .. + 3 (j < NB); a step takes
+// rc_rb rows (4, or 2 where the registers of 4 would spill): each thread's share of their dot products, a wave sum, then a sum over the eight
+// waves through LDS (double-buffered, one barrier per step) gives the residuals, and the rows
+// still in registers are added into the column sums.  The next step's rows are loaded before the
+// reduction so HBM reads continue across it.  x holds FP32 values (for TX = double, values
+// rounded to FP32, as the candidate x' of the refinement is); the products are exact in FP64.
+constexpr int RC_NT = 512;
+constexpr int RC_MAX_NB = 3;
+constexpr int RC_MAX_WG = 256;
+constexpr int rc_rb(int nb, bool wb) { return nb == 3 && wb ? 2 : 4; }
+
+template <int NB, bool WB, typename TX>
+__global__ __launch_bounds__(RC_NT, 1) void rows_cols_fused_kernel(
+    int64_t d, int64_t n, const float* __restrict__ A, int64_t lda, const TX* __restrict__ X,
+    const float* __restrict__ B, int64_t ldb, int64_t rows_per_wg, double* __restrict__ R,
+    double* __restrict__ partial) {
+  constexpr int NV = WB ? 3 : 1;
+  constexpr int RC_RB = rc_rb(NB, WB);
+  __shared__ double red[2][RC_NT / 64][RC_RB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r1 = r0 + rows_per_wg < d ? r0 + rows_per_wg : d;
+  if (r0 >= d) return;  // whole workgroup (uniform)
+  bool cv[NB];
+  float xv[NB][4];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int64_t c = 2048 * j + 4 * tid;
+    cv[j] = c < n;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xv[j][e] = cv[j] ? (float)X[c + e] : 0.f;
+  }
+  double acc[NV][NB][4];
+#pragma unroll
+  for (int m = 0; m < NV; ++m)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[m][j][e] = 0.0;
+
+  auto load_step = [&](int64_t rs, f32x4 (&a)[RC_RB][NB], float (&bq)[RC_RB]) {
+#pragma unroll
+    for (int q = 0; q < RC_RB; ++q) {
+      const bool rv = rs + q < r1;
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        a[q][j] = (rv && cv[j]) ? *(const f32x4*)(A + (rs + q) * lda + 2048 * j + 4 * tid)
+                                : (f32x4){0.f, 0.f, 0.f, 0.f};
+      bq[q] = rv ? B[(rs + q) * ldb] : 0.f;
+    }
+  };
+  f32x4 a[RC_RB][NB], an[RC_RB][NB];
+  float bq[RC_RB], bn[RC_RB];
+  load_step(r0, a, bq);
+  int par = 0;
+  for (int64_t rs = r0; rs < r1; rs += RC_RB) {
+    if (rs + RC_RB < r1) load_step(rs + RC_RB, an, bn);
+    double dot[RC_RB];
+#pragma unroll
+    for (int q = 0; q < RC_RB; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t += (double)a[q][j][e] * (double)xv[j][e];
+      dot[q] = wave_sum(t);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < RC_RB; ++q) red[par][wave][q] = dot[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RC_RB; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < RC_NT / 64; ++w) t += red[par][w][q];
+      // rows past the range have zero A and b, so their residual is 0 and adds nothing
+      const double rq = t - (double)bq[q];
+      if (tid == q && rs + q < r1) R[rs + q] = rq;
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double av = (double)a[q][j][e];
+          acc[0][j][e] += av * rq;
+          if (WB) {
+            acc[1 % NV][j][e] += av * (double)bq[q];
+            acc[2 % NV][j][e] += av * av;
+          }
+        }
+    }
+    par ^= 1;
+#pragma unroll
+    for (int q = 0; q < RC_RB; ++q) {
+      bq[q] = bn[q];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) a[q][j] = an[q][j];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NV; ++m)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      if (cv[j]) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          partial[((int64_t)blockIdx.x * NV + m) * n + 2048 * j + 4 * tid + e] = acc[m][j][e];
+      }
 }
 
 // partial[chunk, m, i] = sum over rows of the chunk of A[r, i] * V_m[r] where the m-th vector is
@@ -656,8 +773,11 @@ static GramRefineWs gram_refine_layout(void* ws, int64_t n, int64_t k) {
 
 size_t refine_ws_bytes(int64_t d, int64_t n, int64_t k) {
   size_t el;
-  if (k <= RF_SMALL_K)
-    el = (size_t)(2 * d * k + 4 * n * k + n + 8 * k) + (size_t)refine_chunks(d, n) * (2 * k + 1) * n;
+  if (k <= RF_SMALL_K) {
+    // partial sums of the two-pass (chunks) or the fused (up to RC_MAX_WG workgroups) form
+    const int64_t ch = refine_chunks(d, n) > RC_MAX_WG ? refine_chunks(d, n) : RC_MAX_WG;
+    el = (size_t)(2 * d * k + 4 * n * k + n + 8 * k) + (size_t)ch * (2 * k + 1) * n;
+  }
   else
     el = (size_t)(n * n + 5 * n * k + n + 9 * k);
   return el * sizeof(double) + 256;
@@ -715,6 +835,40 @@ static void launch_atr(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda,
                      k, wb, w.chunks, (const double*)w.partial, G, w.Atb, w.s);
 }
 
+static bool fused_ok(const void* A, int64_t lda, int64_t n, int64_t k, size_t elem) {
+  return k == 1 && vec_ok(A, lda, n, elem) && n <= 2048 * RC_MAX_NB;
+}
+
+// R = A x - b and G = A^T R (with WB also A^T b and the column norms s) in one read of A.
+template <typename TX>
+static void launch_fused(int64_t d, int64_t n, const float* A, int64_t lda, const TX* X,
+                         const float* B, int64_t ldb, bool with_b, RefineWs& w, double* R,
+                         double* G, hipStream_t st) {
+  // contiguous row ranges, a multiple of 4 rows each (so of every step size)
+  int64_t grid = (d + 3) / 4;
+  if (grid > RC_MAX_WG) grid = RC_MAX_WG;
+  int64_t rows = (d + grid - 1) / grid;
+  rows = (rows + 3) / 4 * 4;
+  grid = (d + rows - 1) / rows;
+  const int nb = (int)((n + 2047) / 2048);
+  dim3 g((unsigned)grid), b(RC_NT);
+#define RC_LAUNCH(NB, WB)                                                                       \
+  hipLaunchKernelGGL((rows_cols_fused_kernel<NB, WB, TX>), g, b, 0, st, d, n, A, lda, X, B, ldb, \
+                     rows, R, w.partial)
+  if (with_b) {
+    if (nb == 1) RC_LAUNCH(1, true);
+    else if (nb == 2) RC_LAUNCH(2, true);
+    else RC_LAUNCH(3, true);
+  } else {
+    if (nb == 1) RC_LAUNCH(1, false);
+    else if (nb == 2) RC_LAUNCH(2, false);
+    else RC_LAUNCH(3, false);
+  }
+#undef RC_LAUNCH
+  hipLaunchKernelGGL(cols_finalize_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, n,
+                     (int64_t)1, with_b ? 1 : 0, grid, (const double*)w.partial, G, w.Atb, w.s);
+}
+
 // C = A^T [M1 | M2] (see gemm_tn_f64_kernel); sq optional.
 template <typename TA, typename TM>
 static void gemm_tn(int64_t K, int64_t N, const TA* A, int64_t lda, int64_t n1, const TM* M1,
@@ -762,16 +916,27 @@ hipError_t launch_refine(int64_t d, int64_t n, int64_t k, const T* A, int64_t ld
     return hipGetLastError();
   }
   RefineWs w = refine_layout(ws, d, n, k);
-  launch_resid<T>(d, n, k, A, lda, X, false, B, ldb, w.R, st);
-  launch_atr<T>(d, n, k, A, lda, w.R, B, ldb, true, w, w.G, st);
+  const bool fused = fused_ok(A, lda, n, k, sizeof(T));
+  if (fused) {
+    launch_fused<T>(d, n, (const float*)A, lda, (const T*)X, (const float*)B, ldb, true, w, w.R,
+                    w.G, st);
+  } else {
+    launch_resid<T>(d, n, k, A, lda, X, false, B, ldb, w.R, st);
+    launch_atr<T>(d, n, k, A, lda, w.R, B, ldb, true, w, w.G, st);
+  }
   hipLaunchKernelGGL(refine_stage1_kernel<T>, dim3((unsigned)k), dim3(256), 0, st, d, n, k,
                      (const T*)X, (const double*)w.R, (const double*)w.G, (const double*)w.Atb,
                      (const double*)w.s, w.D, w.colstat);
   launch_resid<T>(d, n, k, A, lda, w.D, true, (const T*)nullptr, 0, w.V, st);
   hipLaunchKernelGGL(refine_stage2_kernel<T>, dim3((unsigned)k), dim3(256), 0, st, d, n, k,
                      (const T*)X, (const double*)w.V, (const double*)w.D, w.Xn, w.colstat);
-  launch_resid<T>(d, n, k, A, lda, w.Xn, true, B, ldb, w.R, st);
-  launch_atr<T>(d, n, k, A, lda, w.R, B, ldb, false, w, w.G, st);
+  if (fused) {
+    launch_fused<double>(d, n, (const float*)A, lda, (const double*)w.Xn, (const float*)B, ldb,
+                         false, w, w.R, w.G, st);
+  } else {
+    launch_resid<T>(d, n, k, A, lda, w.Xn, true, B, ldb, w.R, st);
+    launch_atr<T>(d, n, k, A, lda, w.R, B, ldb, false, w, w.G, st);
+  }
   hipLaunchKernelGGL(refine_stage3_kernel<T>, dim3((unsigned)k), dim3(256), 0, st, d, n, k, X,
                      (const double*)w.Xn, (const double*)w.R, (const double*)w.G,
                      (const double*)w.s, (const double*)w.colstat, kkt64, obj64);

@@ -194,6 +194,25 @@ def test_refine_many_rhs_matches_oracle(dtype, d, n, k, start):
     reported residual and objective are the oracle's for the returned X, and a column's step is
     kept exactly where the FP64 step lowers the residual without raising the objective."""
     say(f"refine many rhs {np.dtype(dtype).name} d={d} n={n} k={k} start={start}")
+    _refine_case(dtype, d, n, k, start)
+
+
+# one right-hand side with FP32 A, 16-byte rows and n <= 6144 takes the fused row/column pass
+# (one, two or three 2048-column blocks; ragged and tiny d); n % 4 != 0, k > 1 and FP64 A take the
+# two-pass form
+@pytest.mark.parametrize("dtype,d,n,k", [(np.float32, 700, 132, 1), (np.float32, 1001, 2052, 1),
+                                         (np.float32, 523, 4100, 1), (np.float32, 5, 5000, 1),
+                                         (np.float32, 1500, 6144, 1), (np.float32, 600, 130, 1),
+                                         (np.float32, 800, 300, 2), (np.float64, 400, 96, 1)])
+@pytest.mark.parametrize("start", ["loose", "zero"])
+def test_refine_few_rhs_matches_oracle(dtype, d, n, k, start):
+    """FP64 check and refinement step for one to four right-hand sides (passes over A): the same
+    bar as the many right-hand-side path."""
+    say(f"refine few rhs {np.dtype(dtype).name} d={d} n={n} k={k} start={start}")
+    _refine_case(dtype, d, n, k, start)
+
+
+def _refine_case(dtype, d, n, k, start):
     A, B = _uniform_case(31 + k, d, n, k, dtype)
     Q, q, s = N.prepare(dev(A), dev(B))
     if start == "loose":
