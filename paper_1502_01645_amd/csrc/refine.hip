@@ -182,8 +182,9 @@ __global__ __launch_bounds__(256) void cols_partial_vec_kernel(int64_t d, int64_
 // range, and partial[wg, m, i] = sum over those rows of A[r, i] v_m[r] with v_0 = R, and with WB
 // v_1 = b and v_2 = A[r, i] (the squared column norm), in the layout of cols_partial_vec_kernel
 // with one chunk per workgroup.  Thread t owns columns 2048 j + 4 t .. + 3 (j < NB); a step takes
-// rc_rb rows (4, or 2 where the registers of 4 would spill): each thread's share of their dot products, a wave sum, then a sum over the eight
-// waves through LDS (double-buffered, one barrier per step) gives the residuals, and the rows
+// rc_rb rows (4, or 2 where the registers of 4 would spill): each thread's share of their dot
+// products, a wave sum, then a sum over the eight waves through LDS (double-buffered, one barrier
+// per step) gives the residuals, and the rows
 // still in registers are added into the column sums.  The next step's rows are loaded before the
 // reduction so HBM reads continue across it.  x holds FP32 values (for TX = double, values
 // rounded to FP32, as the candidate x' of the refinement is); the products are exact in FP64.
@@ -325,33 +326,38 @@ __global__ __launch_bounds__(256) void cols_partial_kernel(int64_t d, int64_t n,
   for (int m = 0; m < nvec; ++m) partial[(chunk * nvec + m) * n + i] = acc[m];
 }
 
-// Block: 64 columns x all nvec vectors; thread (column tid % 64, group tid / 64) sums the chunks
-// g, g + 4, ... with four accumulators (16 loads of a column in flight across the groups), then
-// the four group sums are added in fixed order.
+// Block: 16 columns x all nvec vectors; thread (column tid % 16, group tid / 16) sums the chunks
+// g, g + 16, ... with four accumulators, then the 16 group sums of a column are added in fixed
+// order.  (A wave reads 16 consecutive doubles of 4 chunks at a time; 16 columns per block give
+// enough blocks to spread the partial sums over the GPU.)
+constexpr int CF_C = 16;
+constexpr int CF_G = 256 / CF_C;
 __global__ __launch_bounds__(256) void cols_finalize_kernel(int64_t n, int64_t k, int with_b,
                                                             int64_t nchunks,
                                                             const double* __restrict__ partial,
                                                             double* __restrict__ G,
                                                             double* __restrict__ Atb,
                                                             double* __restrict__ s) {
-  __shared__ double red[4][64];
-  const int cl = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.x * 64 + cl;
+  __shared__ double red[CF_G][CF_C];
+  const int cl = threadIdx.x % CF_C, grp = threadIdx.x / CF_C;
+  const int64_t i = (int64_t)blockIdx.x * CF_C + cl;
   const int nvec = with_b ? (int)(2 * k + 1) : (int)k;
   for (int m = 0; m < nvec; ++m) {
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     if (i < n) {
       int64_t c = grp;
-      for (; c + 12 < nchunks; c += 16) {
+      for (; c + 3 * CF_G < nchunks; c += 4 * CF_G) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] += partial[((c + 4 * u) * nvec + m) * n + i];
+        for (int u = 0; u < 4; ++u) a[u] += partial[((c + CF_G * u) * nvec + m) * n + i];
       }
-      for (; c < nchunks; c += 4) a[0] += partial[(c * nvec + m) * n + i];
+      for (; c < nchunks; c += CF_G) a[0] += partial[(c * nvec + m) * n + i];
     }
     red[grp][cl] = (a[0] + a[1]) + (a[2] + a[3]);
     __syncthreads();
     if (grp == 0 && i < n) {
-      const double acc = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+      double acc = 0.0;
+#pragma unroll
+      for (int g = 0; g < CF_G; ++g) acc += red[g][cl];
       if (m < k) G[i * k + m] = acc;
       else if (m < 2 * k) Atb[i * k + (m - k)] = acc;
       else s[i] = acc > 0.0 ? sqrt(acc) : 1.0;
@@ -600,20 +606,26 @@ __global__ __launch_bounds__(256) void gref_stage3_kernel(int64_t n, int64_t k,
 }
 
 // ---- per-column steps ---------------------------------------------------------------------
-// sum over r < len of V[r * k + c]^2 by one thread, stride 256 from threadIdx.x, with eight loads
-// in flight (the sums run in eight fixed lanes of accumulation, added in a fixed order).
+// One workgroup of RS_NT threads per right-hand side: the few right-hand-side path has k <= 4
+// columns, so each stage is a handful of workgroups whose time is the latency of their strided
+// walks over d and n; 512 threads make those walks short (1024 would cap the registers at 128
+// and spill).
+constexpr int RS_NT = 512;
+
+// sum over r < len of V[r * k + c]^2 by one thread, stride RS_NT from threadIdx.x, with eight
+// loads in flight (the sums run in eight fixed lanes of accumulation, added in a fixed order).
 __device__ __forceinline__ double strided_sumsq(const double* __restrict__ V, int64_t len,
                                                 int64_t k, int64_t c) {
   double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int64_t r = threadIdx.x;
-  for (; r + 7 * 256 < len; r += 8 * 256) {
+  for (; r + 7 * RS_NT < len; r += 8 * RS_NT) {
     double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = V[(r + u * 256) * k + c];
+    for (int u = 0; u < 8; ++u) v[u] = V[(r + u * RS_NT) * k + c];
 #pragma unroll
     for (int u = 0; u < 8; ++u) a[u] += v[u] * v[u];
   }
-  for (; r < len; r += 256) {
+  for (; r < len; r += RS_NT) {
     const double v = V[r * k + c];
     a[0] += v * v;
   }
@@ -622,7 +634,7 @@ __device__ __forceinline__ double strided_sumsq(const double* __restrict__ V, in
 
 // Stage 1 (after R, G, Atb, s): residual and objective at x, direction D = p ./ s, ||p||^2.
 template <typename TX>
-__global__ __launch_bounds__(256) void refine_stage1_kernel(int64_t d, int64_t n, int64_t k,
+__global__ __launch_bounds__(RS_NT) void refine_stage1_kernel(int64_t d, int64_t n, int64_t k,
                                                             const TX* __restrict__ X,
                                                             const double* __restrict__ R,
                                                             const double* __restrict__ G,
@@ -630,10 +642,11 @@ __global__ __launch_bounds__(256) void refine_stage1_kernel(int64_t d, int64_t n
                                                             const double* __restrict__ s,
                                                             double* __restrict__ D,
                                                             double* __restrict__ colstat) {
-  __shared__ double red[4];
+  __shared__ double red[RS_NT / 64];
   const int64_t c = blockIdx.x;
   double kk = 0.0, aa = 0.0, num = 0.0, ff = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
+#pragma unroll 1
+  for (int64_t i = threadIdx.x; i < n; i += RS_NT) {
     const double y = s[i] * (double)X[i * k + c];
     const double gy = G[i * k + c] / s[i];
     const bool pas = (y > 0.0) || (gy < 0.0);
@@ -646,10 +659,10 @@ __global__ __launch_bounds__(256) void refine_stage1_kernel(int64_t d, int64_t n
     aa += ai * ai;
   }
   ff = strided_sumsq(R, d, k, c);
-  kk = block_sum<double, 256>(kk, red);
-  aa = block_sum<double, 256>(aa, red);
-  num = block_sum<double, 256>(num, red);
-  ff = block_sum<double, 256>(ff, red);
+  kk = block_sum<double, RS_NT>(kk, red);
+  aa = block_sum<double, RS_NT>(aa, red);
+  num = block_sum<double, RS_NT>(num, red);
+  ff = block_sum<double, RS_NT>(ff, red);
   if (threadIdx.x == 0) {
     colstat[c * 8 + 0] = aa > 0.0 ? sqrt(kk) / sqrt(aa) : sqrt(kk);  // residual at x
     colstat[c * 8 + 1] = 0.5 * ff;                                  // objective at x
@@ -660,19 +673,19 @@ __global__ __launch_bounds__(256) void refine_stage1_kernel(int64_t d, int64_t n
 
 // Stage 2 (after V = A D): alpha and the candidate x'.
 template <typename TX>
-__global__ __launch_bounds__(256) void refine_stage2_kernel(int64_t d, int64_t n, int64_t k,
+__global__ __launch_bounds__(RS_NT) void refine_stage2_kernel(int64_t d, int64_t n, int64_t k,
                                                             const TX* __restrict__ X,
                                                             const double* __restrict__ V,
                                                             const double* __restrict__ D,
                                                             double* __restrict__ Xn,
                                                             double* __restrict__ colstat) {
-  __shared__ double red[4];
+  __shared__ double red[RS_NT / 64];
   const int64_t c = blockIdx.x;
   double vv = strided_sumsq(V, d, k, c);
-  vv = block_sum<double, 256>(vv, red);
+  vv = block_sum<double, RS_NT>(vv, red);
   const double num = colstat[c * 8 + 2];
   const double alpha = (vv > 0.0 && __builtin_isfinite(vv)) ? num / vv : 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
+  for (int64_t i = threadIdx.x; i < n; i += RS_NT) {
     const double v = (double)X[i * k + c] - alpha * D[i * k + c];
     // rounded to the output type here, so the residual reported for x' is that of the stored x'
     Xn[i * k + c] = (double)(TX)(v > 0.0 ? v : 0.0);
@@ -682,7 +695,7 @@ __global__ __launch_bounds__(256) void refine_stage2_kernel(int64_t d, int64_t n
 
 // Stage 3 (after R' = A x' - B, G' = A^T R'): accept or reject, write results.
 template <typename TX>
-__global__ __launch_bounds__(256) void refine_stage3_kernel(int64_t d, int64_t n, int64_t k,
+__global__ __launch_bounds__(RS_NT) void refine_stage3_kernel(int64_t d, int64_t n, int64_t k,
                                                             TX* __restrict__ X,
                                                             const double* __restrict__ Xn,
                                                             const double* __restrict__ R2,
@@ -691,17 +704,17 @@ __global__ __launch_bounds__(256) void refine_stage3_kernel(int64_t d, int64_t n
                                                             const double* __restrict__ colstat,
                                                             double* __restrict__ kkt64,
                                                             double* __restrict__ obj64) {
-  __shared__ double red[4];
+  __shared__ double red[RS_NT / 64];
   const int64_t c = blockIdx.x;
   double ff = strided_sumsq(R2, d, k, c), kk = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
+  for (int64_t i = threadIdx.x; i < n; i += RS_NT) {
     const double y = s[i] * Xn[i * k + c];
     const double gy = G2[i * k + c] / s[i];
     const double m = y < gy ? y : gy;
     kk += m * m;
   }
-  ff = block_sum<double, 256>(ff, red);
-  kk = block_sum<double, 256>(kk, red);
+  ff = block_sum<double, RS_NT>(ff, red);
+  kk = block_sum<double, RS_NT>(kk, red);
   const double F1 = 0.5 * ff;
   const double F0 = colstat[c * 8 + 1];
   const double aa = colstat[c * 8 + 3];
@@ -711,7 +724,7 @@ __global__ __launch_bounds__(256) void refine_stage3_kernel(int64_t d, int64_t n
   // problem, can raise the KKT residual; keep it only when neither gets worse.
   const bool accept = (r1 < r0) && (F1 <= F0);
   if (accept) {
-    for (int64_t i = threadIdx.x; i < n; i += 256) X[i * k + c] = (TX)Xn[i * k + c];
+    for (int64_t i = threadIdx.x; i < n; i += RS_NT) X[i * k + c] = (TX)Xn[i * k + c];
   }
   if (threadIdx.x == 0) {
     kkt64[c] = accept ? r1 : r0;
@@ -821,18 +834,22 @@ static void launch_atr(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda,
     const float* Af = (const float*)A;
     const float* Bf = (const float*)B;
     switch (k) {
-      case 1: hipLaunchKernelGGL(cols_partial_vec_kernel<1>, g1, dim3(256), 0, st, d, n, Af, lda, R, Bf, ldb, wb, rows, w.partial); break;
-      case 2: hipLaunchKernelGGL(cols_partial_vec_kernel<2>, g1, dim3(256), 0, st, d, n, Af, lda, R, Bf, ldb, wb, rows, w.partial); break;
-      case 3: hipLaunchKernelGGL(cols_partial_vec_kernel<3>, g1, dim3(256), 0, st, d, n, Af, lda, R, Bf, ldb, wb, rows, w.partial); break;
-      default: hipLaunchKernelGGL(cols_partial_vec_kernel<4>, g1, dim3(256), 0, st, d, n, Af, lda, R, Bf, ldb, wb, rows, w.partial); break;
+#define CP_LAUNCH(KV)                                                                         \
+  hipLaunchKernelGGL(cols_partial_vec_kernel<KV>, g1, dim3(256), 0, st, d, n, Af, lda, R, Bf, ldb, \
+                     wb, rows, w.partial)
+      case 1: CP_LAUNCH(1); break;
+      case 2: CP_LAUNCH(2); break;
+      case 3: CP_LAUNCH(3); break;
+      default: CP_LAUNCH(4); break;
+#undef CP_LAUNCH
     }
   } else {
     dim3 g1((unsigned)((n + 255) / 256), (unsigned)w.chunks);
     hipLaunchKernelGGL(cols_partial_kernel<T>, g1, dim3(256), 0, st, d, n, k, A, lda, R, B, ldb,
                        wb, rows, w.partial);
   }
-  hipLaunchKernelGGL(cols_finalize_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, n,
-                     k, wb, w.chunks, (const double*)w.partial, G, w.Atb, w.s);
+  hipLaunchKernelGGL(cols_finalize_kernel, dim3((unsigned)((n + CF_C - 1) / CF_C)), dim3(256), 0,
+                     st, n, k, wb, w.chunks, (const double*)w.partial, G, w.Atb, w.s);
 }
 
 static bool fused_ok(const void* A, int64_t lda, int64_t n, int64_t k, size_t elem) {
@@ -865,8 +882,9 @@ static void launch_fused(int64_t d, int64_t n, const float* A, int64_t lda, cons
     else RC_LAUNCH(3, false);
   }
 #undef RC_LAUNCH
-  hipLaunchKernelGGL(cols_finalize_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, n,
-                     (int64_t)1, with_b ? 1 : 0, grid, (const double*)w.partial, G, w.Atb, w.s);
+  hipLaunchKernelGGL(cols_finalize_kernel, dim3((unsigned)((n + CF_C - 1) / CF_C)), dim3(256), 0,
+                     st, n, (int64_t)1, with_b ? 1 : 0, grid, (const double*)w.partial, G, w.Atb,
+                     w.s);
 }
 
 // C = A^T [M1 | M2] (see gemm_tn_f64_kernel); sq optional.
@@ -924,11 +942,11 @@ hipError_t launch_refine(int64_t d, int64_t n, int64_t k, const T* A, int64_t ld
     launch_resid<T>(d, n, k, A, lda, X, false, B, ldb, w.R, st);
     launch_atr<T>(d, n, k, A, lda, w.R, B, ldb, true, w, w.G, st);
   }
-  hipLaunchKernelGGL(refine_stage1_kernel<T>, dim3((unsigned)k), dim3(256), 0, st, d, n, k,
+  hipLaunchKernelGGL(refine_stage1_kernel<T>, dim3((unsigned)k), dim3(RS_NT), 0, st, d, n, k,
                      (const T*)X, (const double*)w.R, (const double*)w.G, (const double*)w.Atb,
                      (const double*)w.s, w.D, w.colstat);
   launch_resid<T>(d, n, k, A, lda, w.D, true, (const T*)nullptr, 0, w.V, st);
-  hipLaunchKernelGGL(refine_stage2_kernel<T>, dim3((unsigned)k), dim3(256), 0, st, d, n, k,
+  hipLaunchKernelGGL(refine_stage2_kernel<T>, dim3((unsigned)k), dim3(RS_NT), 0, st, d, n, k,
                      (const T*)X, (const double*)w.V, (const double*)w.D, w.Xn, w.colstat);
   if (fused) {
     launch_fused<double>(d, n, (const float*)A, lda, (const double*)w.Xn, (const float*)B, ldb,
@@ -937,7 +955,7 @@ hipError_t launch_refine(int64_t d, int64_t n, int64_t k, const T* A, int64_t ld
     launch_resid<T>(d, n, k, A, lda, w.Xn, true, B, ldb, w.R, st);
     launch_atr<T>(d, n, k, A, lda, w.R, B, ldb, false, w, w.G, st);
   }
-  hipLaunchKernelGGL(refine_stage3_kernel<T>, dim3((unsigned)k), dim3(256), 0, st, d, n, k, X,
+  hipLaunchKernelGGL(refine_stage3_kernel<T>, dim3((unsigned)k), dim3(RS_NT), 0, st, d, n, k, X,
                      (const double*)w.Xn, (const double*)w.R, (const double*)w.G,
                      (const double*)w.s, (const double*)w.colstat, kkt64, obj64);
   return hipGetLastError();
