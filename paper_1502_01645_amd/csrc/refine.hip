@@ -53,9 +53,11 @@ __global__ __launch_bounds__(256) void rows_residual_kernel(int64_t d, int64_t n
 }
 
 // Vectorized form of the same product for FP32 A with 16-byte aligned rows (lda % 4 == 0): each
-// wave takes RF_RPW rows at once, each lane 4 consecutive columns per step, so one load of x
-// serves RF_RPW rows and RF_RPW independent 16-byte loads of A are in flight per step.
+// wave takes RPW rows at once, each lane 4 consecutive columns per step, so one load of x serves
+// RPW rows and RPW independent 16-byte loads of A are in flight per step.  KV is the number of
+// right-hand sides the registers are sized for (k <= KV): 1 leaves room for 8 rows per wave.
 constexpr int RF_RPW = 4;
+constexpr int RF_RPW1 = 8;
 
 template <typename TX>
 __device__ __forceinline__ void load_x4(const TX* X, int64_t i, int64_t k, int c, double* xv) {
@@ -63,7 +65,7 @@ __device__ __forceinline__ void load_x4(const TX* X, int64_t i, int64_t k, int c
   for (int e = 0; e < 4; ++e) xv[e] = (double)X[(i + e) * k + c];
 }
 
-template <typename TX>
+template <typename TX, int KV, int RPW>
 __global__ __launch_bounds__(256) void rows_residual_vec_kernel(int64_t d, int64_t n, int64_t k,
                                                                 const float* __restrict__ A,
                                                                 int64_t lda,
@@ -72,34 +74,34 @@ __global__ __launch_bounds__(256) void rows_residual_vec_kernel(int64_t d, int64
                                                                 int64_t ldb,
                                                                 double* __restrict__ R) {
   const int lane = threadIdx.x & 63;
-  const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RF_RPW;
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW;
   if (r0 >= d) return;
-  double acc[RF_RPW][RF_SMALL_K];
+  double acc[RPW][KV];
 #pragma unroll
-  for (int q = 0; q < RF_RPW; ++q)
+  for (int q = 0; q < RPW; ++q)
 #pragma unroll
-    for (int c = 0; c < RF_SMALL_K; ++c) acc[q][c] = 0.0;
+    for (int c = 0; c < KV; ++c) acc[q][c] = 0.0;
   for (int64_t i = 4 * lane; i < n; i += 256) {
-    f32x4 a[RF_RPW];
+    f32x4 a[RPW];
 #pragma unroll
-    for (int q = 0; q < RF_RPW; ++q)
+    for (int q = 0; q < RPW; ++q)
       a[q] = (r0 + q < d) ? *(const f32x4*)(A + (r0 + q) * lda + i) : (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int c = 0; c < RF_SMALL_K; ++c) {
+    for (int c = 0; c < KV; ++c) {
       if (c < k) {
         double xv[4];
         load_x4(X, i, k, c, xv);
 #pragma unroll
-        for (int q = 0; q < RF_RPW; ++q)
+        for (int q = 0; q < RPW; ++q)
 #pragma unroll
           for (int e = 0; e < 4; ++e) acc[q][c] += (double)a[q][e] * xv[e];
       }
     }
   }
 #pragma unroll
-  for (int q = 0; q < RF_RPW; ++q) {
+  for (int q = 0; q < RPW; ++q) {
 #pragma unroll
-    for (int c = 0; c < RF_SMALL_K; ++c) {
+    for (int c = 0; c < KV; ++c) {
       if (c < k) {
         const double v = wave_sum(acc[q][c]);
         if (lane == 0 && r0 + q < d)
@@ -182,16 +184,18 @@ __global__ __launch_bounds__(256) void cols_partial_vec_kernel(int64_t d, int64_
 // range, and partial[wg, m, i] = sum over those rows of A[r, i] v_m[r] with v_0 = R, and with WB
 // v_1 = b and v_2 = A[r, i] (the squared column norm), in the layout of cols_partial_vec_kernel
 // with one chunk per workgroup.  Thread t owns columns 2048 j + 4 t .. + 3 (j < NB); a step takes
-// rc_rb rows (4, or 2 where the registers of 4 would spill): each thread's share of their dot
-// products, a wave sum, then a sum over the eight waves through LDS (double-buffered, one barrier
-// per step) gives the residuals, and the rows
-// still in registers are added into the column sums.  The next step's rows are loaded before the
-// reduction so HBM reads continue across it.  x holds FP32 values (for TX = double, values
+// RC_RB rows: each thread's share of their dot products, a wave sum, then a sum over the eight
+// waves through LDS (double-buffered, one barrier per step) gives the residuals, and the rows
+// still in registers are added into the column sums.  The rows of the next PF - 1 steps are in
+// flight meanwhile (a ring of PF register buffers, rotated by unrolling the step loop PF times),
+// so HBM reads continue across the reductions.  x holds FP32 values (for TX = double, values
 // rounded to FP32, as the candidate x' of the refinement is); the products are exact in FP64.
 constexpr int RC_NT = 512;
+constexpr int RC_RB = 2;
 constexpr int RC_MAX_NB = 3;
 constexpr int RC_MAX_WG = 256;
-constexpr int rc_rb(int nb, bool wb) { return nb == 3 && wb ? 2 : 4; }
+// steps in flight: as many as the registers hold next to the column sums
+constexpr int rc_pf(int nb, bool wb) { return nb == 1 ? 4 : (wb ? (nb == 3 ? 3 : 4) : 4); }
 
 template <int NB, bool WB, typename TX>
 __global__ __launch_bounds__(RC_NT, 1) void rows_cols_fused_kernel(
@@ -199,7 +203,7 @@ __global__ __launch_bounds__(RC_NT, 1) void rows_cols_fused_kernel(
     const float* __restrict__ B, int64_t ldb, int64_t rows_per_wg, double* __restrict__ R,
     double* __restrict__ partial) {
   constexpr int NV = WB ? 3 : 1;
-  constexpr int RC_RB = rc_rb(NB, WB);
+  constexpr int PF = rc_pf(NB, WB);
   __shared__ double red[2][RC_NT / 64][RC_RB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
@@ -222,23 +226,21 @@ __global__ __launch_bounds__(RC_NT, 1) void rows_cols_fused_kernel(
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[m][j][e] = 0.0;
 
-  auto load_step = [&](int64_t rs, f32x4 (&a)[RC_RB][NB], float (&bq)[RC_RB]) {
+  f32x4 a[PF][RC_RB][NB];
+  float bq[PF][RC_RB];
+  auto load_step = [&](int64_t rs, f32x4 (&av)[RC_RB][NB], float (&bv)[RC_RB]) {
 #pragma unroll
     for (int q = 0; q < RC_RB; ++q) {
       const bool rv = rs + q < r1;
 #pragma unroll
       for (int j = 0; j < NB; ++j)
-        a[q][j] = (rv && cv[j]) ? *(const f32x4*)(A + (rs + q) * lda + 2048 * j + 4 * tid)
-                                : (f32x4){0.f, 0.f, 0.f, 0.f};
-      bq[q] = rv ? B[(rs + q) * ldb] : 0.f;
+        av[q][j] = (rv && cv[j]) ? *(const f32x4*)(A + (rs + q) * lda + 2048 * j + 4 * tid)
+                                 : (f32x4){0.f, 0.f, 0.f, 0.f};
+      bv[q] = rv ? B[(rs + q) * ldb] : 0.f;
     }
   };
-  f32x4 a[RC_RB][NB], an[RC_RB][NB];
-  float bq[RC_RB], bn[RC_RB];
-  load_step(r0, a, bq);
-  int par = 0;
-  for (int64_t rs = r0; rs < r1; rs += RC_RB) {
-    if (rs + RC_RB < r1) load_step(rs + RC_RB, an, bn);
+  auto process = [&](int64_t rs, const f32x4 (&av)[RC_RB][NB], const float (&bv)[RC_RB],
+                     int par) {
     double dot[RC_RB];
 #pragma unroll
     for (int q = 0; q < RC_RB; ++q) {
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(RC_NT, 1) void rows_cols_fused_kernel(
 #pragma unroll
       for (int j = 0; j < NB; ++j)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) t += (double)a[q][j][e] * (double)xv[j][e];
+        for (int e = 0; e < 4; ++e) t += (double)av[q][j][e] * (double)xv[j][e];
       dot[q] = wave_sum(t);
     }
     if (lane == 0) {
@@ -260,27 +262,39 @@ __global__ __launch_bounds__(RC_NT, 1) void rows_cols_fused_kernel(
 #pragma unroll
       for (int w = 0; w < RC_NT / 64; ++w) t += red[par][w][q];
       // rows past the range have zero A and b, so their residual is 0 and adds nothing
-      const double rq = t - (double)bq[q];
+      const double rq = t - (double)bv[q];
       if (tid == q && rs + q < r1) R[rs + q] = rq;
 #pragma unroll
       for (int j = 0; j < NB; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const double av = (double)a[q][j][e];
-          acc[0][j][e] += av * rq;
+          const double x = (double)av[q][j][e];
+          acc[0][j][e] += x * rq;
           if (WB) {
-            acc[1 % NV][j][e] += av * (double)bq[q];
-            acc[2 % NV][j][e] += av * av;
+            acc[1 % NV][j][e] += x * (double)bv[q];
+            acc[2 % NV][j][e] += x * x;
           }
         }
     }
-    par ^= 1;
+  };
+
 #pragma unroll
-    for (int q = 0; q < RC_RB; ++q) {
-      bq[q] = bn[q];
+  for (int p = 0; p + 1 < PF; ++p)
+    if (r0 + p * RC_RB < r1) load_step(r0 + p * RC_RB, a[p], bq[p]);
+  // step u of a round uses buffer u; the buffer it refills, (u + PF - 1) % PF, was used by the
+  // step before; the LDS parity alternates with the step (PF * round + u), so PF even keeps it
+  // a compile-time value and PF odd flips it once per round
+  int round_par = 0;
+  for (int64_t rs = r0; rs < r1; rs += PF * RC_RB) {
 #pragma unroll
-      for (int j = 0; j < NB; ++j) a[q][j] = an[q][j];
+    for (int u = 0; u < PF; ++u) {
+      const int64_t rc = rs + u * RC_RB;
+      if (rc >= r1) break;
+      const int64_t rn = rc + (PF - 1) * RC_RB;
+      if (rn < r1) load_step(rn, a[(u + PF - 1) % PF], bq[(u + PF - 1) % PF]);
+      process(rc, a[u], bq[u], (round_par + u) & 1);
     }
+    round_par ^= PF & 1;
   }
 #pragma unroll
   for (int m = 0; m < NV; ++m)
@@ -805,13 +819,25 @@ static void launch_resid(int64_t d, int64_t n, int64_t k, const T* A, int64_t ld
                          const void* X, bool x_is_double, const T* B, int64_t ldb, double* R,
                          hipStream_t st) {
   if (vec_ok(A, lda, n, sizeof(T))) {
-    dim3 grid((unsigned)((d + 4 * RF_RPW - 1) / (4 * RF_RPW)));
-    if (x_is_double)
-      hipLaunchKernelGGL(rows_residual_vec_kernel<double>, grid, dim3(256), 0, st, d, n, k,
-                         (const float*)A, lda, (const double*)X, (const float*)B, ldb, R);
-    else
-      hipLaunchKernelGGL(rows_residual_vec_kernel<float>, grid, dim3(256), 0, st, d, n, k,
-                         (const float*)A, lda, (const float*)X, (const float*)B, ldb, R);
+    const int rpw = k == 1 ? RF_RPW1 : RF_RPW;
+    dim3 grid((unsigned)((d + 4 * rpw - 1) / (4 * rpw)));
+    const float* Af = (const float*)A;
+    const float* Bf = (const float*)B;
+    if (k == 1) {
+      if (x_is_double)
+        hipLaunchKernelGGL((rows_residual_vec_kernel<double, 1, RF_RPW1>), grid, dim3(256), 0, st,
+                           d, n, k, Af, lda, (const double*)X, Bf, ldb, R);
+      else
+        hipLaunchKernelGGL((rows_residual_vec_kernel<float, 1, RF_RPW1>), grid, dim3(256), 0, st,
+                           d, n, k, Af, lda, (const float*)X, Bf, ldb, R);
+    } else {
+      if (x_is_double)
+        hipLaunchKernelGGL((rows_residual_vec_kernel<double, RF_SMALL_K, RF_RPW>), grid, dim3(256),
+                           0, st, d, n, k, Af, lda, (const double*)X, Bf, ldb, R);
+      else
+        hipLaunchKernelGGL((rows_residual_vec_kernel<float, RF_SMALL_K, RF_RPW>), grid, dim3(256),
+                           0, st, d, n, k, Af, lda, (const float*)X, Bf, ldb, R);
+    }
   } else {
     dim3 grid((unsigned)((d + 3) / 4));
     if (x_is_double)
