@@ -348,7 +348,9 @@ __device__ __forceinline__ void gram_tile_bf16x3(f32x4 (&acc)[4][4], int64_t r_b
 // staged 32 rows at a time in two LDS stages of 64 KB (Xh, Xl, Yh, Yl parts of 256 columns x 32
 // values).  Each stage is filled by global_load_lds_dwordx4 (16 bytes per lane straight into
 // LDS): the loads of step s+1 are issued right after the barrier of step s and land while the
-// waves run the 3 x 32 MFMAs (hi*hi + hi*lo + lo*hi, v_mfma_f32_16x16x32_bf16) of step s.
+// waves run the 3 x 32 MFMAs (hi*hi + hi*lo + lo*hi, v_mfma_f32_16x16x32_bf16) of step s; the
+// LDS reads of the next 16-row A fragment pair are placed under the MFMAs of the current one
+// (scheduling group barriers), so they do not stall the matrix cores.
 // Inside a stage, the four 16-byte k-groups of a column are stored XOR-swizzled by gd_swz of the
 // column, so the fragment reads of 8 or 16 consecutive columns hit distinct bank groups.  The
 // swizzle is applied on the global side: lane i of a load instruction fetches the k-group that
@@ -526,11 +528,18 @@ __global__ __launch_bounds__(GD_NT, 1) void gram_dma_kernel(
       bh[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&st[2 * GD_PART + yo]);
       bl[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&st[3 * GD_PART + yo]);
     }
+    // the A fragments of row block a + 1 are read while the MFMAs of block a run
+    const int xo0 = (wm + fr) * GD_BK + 8 * fp;
+    bf16x8 ahn = __builtin_bit_cast(bf16x8, *(const u32x4*)&st[xo0]);
+    bf16x8 aln = __builtin_bit_cast(bf16x8, *(const u32x4*)&st[GD_PART + xo0]);
 #pragma unroll
     for (int a = 0; a < GD_MT; ++a) {
-      const int xo = (wm + a * 16 + fr) * GD_BK + 8 * fp;
-      const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u32x4*)&st[xo]);
-      const bf16x8 al = __builtin_bit_cast(bf16x8, *(const u32x4*)&st[GD_PART + xo]);
+      const bf16x8 ah = ahn, al = aln;
+      if (a + 1 < GD_MT) {
+        const int xo = xo0 + (a + 1) * 16 * GD_BK;
+        ahn = __builtin_bit_cast(bf16x8, *(const u32x4*)&st[xo]);
+        aln = __builtin_bit_cast(bf16x8, *(const u32x4*)&st[GD_PART + xo]);
+      }
 #pragma unroll
       for (int b = 0; b < GD_NTL; ++b) {
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[b], acc[a][b], 0, 0, 0);
@@ -538,6 +547,17 @@ __global__ __launch_bounds__(GD_NT, 1) void gram_dma_kernel(
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
       }
     }
+    // instruction order of the step: the B fragments and the first A pair, then per row block
+    // 2 MFMAs, the LDS reads of the next A pair, and the block's other 10 MFMAs, so each read
+    // has a block of MFMAs to land under
+    __builtin_amdgcn_sched_group_barrier(0x100, 2 * GD_NTL + 2, 0);
+#pragma unroll
+    for (int a = 0; a + 1 < GD_MT; ++a) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 3 * GD_NTL - 2, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 3 * GD_NTL, 0);
   }
 
   // D fragment layout of the 16x16 FP32 MFMA: lane holds column (lane & 15), rows
