@@ -320,6 +320,7 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
 
     // ---- B: w_I = Q[I, :] gbar, den partial
     reg_product<RPC, CS, NT>(qr, vs, red, prod);
+    const float w_own = own ? prod[t] : 0.f;
     if (wave == 0) {
       const bool pas = own && ((y_own > 0.f) || (g_own < 0.f));
       const float v = wave_sum(pas ? g_own * prod[t] : 0.f);
@@ -362,21 +363,36 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
     const float alpha = num / den;
 
     // projection on the own columns (a thread reads and writes only its own entries of ys and
-    // vs, so no barrier is needed); vs becomes d = y' - y
+    // vs, so no barrier is needed).  With v = y - alpha gbar, d = y' - y = -alpha gbar + c where
+    // c = -v on the clipped entries and 0 elsewhere; vs becomes c.
 #pragma unroll
     for (int s = 0; s < CS; ++s) {
       const float yo = ys[s * NT + t];
       const float v = yo - alpha * vs[s * NT + t];
-      const float yn = v > 0.f ? v : 0.f;
-      clipped += (v < 0.f) ? 1 : 0;
-      vs[s * NT + t] = yn - yo;
-      ys[s * NT + t] = yn;
+      const bool clip = v < 0.f;
+      clipped += clip ? 1 : 0;
+      vs[s * NT + t] = clip ? -v : 0.f;
+      ys[s * NT + t] = clip ? 0.f : v;
     }
 
-    // ---- D: g'_I = g_I + Q[I, :] d, publish gbar(e + 1)
-    reg_product<RPC, CS, NT>(qr, vs, red, prod);
+    // ---- D: g'_I = g_I + Q[I, :] d = g_I - alpha w_I + Q[I, :] c, publish gbar(e + 1); the
+    // product runs over the clipped columns only
+    {
+      float acc[RPC];
+#pragma unroll
+      for (int r = 0; r < RPC; ++r) acc[r] = 0.f;
+#pragma unroll
+      for (int s = 0; s < CS; ++s) {
+        const float c = vs[s * NT + t];
+        if (c != 0.f) {
+#pragma unroll
+          for (int r = 0; r < RPC; ++r) acc[r] += qr[r][s] * c;
+        }
+      }
+      rows_reduce<RPC, NT>(acc, red, prod);
+    }
     if (own) {
-      g_own += prod[t];
+      g_own = (g_own - alpha * w_own) + prod[t];
       const int i = i0 + t;
       y_own = ys[(i / NT) * NT + (i % NT)];
     }
