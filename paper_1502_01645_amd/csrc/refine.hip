@@ -390,6 +390,9 @@ __global__ __launch_bounds__(256) void cols_finalize_kernel(int64_t n, int64_t k
 // 32 x 32, K staged through LDS 32 rows at a time (zero-filled past the edges) with the next
 // chunk loaded into registers while the current one is multiplied.  With sq != nullptr the
 // workgroups of row tile 0 also write sq[j] = sum_r M2[r, j]^2 for their M2 columns.
+// Split over K (part != nullptr): workgroup z of gridDim.z takes rows [z kps, (z + 1) kps) of the
+// sum and writes its partial tile to part[z][i][j] (j over all n1 + n2 columns) and its partial
+// squares to part_sq[z][j - n1]; gemm_tn_reduce_kernel adds the partials in order of z.
 constexpr int TN_T = 64, TN_BK = 32, TN_LD = TN_T + 2;
 
 template <typename TA, typename TM>
@@ -397,7 +400,8 @@ __global__ __launch_bounds__(256) void gemm_tn_f64_kernel(
     int64_t K, int64_t N, int64_t n1, int64_t n2, const TA* __restrict__ A, int64_t lda,
     const TM* __restrict__ M1, int64_t ld1, const TM* __restrict__ M2, int64_t ld2,
     double* __restrict__ C1, int64_t ldc1, double* __restrict__ C2, int64_t ldc2,
-    double* __restrict__ sq) {
+    double* __restrict__ sq, int64_t kps, double* __restrict__ part,
+    double* __restrict__ part_sq) {
   __shared__ double sa[TN_BK][TN_LD];
   __shared__ double sm[TN_BK][TN_LD];
   __shared__ double sqred[4][TN_T];
@@ -421,12 +425,15 @@ __global__ __launch_bounds__(256) void gemm_tn_f64_kernel(
   double sqacc = 0.0;
   TA ra[TN_BK / 4];
   TM rm[TN_BK / 4];
+  // rows [kb, ke) of the sum: all of them, or this split's share
+  const int64_t kb = part != nullptr ? (int64_t)blockIdx.z * kps : 0;
+  const int64_t ke = part != nullptr ? (kb + kps < K ? kb + kps : K) : K;
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int u = 0; u < TN_BK / 4; ++u) {
       const int64_t gr = k0 + r0 + 4 * u;
-      ra[u] = (a_ok && gr < K) ? A[gr * lda + ia] : (TA)0;
-      rm[u] = (mp != nullptr && gr < K) ? mp[gr * mld] : (TM)0;
+      ra[u] = (a_ok && gr < ke) ? A[gr * lda + ia] : (TA)0;
+      rm[u] = (mp != nullptr && gr < ke) ? mp[gr * mld] : (TM)0;
     }
   };
   auto store = [&]() {
@@ -445,11 +452,11 @@ __global__ __launch_bounds__(256) void gemm_tn_f64_kernel(
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
   const int col = lane & 15, kq = lane >> 4;
-  if (K > 0) load(0);
-  for (int64_t k0 = 0; k0 < K; k0 += TN_BK) {
+  if (kb < ke) load(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += TN_BK) {
     store();
     __syncthreads();
-    if (k0 + TN_BK < K) load(k0 + TN_BK);  // in flight during the MFMAs below
+    if (k0 + TN_BK < ke) load(k0 + TN_BK);  // in flight during the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < TN_BK; kk += 4) {
       const int kr = kk + kq;
@@ -473,14 +480,44 @@ __global__ __launch_bounds__(256) void gemm_tn_f64_kernel(
         const int64_t i = i0 + wi + a * 16 + kq + 4 * e;
         const int64_t j = j0 + wj + b * 16 + col;
         if (i >= N) continue;
-        if (j < n1) C1[i * ldc1 + j] = acc[a][b][e];
-        else if (j < n1 + n2) C2[i * ldc2 + (j - n1)] = acc[a][b][e];
+        if (part != nullptr) {
+          if (j < n1 + n2) part[((int64_t)blockIdx.z * N + i) * (n1 + n2) + j] = acc[a][b][e];
+        } else if (j < n1) {
+          C1[i * ldc1 + j] = acc[a][b][e];
+        } else if (j < n1 + n2) {
+          C2[i * ldc2 + (j - n1)] = acc[a][b][e];
+        }
       }
   if (sq != nullptr && blockIdx.y == 0) {
     sqred[r0][c] = sqacc;
     __syncthreads();
-    if (tid < TN_T && want_sq)
-      sq[jm - n1] = (sqred[0][tid] + sqred[1][tid]) + (sqred[2][tid] + sqred[3][tid]);
+    if (tid < TN_T && want_sq) {
+      const double v = (sqred[0][tid] + sqred[1][tid]) + (sqred[2][tid] + sqred[3][tid]);
+      if (part != nullptr) part_sq[(int64_t)blockIdx.z * n2 + (jm - n1)] = v;
+      else sq[jm - n1] = v;
+    }
+  }
+}
+
+// C1 / C2 (and sq) from the split partials of gemm_tn_f64_kernel: element e of the N x (n1 + n2)
+// result (then of the n2 squares) is the sum over z < S of its partials, in order of z.
+__global__ __launch_bounds__(256) void gemm_tn_reduce_kernel(
+    int S, int64_t N, int64_t n1, int64_t n2, const double* __restrict__ part,
+    const double* __restrict__ part_sq, double* __restrict__ C1, int64_t ldc1,
+    double* __restrict__ C2, int64_t ldc2, double* __restrict__ sq) {
+  const int64_t w = n1 + n2, tot = N * w;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < tot) {
+    double v = 0.0;
+    for (int z = 0; z < S; ++z) v += part[(int64_t)z * tot + e];
+    const int64_t i = e / w, j = e % w;
+    if (j < n1) C1[i * ldc1 + j] = v;
+    else C2[i * ldc2 + (j - n1)] = v;
+  } else if (sq != nullptr && e < tot + n2) {
+    const int64_t j = e - tot;
+    double v = 0.0;
+    for (int z = 0; z < S; ++z) v += part_sq[(int64_t)z * n2 + j];
+    sq[j] = v;
   }
 }
 
@@ -778,9 +815,9 @@ static RefineWs refine_layout(void* ws, int64_t d, int64_t n, int64_t k) {
 }
 
 // Gram path workspace: H [n, n], a, HX, D, HD (reused for H X'), X' [n, k], s [n],
-// colstat [8 k], ||b||^2 [k].
+// colstat [8 k], ||b||^2 [k], and the partials of a split product.
 struct GramRefineWs {
-  double *H, *a, *HX, *D, *HD, *Xn, *s, *colstat, *bb;
+  double *H, *a, *HX, *D, *HD, *Xn, *s, *colstat, *bb, *part;
 };
 
 static GramRefineWs gram_refine_layout(void* ws, int64_t n, int64_t k) {
@@ -794,9 +831,12 @@ static GramRefineWs gram_refine_layout(void* ws, int64_t n, int64_t k) {
   w.Xn = p; p += n * k;
   w.s = p; p += n;
   w.colstat = p; p += 8 * k;
-  w.bb = p;
+  w.bb = p; p += k;
+  w.part = p;
   return w;
 }
+
+static int gref_splits(int64_t d, int64_t n, int64_t k);
 
 size_t refine_ws_bytes(int64_t d, int64_t n, int64_t k) {
   size_t el;
@@ -806,7 +846,8 @@ size_t refine_ws_bytes(int64_t d, int64_t n, int64_t k) {
     el = (size_t)(2 * d * k + 4 * n * k + n + 8 * k) + (size_t)ch * (2 * k + 1) * n;
   }
   else
-    el = (size_t)(n * n + 5 * n * k + n + 9 * k);
+    el = (size_t)(n * n + 5 * n * k + n + 9 * k) +
+         (size_t)gref_splits(d, n, k) * (size_t)(n * (n + k) + k);
   return el * sizeof(double) + 256;
 }
 
@@ -913,14 +954,48 @@ static void launch_fused(int64_t d, int64_t n, const float* A, int64_t lda, cons
                      w.s);
 }
 
-// C = A^T [M1 | M2] (see gemm_tn_f64_kernel); sq optional.
+// C = A^T [M1 | M2] (see gemm_tn_f64_kernel); sq optional.  S > 1 splits the sum over K into
+// S row ranges with partials in part (S (N (n1 + n2) + n2) doubles), added by a second kernel.
 template <typename TA, typename TM>
 static void gemm_tn(int64_t K, int64_t N, const TA* A, int64_t lda, int64_t n1, const TM* M1,
                     int64_t ld1, double* C1, int64_t ldc1, int64_t n2, const TM* M2, int64_t ld2,
-                    double* C2, int64_t ldc2, double* sq, hipStream_t st) {
-  dim3 grid((unsigned)((n1 + n2 + TN_T - 1) / TN_T), (unsigned)((N + TN_T - 1) / TN_T));
+                    double* C2, int64_t ldc2, double* sq, hipStream_t st, int S = 1,
+                    double* part = nullptr) {
+  if (S <= 1) part = nullptr;
+  const int64_t kps = part ? ((K + S - 1) / S + TN_BK - 1) / TN_BK * TN_BK : K;
+  double* part_sq = part ? part + (int64_t)S * N * (n1 + n2) : nullptr;
+  dim3 grid((unsigned)((n1 + n2 + TN_T - 1) / TN_T), (unsigned)((N + TN_T - 1) / TN_T),
+            part ? (unsigned)S : 1u);
   hipLaunchKernelGGL((gemm_tn_f64_kernel<TA, TM>), grid, dim3(256), 0, st, K, N, n1, n2, A, lda,
-                     M1, ld1, M2, ld2, C1, ldc1, C2, ldc2, sq);
+                     M1, ld1, M2, ld2, C1, ldc1, C2, ldc2, sq, kps, part, part_sq);
+  if (part) {
+    const int64_t tot = N * (n1 + n2) + (sq ? n2 : 0);
+    hipLaunchKernelGGL(gemm_tn_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                       st, S, N, n1, n2, (const double*)part, (const double*)part_sq, C1, ldc1,
+                       C2, ldc2, sq);
+  }
+}
+
+// K splits of the FP64 Gram [A | B]^T A.  With fewer than two 64 x 64 tiles per compute unit
+// the busiest unit does ceil(tiles / CUs) tiles; splitting K S ways makes that
+// ceil(tiles S / CUs) / S tiles' worth.  S minimises that plus 1 % per split (the partials), at
+// most 8 splits of at least 256 rows each.
+static int gref_splits(int64_t d, int64_t n, int64_t k) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t tiles = ((n + k + TN_T - 1) / TN_T) * ((n + TN_T - 1) / TN_T);
+  if (cus < 1 || tiles >= 2 * (int64_t)cus) return 1;
+  int best = 1;
+  double best_cost = 1e30;
+  for (int S = 1; S <= 8 && (S == 1 || (int64_t)S * 256 <= d); ++S) {
+    const double cost = (double)((tiles * S + cus - 1) / cus) / S + 0.01 * S;
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = S;
+    }
+  }
+  return best;
 }
 
 template <typename T>
@@ -930,7 +1005,8 @@ static void launch_refine_gram(int64_t d, int64_t n, int64_t k, const T* A, int6
   GramRefineWs w = gram_refine_layout(ws, n, k);
   const unsigned cb = (unsigned)((k + GS_C - 1) / GS_C);
   // H = A^T A and a = A^T B in one launch over the columns of [A | B], with ||b||^2
-  gemm_tn<T, T>(d, n, A, lda, n, A, lda, w.H, n, k, B, ldb, w.a, k, w.bb, st);
+  gemm_tn<T, T>(d, n, A, lda, n, A, lda, w.H, n, k, B, ldb, w.a, k, w.bb, st,
+                gref_splits(d, n, k), w.part);
   hipLaunchKernelGGL(diag_scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
                      (const double*)w.H, w.s);
   // H is symmetric, so H^T M = H M: the same transposed product with K = n

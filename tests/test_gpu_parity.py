@@ -186,8 +186,9 @@ def test_many_rhs_small():
     _check_solution(A, B, host(res["X"]), 1e-5, ref, "many-rhs")
 
 
+# (700, 130, 70) and (2100, 64, 40) split the FP64 product over K (2 and 8 ways)
 @pytest.mark.parametrize("dtype,d,n,k", [(np.float32, 700, 130, 70), (np.float64, 500, 67, 9),
-                                         (np.float32, 300, 256, 5)])
+                                         (np.float32, 300, 256, 5), (np.float32, 2100, 64, 40)])
 @pytest.mark.parametrize("start", ["loose", "zero"])
 def test_refine_many_rhs_matches_oracle(dtype, d, n, k, start):
     """FP64 check and refinement step for more than four right-hand sides (the FP64 Gram path):
