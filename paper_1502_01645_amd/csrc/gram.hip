@@ -48,26 +48,32 @@ __global__ __launch_bounds__(256) void colnorm_partial_kernel(int64_t d, int64_t
   partial[chunk * n + col] = acc0 + acc1;
 }
 
-// Block: 64 columns; thread (column tid % 64, group tid / 64) sums the chunks g, g + 4, ... with
-// four accumulators, then the four group sums are added in fixed order.
+// Block: 16 columns; thread (column tid % 16, group tid / 16) sums the chunks g, g + 16, ... with
+// four accumulators, then the 16 group sums of a column are added in fixed order.  (A wave reads
+// 16 consecutive doubles of 4 chunks at a time; 16 columns per block give enough blocks to
+// spread the partial sums over the GPU.)
+constexpr int CN_C = 16;
+constexpr int CN_G = 256 / CN_C;
 __global__ __launch_bounds__(256) void colnorm_finalize_kernel(int64_t n, int64_t nchunks,
                                                                const double* partial, double* s) {
-  __shared__ double red[4][64];
-  const int cl = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int64_t col = (int64_t)blockIdx.x * 64 + cl;
+  __shared__ double red[CN_G][CN_C];
+  const int cl = threadIdx.x % CN_C, grp = threadIdx.x / CN_C;
+  const int64_t col = (int64_t)blockIdx.x * CN_C + cl;
   double a[4] = {0.0, 0.0, 0.0, 0.0};
   if (col < n) {
     int64_t c = grp;
-    for (; c + 12 < nchunks; c += 16) {
+    for (; c + 3 * CN_G < nchunks; c += 4 * CN_G) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] += partial[(c + 4 * u) * n + col];
+      for (int u = 0; u < 4; ++u) a[u] += partial[(c + CN_G * u) * n + col];
     }
-    for (; c < nchunks; c += 4) a[0] += partial[c * n + col];
+    for (; c < nchunks; c += CN_G) a[0] += partial[c * n + col];
   }
   red[grp][cl] = (a[0] + a[1]) + (a[2] + a[3]);
   __syncthreads();
   if (grp == 0 && col < n) {
-    const double acc = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+    double acc = 0.0;
+#pragma unroll
+    for (int g = 0; g < CN_G; ++g) acc += red[g][cl];
     s[col] = acc > 0.0 ? sqrt(acc) : 1.0;
   }
 }
@@ -843,8 +849,8 @@ hipError_t launch_colnorm(int64_t d, int64_t n, const T* A, int64_t lda, double*
   const int64_t rows = (d + chunks - 1) / chunks;
   dim3 g1((unsigned)((n + 255) / 256), (unsigned)chunks);
   hipLaunchKernelGGL(colnorm_partial_kernel<T>, g1, dim3(256), 0, st, d, n, A, lda, rows, ws);
-  hipLaunchKernelGGL(colnorm_finalize_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st,
-                     n, chunks, (const double*)ws, s);
+  hipLaunchKernelGGL(colnorm_finalize_kernel, dim3((unsigned)((n + CN_C - 1) / CN_C)), dim3(256),
+                     0, st, n, chunks, (const double*)ws, s);
   return hipGetLastError();
 }
 template hipError_t launch_colnorm<float>(int64_t, int64_t, const float*, int64_t, double*,
@@ -914,8 +920,8 @@ static hipError_t gram_bf16x3_run(int64_t d, int64_t n, int64_t k, const float* 
   hipLaunchKernelGGL(presplit_kernel, g0, dim3(256), 0, st, d, n, k, A, lda, B, ldb, p.dpad, Ph,
                      Pl, s_out != nullptr ? colsq : nullptr);
   if (s_out != nullptr)
-    hipLaunchKernelGGL(colnorm_finalize_kernel, dim3((unsigned)((n + 63) / 64)), dim3(256), 0,
-                       st, n, p.dpad / PS_T, (const double*)colsq, s_out);
+    hipLaunchKernelGGL(colnorm_finalize_kernel, dim3((unsigned)((n + CN_C - 1) / CN_C)),
+                       dim3(256), 0, st, n, p.dpad / PS_T, (const double*)colsq, s_out);
   const int blocks = schedule_blocks(p.ntiles, p.splits);
   dim3 grid((unsigned)blocks);
   hipError_t e = hipFuncSetAttribute((const void*)gram_dma_kernel,
