@@ -76,36 +76,41 @@ __device__ void mfma_product(const MrArgs& A, const float* V, float* W) {
   }
 }
 
-// W = Q * V with Q held in registers (n <= 256): wave w owns the row tiles t = w + 4 tt
-// (tt < TPW, np = 64 TPW); lane l holds Q[16 t + l % 16][4 ks + l / 16] for every k step ks,
-// the A operand of MFMA ks, so a product reads only V from LDS (lane l: row 4 ks + l / 16, slot
-// l % 16; 16 consecutive lanes hit 16 consecutive banks) and one V value feeds TPW MFMAs.
-template <int TPW>
-__device__ __forceinline__ void mfma_product_reg(const float (&qa)[TPW][16 * TPW],
-                                                 const float* V, float* W) {
+// W = Q * V with Q held in registers (n <= 256): of NW waves, wave w owns the row tiles
+// t = w + NW tt (tt < TW); lane l holds Q[16 t + l % 16][4 ks + l / 16] for every k step
+// ks < KS (np = 4 KS), the A operand of MFMA ks, so a product reads only V from LDS (lane l: row
+// 4 ks + l / 16, slot l % 16; 16 consecutive lanes hit 16 consecutive banks) and one V value
+// feeds TW MFMAs.
+template <int TW, int KS, int NW>
+__device__ __forceinline__ void mfma_product_reg(const float (&qa)[TW][KS], const float* V,
+                                                 float* W) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 15, lg = lane >> 4;
-  f32x4 acc[TPW];
+  f32x4 acc[TW];
 #pragma unroll
-  for (int tt = 0; tt < TPW; ++tt) acc[tt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int tt = 0; tt < TW; ++tt) acc[tt] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int ks = 0; ks < 16 * TPW; ++ks) {
+  for (int ks = 0; ks < KS; ++ks) {
     const float b = V[(4 * ks + lg) * MR_SLOTS + lr];
 #pragma unroll
-    for (int tt = 0; tt < TPW; ++tt)
+    for (int tt = 0; tt < TW; ++tt)
       acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[tt][ks], b, acc[tt], 0, 0, 0);
   }
 #pragma unroll
-  for (int tt = 0; tt < TPW; ++tt) {
-    const int t = wave + 4 * tt;
+  for (int tt = 0; tt < TW; ++tt) {
+    const int t = wave + NW * tt;
 #pragma unroll
     for (int e = 0; e < 4; ++e) W[(t * 16 + 4 * lg + e) * MR_SLOTS + lr] = acc[tt][e];
   }
 }
 
-// TPW > 0: Q in registers (n <= 64 TPW); TPW == 0: Q read from L2 by mfma_product.
-template <int TPW>
-__global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrArgs A) {
+// TPW > 0: Q in registers (n <= 64 TPW); TPW == 0: Q read from L2 by mfma_product.  NT threads
+// per workgroup: 256, or 512 for TPW = 4, where 8 waves of two row tiles each hold Q with 128
+// registers per lane and two waves per SIMD let one wave's vector work run beside the other's
+// matrix-core products.
+template <int TPW, int NT>
+__global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrArgs A) {
+  static_assert(TPW == 0 ? NT == MR_NT : (4 * TPW) % (NT / 64) == 0, "row tiles per wave");
   extern __shared__ __attribute__((aligned(16))) float sm[];
   const int np = A.np, n = A.n;
   float* Y = sm;                       // [np][16]
@@ -114,8 +119,8 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
   float* W = P + np * MR_SLOTS;        // [np][16] product result
   float* colf = W + np * MR_SLOTS;     // per-slot floats [8][16]
   int* coli = (int*)(colf + 8 * MR_SLOTS);  // per-slot ints [9][16]
-  float* red = (float*)(coli + 9 * MR_SLOTS);  // [4 waves][16 slots][4]
-  int* s_anyclip = (int*)(red + 4 * MR_SLOTS * 4);  // some slot clipped in this update
+  float* red = (float*)(coli + 9 * MR_SLOTS);  // [NT / 64 waves][16 slots][4]
+  int* s_anyclip = (int*)(red + (NT / kWave) * MR_SLOTS * 4);  // some slot clipped this update
 
   // per-slot state in LDS
   float* s_num = colf + 0 * MR_SLOTS;
@@ -140,30 +145,32 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
   const int slot = tid & 15;              // elementwise mapping: slot = tid % 16,
   const int row0 = tid >> 4;              // rows row0 + 16 m
 
-  // Q in registers for the matrix-core products (TPW > 0)
-  constexpr int QT = TPW > 0 ? TPW : 1;
-  float qa[QT][16 * QT];
+  // Q in registers for the matrix-core products (TPW > 0): TW row tiles per wave, KS k steps
+  constexpr int NW = NT / kWave;
+  constexpr int TW = TPW > 0 ? 4 * TPW / NW : 1;
+  constexpr int KS = TPW > 0 ? 16 * TPW : 1;
+  float qa[TW][KS];
   if (TPW > 0) {
     const int lr = lane & 15, lg = lane >> 4;
 #pragma unroll
-    for (int tt = 0; tt < QT; ++tt) {
-      const int m = (wave + 4 * tt) * 16 + lr;
+    for (int tt = 0; tt < TW; ++tt) {
+      const int m = (wave + NW * tt) * 16 + lr;
 #pragma unroll
-      for (int ks = 0; ks < 16 * QT; ++ks) {
+      for (int ks = 0; ks < KS; ++ks) {
         const int kk = 4 * ks + lg;
         qa[tt][ks] = (m < n && kk < n) ? A.Q[(int64_t)m * n + kk] : 0.f;
       }
     }
   }
   auto product = [&](const float* V, float* Wout) {
-    if constexpr (TPW > 0) mfma_product_reg<QT>(qa, V, Wout);
+    if constexpr (TPW > 0) mfma_product_reg<TW, KS, NW>(qa, V, Wout);
     else mfma_product(A, V, Wout);
   };
 
   // -- load a column into a slot: y = max(Y0, 0) or 0, gradient = q (exact for a cold start)
   auto load_slot = [&](int sl, int col) {
     // called by the 16 threads of slot sl (tid % 16 == sl)
-    for (int i = row0; i < np; i += MR_NT / MR_SLOTS) {
+    for (int i = row0; i < np; i += NT / MR_SLOTS) {
       float qi = 0.f, yi = 0.f;
       if (col >= 0 && i < n) {
         qi = A.q[(int64_t)i * A.k + col];
@@ -217,7 +224,7 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
     if (tid < MR_SLOTS) {
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
 #pragma unroll
-      for (int w = 0; w < MR_NT / kWave; ++w) {
+      for (int w = 0; w < NT / kWave; ++w) {
         const float* r = red + (w * MR_SLOTS + tid) * 4;
         a0 += r[0];
         a1 += r[1];
@@ -246,7 +253,7 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
     float acc = 0.f;
     const int col = s_col[slot];
     if (col >= 0)
-      for (int i = row0; i < n; i += MR_NT / MR_SLOTS) {
+      for (int i = row0; i < n; i += NT / MR_SLOTS) {
         const float qi = A.q[(int64_t)i * A.k + col];
         acc += qi * qi;
       }
@@ -259,13 +266,13 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
   for (;;) {
     // ---- exact gradient for slots that asked for it: W = Q Y, grad = W + q
     if (any_slot(s_ref, true)) {
-      for (int e = tid; e < np * MR_SLOTS; e += MR_NT) P[e] = Y[e];
+      for (int e = tid; e < np * MR_SLOTS; e += NT) P[e] = Y[e];
       __syncthreads();
       product(P, W);
       __syncthreads();
       if (s_ref[slot] && s_col[slot] >= 0) {
         const int col = s_col[slot];
-        for (int i = row0; i < n; i += MR_NT / MR_SLOTS)
+        for (int i = row0; i < n; i += NT / MR_SLOTS)
           Gr[i * MR_SLOTS + slot] = W[i * MR_SLOTS + slot] + A.q[(int64_t)i * A.k + col];
       }
       __syncthreads();
@@ -283,7 +290,7 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
     {
       float num = 0.f, res = 0.f, cnt = 0.f, bad = 0.f;
       const bool live = s_col[slot] >= 0;
-      for (int i = row0; i < np; i += MR_NT / MR_SLOTS) {
+      for (int i = row0; i < np; i += NT / MR_SLOTS) {
         const int e = i * MR_SLOTS + slot;
         const float yi = Y[e], gi = Gr[e];
         const bool valid = live && i < n;
@@ -336,7 +343,7 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
       const bool fin = s_col[slot] >= 0 && s_done[slot];
       if (fin) {
         const int col = s_col[slot];
-        for (int i = row0; i < n; i += MR_NT / MR_SLOTS) {
+        for (int i = row0; i < n; i += NT / MR_SLOTS) {
           const float yi = Y[i * MR_SLOTS + slot];
           A.X[(int64_t)i * A.k + col] = A.s ? (float)((double)yi / A.s[i]) : yi;
         }
@@ -374,7 +381,7 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
     __syncthreads();
     {
       float den = 0.f;
-      for (int i = row0; i < np; i += MR_NT / MR_SLOTS) {
+      for (int i = row0; i < np; i += NT / MR_SLOTS) {
         const int e = i * MR_SLOTS + slot;
         den += P[e] * W[e];
       }
@@ -405,7 +412,7 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
     {
       const bool act = s_act[slot];
       const float alpha = act ? s_alpha[slot] : 0.f;
-      for (int i = row0; i < np; i += MR_NT / MR_SLOTS) {
+      for (int i = row0; i < np; i += NT / MR_SLOTS) {
         const int e = i * MR_SLOTS + slot;
         float d = 0.f;
         if (act && i < n) {
@@ -432,13 +439,13 @@ __global__ __launch_bounds__(MR_NT, TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrA
         product(P, W);
         __syncthreads();
         if (act)
-          for (int i = row0; i < n; i += MR_NT / MR_SLOTS)
+          for (int i = row0; i < n; i += NT / MR_SLOTS)
             Gr[i * MR_SLOTS + slot] += W[i * MR_SLOTS + slot];
       } else if (act) {
         // no slot clipped: d = -alpha gbar in every slot, so Q d = -alpha W with the
         // line-search product W = Q gbar, still intact
         const float alpha = s_alpha[slot];
-        for (int i = row0; i < n; i += MR_NT / MR_SLOTS)
+        for (int i = row0; i < n; i += NT / MR_SLOTS)
           Gr[i * MR_SLOTS + slot] -= alpha * W[i * MR_SLOTS + slot];
       }
     }
@@ -466,11 +473,15 @@ static int mr_np(int64_t n) {
   return tpw > 0 ? 64 * tpw : (int)((n + 15) / 16 * 16);
 }
 
+// threads per workgroup of the kernel instance that serves n
+static int mr_nt(int64_t n) { return mr_tpw(n) == 4 ? 512 : MR_NT; }
+
 size_t solve_mrhs_lds_bytes(int64_t n) {
   const size_t np = (size_t)mr_np(n);
+  const size_t nw = (size_t)mr_nt(n) / kWave;
   return sizeof(float) * 4 * np * MR_SLOTS +
          sizeof(float) * 8 * MR_SLOTS + sizeof(int) * 9 * MR_SLOTS +
-         sizeof(float) * 4 * MR_SLOTS * 4 + sizeof(int) * 8 + 64;
+         sizeof(float) * nw * MR_SLOTS * 4 + sizeof(int) * 8 + 64;
 }
 
 bool solve_mrhs_supported(int64_t n, int64_t k) {
@@ -489,16 +500,17 @@ hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* 
   const size_t lds = solve_mrhs_lds_bytes(n);
   const void* kern = nullptr;
   switch (mr_tpw(n)) {
-    case 1: kern = (const void*)solve_mrhs_kernel<1>; break;
-    case 2: kern = (const void*)solve_mrhs_kernel<2>; break;
-    case 3: kern = (const void*)solve_mrhs_kernel<3>; break;
-    case 4: kern = (const void*)solve_mrhs_kernel<4>; break;
-    default: kern = (const void*)solve_mrhs_kernel<0>; break;
+    case 1: kern = (const void*)solve_mrhs_kernel<1, MR_NT>; break;
+    case 2: kern = (const void*)solve_mrhs_kernel<2, MR_NT>; break;
+    case 3: kern = (const void*)solve_mrhs_kernel<3, MR_NT>; break;
+    case 4: kern = (const void*)solve_mrhs_kernel<4, 512>; break;
+    default: kern = (const void*)solve_mrhs_kernel<0, MR_NT>; break;
   }
+  const int nt = mr_nt(n);
   int per_cu = 1;
   hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, MR_NT, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nt, lds);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   int64_t groups = (k + MR_SLOTS - 1) / MR_SLOTS;
@@ -523,7 +535,7 @@ hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* 
   hipLaunchKernelGGL(solve_mrhs_queue_init, dim3(1), dim3(64), 0, st, A.queue,
                      (int)(groups * MR_SLOTS));
   void* args[] = {&A};
-  e = hipLaunchKernel(kern, dim3((unsigned)groups), dim3(MR_NT), args, lds, st);
+  e = hipLaunchKernel(kern, dim3((unsigned)groups), dim3((unsigned)nt), args, lds, st);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
