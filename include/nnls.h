@@ -159,12 +159,13 @@ int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, co
  * nnls_refine -- FP64 check and one refinement step against the ORIGINAL data (A, B).
  * For every column: r = A x - b and grad = A^T r in FP64; in the rescaled variables one masked
  * exact-line-search projected step of Algorithm 2 (the step length from ||A (gbar ./ s)||^2 in
- * FP64); the step is kept only if it lowers 1/2 ||A x - b||^2.  Writes back X (FP32 or FP64 as
- * `dtype`) and, for the returned x:
+ * FP64); the step is kept only if it lowers the KKT residual (below) without raising
+ * 1/2 ||A x - b||^2.  Writes back X (FP32 or FP64 as `dtype`) and, for the returned x:
  *   kkt64 out [k]  relative KKT residual ||min(s .* x, grad ./ s)|| / ||A^T b ./ s|| in FP64,
  *                  with s the FP64 column norms of A (the rescaled-space residual of y = s .* x)
  *   obj64 out [k]  1/2 ||A x - b||^2 in FP64
- * A, B, X have element type `dtype`.
+ * A, B, X have element type `dtype`.  Workspace: nnls_workspace_bytes(NNLS_OP_REFINE, ...);
+ * errors NNLS_E_ARG (sizes < 1, null pointers, lda < n, ldb < k), NNLS_E_WORKSPACE.
  */
 int nnls_refine(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
                 int64_t ldb, int dtype, void* X, double* kkt64, double* obj64, void* ws,
