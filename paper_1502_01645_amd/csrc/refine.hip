@@ -531,16 +531,25 @@ __global__ void diag_scale_kernel(int64_t n, const double* __restrict__ H, doubl
   }
 }
 
-// Per-column stages of the Gram path: 64 columns per block, thread t on column t % 64 and rows
-// t / 64, t / 64 + 4, ... (a wave reads 64 consecutive columns of one row).
-constexpr int GS_C = 64;
+// Per-column stages of the Gram path: 16 columns per block, thread t on column t % 16 and rows
+// t / 16, t / 16 + 16, ... (a wave reads 16 consecutive columns of 4 rows; 16 columns per block
+// give k / 16 blocks, enough to spread k = 4096 over the GPU).
+constexpr int GS_C = 16;
+constexpr int GS_G = 256 / GS_C;  // row groups
 
+// Sum over the GS_G row groups of a column, pairwise in a fixed order; every thread gets it.
 __device__ __forceinline__ double gs_reduce(double v, double (*red)[GS_C], int rg, int cl) {
   red[rg][cl] = v;
   __syncthreads();
-  const double t = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+  double t[GS_G / 2];
+#pragma unroll
+  for (int g = 0; g < GS_G / 2; ++g) t[g] = red[2 * g][cl] + red[2 * g + 1][cl];
+#pragma unroll
+  for (int w = GS_G / 4; w >= 1; w >>= 1)
+#pragma unroll
+    for (int g = 0; g < w; ++g) t[g] = t[2 * g] + t[2 * g + 1];
   __syncthreads();
-  return t;
+  return t[0];
 }
 
 // Stage 1: residual and objective at x, direction D = p ./ s, ||p||^2.
@@ -553,13 +562,13 @@ __global__ __launch_bounds__(256) void gref_stage1_kernel(int64_t n, int64_t k,
                                                           const double* __restrict__ bb,
                                                           double* __restrict__ D,
                                                           double* __restrict__ colstat) {
-  __shared__ double red[4][GS_C];
-  const int cl = threadIdx.x & (GS_C - 1), rg = threadIdx.x >> 6;
+  __shared__ double red[GS_G][GS_C];
+  const int cl = threadIdx.x % GS_C, rg = threadIdx.x / GS_C;
   const int64_t c = (int64_t)blockIdx.x * GS_C + cl;
   const bool in = c < k;
   double kk = 0.0, aa = 0.0, num = 0.0, fx = 0.0;
   if (in) {
-    for (int64_t i = rg; i < n; i += 4) {
+    for (int64_t i = rg; i < n; i += GS_G) {
       const int64_t o = i * k + c;
       const double x = (double)X[o], a = Atb[o], hx = GX[o], si = s[i];
       const double y = si * x, gy = (hx - a) / si;
@@ -593,18 +602,18 @@ __global__ __launch_bounds__(256) void gref_stage2_kernel(int64_t n, int64_t k,
                                                           const double* __restrict__ HD,
                                                           double* __restrict__ Xn,
                                                           const double* __restrict__ colstat) {
-  __shared__ double red[4][GS_C];
-  const int cl = threadIdx.x & (GS_C - 1), rg = threadIdx.x >> 6;
+  __shared__ double red[GS_G][GS_C];
+  const int cl = threadIdx.x % GS_C, rg = threadIdx.x / GS_C;
   const int64_t c = (int64_t)blockIdx.x * GS_C + cl;
   const bool in = c < k;
   double den = 0.0;
   if (in)
-    for (int64_t i = rg; i < n; i += 4) den += D[i * k + c] * HD[i * k + c];
+    for (int64_t i = rg; i < n; i += GS_G) den += D[i * k + c] * HD[i * k + c];
   den = gs_reduce(den, red, rg, cl);
   if (!in) return;
   const double num = colstat[c * 8 + 2];
   const double alpha = (den > 0.0 && __builtin_isfinite(den)) ? num / den : 0.0;
-  for (int64_t i = rg; i < n; i += 4) {
+  for (int64_t i = rg; i < n; i += GS_G) {
     const int64_t o = i * k + c;
     const double v = (double)X[o] - alpha * D[o];
     Xn[o] = (double)(TX)(v > 0.0 ? v : 0.0);
@@ -623,14 +632,14 @@ __global__ __launch_bounds__(256) void gref_stage3_kernel(int64_t n, int64_t k,
                                                           const double* __restrict__ colstat,
                                                           double* __restrict__ kkt64,
                                                           double* __restrict__ obj64) {
-  __shared__ double red[4][GS_C];
+  __shared__ double red[GS_G][GS_C];
   __shared__ int acc_s[GS_C];
-  const int cl = threadIdx.x & (GS_C - 1), rg = threadIdx.x >> 6;
+  const int cl = threadIdx.x % GS_C, rg = threadIdx.x / GS_C;
   const int64_t c = (int64_t)blockIdx.x * GS_C + cl;
   const bool in = c < k;
   double kk = 0.0, df = 0.0;
   if (in) {
-    for (int64_t i = rg; i < n; i += 4) {
+    for (int64_t i = rg; i < n; i += GS_G) {
       const int64_t o = i * k + c;
       const double a = Atb[o], si = s[i];
       const double xn = Xn[o];
@@ -654,7 +663,7 @@ __global__ __launch_bounds__(256) void gref_stage3_kernel(int64_t n, int64_t k,
   }
   __syncthreads();
   if (in && acc_s[cl])
-    for (int64_t i = rg; i < n; i += 4) X[i * k + c] = (TX)Xn[i * k + c];
+    for (int64_t i = rg; i < n; i += GS_G) X[i * k + c] = (TX)Xn[i * k + c];
 }
 
 // ---- per-column steps ---------------------------------------------------------------------
