@@ -102,3 +102,77 @@ def test_unscaled_ablation_on_lopsided_columns(orc):
     x_u, it, r_own, st = orc.nqp(H, h[:, 0], 1e-5, 100000)
     r_u, _ = orc.kkt_x(A, b, x_u.reshape(-1, 1))
     assert st == 0 and r_own <= 1e-5 and r_u[0] >= 100 * r_s[0]
+
+
+# ---- the relative objective gap behind every parity check ---------------------------------------
+def _gap_flipped(F, ref):
+    """Planted slip: the difference taken the wrong way round."""
+    F = np.asarray(F, dtype=np.float64)
+    fstar = ref.F - ref.half_bb
+    return (ref.F - F) / np.where(np.abs(fstar) > 0, np.abs(fstar), 1.0)
+
+
+def _gap_over_Fstar(F, ref):
+    """Planted slip: (F - F*) / F*, the residual-relative reading, undefined at F* = 0."""
+    F = np.asarray(F, dtype=np.float64)
+    return (F - ref.F) / np.where(ref.F > 0, ref.F, 1.0)
+
+
+def _gap_whole_bb(F, ref):
+    """Planted slip: f = F - ||b||^2 (the 1/2 dropped) in the denominator."""
+    F = np.asarray(F, dtype=np.float64)
+    fstar = ref.F - 2.0 * ref.half_bb
+    return (F - ref.F) / np.where(np.abs(fstar) > 0, np.abs(fstar), 1.0)
+
+
+def _gap_pins(gap, orc):
+    """What the definition of the gap fixes without the oracle's help.
+    For n = 1, f(x) = 1/2 ||a||^2 x^2 - (a^T b) x is a parabola with minimum x* = a^T b / ||a||^2
+    and f* = -(a^T b)^2 / (2 ||a||^2), so gap(x) = (f(x) - f*) / |f*| = ((x - x*) / x*)^2 exactly;
+    where a^T b <= 0, x* = 0, f* = 0 and the gap is the absolute f(x).  For any instance with
+    f* < 0, x = 0 gives f = 0 and so gap = 1; the solution gives 0 and any other feasible point
+    a positive gap."""
+    rng = np.random.default_rng(41)
+    for _ in range(4):
+        a = rng.random((9, 1)) + 0.1
+        b = (2.0 * a[:, 0] + 0.3 * rng.standard_normal(9)).reshape(9, 1)
+        ab, aa = float(a[:, 0] @ b[:, 0]), float(a[:, 0] @ a[:, 0])
+        assert ab > 0
+        xs = ab / aa
+        ref = O.reference_solution(a, b, orc=orc)
+        for t in (0.0, 0.5, 1.0, 1.3, 2.0):
+            x = np.array([[t * xs]])
+            _, F = orc.kkt_x(a, b, x)
+            g = float(gap(F, ref)[0])
+            assert abs(g - (t - 1.0) ** 2) <= 1e-9, (t, g)
+    # x* = 0: f* = 0, the gap is f(x) itself
+    a = rng.random((9, 1)) + 0.1
+    b = -(a + 0.1 * rng.random((9, 1)))
+    ab, aa = float(a[:, 0] @ b[:, 0]), float(a[:, 0] @ a[:, 0])
+    ref = O.reference_solution(a, b, orc=orc)
+    for x in (0.0, 0.7):
+        _, F = orc.kkt_x(a, b, np.array([[x]]))
+        g = float(gap(F, ref)[0])
+        assert abs(g - (0.5 * aa * x * x - ab * x)) <= 1e-12 * (1 + abs(ab)), (x, g)
+    # a generic instance: 1 at the origin, 0 at the solution, positive elsewhere
+    A = rng.random((40, 12))
+    x_true = np.where(rng.random(12) < 0.5, 0.0, rng.random(12))
+    B = (A @ x_true + 0.05 * rng.standard_normal(40)).reshape(40, 1)
+    ref = O.reference_solution(A, B, orc=orc)
+    _, F0 = orc.kkt_x(A, B, np.zeros((12, 1)))
+    assert abs(float(gap(F0, ref)[0]) - 1.0) <= 1e-12
+    assert abs(float(gap(ref.F, ref)[0])) <= 1e-15
+    xp = ref.X + 0.01 * rng.random((12, 1))
+    _, Fp = orc.kkt_x(A, B, xp)
+    assert float(gap(Fp, ref)[0]) > 0
+
+
+def test_relative_gap_pins(orc):
+    _gap_pins(O.relative_gap, orc)
+
+
+@pytest.mark.parametrize("planted", [_gap_flipped, _gap_over_Fstar, _gap_whole_bb],
+                         ids=lambda f: f.__name__)
+def test_gap_pins_catch_planted_mistake(orc, planted):
+    with pytest.raises(AssertionError):
+        _gap_pins(planted, orc)
