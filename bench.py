@@ -292,7 +292,6 @@ def bench_manyrhs(args):
     status = torch.empty(k, dtype=torch.int32, device=dev)
     rows = torch.zeros(k, dtype=torch.int64, device=dev)
     kkt64 = torch.empty(k, dtype=torch.float64, device=dev)
-    obj64 = torch.empty(k, dtype=torch.float64, device=dev)
     mk = lambda op, mode=0: torch.empty(max(N.workspace_bytes(op, d, n, k, mode, N.F32), 1),  # noqa
                                         dtype=torch.uint8, device=dev)
     ws_p, ws_v, ws_r = mk(N.OP_PREPARE, N.GRAM_BF16X3), mk(N.OP_SOLVE), mk(N.OP_REFINE)
@@ -308,7 +307,7 @@ def bench_manyrhs(args):
         N.solve(Q, q, s, tol=INNER_TOL, max_iter=5 * n, out=(X, iters, kkt, status), ws=ws_v,
                 rows_read=rows)
         e[2].record()
-        N.refine(A, B, X, out=(kkt64, obj64), ws=ws_r)
+        N.refine(A, B, X, out=(kkt64, None), ws=ws_r)
         e[3].record()
 
     for i in range(args.warmup):
@@ -805,7 +804,6 @@ def bench_warm(args):
     status = torch.empty(k, dtype=torch.int32, device=dev)
     rows = torch.zeros(k, dtype=torch.int64, device=dev)
     kkt64 = torch.empty(k, dtype=torch.float64, device=dev)
-    obj64 = torch.empty(k, dtype=torch.float64, device=dev)
     mk = lambda op, mode=0: torch.empty(max(N.workspace_bytes(op, d, n, k, mode, N.F32), 1),  # noqa
                                         dtype=torch.uint8, device=dev)
     ws_p, ws_v, ws_r = mk(N.OP_PREPARE, N.GRAM_BF16X3), mk(N.OP_SOLVE), mk(N.OP_REFINE)
@@ -826,7 +824,7 @@ def bench_warm(args):
             N.solve(Q, q, s, tol=INNER_TOL, max_iter=5 * n, Y0=Y0 if warm else None,
                     out=(X, iters, kkt, status), ws=ws_v, rows_read=rows)
             m[3].record()
-            N.refine(A, Bev, X, out=(kkt64, obj64), ws=ws_r)
+            N.refine(A, Bev, X, out=(kkt64, None), ws=ws_r)
             m[4].record()
 
         for i in range(args.warmup):

@@ -47,7 +47,9 @@ enum nnls_error {
 enum nnls_col_status {
     NNLS_CONVERGED = 0,  /* relative KKT residual <= tol, or empty passive set */
     NNLS_MAXITER = 1,    /* max_iter updates done without meeting tol */
-    NNLS_BREAKDOWN = 2,  /* line-search denominator gbar^T Q gbar not positive and finite */
+    NNLS_BREAKDOWN = 2,  /* line-search denominator gbar^T Q gbar not positive and finite; or
+                            the workgroups of a whole-GPU solver stopped waiting for one another
+                            (then iters = -1 and kkt = NaN) */
     NNLS_NONFINITE = 3,  /* NaN or Inf in the inputs or the iterate */
     NNLS_FELL_BACK = 4   /* warm start rejected (it raised the objective); solved from y = 0 */
 };
@@ -148,7 +150,10 @@ int nnls_gram_rescaled(int64_t d, int64_t n, int64_t k, const void* A, int64_t l
  * the current device.  The environment variable NNLS_SOLVER=wg|regq|persistent|mrhs forces
  * the one-workgroup-per-column solver, the whole-GPU single-right-hand-side solver with Q held
  * in registers (n <= 5120) or streamed from memory, or the matrix-core many-right-hand-side
- * solver, where valid.
+ * solver, where valid.  Every wait of the whole-GPU solvers is bounded (2^24 polls; the
+ * environment variable NNLS_SPIN_LIMIT=m, 0 <= m <= 2^24, lowers it to test the give-up path):
+ * a workgroup that gives up sets an abort word that ends the waits of all the others, and the
+ * solve reports BREAKDOWN with iters = -1.
  */
 int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, const double* s,
                double tol, int32_t max_iter, const void* Y0, void* X, int32_t* iters,
@@ -163,9 +168,14 @@ int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, co
  * 1/2 ||A x - b||^2.  Writes back X (FP32 or FP64 as `dtype`) and, for the returned x:
  *   kkt64 out [k]  relative KKT residual ||min(s .* x, grad ./ s)|| / ||A^T b ./ s|| in FP64,
  *                  with s the FP64 column norms of A (the rescaled-space residual of y = s .* x)
- *   obj64 out [k]  1/2 ||A x - b||^2 in FP64
+ *   obj64 out [k]  F = 1/2 ||A x - b||^2 of Problem (1) in FP64, summed from the residuals
+ *                  A x - b (never from the Gram form 1/2 x^T H x + h^T x + 1/2 ||b||^2, which
+ *                  cancels near a noiseless fit).  May be NULL: then F is not formed.  For
+ *                  k > 4 forming it costs one more FP64 product A X (2 d n k flops); for
+ *                  k <= 4 the residuals are formed anyway.
  * A, B, X have element type `dtype`.  Workspace: nnls_workspace_bytes(NNLS_OP_REFINE, ...);
- * errors NNLS_E_ARG (sizes < 1, null pointers, lda < n, ldb < k), NNLS_E_WORKSPACE.
+ * errors NNLS_E_ARG (sizes < 1, null pointers other than obj64, lda < n, ldb < k),
+ * NNLS_E_WORKSPACE.
  */
 int nnls_refine(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
                 int64_t ldb, int dtype, void* X, double* kkt64, double* obj64, void* ws,

@@ -23,6 +23,16 @@ int hip_fail(hipError_t e) {
 
 void nnls::record_hip_error(hipError_t e) { g_last_hip_error = hipGetErrorString(e); }
 
+int nnls::spin_limit_setting() {
+  const char* v = getenv("NNLS_SPIN_LIMIT");
+  if (v != nullptr && *v != '\0') {
+    char* end = nullptr;
+    const long x = strtol(v, &end, 10);
+    if (end != v && *end == '\0' && x >= 0 && x <= (1L << 24)) return (int)x;
+  }
+  return 1 << 24;
+}
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -280,7 +290,7 @@ int nnls_refine(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, con
                 int64_t ldb, int dtype, void* X, double* kkt64, double* obj64, void* ws,
                 size_t ws_bytes, void* stream) {
   if (d < 1 || n < 1 || k < 1 || !valid_dtype(dtype)) return NNLS_E_ARG;
-  if (!A || !B || !X || !kkt64 || !obj64 || lda < n || ldb < k) return NNLS_E_ARG;
+  if (!A || !B || !X || !kkt64 || lda < n || ldb < k) return NNLS_E_ARG;
   if (n > (int64_t)1 << 30 || k > (int64_t)1 << 31) return NNLS_E_UNSUPPORTED;
   const size_t need = align_up(nnls::refine_ws_bytes(d, n, k));
   if (ws_bytes < need || !ws) return NNLS_E_WORKSPACE;

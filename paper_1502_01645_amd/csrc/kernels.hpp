@@ -16,6 +16,11 @@ constexpr int NNLS_FELL_BACK_DEV = 4;
 // Remembers the text of a failed HIP call for nnls_last_hip_error (capi.hip).
 void record_hip_error(hipError_t e);
 
+// Poll limit of every wait of the whole-GPU solvers (capi.hip): 1 << 24, a bound no normal
+// launch reaches, or NNLS_SPIN_LIMIT from the environment, a test hook that forces the give-up
+// path (every wait still ends, the solve reports BREAKDOWN with iters = -1).
+int spin_limit_setting();
+
 // One problem of an uneven batch (device copy of the caller's descriptor): A is [d, n] at
 // A_pool + offA, b is [d] at B_pool + offB, Q is [n, n] at Q_pool + offQ, q, s and x are [n] at
 // offset offq of their pools (s in the FP64 pool), x at X_pool + offX.

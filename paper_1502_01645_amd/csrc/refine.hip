@@ -12,9 +12,13 @@
 // of A in registers, forms their residuals and adds their share of A^T R before it moves on, so
 // (R, g) and (R', g') each cost one read of A: three reads instead of five.
 // Many right-hand sides form the FP64 Gram matrix once, on the FP64 matrix cores:
-//   H = A^T A, a = A^T B, ||b||^2;  g = H X - a,  D^T H D from H D,  g' = H X' - a,
-//   F(x) = 1/2 (x^T (H x - 2 a) + ||b||^2) and F(x') - F(x) = 1/2 (x' - x)^T (g + g'),
-// so the work over the d rows of A is one product instead of five.
+//   H = A^T A, a = A^T B;  g = H X - a,  D^T H D from H D,  g' = H X' - a,
+//   F(x') - F(x) = 1/2 (x' - x)^T (g + g') for the keep decision,
+// so the work over the d rows of A is one product instead of five.  The objective that is
+// reported, F = 1/2 ||A x - b||^2 of the returned x, comes from the residuals R = A X - B (one
+// more FP64 product, only when the caller asks for it): the Gram form
+// 1/2 (x^T (H x - 2 a) + ||b||^2) loses every digit of F near a noiseless fit, where its three
+// terms are each about 1/2 ||b||^2 and F is not.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -380,19 +384,15 @@ __global__ __launch_bounds__(256) void cols_finalize_kernel(int64_t n, int64_t k
   }
 }
 
-// ---- many right-hand sides: tiled FP64 products -----------------------------------------------
-// TRANS = false: C[M, N] = A[M, K] * Bm[K, N] - Cin      (A row-major [d, n], M = d, K = n)
-// TRANS = true:  C[M, N] = A^T[M, K] * Bm[K, N]           (A row-major [d, n], M = n, K = d)
 // ---- many right-hand sides: FP64 Gram path ---------------------------------------------------
 // C[i, j] = sum_r A[r, i] M[r, j] for i < N, r < K, with M = [M1 | M2] (columns j < n1 from M1,
 // the next n2 from M2; all row-major with r as the row), written to C1 (j < n1) and C2 (the rest)
 // in FP64 on the matrix cores (v_mfma_f64_16x16x4f64): 64 x 64 output tiles, four waves of
 // 32 x 32, K staged through LDS 32 rows at a time (zero-filled past the edges) with the next
-// chunk loaded into registers while the current one is multiplied.  With sq != nullptr the
-// workgroups of row tile 0 also write sq[j] = sum_r M2[r, j]^2 for their M2 columns.
+// chunk loaded into registers while the current one is multiplied.
 // Split over K (part != nullptr): workgroup z of gridDim.z takes rows [z kps, (z + 1) kps) of the
-// sum and writes its partial tile to part[z][i][j] (j over all n1 + n2 columns) and its partial
-// squares to part_sq[z][j - n1]; gemm_tn_reduce_kernel adds the partials in order of z.
+// sum and writes its partial tile to part[z][i][j] (j over all n1 + n2 columns);
+// gemm_tn_reduce_kernel adds the partials in order of z.
 // Four workgroups per CU (126 registers, 4 x 36 KB of LDS): 3-4 % faster than three.
 constexpr int TN_T = 64, TN_BK = 32, TN_LD = TN_T + 2;
 
@@ -400,12 +400,10 @@ template <typename TA, typename TM>
 __global__ __launch_bounds__(256, 4) void gemm_tn_f64_kernel(
     int64_t K, int64_t N, int64_t n1, int64_t n2, const TA* __restrict__ A, int64_t lda,
     const TM* __restrict__ M1, int64_t ld1, const TM* __restrict__ M2, int64_t ld2,
-    double* __restrict__ C1, int64_t ldc1, double* __restrict__ C2, int64_t ldc2,
-    double* __restrict__ sq, int64_t kps, double* __restrict__ part,
-    double* __restrict__ part_sq) {
+    double* __restrict__ C1, int64_t ldc1, double* __restrict__ C2, int64_t ldc2, int64_t kps,
+    double* __restrict__ part) {
   __shared__ double sa[TN_BK][TN_LD];
   __shared__ double sm[TN_BK][TN_LD];
-  __shared__ double sqred[4][TN_T];
   const int64_t i0 = (int64_t)blockIdx.y * TN_T, j0 = (int64_t)blockIdx.x * TN_T;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
@@ -422,8 +420,6 @@ __global__ __launch_bounds__(256, 4) void gemm_tn_f64_kernel(
     mp = M2 + (jm - n1);
     mld = ld2;
   }
-  const bool want_sq = sq != nullptr && blockIdx.y == 0 && jm >= n1 && jm < n1 + n2;
-  double sqacc = 0.0;
   TA ra[TN_BK / 4];
   TM rm[TN_BK / 4];
   // rows [kb, ke) of the sum: all of them, or this split's share
@@ -441,9 +437,7 @@ __global__ __launch_bounds__(256, 4) void gemm_tn_f64_kernel(
 #pragma unroll
     for (int u = 0; u < TN_BK / 4; ++u) {
       sa[r0 + 4 * u][c] = (double)ra[u];
-      const double mv = (double)rm[u];
-      sm[r0 + 4 * u][c] = mv;
-      if (want_sq) sqacc += mv * mv;
+      sm[r0 + 4 * u][c] = (double)rm[u];
     }
   };
 
@@ -489,23 +483,13 @@ __global__ __launch_bounds__(256, 4) void gemm_tn_f64_kernel(
           C2[i * ldc2 + (j - n1)] = acc[a][b][e];
         }
       }
-  if (sq != nullptr && blockIdx.y == 0) {
-    sqred[r0][c] = sqacc;
-    __syncthreads();
-    if (tid < TN_T && want_sq) {
-      const double v = (sqred[0][tid] + sqred[1][tid]) + (sqred[2][tid] + sqred[3][tid]);
-      if (part != nullptr) part_sq[(int64_t)blockIdx.z * n2 + (jm - n1)] = v;
-      else sq[jm - n1] = v;
-    }
-  }
 }
 
-// C1 / C2 (and sq) from the split partials of gemm_tn_f64_kernel: element e of the N x (n1 + n2)
-// result (then of the n2 squares) is the sum over z < S of its partials, in order of z.
+// C1 / C2 from the split partials of gemm_tn_f64_kernel: element e of the N x (n1 + n2) result
+// is the sum over z < S of its partials, in order of z.
 __global__ __launch_bounds__(256) void gemm_tn_reduce_kernel(
     int S, int64_t N, int64_t n1, int64_t n2, const double* __restrict__ part,
-    const double* __restrict__ part_sq, double* __restrict__ C1, int64_t ldc1,
-    double* __restrict__ C2, int64_t ldc2, double* __restrict__ sq) {
+    double* __restrict__ C1, int64_t ldc1, double* __restrict__ C2, int64_t ldc2) {
   const int64_t w = n1 + n2, tot = N * w;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e < tot) {
@@ -514,11 +498,6 @@ __global__ __launch_bounds__(256) void gemm_tn_reduce_kernel(
     const int64_t i = e / w, j = e % w;
     if (j < n1) C1[i * ldc1 + j] = v;
     else C2[i * ldc2 + (j - n1)] = v;
-  } else if (sq != nullptr && e < tot + n2) {
-    const int64_t j = e - tot;
-    double v = 0.0;
-    for (int z = 0; z < S; ++z) v += part_sq[(int64_t)z * n2 + j];
-    sq[j] = v;
   }
 }
 
@@ -552,21 +531,20 @@ __device__ __forceinline__ double gs_reduce(double v, double (*red)[GS_C], int r
   return t[0];
 }
 
-// Stage 1: residual and objective at x, direction D = p ./ s, ||p||^2.
+// Stage 1: residual at x, direction D = p ./ s, ||p||^2.
 template <typename TX>
 __global__ __launch_bounds__(256) void gref_stage1_kernel(int64_t n, int64_t k,
                                                           const TX* __restrict__ X,
                                                           const double* __restrict__ GX,
                                                           const double* __restrict__ Atb,
                                                           const double* __restrict__ s,
-                                                          const double* __restrict__ bb,
                                                           double* __restrict__ D,
                                                           double* __restrict__ colstat) {
   __shared__ double red[GS_G][GS_C];
   const int cl = threadIdx.x % GS_C, rg = threadIdx.x / GS_C;
   const int64_t c = (int64_t)blockIdx.x * GS_C + cl;
   const bool in = c < k;
-  double kk = 0.0, aa = 0.0, num = 0.0, fx = 0.0;
+  double kk = 0.0, aa = 0.0, num = 0.0;
   if (in) {
     for (int64_t i = rg; i < n; i += GS_G) {
       const int64_t o = i * k + c;
@@ -579,16 +557,13 @@ __global__ __launch_bounds__(256) void gref_stage1_kernel(int64_t n, int64_t k,
       kk += m * m;
       const double ai = a / si;
       aa += ai * ai;
-      fx += x * (hx - 2.0 * a);
     }
   }
   kk = gs_reduce(kk, red, rg, cl);
   aa = gs_reduce(aa, red, rg, cl);
   num = gs_reduce(num, red, rg, cl);
-  fx = gs_reduce(fx, red, rg, cl);
   if (in && rg == 0) {
     colstat[c * 8 + 0] = aa > 0.0 ? sqrt(kk) / sqrt(aa) : sqrt(kk);
-    colstat[c * 8 + 1] = 0.5 * (fx + bb[c]);
     colstat[c * 8 + 2] = num;
     colstat[c * 8 + 3] = aa;
   }
@@ -630,8 +605,7 @@ __global__ __launch_bounds__(256) void gref_stage3_kernel(int64_t n, int64_t k,
                                                           const double* __restrict__ Atb,
                                                           const double* __restrict__ s,
                                                           const double* __restrict__ colstat,
-                                                          double* __restrict__ kkt64,
-                                                          double* __restrict__ obj64) {
+                                                          double* __restrict__ kkt64) {
   __shared__ double red[GS_G][GS_C];
   __shared__ int acc_s[GS_C];
   const int cl = threadIdx.x % GS_C, rg = threadIdx.x / GS_C;
@@ -659,11 +633,108 @@ __global__ __launch_bounds__(256) void gref_stage3_kernel(int64_t n, int64_t k,
     const bool accept = (r1 < r0) && (df <= 0.0);
     acc_s[cl] = accept ? 1 : 0;
     kkt64[c] = accept ? r1 : r0;
-    obj64[c] = colstat[c * 8 + 1] + (accept ? df : 0.0);
   }
   __syncthreads();
   if (in && acc_s[cl])
     for (int64_t i = rg; i < n; i += GS_G) X[i * k + c] = (TX)Xn[i * k + c];
+}
+
+// F = 1/2 ||A X - B||^2 per column, from the residuals.  A 64 x 64 tile of R = A X - B (rows i of
+// A, columns c of X) is summed over n on the FP64 matrix cores, as gemm_tn_f64_kernel sums over d,
+// then squared and summed over its 64 rows: part[tile row][c].  resid_sq_reduce_kernel adds the
+// row tiles in order.  Staging: A as sa[kk][i] (a thread loads column kk = tid % 32 of rows
+// tid / 32 + 8 u), X as sx[kk][c] (column tid % 64 of rows tid / 64 + 4 u).
+template <typename TA, typename TX>
+__global__ __launch_bounds__(256, 4) void resid_sq_f64_kernel(int64_t d, int64_t n, int64_t k,
+                                                              const TA* __restrict__ A,
+                                                              int64_t lda,
+                                                              const TX* __restrict__ X,
+                                                              const TA* __restrict__ B,
+                                                              int64_t ldb,
+                                                              double* __restrict__ part) {
+  __shared__ double sa[TN_BK][TN_LD];
+  __shared__ double sx[TN_BK][TN_LD];
+  __shared__ double colred[2][TN_T];
+  const int64_t i0 = (int64_t)blockIdx.y * TN_T, c0 = (int64_t)blockIdx.x * TN_T;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  const int ak = tid & 31, ar = tid >> 5;
+  const int xc = tid & 63, xr = tid >> 6;
+  TA ra[8];
+  TX rx[8];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = i0 + ar + 8 * u, kk = k0 + ak;
+      ra[u] = (i < d && kk < n) ? A[i * lda + kk] : (TA)0;
+      const int64_t kx = k0 + xr + 4 * u, c = c0 + xc;
+      rx[u] = (kx < n && c < k) ? X[kx * k + c] : (TX)0;
+    }
+  };
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  const int col = lane & 15, kq = lane >> 4;
+  load(0);
+  for (int64_t k0 = 0; k0 < n; k0 += TN_BK) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sa[ak][ar + 8 * u] = (double)ra[u];
+      sx[xr + 4 * u][xc] = (double)rx[u];
+    }
+    __syncthreads();
+    if (k0 + TN_BK < n) load(k0 + TN_BK);  // in flight during the MFMAs below
+#pragma unroll
+    for (int kk = 0; kk < TN_BK; kk += 4) {
+      const int kr = kk + kq;
+      const double a0 = sa[kr][wi + col], a1 = sa[kr][wi + 16 + col];
+      const double b0 = sx[kr][wj + col], b1 = sx[kr][wj + 16 + col];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // lane l holds column l % 16 and rows l / 16 + 4 e of each 16 x 16 block
+  double sq[2] = {0.0, 0.0};
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int64_t c = c0 + wj + b * 16 + col;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = i0 + wi + a * 16 + kq + 4 * e;
+        if (i < d && c < k) {
+          const double r = acc[a][b][e] - (double)B[i * ldb + c];
+          sq[b] += r * r;
+        }
+      }
+    // the four row groups of a column (lanes col + 16 kq), in a fixed order
+    sq[b] += __shfl_xor(sq[b], 16);
+    sq[b] += __shfl_xor(sq[b], 32);
+  }
+  if (kq == 0) {
+    colred[wave >> 1][wj + col] = sq[0];
+    colred[wave >> 1][wj + 16 + col] = sq[1];
+  }
+  __syncthreads();
+  if (tid < TN_T && c0 + tid < k)
+    part[(int64_t)blockIdx.y * k + c0 + tid] = colred[0][tid] + colred[1][tid];
+}
+
+// obj64[c] = 1/2 * sum over the row tiles t of part[t][c], in order of t.
+__global__ __launch_bounds__(256) void resid_sq_reduce_kernel(int64_t tiles, int64_t k,
+                                                              const double* __restrict__ part,
+                                                              double* __restrict__ obj64) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= k) return;
+  double v = 0.0;
+  for (int64_t t = 0; t < tiles; ++t) v += part[t * k + c];
+  obj64[c] = 0.5 * v;
 }
 
 // ---- per-column steps ---------------------------------------------------------------------
@@ -789,7 +860,7 @@ __global__ __launch_bounds__(RS_NT) void refine_stage3_kernel(int64_t d, int64_t
   }
   if (threadIdx.x == 0) {
     kkt64[c] = accept ? r1 : r0;
-    obj64[c] = accept ? F1 : F0;
+    if (obj64 != nullptr) obj64[c] = accept ? F1 : F0;
   }
 }
 
@@ -825,12 +896,15 @@ static RefineWs refine_layout(void* ws, int64_t d, int64_t n, int64_t k) {
 }
 
 // Gram path workspace: H [n, n], a, HX, D, HD (reused for H X'), X' [n, k], s [n],
-// colstat [8 k], ||b||^2 [k], and the partials of a split product.
+// colstat [8 k], the row-tile sums of squared residuals [ceil(d / 64), k], and the partials of a
+// split product.
 struct GramRefineWs {
-  double *H, *a, *HX, *D, *HD, *Xn, *s, *colstat, *bb, *part;
+  double *H, *a, *HX, *D, *HD, *Xn, *s, *colstat, *rsq, *part;
 };
 
-static GramRefineWs gram_refine_layout(void* ws, int64_t n, int64_t k) {
+static int64_t resid_tiles(int64_t d) { return (d + TN_T - 1) / TN_T; }
+
+static GramRefineWs gram_refine_layout(void* ws, int64_t d, int64_t n, int64_t k) {
   GramRefineWs w;
   double* p = (double*)ws;
   w.H = p; p += n * n;
@@ -841,7 +915,7 @@ static GramRefineWs gram_refine_layout(void* ws, int64_t n, int64_t k) {
   w.Xn = p; p += n * k;
   w.s = p; p += n;
   w.colstat = p; p += 8 * k;
-  w.bb = p; p += k;
+  w.rsq = p; p += resid_tiles(d) * k;
   w.part = p;
   return w;
 }
@@ -856,8 +930,8 @@ size_t refine_ws_bytes(int64_t d, int64_t n, int64_t k) {
     el = (size_t)(2 * d * k + 4 * n * k + n + 8 * k) + (size_t)ch * (2 * k + 1) * n;
   }
   else
-    el = (size_t)(n * n + 5 * n * k + n + 9 * k) +
-         (size_t)gref_splits(d, n, k) * (size_t)(n * (n + k) + k);
+    el = (size_t)(n * n + 5 * n * k + n + 8 * k) + (size_t)(resid_tiles(d) * k) +
+         (size_t)gref_splits(d, n, k) * (size_t)(n * (n + k));
   return el * sizeof(double) + 256;
 }
 
@@ -964,25 +1038,23 @@ static void launch_fused(int64_t d, int64_t n, const float* A, int64_t lda, cons
                      w.s);
 }
 
-// C = A^T [M1 | M2] (see gemm_tn_f64_kernel); sq optional.  S > 1 splits the sum over K into
-// S row ranges with partials in part (S (N (n1 + n2) + n2) doubles), added by a second kernel.
+// C = A^T [M1 | M2] (see gemm_tn_f64_kernel).  S > 1 splits the sum over K into S row ranges
+// with partials in part (S N (n1 + n2) doubles), added by a second kernel.
 template <typename TA, typename TM>
 static void gemm_tn(int64_t K, int64_t N, const TA* A, int64_t lda, int64_t n1, const TM* M1,
                     int64_t ld1, double* C1, int64_t ldc1, int64_t n2, const TM* M2, int64_t ld2,
-                    double* C2, int64_t ldc2, double* sq, hipStream_t st, int S = 1,
+                    double* C2, int64_t ldc2, hipStream_t st, int S = 1,
                     double* part = nullptr) {
   if (S <= 1) part = nullptr;
   const int64_t kps = part ? ((K + S - 1) / S + TN_BK - 1) / TN_BK * TN_BK : K;
-  double* part_sq = part ? part + (int64_t)S * N * (n1 + n2) : nullptr;
   dim3 grid((unsigned)((n1 + n2 + TN_T - 1) / TN_T), (unsigned)((N + TN_T - 1) / TN_T),
             part ? (unsigned)S : 1u);
   hipLaunchKernelGGL((gemm_tn_f64_kernel<TA, TM>), grid, dim3(256), 0, st, K, N, n1, n2, A, lda,
-                     M1, ld1, M2, ld2, C1, ldc1, C2, ldc2, sq, kps, part, part_sq);
+                     M1, ld1, M2, ld2, C1, ldc1, C2, ldc2, kps, part);
   if (part) {
-    const int64_t tot = N * (n1 + n2) + (sq ? n2 : 0);
+    const int64_t tot = N * (n1 + n2);
     hipLaunchKernelGGL(gemm_tn_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                       st, S, N, n1, n2, (const double*)part, (const double*)part_sq, C1, ldc1,
-                       C2, ldc2, sq);
+                       st, S, N, n1, n2, (const double*)part, C1, ldc1, C2, ldc2);
   }
 }
 
@@ -1012,29 +1084,36 @@ template <typename T>
 static void launch_refine_gram(int64_t d, int64_t n, int64_t k, const T* A, int64_t lda,
                                const T* B, int64_t ldb, T* X, double* kkt64, double* obj64,
                                void* ws, hipStream_t st) {
-  GramRefineWs w = gram_refine_layout(ws, n, k);
+  GramRefineWs w = gram_refine_layout(ws, d, n, k);
   const unsigned cb = (unsigned)((k + GS_C - 1) / GS_C);
-  // H = A^T A and a = A^T B in one launch over the columns of [A | B], with ||b||^2
-  gemm_tn<T, T>(d, n, A, lda, n, A, lda, w.H, n, k, B, ldb, w.a, k, w.bb, st,
-                gref_splits(d, n, k), w.part);
+  // H = A^T A and a = A^T B in one launch over the columns of [A | B]
+  gemm_tn<T, T>(d, n, A, lda, n, A, lda, w.H, n, k, B, ldb, w.a, k, st, gref_splits(d, n, k),
+                w.part);
   hipLaunchKernelGGL(diag_scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,
                      (const double*)w.H, w.s);
   // H is symmetric, so H^T M = H M: the same transposed product with K = n
-  gemm_tn<double, T>(n, n, w.H, n, k, X, k, w.HX, k, 0, (const T*)nullptr, 0, nullptr, 0,
-                     nullptr, st);
+  gemm_tn<double, T>(n, n, w.H, n, k, X, k, w.HX, k, 0, (const T*)nullptr, 0, nullptr, 0, st);
   hipLaunchKernelGGL(gref_stage1_kernel<T>, dim3(cb), dim3(256), 0, st, n, k, (const T*)X,
-                     (const double*)w.HX, (const double*)w.a, (const double*)w.s,
-                     (const double*)w.bb, w.D, w.colstat);
+                     (const double*)w.HX, (const double*)w.a, (const double*)w.s, w.D,
+                     w.colstat);
   gemm_tn<double, double>(n, n, w.H, n, k, w.D, k, w.HD, k, 0, (const double*)nullptr, 0,
-                          nullptr, 0, nullptr, st);
+                          nullptr, 0, st);
   hipLaunchKernelGGL(gref_stage2_kernel<T>, dim3(cb), dim3(256), 0, st, n, k, (const T*)X,
                      (const double*)w.D, (const double*)w.HD, w.Xn, (const double*)w.colstat);
   gemm_tn<double, double>(n, n, w.H, n, k, w.Xn, k, w.HD, k, 0, (const double*)nullptr, 0,
-                          nullptr, 0, nullptr, st);  // H x' (reuses HD)
+                          nullptr, 0, st);  // H x' (reuses HD)
   hipLaunchKernelGGL(gref_stage3_kernel<T>, dim3(cb), dim3(256), 0, st, n, k, X,
                      (const double*)w.Xn, (const double*)w.HD, (const double*)w.HX,
-                     (const double*)w.a, (const double*)w.s, (const double*)w.colstat, kkt64,
-                     obj64);
+                     (const double*)w.a, (const double*)w.s, (const double*)w.colstat, kkt64);
+  if (obj64 != nullptr) {
+    // F of the returned X from its residuals
+    const int64_t tiles = resid_tiles(d);
+    dim3 g((unsigned)((k + TN_T - 1) / TN_T), (unsigned)tiles);
+    hipLaunchKernelGGL((resid_sq_f64_kernel<T, T>), g, dim3(256), 0, st, d, n, k, A, lda,
+                       (const T*)X, B, ldb, w.rsq);
+    hipLaunchKernelGGL(resid_sq_reduce_kernel, dim3((unsigned)((k + 255) / 256)), dim3(256), 0,
+                       st, tiles, k, (const double*)w.rsq, obj64);
+  }
 }
 
 template <typename T>

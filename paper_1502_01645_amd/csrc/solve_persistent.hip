@@ -56,7 +56,8 @@ struct SpArgs {
   float *y[2], *g[2], *p[2], *t[2];  // t: clip threshold y_i / gbar_i, +inf if i cannot clip
   uint64_t *pmask[2], *ymask[2];
   float *part, *scal;
-  unsigned* bar;
+  unsigned* bar;   // grid barrier words, with the abort word (grid_sync.hpp)
+  int spin_limit;  // polls before a barrier wait gives up (never reached in a normal launch)
 };
 
 __device__ __forceinline__ float sp_block_sum(float v, float* red) {
@@ -279,7 +280,8 @@ __global__ __launch_bounds__(SP_NT) void solve_persistent_kernel(SpArgs A) {
     qn2 = sp_block_sum(acc, L.redF);
   }
   const double qscale = qn2 > 0.f ? sqrt((double)qn2) : 1.0;
-  grid_barrier(A.bar, G, epoch);
+  // a barrier that gave up (every workgroup leaves at its next wait) ends the solve
+  bool timed_out = !grid_barrier(A.bar, G, epoch, A.spin_limit);
 
   int cur = 0;
   int it = 0;
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(SP_NT) void solve_persistent_kernel(SpArgs A) {
   int status = NNLS_MAXITER_DEV;
   double r_now = 0.0;
 
-  for (;;) {
+  while (!timed_out) {
     if (need_refresh) {
       // gradient = Q y + q over the rows with y > 0
       {
@@ -297,7 +299,10 @@ __global__ __launch_bounds__(SP_NT) void solve_persistent_kernel(SpArgs A) {
         rows += (int64_t)sp_block_sum(v, L.redF);
       }
       rows_product(A, A.ymask[cur], A.y[cur], L);
-      grid_barrier(A.bar, G, epoch);
+      if (!grid_barrier(A.bar, G, epoch, A.spin_limit)) {
+        timed_out = true;
+        break;
+      }
       if (threadIdx.x < 8) L.stats[threadIdx.x] = 0.f;
       __syncthreads();
       if (owner) {
@@ -313,7 +318,10 @@ __global__ __launch_bounds__(SP_NT) void solve_persistent_kernel(SpArgs A) {
         }
       }
       publish_stats(A, L);
-      grid_barrier(A.bar, G, epoch);
+      if (!grid_barrier(A.bar, G, epoch, A.spin_limit)) {
+        timed_out = true;
+        break;
+      }
       cur ^= 1;
       need_refresh = false;
       fresh = true;
@@ -385,7 +393,10 @@ __global__ __launch_bounds__(SP_NT) void solve_persistent_kernel(SpArgs A) {
       break;
     }
     rows += (int64_t)npass;
-    grid_barrier(A.bar, G, epoch);
+    if (!grid_barrier(A.bar, G, epoch, A.spin_limit)) {
+      timed_out = true;
+      break;
+    }
 
     // ---- phase 2
     float dv = (threadIdx.x < G) ? ld_sc(A.scal + threadIdx.x * 8 + 0) : 0.f;
@@ -455,7 +466,10 @@ __global__ __launch_bounds__(SP_NT) void solve_persistent_kernel(SpArgs A) {
       }
     }
     publish_stats(A, L);
-    grid_barrier(A.bar, G, epoch);
+    if (!grid_barrier(A.bar, G, epoch, A.spin_limit)) {
+      timed_out = true;
+      break;
+    }
     cur ^= 1;
     ++it;
     fresh = false;
@@ -467,9 +481,9 @@ __global__ __launch_bounds__(SP_NT) void solve_persistent_kernel(SpArgs A) {
     A.X[oi] = A.s ? (float)((double)yi / A.s[oi]) : yi;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    A.iters[0] = it;
-    A.kkt[0] = status == NNLS_NONFINITE_DEV ? __builtin_nan("") : r_now;
-    A.status[0] = status;
+    A.iters[0] = timed_out ? -1 : it;
+    A.kkt[0] = (status == NNLS_NONFINITE_DEV || timed_out) ? __builtin_nan("") : r_now;
+    A.status[0] = timed_out ? NNLS_BREAKDOWN_DEV : status;
     if (A.rows_read) A.rows_read[0] = rows;
   }
 }
@@ -550,6 +564,7 @@ hipError_t launch_solve_persistent(int64_t n, const float* Q, const float* q, co
   A.kkt = kkt;
   A.status = status;
   A.rows_read = rows_read;
+  A.spin_limit = spin_limit_setting();
   char* p = (char*)ws;
   auto take = [&](size_t bytes) {
     char* r = p;

@@ -50,8 +50,10 @@ struct RqArgs {
   uint64_t* fl;  // [G] publish flags: update number of the last gbar / statistics written
   uint64_t* dw;  // [G] line-search denominator partials, tagged with the update number, in
                  // RQ_DREP copies RQ_DREP_WORDS apart
-  unsigned* bar;
-  int spin_limit;  // polls before a workgroup gives up waiting (a guard that never fires)
+  unsigned* bar;   // grid barrier words, with the abort word (grid_sync.hpp)
+  int spin_limit;  // polls before a workgroup gives up waiting: a guard that never fires in a
+                   // normal launch; a workgroup that gives up sets the abort word, which ends
+                   // every other workgroup's waits too
 };
 
 // The denominator partials are polled by every workgroup at once; each is written to RQ_DREP
@@ -234,7 +236,12 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
     for (int poll = 0;; ++poll) {
       const bool ok = t >= G || tag_ok(ld_sc(A.fl + t), ep);
       if (__syncthreads_and(ok)) break;
-      if (poll >= A.spin_limit) return false;
+      // (poll is the same in every thread, so either all threads reach the _or or none)
+      if (poll >= A.spin_limit ||
+          ((poll & 63) == 63 && __syncthreads_or(t == 0 && grid_aborted(A.bar)))) {
+        if (t == 0) grid_abort(A.bar);
+        return false;
+      }
       __builtin_amdgcn_s_sleep(1);
     }
     // gbar at the own columns straight into vs, and the statistics of every workgroup into
@@ -286,7 +293,10 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
       // exact gradient g_I = q_I + Q[I, :] y; everyone has finished reading gbar(ep) before
       // the owners overwrite it
       rows += (int64_t)st5[4];
-      grid_barrier(A.bar, G, epoch);
+      if (!grid_barrier(A.bar, G, epoch, A.spin_limit)) {
+        timed_out = true;
+        break;
+      }
       reg_product<RPC, CS, NT>(qr, ys, red, prod);
       if (own) g_own = A.q[i0 + t] + prod[t];
       publish(++ep);
@@ -347,10 +357,13 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
           got = true;
           break;
         }
-        if (poll >= A.spin_limit) break;
+        if (poll >= A.spin_limit ||
+            ((poll & 63) == 63 && __syncthreads_or(t == 0 && grid_aborted(A.bar))))
+          break;
         __builtin_amdgcn_s_sleep(2);
       }
       if (!got) {
+        if (t == 0) grid_abort(A.bar);
         timed_out = true;
         break;
       }
@@ -515,7 +528,7 @@ hipError_t launch_solve_regq(int64_t n, const float* Q, const float* q, const do
   A.dw = (uint64_t*)take(sizeof(uint64_t) * RQ_DREP * (size_t)RQ_DREP_WORDS);
   A.gf = (float*)take(sizeof(float) * RQ_GF);
   A.sf = (float*)take(sizeof(float) * 8 * (size_t)G);
-  A.spin_limit = 1 << 24;
+  A.spin_limit = spin_limit_setting();
   hipLaunchKernelGGL(regq_init_kernel, dim3(8), dim3(256), 0, st, A.bar, A.fl, A.dw, G, A.gf,
                      (int64_t)RQ_GF);
   hipError_t e = hipGetLastError();

@@ -299,9 +299,10 @@ def solve(Q: torch.Tensor, q: torch.Tensor, s: torch.Tensor | None = None, tol: 
     return X, iters, kkt, status
 
 
-def refine(A: torch.Tensor, B: torch.Tensor, X: torch.Tensor, out=None, ws=None):
+def refine(A: torch.Tensor, B: torch.Tensor, X: torch.Tensor, out=None, ws=None,
+           objective: bool = True):
     """FP64 check + one refinement step against (A, B); X is updated in place.
-    Returns (kkt64, obj64)."""
+    Returns (kkt64, obj64); obj64 is None when objective is False (or out[1] is None)."""
     d, n = A.shape
     if B.dim() == 1:
         B = B.reshape(d, 1)
@@ -310,7 +311,7 @@ def refine(A: torch.Tensor, B: torch.Tensor, X: torch.Tensor, out=None, ws=None)
     assert X.shape == (n, k) and X.is_contiguous() and X.dtype == A.dtype
     if out is None:
         kkt64 = torch.empty(k, dtype=torch.float64, device=A.device)
-        obj64 = torch.empty(k, dtype=torch.float64, device=A.device)
+        obj64 = torch.empty(k, dtype=torch.float64, device=A.device) if objective else None
     else:
         kkt64, obj64 = out
     wsb = workspace_bytes(OP_REFINE, d, n, k, 0, dt)

@@ -150,13 +150,16 @@ def test_refine_rejects_bad_arguments(L):
     big = 1 << 40
     base = dict(d=50, n=10, k=2, A=FAKE, lda=10, B=FAKE, ldb=2, dt=N.F32, X=FAKE, kk=FAKE, ob=FAKE)
     for c in [dict(d=0), dict(n=0), dict(k=0), dict(A=None), dict(B=None), dict(X=None),
-              dict(kk=None), dict(ob=None), dict(lda=9), dict(ldb=1), dict(dt=9)]:
+              dict(kk=None), dict(lda=9), dict(ldb=1), dict(dt=9)]:
         a = dict(base)
         a.update(c)
         rc = L.nnls_refine(a["d"], a["n"], a["k"], a["A"], a["lda"], a["B"], a["ldb"], a["dt"],
                            a["X"], a["kk"], a["ob"], FAKE, big, None)
         assert rc == N.E_ARG, c
     rc = L.nnls_refine(50, 10, 2, FAKE, 10, FAKE, 2, N.F32, FAKE, FAKE, FAKE, FAKE, 8, None)
+    assert rc == N.E_WORKSPACE
+    # obj64 may be NULL (the objective is then not formed): argument checks pass
+    rc = L.nnls_refine(50, 10, 2, FAKE, 10, FAKE, 2, N.F32, FAKE, FAKE, None, FAKE, 8, None)
     assert rc == N.E_WORKSPACE
 
 

@@ -213,6 +213,44 @@ def test_refine_few_rhs_matches_oracle(dtype, d, n, k, start):
     _refine_case(dtype, d, n, k, start)
 
 
+@pytest.mark.parametrize("d,n,k", [(600, 96, 3), (900, 160, 40), (1100, 256, 70)])
+def test_refine_objective_noiseless(d, n, k):
+    """Noiseless data b = A x*: F* = 0 and F at the returned x is tiny against 1/2 ||b||^2, so
+    the reported objective must come from the residuals.  Checked relative to F itself (the
+    Gram form 1/2 (x^T H x - 2 a^T x + ||b||^2) would be off by about eps ||b||^2 here, many
+    times F), once after a solve and once at x* itself, where F is only the FP32 rounding of b;
+    obj64 = NULL leaves the check and step unchanged."""
+    say(f"refine noiseless objective d={d} n={n} k={k}")
+    rng = np.random.default_rng(71 + k)
+    A = rng.random((d, n)).astype(np.float32)
+    Xt = np.where(rng.random((n, k)) < 0.5, 0.0, rng.random((n, k))).astype(np.float32)
+    B = (A.astype(np.float64) @ Xt.astype(np.float64)).astype(np.float32)
+    bb = 0.5 * (B.astype(np.float64) ** 2).sum(0)
+    res = N.nnls(dev(A), dev(B), tol=1e-5, max_iter=100000, inner_tol=3e-6)
+    X1 = host(res["X"])
+    _, F1 = orc().kkt_x(A, B, X1)
+    obj = host(res["obj64"])
+    say(f"  after solve: F/(||b||^2/2) max {(F1 / bb).max():.2e}, "
+        f"max |obj - F|/F {np.max(np.abs(obj - F1) / F1):.2e}")
+    assert np.all(F1 < 1e-6 * bb)
+    np.testing.assert_allclose(obj, F1, rtol=1e-6, atol=0)
+    # at x* itself
+    X = dev(Xt)
+    kkt64, obj64 = N.refine(dev(A), dev(B), X)
+    Xr = host(X)
+    r2, F2 = orc().kkt_x(A, B, Xr)
+    say(f"  at x*: F/(||b||^2/2) max {(F2 / bb).max():.2e}, "
+        f"max |obj - F|/F {np.max(np.abs(host(obj64) - F2) / F2):.2e}")
+    np.testing.assert_allclose(host(obj64), F2, rtol=1e-5, atol=0)
+    np.testing.assert_allclose(host(kkt64), r2, rtol=1e-6, atol=1e-14)
+    # without the objective: same X and residual
+    X = dev(Xt)
+    kkt_b, obj_b = N.refine(dev(A), dev(B), X, objective=False)
+    assert obj_b is None
+    np.testing.assert_array_equal(host(X), Xr)
+    np.testing.assert_array_equal(host(kkt_b), host(kkt64))
+
+
 def _refine_case(dtype, d, n, k, start):
     A, B = _uniform_case(31 + k, d, n, k, dtype)
     Q, q, s = N.prepare(dev(A), dev(B))
@@ -362,6 +400,48 @@ def test_persistent_statuses(whole_gpu):
     qp = q.abs()
     X, it, kkt, st = N.solve(Q, qp, s, tol=1e-6, max_iter=50)
     assert host(st)[0] == N.CONVERGED and host(it)[0] == 0 and np.all(host(X) == 0)
+
+
+def test_whole_gpu_give_up_ends_every_wait(whole_gpu, monkeypatch):
+    """A poll limit of 0, forced from the host: the first workgroup that does not find the
+    others ready gives up and sets the abort word, every other workgroup leaves its wait at its
+    next check, and the launch ends normally with BREAKDOWN, iters = -1 and a NaN residual.  A
+    solve with the normal limit on the same workspace afterwards is unaffected."""
+    say(f"{whole_gpu} forced give-up")
+    A, b, _ = W.make_large(seed=9, d=3000, n=1600)
+    n = A.shape[1]
+    Q, q, s = N.prepare(dev(A), dev(b))
+    ws = torch.empty(N.workspace_bytes(N.OP_SOLVE, 0, n, 1, 0, N.F32), dtype=torch.uint8,
+                     device=DEV)
+    X0, it0, kkt0, st0 = N.solve(Q, q, s, tol=1e-5, max_iter=100000, ws=ws)
+    monkeypatch.setenv("NNLS_SPIN_LIMIT", "0")
+    X, it, kkt, st = N.solve(Q, q, s, tol=1e-5, max_iter=100000, ws=ws)
+    assert host(st)[0] == N.BREAKDOWN and host(it)[0] == -1 and np.isnan(host(kkt)[0])
+    monkeypatch.delenv("NNLS_SPIN_LIMIT")
+    X1, it1, kkt1, st1 = N.solve(Q, q, s, tol=1e-5, max_iter=100000, ws=ws)
+    assert host(st1)[0] == N.CONVERGED and host(it1)[0] == host(it0)[0]
+    np.testing.assert_array_equal(host(X1), host(X0))
+
+
+def test_whole_gpu_solve_is_bitwise_reproducible(whole_gpu):
+    """The exchanges between workgroups fix the order of every sum (partials added in workgroup
+    order, whichever workgroup publishes first), so the full-size large single right-hand-side
+    workload (20000 x 5000) prepared and solved twice gives bitwise the same Q, X, iteration
+    count and residual."""
+    say(f"{whole_gpu} reproducible 20000x5000")
+    A, b, _ = W.make_large()
+    Ad, bd = dev(A), dev(b)
+    runs = []
+    for _ in range(3):
+        Q, q, s = N.prepare(Ad, bd)
+        X, it, kkt, st = N.solve(Q, q, s, tol=8e-6, max_iter=25000)
+        runs.append((host(Q), host(X), int(host(it)[0]), float(host(kkt)[0]), int(host(st)[0])))
+    say(f"  iters {[r[2] for r in runs]} kkt {[r[3] for r in runs]}")
+    assert runs[0][4] == N.CONVERGED
+    for r in runs[1:]:
+        np.testing.assert_array_equal(r[0], runs[0][0])
+        np.testing.assert_array_equal(r[1], runs[0][1])
+        assert r[2:] == runs[0][2:]
 
 
 def test_regq_rows_read_counts_passive_and_clipped(monkeypatch):
