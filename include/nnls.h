@@ -161,6 +161,27 @@ int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, co
                void* stream);
 
 /*
+ * nnls_solve_noalloc -- nnls_solve for callers that cannot allocate device memory or pass a
+ * workspace: code under graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, solvers, results and errors as nnls_solve, without ws / ws_bytes: the solver
+ * state lives in a fixed device array of NNLS_NOALLOC_SCRATCH_BYTES inside the library, one
+ * per GPU, held from the first call on that GPU until the process ends.  The call allocates
+ * nothing (no hipMalloc, no allocating library routine); the caller still owns Q, q, s, Y0 and
+ * the outputs.
+ *   - Returns NNLS_E_WORKSPACE when the solve would need more than NNLS_NOALLOC_SCRATCH_BYTES
+ *     (nnls_workspace_bytes(NNLS_OP_SOLVE, ...) tells; the per-column solver needs 12 n k bytes
+ *     for FP32, so that path is limited to n k <= 699050).
+ *   - Every call on one GPU shares that GPU's array and the solvers reset what they read before
+ *     they read it, so consecutive calls are independent; calls that overlap in time on one GPU
+ *     (different streams, or host threads) race on the array and must not be issued.
+ */
+#define NNLS_NOALLOC_SCRATCH_BYTES (8u << 20)
+int nnls_solve_noalloc(int64_t n, int64_t k, int dtype, const void* Q, const void* q,
+                       const double* s, double tol, int32_t max_iter, const void* Y0, void* X,
+                       int32_t* iters, double* kkt, int32_t* status, int64_t* rows_read,
+                       void* stream);
+
+/*
  * nnls_refine -- FP64 check and one refinement step against the ORIGINAL data (A, B).
  * For every column: r = A x - b and grad = A^T r in FP64; in the rescaled variables one masked
  * exact-line-search projected step of Algorithm 2 (the step length from ||A (gbar ./ s)||^2 in

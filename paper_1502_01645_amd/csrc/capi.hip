@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "../../include/nnls.h"
@@ -110,6 +111,33 @@ size_t solve_ws(int64_t n, int64_t k, int dt) {
     default:
       return align_up(elem_size(dt) * 3 * n * k);
   }
+}
+
+// ---- scratch of the solve that allocates nothing ------------------------------------------
+// One copy per GPU the library runs on, held until the process ends.  In host code `scratch` is
+// a host-side stand-in, not a device address: host code uses only the address that
+// hipGetSymbolAddress returns for the current device, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[NNLS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+hipError_t scratch_of_current_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace
@@ -245,19 +273,24 @@ int nnls_prepare(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, co
   return e == hipSuccess ? NNLS_OK : hip_fail(e);
 }
 
-int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, const double* s,
-               double tol, int32_t max_iter, const void* Y0, void* X, int32_t* iters,
-               double* kkt, int32_t* status, int64_t* rows_read, void* ws, size_t ws_bytes,
-               void* stream) {
+// Host checks of a solve (every argument but the workspace).
+static int validate_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q,
+                          double tol, int32_t max_iter, const void* X, const int32_t* iters,
+                          const double* kkt, const int32_t* status) {
   if (n < 1 || k < 1 || !valid_dtype(dtype)) return NNLS_E_ARG;
   if (!Q || !q || !X || !iters || !kkt || !status) return NNLS_E_ARG;
   if (!(tol >= 0.0) || !isfinite(tol) || max_iter < 0) return NNLS_E_ARG;
   if (n > (int64_t)1 << 30 || k > (int64_t)1 << 31) return NNLS_E_UNSUPPORTED;
   if (!solver_supported(n, k, dtype)) return NNLS_E_UNSUPPORTED;
-  const size_t need = solve_ws(n, k, dtype);
-  if (ws_bytes < need || !ws) return NNLS_E_WORKSPACE;
+  return NNLS_OK;
+}
+
+// The solver launch of a validated solve, with its scratch state in ws.
+static int run_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q,
+                     const double* s, double tol, int32_t max_iter, const void* Y0, void* X,
+                     int32_t* iters, double* kkt, int32_t* status, int64_t* rows_read, void* ws,
+                     hipStream_t st) {
   const int mi = max_iter == 0 ? (int)(5 * n < (1 << 30) ? 5 * n : (1 << 30)) : max_iter;
-  hipStream_t st = (hipStream_t)stream;
   hipError_t e;
   const SolverKind kind = pick_solver(n, k, dtype);
   if (kind == SOLVER_MRHS) {
@@ -284,6 +317,32 @@ int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, co
                                      (float*)ws, st);
   if (e != hipSuccess) return hip_fail(e);
   return NNLS_OK;
+}
+
+int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, const double* s,
+               double tol, int32_t max_iter, const void* Y0, void* X, int32_t* iters,
+               double* kkt, int32_t* status, int64_t* rows_read, void* ws, size_t ws_bytes,
+               void* stream) {
+  const int rc = validate_solve(n, k, dtype, Q, q, tol, max_iter, X, iters, kkt, status);
+  if (rc != NNLS_OK) return rc;
+  const size_t need = solve_ws(n, k, dtype);
+  if (ws_bytes < need || !ws) return NNLS_E_WORKSPACE;
+  return run_solve(n, k, dtype, Q, q, s, tol, max_iter, Y0, X, iters, kkt, status, rows_read, ws,
+                   (hipStream_t)stream);
+}
+
+int nnls_solve_noalloc(int64_t n, int64_t k, int dtype, const void* Q, const void* q,
+                       const double* s, double tol, int32_t max_iter, const void* Y0, void* X,
+                       int32_t* iters, double* kkt, int32_t* status, int64_t* rows_read,
+                       void* stream) {
+  const int rc = validate_solve(n, k, dtype, Q, q, tol, max_iter, X, iters, kkt, status);
+  if (rc != NNLS_OK) return rc;
+  if (solve_ws(n, k, dtype) > (size_t)NNLS_NOALLOC_SCRATCH_BYTES) return NNLS_E_WORKSPACE;
+  void* ws = nullptr;
+  const hipError_t e = scratch_of_current_device(&ws);
+  if (e != hipSuccess) return hip_fail(e);
+  return run_solve(n, k, dtype, Q, q, s, tol, max_iter, Y0, X, iters, kkt, status, rows_read, ws,
+                   (hipStream_t)stream);
 }
 
 int nnls_refine(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,

@@ -20,6 +20,7 @@ CONVERGED, MAXITER, BREAKDOWN, NONFINITE, FELL_BACK = 0, 1, 2, 3, 4
 GRAM_FP64, GRAM_FP32, GRAM_BF16X3 = 0, 1, 2
 F32, F64 = 0, 1
 OP_PREPARE, OP_SOLVE, OP_REFINE, OP_SCALES, OP_GRAM = 0, 1, 2, 3, 4
+NOALLOC_SCRATCH_BYTES = 8 << 20   # NNLS_NOALLOC_SCRATCH_BYTES
 
 _ERRORS = {E_ARG: "invalid argument", E_WORKSPACE: "workspace too small",
            E_HIP: "HIP runtime error", E_UNSUPPORTED: "unsupported shape"}
@@ -54,6 +55,9 @@ def lib():
         L.nnls_prepare.restype = ctypes.c_int
         L.nnls_solve.argtypes = [_i64, _i64, ctypes.c_int, _vp, _vp, _vp, ctypes.c_double, _i32, _vp,
                                  _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.nnls_solve_noalloc.argtypes = [_i64, _i64, ctypes.c_int, _vp, _vp, _vp, ctypes.c_double,
+                                         _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.nnls_solve_noalloc.restype = ctypes.c_int
         L.nnls_column_scales.argtypes = [_i64, _i64, _vp, _i64, ctypes.c_int, _vp, _vp, _sz, _vp]
         L.nnls_column_scales.restype = ctypes.c_int
         L.nnls_gram_rescaled.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int,
@@ -296,6 +300,28 @@ def solve(Q: torch.Tensor, q: torch.Tensor, s: torch.Tensor | None = None, tol: 
                           _ptr(X), _ptr(iters), _ptr(kkt), _ptr(status), _ptr(rows_read), _ptr(ws),
                           wsb, _stream(Q.device))
     _check(rc, "nnls_solve")
+    return X, iters, kkt, status
+
+
+def solve_noalloc(Q: torch.Tensor, q: torch.Tensor, s: torch.Tensor | None, tol: float,
+                  max_iter: int, Y0: torch.Tensor | None, out, rows_read=None):
+    """nnls_solve_noalloc: as solve(), with the solver state in the library's fixed device
+    array instead of a workspace.  The caller passes every output (out = (X, iters, kkt,
+    status)); nothing is allocated here or in the library."""
+    n = Q.shape[0]
+    if q.dim() == 1:
+        q = q.reshape(n, 1)
+    k = q.shape[1]
+    dt = _dtype_code(Q)
+    assert Q.is_contiguous() and q.is_contiguous() and q.dtype == Q.dtype
+    if Y0 is not None:
+        Y0 = Y0.reshape(n, k)
+        assert Y0.is_contiguous() and Y0.dtype == Q.dtype
+    X, iters, kkt, status = out
+    rc = lib().nnls_solve_noalloc(n, k, dt, _ptr(Q), _ptr(q), _ptr(s), float(tol), int(max_iter),
+                                  _ptr(Y0), _ptr(X), _ptr(iters), _ptr(kkt), _ptr(status),
+                                  _ptr(rows_read), _stream(Q.device))
+    _check(rc, "nnls_solve_noalloc")
     return X, iters, kkt, status
 
 

@@ -145,6 +145,21 @@ def test_nmf_helpers_reject_bad_arguments(L):
     assert L.nnls_rescale_start(3, 3, FAKE, FAKE, None, None) == N.E_ARG
 
 
+def test_solve_noalloc_rejects_bad_arguments_and_oversized_scratch(L):
+    from paper_1502_01645_amd import nnls as N
+    args = lambda n, k, dt, Q=FAKE, tol=1e-5: (n, k, dt, Q, FAKE, None, tol, 0, None, FAKE, FAKE,  # noqa
+                                               FAKE, FAKE, None, None)
+    assert L.nnls_solve_noalloc(*args(0, 3, N.F32)) == N.E_ARG
+    assert L.nnls_solve_noalloc(*args(10, 3, N.F32, Q=None)) == N.E_ARG
+    assert L.nnls_solve_noalloc(*args(10, 3, N.F32, tol=-1.0)) == N.E_ARG
+    assert L.nnls_solve_noalloc(*args(10, 3, 9)) == N.E_ARG
+    # the per-column solver needs 12 n k (FP32) or 24 n k (FP64) bytes: past the fixed scratch
+    # the call is refused before any device work
+    assert L.nnls_solve_noalloc(*args(1001, 1000, N.F32)) == N.E_WORKSPACE
+    assert L.nnls_solve_noalloc(*args(500, 1000, N.F64)) == N.E_WORKSPACE
+    assert N.workspace_bytes(N.OP_SOLVE, 0, 500, 1000, 0, N.F64) > N.NOALLOC_SCRATCH_BYTES
+
+
 def test_refine_rejects_bad_arguments(L):
     from paper_1502_01645_amd import nnls as N
     big = 1 << 40
