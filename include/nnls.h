@@ -146,6 +146,13 @@ int nnls_gram_rescaled(int64_t d, int64_t n, int64_t k, const void* A, int64_t l
  *             rows of the line-search products, clipped rows of the gradient corrections, rows
  *             of exact gradient recomputations); 4 n bytes each for FP32 Q.  This is the
  *             S(n)-weighted work of the complexity lemma of Section 4.
+ *   trace     out [k, trace_len, 2] FP32, may be NULL (then trace_len is ignored; otherwise
+ *             trace_len >= 1): per column c and update count t < trace_len,
+ *             trace[c][t][0] = r(y_t) and trace[c][t][1] = ||gbar_t||^2 of the iterate y_t after
+ *             t updates, as the solve evaluated them (the convergence record that Figures 3 and
+ *             4 of Section 5 plot against time).  Where the solve recomputed the gradient
+ *             exactly at y_t, the entry holds the recomputed values.  Entries for t > iters[c]
+ *             are not written.
  * The workspace size depends on the solver chosen for the shape; NNLS_OP_SOLVE sizes it for
  * the current device.  The environment variable NNLS_SOLVER=wg|regq|persistent|mrhs forces
  * the one-workgroup-per-column solver, the whole-GPU single-right-hand-side solver with Q held
@@ -157,8 +164,8 @@ int nnls_gram_rescaled(int64_t d, int64_t n, int64_t k, const void* A, int64_t l
  */
 int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, const double* s,
                double tol, int32_t max_iter, const void* Y0, void* X, int32_t* iters,
-               double* kkt, int32_t* status, int64_t* rows_read, void* ws, size_t ws_bytes,
-               void* stream);
+               double* kkt, int32_t* status, int64_t* rows_read, float* trace,
+               int32_t trace_len, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * nnls_solve_noalloc -- nnls_solve for callers that cannot allocate device memory or pass a
@@ -179,7 +186,7 @@ int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, co
 int nnls_solve_noalloc(int64_t n, int64_t k, int dtype, const void* Q, const void* q,
                        const double* s, double tol, int32_t max_iter, const void* Y0, void* X,
                        int32_t* iters, double* kkt, int32_t* status, int64_t* rows_read,
-                       void* stream);
+                       float* trace, int32_t trace_len, void* stream);
 
 /*
  * nnls_refine -- FP64 check and one refinement step against the ORIGINAL data (A, B).

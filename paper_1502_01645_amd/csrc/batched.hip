@@ -60,6 +60,8 @@ __global__ __launch_bounds__(SW_NT) void batched_solve_kernel(BatchSolveArgs B) 
     P.w = P.g + D.n;
     P.x = B.X_pool + D.offX;
     P.s = B.s_pool + D.offq;
+    P.trace = nullptr;
+    P.trace_len = 0;
     const int mi = B.max_iter > 0 ? B.max_iter : (int)(5 * D.n);
     solve_column<float>(P, B.tol, mi, B.iters + p, B.kkt + p, B.status + p,
                         B.rows_read ? B.rows_read + p : nullptr, (float*)(smem + L.val),

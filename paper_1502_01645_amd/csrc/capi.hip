@@ -276,9 +276,12 @@ int nnls_prepare(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, co
 // Host checks of a solve (every argument but the workspace).
 static int validate_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q,
                           double tol, int32_t max_iter, const void* X, const int32_t* iters,
-                          const double* kkt, const int32_t* status) {
+                          const double* kkt, const int32_t* status, const float* trace,
+                          int32_t trace_len) {
   if (n < 1 || k < 1 || !valid_dtype(dtype)) return NNLS_E_ARG;
   if (!Q || !q || !X || !iters || !kkt || !status) return NNLS_E_ARG;
+  if (trace_len < 0 || (trace != nullptr && trace_len == 0)) return NNLS_E_ARG;
+  if (trace != nullptr && k * (int64_t)trace_len > ((int64_t)1 << 40)) return NNLS_E_UNSUPPORTED;
   if (!(tol >= 0.0) || !isfinite(tol) || max_iter < 0) return NNLS_E_ARG;
   if (n > (int64_t)1 << 30 || k > (int64_t)1 << 31) return NNLS_E_UNSUPPORTED;
   if (!solver_supported(n, k, dtype)) return NNLS_E_UNSUPPORTED;
@@ -288,61 +291,64 @@ static int validate_solve(int64_t n, int64_t k, int dtype, const void* Q, const 
 // The solver launch of a validated solve, with its scratch state in ws.
 static int run_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q,
                      const double* s, double tol, int32_t max_iter, const void* Y0, void* X,
-                     int32_t* iters, double* kkt, int32_t* status, int64_t* rows_read, void* ws,
-                     hipStream_t st) {
+                     int32_t* iters, double* kkt, int32_t* status, int64_t* rows_read,
+                     float* trace, int32_t trace_len, void* ws, hipStream_t st) {
+  const int tl = trace != nullptr ? trace_len : 0;
   const int mi = max_iter == 0 ? (int)(5 * n < (1 << 30) ? 5 * n : (1 << 30)) : max_iter;
   hipError_t e;
   const SolverKind kind = pick_solver(n, k, dtype);
   if (kind == SOLVER_MRHS) {
     if (((uintptr_t)Q & 15) != 0) return NNLS_E_ARG;  // rows are read as 16-byte vectors
     e = nnls::launch_solve_mrhs(n, k, (const float*)Q, (const float*)q, s, tol, mi,
-                                (const float*)Y0, (float*)X, iters, kkt, status, rows_read, ws,
-                                st);
+                                (const float*)Y0, (float*)X, iters, kkt, status, rows_read, trace,
+                                tl, ws, st);
   } else if (kind == SOLVER_REGQ) {
     e = nnls::launch_solve_regq(n, (const float*)Q, (const float*)q, s, tol, mi,
-                                (const float*)Y0, (float*)X, iters, kkt, status, rows_read, ws,
-                                st);
+                                (const float*)Y0, (float*)X, iters, kkt, status, rows_read, trace,
+                                tl, ws, st);
   } else if (kind == SOLVER_PERSISTENT) {
     if (((uintptr_t)Q & 15) != 0) return NNLS_E_ARG;  // rows are read as 16-byte vectors
     e = nnls::launch_solve_persistent(n, (const float*)Q, (const float*)q, s, tol, mi,
                                       (const float*)Y0, (float*)X, iters, kkt, status,
-                                      rows_read, ws, st);
+                                      rows_read, trace, tl, ws, st);
   } else if (dtype == NNLS_F64)
     e = nnls::launch_solve_wg<double>(n, k, (const double*)Q, (const double*)q, s, tol, mi,
                                       (const double*)Y0, (double*)X, iters, kkt, status,
-                                      rows_read, (double*)ws, st);
+                                      rows_read, trace, tl, (double*)ws, st);
   else
     e = nnls::launch_solve_wg<float>(n, k, (const float*)Q, (const float*)q, s, tol, mi,
                                      (const float*)Y0, (float*)X, iters, kkt, status, rows_read,
-                                     (float*)ws, st);
+                                     trace, tl, (float*)ws, st);
   if (e != hipSuccess) return hip_fail(e);
   return NNLS_OK;
 }
 
 int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, const double* s,
                double tol, int32_t max_iter, const void* Y0, void* X, int32_t* iters,
-               double* kkt, int32_t* status, int64_t* rows_read, void* ws, size_t ws_bytes,
-               void* stream) {
-  const int rc = validate_solve(n, k, dtype, Q, q, tol, max_iter, X, iters, kkt, status);
+               double* kkt, int32_t* status, int64_t* rows_read, float* trace,
+               int32_t trace_len, void* ws, size_t ws_bytes, void* stream) {
+  const int rc = validate_solve(n, k, dtype, Q, q, tol, max_iter, X, iters, kkt, status, trace,
+                                trace_len);
   if (rc != NNLS_OK) return rc;
   const size_t need = solve_ws(n, k, dtype);
   if (ws_bytes < need || !ws) return NNLS_E_WORKSPACE;
-  return run_solve(n, k, dtype, Q, q, s, tol, max_iter, Y0, X, iters, kkt, status, rows_read, ws,
-                   (hipStream_t)stream);
+  return run_solve(n, k, dtype, Q, q, s, tol, max_iter, Y0, X, iters, kkt, status, rows_read,
+                   trace, trace_len, ws, (hipStream_t)stream);
 }
 
 int nnls_solve_noalloc(int64_t n, int64_t k, int dtype, const void* Q, const void* q,
                        const double* s, double tol, int32_t max_iter, const void* Y0, void* X,
                        int32_t* iters, double* kkt, int32_t* status, int64_t* rows_read,
-                       void* stream) {
-  const int rc = validate_solve(n, k, dtype, Q, q, tol, max_iter, X, iters, kkt, status);
+                       float* trace, int32_t trace_len, void* stream) {
+  const int rc = validate_solve(n, k, dtype, Q, q, tol, max_iter, X, iters, kkt, status, trace,
+                                trace_len);
   if (rc != NNLS_OK) return rc;
   if (solve_ws(n, k, dtype) > (size_t)NNLS_NOALLOC_SCRATCH_BYTES) return NNLS_E_WORKSPACE;
   void* ws = nullptr;
   const hipError_t e = scratch_of_current_device(&ws);
   if (e != hipSuccess) return hip_fail(e);
-  return run_solve(n, k, dtype, Q, q, s, tol, max_iter, Y0, X, iters, kkt, status, rows_read, ws,
-                   (hipStream_t)stream);
+  return run_solve(n, k, dtype, Q, q, s, tol, max_iter, Y0, X, iters, kkt, status, rows_read,
+                   trace, trace_len, ws, (hipStream_t)stream);
 }
 
 int nnls_refine(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,

@@ -55,19 +55,21 @@ hipError_t launch_batched_gram(const BatchDesc* desc, int64_t count, const float
 
 // solve_wg.hip
 size_t solve_wg_lds_bytes(int64_t n, int elem);
+// Every solver launcher takes the per-update trace: trace [k][trace_len][2] FP32 (r of the
+// iterate after t updates, ||gbar||^2 of it) for t < trace_len, or nullptr.
 template <typename T>
 hipError_t launch_solve_wg(int64_t n, int64_t k, const T* Q, const T* q, const double* s,
                            double tol, int max_iter, const T* Y0, T* X, int32_t* iters,
-                           double* kkt, int32_t* status, int64_t* rows_read, T* ws,
-                           hipStream_t st);
+                           double* kkt, int32_t* status, int64_t* rows_read, float* trace,
+                           int trace_len, T* ws, hipStream_t st);
 
 // solve_regq.hip (one right-hand side, Q held in the register file of the whole GPU)
 bool solve_regq_supported(int64_t n, int64_t k);
 size_t solve_regq_ws_bytes(int64_t n);
 hipError_t launch_solve_regq(int64_t n, const float* Q, const float* q, const double* s,
                              double tol, int max_iter, const float* Y0, float* X, int32_t* iters,
-                             double* kkt, int32_t* status, int64_t* rows_read, void* ws,
-                             hipStream_t st);
+                             double* kkt, int32_t* status, int64_t* rows_read, float* trace,
+                             int trace_len, void* ws, hipStream_t st);
 
 // solve_persistent.hip
 bool solve_persistent_supported(int64_t n, int64_t k);
@@ -75,7 +77,8 @@ size_t solve_persistent_ws_bytes(int64_t n);
 hipError_t launch_solve_persistent(int64_t n, const float* Q, const float* q, const double* s,
                                    double tol, int max_iter, const float* Y0, float* X,
                                    int32_t* iters, double* kkt, int32_t* status,
-                                   int64_t* rows_read, void* ws, hipStream_t st);
+                                   int64_t* rows_read, float* trace, int trace_len, void* ws,
+                                   hipStream_t st);
 
 // solve_mrhs.hip
 bool solve_mrhs_supported(int64_t n, int64_t k);
@@ -83,7 +86,8 @@ size_t solve_mrhs_ws_bytes();
 hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* q,
                              const double* s, double tol, int max_iter, const float* Y0,
                              float* X, int32_t* iters, double* kkt, int32_t* status,
-                             int64_t* rows_read, void* ws, hipStream_t st);
+                             int64_t* rows_read, float* trace, int trace_len, void* ws,
+                             hipStream_t st);
 
 // refine.hip
 size_t refine_ws_bytes(int64_t d, int64_t n, int64_t k);

@@ -29,6 +29,8 @@ struct SolveCol {
   T* w;            // workspace [n]: Q gbar of the current pass
   T* x;            // output entries x[i * qs]
   const double* s; // scales or nullptr
+  float* trace;    // [trace_len][2] per-update record of this column, or nullptr
+  int trace_len;
 };
 
 // sum over the compacted list (idx, val) of val_m * Q[idx_m, i]: row idx_m of Q is read at
@@ -151,6 +153,10 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
     }
     const double r = (double)(sqrt(res) / scale);
     r_final = r;
+    if (P.trace != nullptr && tid == 0 && it < P.trace_len) {
+      P.trace[2 * it] = (float)r;
+      P.trace[2 * it + 1] = (float)num;
+    }
     if (total == 0 || r <= tol) {
       if (fresh) {
         status = NNLS_CONVERGED_DEV;

@@ -33,6 +33,8 @@ struct MrArgs {
   double* kkt;
   int32_t* status;
   int64_t* rows_read;
+  float* trace;  // [k][trace_len][2] per-update record (r, ||gbar||^2), or nullptr
+  int trace_len;
   int* queue;  // next unassigned column (starts at 16 * gridDim.x)
 };
 
@@ -314,6 +316,11 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
       const int col = s_col[tid];
       if (col >= 0 && !s_done[tid]) {
         const double r = sqrt((double)s_res[tid]) / (double)s_qn[tid];
+        if (A.trace != nullptr && s_it[tid] < A.trace_len) {
+          float* tr = A.trace + ((int64_t)col * A.trace_len + s_it[tid]) * 2;
+          tr[0] = (float)r;
+          tr[1] = s_num[tid];
+        }
         int st = -1;
         if (s_bad[tid] > 0.f) {
           st = NNLS_NONFINITE_DEV;
@@ -493,7 +500,8 @@ size_t solve_mrhs_ws_bytes() { return 256; }
 hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* q,
                              const double* s, double tol, int max_iter, const float* Y0,
                              float* X, int32_t* iters, double* kkt, int32_t* status,
-                             int64_t* rows_read, void* ws, hipStream_t st) {
+                             int64_t* rows_read, float* trace, int trace_len, void* ws,
+                             hipStream_t st) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -531,6 +539,8 @@ hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* 
   A.kkt = kkt;
   A.status = status;
   A.rows_read = rows_read;
+  A.trace = trace;
+  A.trace_len = trace_len;
   A.queue = (int*)ws;
   hipLaunchKernelGGL(solve_mrhs_queue_init, dim3(1), dim3(64), 0, st, A.queue,
                      (int)(groups * MR_SLOTS));

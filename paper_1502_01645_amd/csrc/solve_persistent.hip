@@ -52,6 +52,8 @@ struct SpArgs {
   double* kkt;
   int32_t* status;
   int64_t* rows_read;
+  float* trace;  // [trace_len][2] per-update record (r, ||gbar||^2), or nullptr
+  int trace_len;
   // workspace; y, g, p, t and the masks have two copies selected by iteration parity
   float *y[2], *g[2], *p[2], *t[2];  // t: clip threshold y_i / gbar_i, +inf if i cannot clip
   uint64_t *pmask[2], *ymask[2];
@@ -376,6 +378,10 @@ __global__ __launch_bounds__(SP_NT) void solve_persistent_kernel(SpArgs A) {
       break;
     }
     r_now = sqrt((double)res) / qscale;
+    if (A.trace != nullptr && blockIdx.x == 0 && threadIdx.x == 0 && it < A.trace_len) {
+      A.trace[2 * it] = (float)r_now;
+      A.trace[2 * it + 1] = num;
+    }
     if (npass == 0.f || r_now <= A.tol) {
       if (fresh) {
         status = NNLS_CONVERGED_DEV;
@@ -544,7 +550,8 @@ size_t solve_persistent_ws_bytes(int64_t n) {
 hipError_t launch_solve_persistent(int64_t n, const float* Q, const float* q, const double* s,
                                    double tol, int max_iter, const float* Y0, float* X,
                                    int32_t* iters, double* kkt, int32_t* status,
-                                   int64_t* rows_read, void* ws, hipStream_t st) {
+                                   int64_t* rows_read, float* trace, int trace_len, void* ws,
+                                   hipStream_t st) {
   const SpPlan P = sp_plan(n, sp_device_cus());
   SpArgs A;
   A.n = (int)n;
@@ -564,6 +571,8 @@ hipError_t launch_solve_persistent(int64_t n, const float* Q, const float* q, co
   A.kkt = kkt;
   A.status = status;
   A.rows_read = rows_read;
+  A.trace = trace;
+  A.trace_len = trace_len;
   A.spin_limit = spin_limit_setting();
   char* p = (char*)ws;
   auto take = [&](size_t bytes) {

@@ -44,6 +44,8 @@ struct RqArgs {
   double* kkt;
   int32_t* status;
   int64_t* rows_read;
+  float* trace;  // [trace_len][2] per-update record (r, ||gbar||^2), or nullptr
+  int trace_len;
   float* gf;     // [CS NT] masked gradient of the current iterate, written by the row owners
                  // (entries past n stay zero)
   float* sf;     // [8 G] statistics partials
@@ -310,6 +312,10 @@ __global__ __launch_bounds__(NT, 1) void solve_regq_kernel(RqArgs A) {
       break;
     }
     r_now = sqrt((double)res) / qscale;
+    if (A.trace != nullptr && blockIdx.x == 0 && t == 0 && it < A.trace_len) {
+      A.trace[2 * it] = (float)r_now;
+      A.trace[2 * it + 1] = num;
+    }
     if (npass == 0.f || r_now <= A.tol) {
       if (fresh) {
         status = NNLS_CONVERGED_DEV;
@@ -498,8 +504,8 @@ size_t solve_regq_ws_bytes(int64_t n) {
 
 hipError_t launch_solve_regq(int64_t n, const float* Q, const float* q, const double* s,
                              double tol, int max_iter, const float* Y0, float* X, int32_t* iters,
-                             double* kkt, int32_t* status, int64_t* rows_read, void* ws,
-                             hipStream_t st) {
+                             double* kkt, int32_t* status, int64_t* rows_read, float* trace,
+                             int trace_len, void* ws, hipStream_t st) {
   const int G = rq_cus();
   const int pick = G > 0 ? rq_pick(n, G) : -1;
   if (pick < 0) return hipErrorInvalidValue;
@@ -517,6 +523,8 @@ hipError_t launch_solve_regq(int64_t n, const float* Q, const float* q, const do
   A.kkt = kkt;
   A.status = status;
   A.rows_read = rows_read;
+  A.trace = trace;
+  A.trace_len = trace_len;
   char* p = (char*)ws;
   auto take = [&](size_t bytes) {
     char* r = p;

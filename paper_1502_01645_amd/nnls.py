@@ -54,9 +54,9 @@ def lib():
                                    _vp, _vp, _vp, _vp, _sz, _vp]
         L.nnls_prepare.restype = ctypes.c_int
         L.nnls_solve.argtypes = [_i64, _i64, ctypes.c_int, _vp, _vp, _vp, ctypes.c_double, _i32, _vp,
-                                 _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+                                 _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _sz, _vp]
         L.nnls_solve_noalloc.argtypes = [_i64, _i64, ctypes.c_int, _vp, _vp, _vp, ctypes.c_double,
-                                         _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+                                         _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]
         L.nnls_solve_noalloc.restype = ctypes.c_int
         L.nnls_column_scales.argtypes = [_i64, _i64, _vp, _i64, ctypes.c_int, _vp, _vp, _sz, _vp]
         L.nnls_column_scales.restype = ctypes.c_int
@@ -275,9 +275,11 @@ def rescale_start(s: torch.Tensor, X: torch.Tensor, out=None) -> torch.Tensor:
 
 
 def solve(Q: torch.Tensor, q: torch.Tensor, s: torch.Tensor | None = None, tol: float = 1e-5,
-          max_iter: int = 0, Y0: torch.Tensor | None = None, out=None, ws=None, rows_read=None):
+          max_iter: int = 0, Y0: torch.Tensor | None = None, out=None, ws=None, rows_read=None,
+          trace=None):
     """Algorithm 2 on every column of q, then x = y / s.  Returns (X, iters, kkt, status).
-    rows_read (optional int64 [k] tensor) receives the rows of Q the products read."""
+    rows_read (optional int64 [k] tensor) receives the rows of Q the products read; trace
+    (optional FP32 [k, T, 2] tensor) the per-update record (r, ||gbar||^2) for t < T."""
     n = Q.shape[0]
     if q.dim() == 1:
         q = q.reshape(n, 1)
@@ -296,15 +298,24 @@ def solve(Q: torch.Tensor, q: torch.Tensor, s: torch.Tensor | None = None, tol: 
         X, iters, kkt, status = out
     wsb = workspace_bytes(OP_SOLVE, 0, n, k, 0, dt)
     ws = _workspace(wsb, Q.device, ws)
+    tl = _trace_len(trace, k)
     rc = lib().nnls_solve(n, k, dt, _ptr(Q), _ptr(q), _ptr(s), float(tol), int(max_iter), _ptr(Y0),
-                          _ptr(X), _ptr(iters), _ptr(kkt), _ptr(status), _ptr(rows_read), _ptr(ws),
-                          wsb, _stream(Q.device))
+                          _ptr(X), _ptr(iters), _ptr(kkt), _ptr(status), _ptr(rows_read),
+                          _ptr(trace), tl, _ptr(ws), wsb, _stream(Q.device))
     _check(rc, "nnls_solve")
     return X, iters, kkt, status
 
 
+def _trace_len(trace, k):
+    if trace is None:
+        return 0
+    assert trace.dtype == torch.float32 and trace.is_contiguous()
+    assert trace.dim() == 3 and trace.shape[0] == k and trace.shape[2] == 2
+    return int(trace.shape[1])
+
+
 def solve_noalloc(Q: torch.Tensor, q: torch.Tensor, s: torch.Tensor | None, tol: float,
-                  max_iter: int, Y0: torch.Tensor | None, out, rows_read=None):
+                  max_iter: int, Y0: torch.Tensor | None, out, rows_read=None, trace=None):
     """nnls_solve_noalloc: as solve(), with the solver state in the library's fixed device
     array instead of a workspace.  The caller passes every output (out = (X, iters, kkt,
     status)); nothing is allocated here or in the library."""
@@ -320,7 +331,8 @@ def solve_noalloc(Q: torch.Tensor, q: torch.Tensor, s: torch.Tensor | None, tol:
     X, iters, kkt, status = out
     rc = lib().nnls_solve_noalloc(n, k, dt, _ptr(Q), _ptr(q), _ptr(s), float(tol), int(max_iter),
                                   _ptr(Y0), _ptr(X), _ptr(iters), _ptr(kkt), _ptr(status),
-                                  _ptr(rows_read), _stream(Q.device))
+                                  _ptr(rows_read), _ptr(trace), _trace_len(trace, k),
+                                  _stream(Q.device))
     _check(rc, "nnls_solve_noalloc")
     return X, iters, kkt, status
 

@@ -88,22 +88,28 @@ def test_solve_rejects_bad_arguments(L):
     from paper_1502_01645_amd import nnls as N
     big = 1 << 40
     base = dict(n=10, k=2, dt=N.F32, Q=FAKE, q=FAKE, tol=1e-5, mi=0, X=FAKE, it=FAKE, kkt=FAKE,
-                st=FAKE, ws=FAKE, wsb=big)
+                st=FAKE, tr=None, tl=0, ws=FAKE, wsb=big)
     cases = [dict(n=0), dict(k=0), dict(dt=3), dict(Q=None), dict(q=None), dict(X=None),
              dict(it=None), dict(kkt=None), dict(st=None), dict(tol=-1.0), dict(tol=float("nan")),
-             dict(tol=float("inf")), dict(mi=-1)]
+             dict(tol=float("inf")), dict(mi=-1), dict(tl=-1), dict(tr=FAKE, tl=0)]
     for c in cases:
         a = dict(base)
         a.update(c)
         rc = L.nnls_solve(a["n"], a["k"], a["dt"], a["Q"], a["q"], None, a["tol"], a["mi"], None,
-                          a["X"], a["it"], a["kkt"], a["st"], None, a["ws"], a["wsb"], None)
+                          a["X"], a["it"], a["kkt"], a["st"], None, a["tr"], a["tl"], a["ws"],
+                          a["wsb"], None)
         assert rc == N.E_ARG, c
     rc = L.nnls_solve(10, 2, N.F32, FAKE, FAKE, None, 1e-5, 0, None, FAKE, FAKE, FAKE, FAKE, None,
-                      FAKE, 4, None)
+                      None, 0, FAKE, 4, None)
     assert rc == N.E_WORKSPACE
     rc = L.nnls_solve(10, 2, N.F32, FAKE, FAKE, None, 1e-5, 0, None, FAKE, FAKE, FAKE, FAKE, None,
-                      None, big, None)
+                      None, 0, None, big, None)
     assert rc == N.E_WORKSPACE
+    # a trace with a length passes the checks (and a NULL trace ignores its length)
+    for tr, tl in [(FAKE, 5), (None, 7)]:
+        rc = L.nnls_solve(10, 2, N.F32, FAKE, FAKE, None, 1e-5, 0, None, FAKE, FAKE, FAKE, FAKE,
+                          None, tr, tl, FAKE, 4, None)
+        assert rc == N.E_WORKSPACE
 
 
 def test_split_prepare_rejects_bad_arguments(L):
@@ -148,7 +154,7 @@ def test_nmf_helpers_reject_bad_arguments(L):
 def test_solve_noalloc_rejects_bad_arguments_and_oversized_scratch(L):
     from paper_1502_01645_amd import nnls as N
     args = lambda n, k, dt, Q=FAKE, tol=1e-5: (n, k, dt, Q, FAKE, None, tol, 0, None, FAKE, FAKE,  # noqa
-                                               FAKE, FAKE, None, None)
+                                               FAKE, FAKE, None, None, 0, None)
     assert L.nnls_solve_noalloc(*args(0, 3, N.F32)) == N.E_ARG
     assert L.nnls_solve_noalloc(*args(10, 3, N.F32, Q=None)) == N.E_ARG
     assert L.nnls_solve_noalloc(*args(10, 3, N.F32, tol=-1.0)) == N.E_ARG
