@@ -222,32 +222,57 @@ __global__ __launch_bounds__(256) void mlp_loss_kernel(int64_t batch, const floa
   if (j == 0) loss_part[r] = l / (float)batch;
 }
 
-// out[j] = sum_r in[r, j] (FP32 or BF16 rows), one thread per column.
-template <typename TI>
-__global__ void colsum_kernel(int64_t rows, int64_t cols, const TI* __restrict__ in,
-                              float* __restrict__ out) {
+// Bias gradients out[j] = sum_r in[r, j] of a BF16 [rows, cols] matrix, in two stages so that
+// the sum over the batch is spread over many workgroups: stage 1, block (256 columns, chunk c of
+// the rows) sums its rows per column into part[c][j]; stage 2 adds the chunk partials of each
+// column in chunk order.  Chunks of max(32, ceil(rows / 64)) rows keep at most 64 partials.
+constexpr int64_t CS_MAX_CHUNKS = 64;
+static int64_t colsum_chunk_rows(int64_t rows) {
+  const int64_t r = (rows + CS_MAX_CHUNKS - 1) / CS_MAX_CHUNKS;
+  return r > 32 ? r : 32;
+}
+
+__global__ __launch_bounds__(256) void colsum_partial_kernel(int64_t rows, int64_t cols,
+                                                             int64_t chunk_rows,
+                                                             const bf16_t* __restrict__ in,
+                                                             float* __restrict__ part) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= cols) return;
+  const int64_t r0 = (int64_t)blockIdx.y * chunk_rows;
+  const int64_t r1 = r0 + chunk_rows < rows ? r0 + chunk_rows : rows;
   float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-  int64_t r = 0;
-  for (; r + 3 < rows; r += 4) {
-    if constexpr (sizeof(TI) == 2) {
-      a0 += from_bf16(in[(r + 0) * cols + j]);
-      a1 += from_bf16(in[(r + 1) * cols + j]);
-      a2 += from_bf16(in[(r + 2) * cols + j]);
-      a3 += from_bf16(in[(r + 3) * cols + j]);
-    } else {
-      a0 += in[(r + 0) * cols + j];
-      a1 += in[(r + 1) * cols + j];
-      a2 += in[(r + 2) * cols + j];
-      a3 += in[(r + 3) * cols + j];
-    }
+  int64_t r = r0;
+  for (; r + 7 < r1; r += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = from_bf16(in[(r + u) * cols + j]);
+    a0 += v[0] + v[4];
+    a1 += v[1] + v[5];
+    a2 += v[2] + v[6];
+    a3 += v[3] + v[7];
   }
-  for (; r < rows; ++r) {
-    if constexpr (sizeof(TI) == 2) a0 += from_bf16(in[r * cols + j]);
-    else a0 += in[r * cols + j];
-  }
-  out[j] = (a0 + a1) + (a2 + a3);
+  for (; r < r1; ++r) a0 += from_bf16(in[r * cols + j]);
+  part[(int64_t)blockIdx.y * cols + j] = (a0 + a1) + (a2 + a3);
+}
+
+__global__ __launch_bounds__(256) void colsum_finish_kernel(int64_t chunks, int64_t cols,
+                                                            const float* __restrict__ part,
+                                                            float* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= cols) return;
+  float a = 0.f;
+  for (int64_t c = 0; c < chunks; ++c) a += part[c * cols + j];
+  out[j] = a;
+}
+
+static void colsum(int64_t rows, int64_t cols, const bf16_t* in, float* part, float* out,
+                   hipStream_t st) {
+  const int64_t cr = colsum_chunk_rows(rows);
+  const int64_t chunks = (rows + cr - 1) / cr;
+  hipLaunchKernelGGL(colsum_partial_kernel, dim3((unsigned)((cols + 255) / 256), (unsigned)chunks),
+                     dim3(256), 0, st, rows, cols, cr, in, part);
+  hipLaunchKernelGGL(colsum_finish_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, st,
+                     chunks, cols, (const float*)part, out);
 }
 
 __global__ void sum_kernel(int64_t count, const float* __restrict__ in, float* __restrict__ out) {
@@ -288,7 +313,7 @@ __global__ void reset_state_kernel(int64_t count, const float* __restrict__ w,
 // ---- workspace layout ------------------------------------------------------------------------
 struct MlpWs {
   bf16_t *X, *A1, *A2, *dZ, *dH2, *dH1;
-  float *H1, *H2, *Z, *grad, *loss_part, *loss;
+  float *H1, *H2, *Z, *grad, *loss_part, *loss, *colpart;
 };
 
 static size_t al(size_t v) { return (v + 255) / 256 * 256; }
@@ -315,6 +340,7 @@ static MlpWs mlp_layout(void* ws, int64_t batch, bool train, size_t* total) {
     W.grad = (float*)take(4 * ML_P);
     W.loss_part = (float*)take(4 * batch);
     W.loss = (float*)take(4);
+    W.colpart = (float*)take(4 * CS_MAX_CHUNKS * ML_H);
   }
   if (total) *total = off;
   return W;
@@ -362,22 +388,19 @@ static void backward(int64_t batch, const void* blob, const float* target, float
   // layer 3: dW3 = A2^T dZ, db3 = colsum dZ, dA2 = dZ W3^T -> dH2 = dA2 * gelu'(H2)
   GemmEpi g3{W.grad + ML_W3, nullptr, nullptr, nullptr, ML_OUT};
   gemm<true, false, EPI_F32>(ML_H, ML_OUT, M, W.A2, ML_H, W.dZ, ML_OUT, g3, st);
-  hipLaunchKernelGGL(colsum_kernel<bf16_t>, dim3((ML_OUT + 255) / 256), dim3(256), 0, st, batch,
-                     (int64_t)ML_OUT, (const bf16_t*)W.dZ, W.grad + ML_B3);
+  colsum(batch, ML_OUT, W.dZ, W.colpart, W.grad + ML_B3, st);
   GemmEpi d2{nullptr, W.dH2, nullptr, W.H2, ML_H};
   gemm<false, true, EPI_GELU_BWD>(M, ML_H, ML_OUT, W.dZ, ML_OUT, Wb + ML_W3, ML_OUT, d2, st);
   // layer 2
   GemmEpi g2{W.grad + ML_W2, nullptr, nullptr, nullptr, ML_H};
   gemm<true, false, EPI_F32>(ML_H, ML_H, M, W.A1, ML_H, W.dH2, ML_H, g2, st);
-  hipLaunchKernelGGL(colsum_kernel<bf16_t>, dim3((ML_H + 255) / 256), dim3(256), 0, st, batch,
-                     (int64_t)ML_H, (const bf16_t*)W.dH2, W.grad + ML_B2);
+  colsum(batch, ML_H, W.dH2, W.colpart, W.grad + ML_B2, st);
   GemmEpi d1{nullptr, W.dH1, nullptr, W.H1, ML_H};
   gemm<false, true, EPI_GELU_BWD>(M, ML_H, ML_H, W.dH2, ML_H, Wb + ML_W2, ML_H, d1, st);
   // layer 1
   GemmEpi g1{W.grad + ML_W1, nullptr, nullptr, nullptr, ML_H};
   gemm<true, false, EPI_F32>(ML_IN, ML_H, M, W.X, ML_IN, W.dH1, ML_H, g1, st);
-  hipLaunchKernelGGL(colsum_kernel<bf16_t>, dim3((ML_H + 255) / 256), dim3(256), 0, st, batch,
-                     (int64_t)ML_H, (const bf16_t*)W.dH1, W.grad + ML_B1);
+  colsum(batch, ML_H, W.dH1, W.colpart, W.grad + ML_B1, st);
 }
 
 // ---- warm start ------------------------------------------------------------------------------

@@ -169,16 +169,23 @@ def make_warm_matrix(d: int = 4096, n: int = 256, dtype=np.float32):
     return np.abs(rng.standard_normal((d, n))).astype(dtype)
 
 
-def make_warm_rhs(A: np.ndarray, count: int, split: int, start: int = 0, dtype=np.float32):
-    """Noiseless right-hand sides b = A x for the warm-start workload.  split 0 = training set,
-    split 1 = held-out evaluation set.  Column j of the result is sample start + j of its split
-    (each sample has its own counter-derived stream, so any slice can be drawn alone)."""
-    d, n = A.shape
+def make_warm_codes(n: int, count: int, split: int, start: int = 0) -> np.ndarray:
+    """Codes x [n, count] of the warm-start workload (85 % zeros, Gamma(1.5, 1) nonzeros).
+    split 0 = training set, split 1 = held-out evaluation set.  Column j is sample start + j of
+    its split (each sample has its own counter-derived stream, so any slice can be drawn
+    alone)."""
     n_zero = int(round(0.85 * n))
     X = np.zeros((n, count), dtype=np.float64)
     for j in range(count):
         rng = np.random.default_rng(np.random.SeedSequence([5, split, start + j]))
         X[:, j] = _zero_pattern(rng, n, n_zero, lambda m: rng.gamma(1.5, 1.0, m))
+    return X
+
+
+def make_warm_rhs(A: np.ndarray, count: int, split: int, start: int = 0, dtype=np.float32):
+    """Noiseless right-hand sides b = A x for the warm-start workload (codes from
+    make_warm_codes), b formed in FP64 and rounded to dtype."""
+    X = make_warm_codes(A.shape[1], count, split, start)
     B = A.astype(np.float64) @ X
     return B.astype(dtype), X
 
