@@ -211,10 +211,15 @@ int nnls_refine(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, con
 
 /*
  * Uneven batch: many independent problems (each Problem (1) with its own A_i [d_i, n_i] and a
- * single right-hand side b_i), solved by Algorithm 1 each, as one captured hipGraph (a batched
- * Gram with the rescale of Problem (5), then a resident grid that takes problems from an atomic
- * queue in longest-first order and runs Algorithm 2 on each).  FP32 data, BF16x3 Gram,
- * n_i <= 1024.
+ * single right-hand side b_i), solved by Algorithm 1 each, as one captured hipGraph: a batched
+ * Gram with the rescale of Problem (5) (every tile of every problem an independent work item:
+ * first the diagonal tiles, which give the scales, then the others), then per solver class a
+ * resident grid that takes its problems from an atomic queue in longest-first order and runs
+ * Algorithm 2 on each.  FP32 data, BF16x3 Gram, n_i <= 1024.
+ *
+ * Problems fall in size classes by n (n <= 64, 128, 256, 512, 1024); each class has a Gram tile
+ * size (64 or 128) and a solver workgroup size (256, 512 or 1024 threads), the defaults (128,
+ * 256) or the ones nnls_autotune measured fastest on this device.
  *
  * Pools are caller-owned device arrays; descriptor offsets are element offsets into them:
  *   A_pool  FP32, problem i's A_i row-major [d_i, n_i] at offA
@@ -231,25 +236,55 @@ typedef struct {
 } nnls_problem_desc;
 typedef struct nnls_plan nnls_plan;
 
-/* Device workspace bytes a plan over these problems needs (descriptors, order, queue and three
- * FP32 vectors per unknown); 0 for invalid arguments.  Host function. */
+/* Device workspace bytes a plan over these problems needs (descriptors, Gram work items, queue
+ * orders and counters, three FP32 vectors per unknown); 0 for invalid arguments.  Host
+ * function. */
 size_t nnls_batched_workspace_bytes(const nnls_problem_desc* host_desc, int64_t count);
 
-/* Validates the descriptors, copies them and the longest-first order into `ws` (a blocking
- * host-to-device copy, done once here), captures the graph on capture_stream (a created stream,
- * not the null stream) and instantiates it.  The workspace must stay allocated and unused by other calls while the plan lives.
- * tol and max_iter as for nnls_solve (max_iter 0: 5 n_i per problem). */
+/* Validates the descriptors, copies them, the Gram work items and the longest-first orders into
+ * `ws` (blocking host-to-device copies, done once here), captures the graph on capture_stream (a
+ * created stream, not the null stream) and instantiates it.  The workspace must stay allocated
+ * and unused by other calls while the plan lives.  tol and max_iter as for nnls_solve (max_iter
+ * 0: 5 n_i per problem).  tune_cache: path of a cache written by nnls_autotune, or NULL; its
+ * entries for this device's architecture set the per-class parameters (a missing or unreadable
+ * file leaves the defaults). */
 int nnls_batched_plan_create(const nnls_problem_desc* host_desc, int64_t count, double tol,
-                             int32_t max_iter, const float* A_pool, const float* B_pool,
-                             float* Q_pool, float* q_pool, double* s_pool, float* X_pool,
-                             int32_t* iters, double* kkt, int32_t* status, int64_t* rows_read,
-                             void* ws, size_t ws_bytes, void* capture_stream, nnls_plan** out);
+                             int32_t max_iter, const char* tune_cache, const float* A_pool,
+                             const float* B_pool, float* Q_pool, float* q_pool, double* s_pool,
+                             float* X_pool, int32_t* iters, double* kkt, int32_t* status,
+                             int64_t* rows_read, void* ws, size_t ws_bytes, void* capture_stream,
+                             nnls_plan** out);
 
 /* One launch of the plan's graph on `stream` (asynchronous). */
 int nnls_batched_plan_launch(nnls_plan* plan, void* stream);
 
 /* Releases the plan's graph (not the pools or the workspace). */
 void nnls_batched_plan_destroy(nnls_plan* plan);
+
+/* Operations nnls_autotune can tune. */
+enum nnls_tune_op {
+    NNLS_TUNE_BATCHED = 1  /* the uneven batch: Gram tile size and solver workgroup size */
+};
+
+/*
+ * nnls_autotune -- measures, on this device, the per-size-class parameters of operation `op`
+ * for problems of the given shapes and records the fastest in the JSON cache file cache_path
+ * (created or updated; entries are keyed by architecture, operation, size class and dtype, and
+ * an entry measured now replaces the old one with its key; the file is written to a temporary
+ * name and renamed, and reads and writes of cache files in one process are serialised).
+ *   shapes  host array of `count` pairs (d_i, n_i), 1 <= n_i <= 1024, d_i <= 16384: the
+ *           problems the tuned plans will see (each class is measured on up to 256 of them).
+ * For NNLS_TUNE_BATCHED each class present is timed with HIP events on synthetic problems of
+ * its shapes (A U[0, 1], x 60 % zeros else U[0, 1], b = A x with 1 % noise, drawn on the device
+ * from SplitMix64): the batched Gram at tile sizes 64 and 128, then the batched solver at 256,
+ * 512 and 1024 threads per workgroup (tolerance 5e-6, at most 20000 updates), best of 3 runs
+ * after a warm-up each.  Unlike the other calls this one is a setup step: it allocates and
+ * frees its own device memory and synchronises `stream`.  Errors: NNLS_E_ARG (bad pointers,
+ * shapes or op, or the cache could not be written), NNLS_E_UNSUPPORTED (n_i > 1024 or
+ * d_i > 16384), NNLS_E_HIP.
+ */
+int nnls_autotune(const char* cache_path, int op, const int64_t* shapes, int64_t count,
+                  void* stream);
 
 /* ---- Learned warm start --------------------------------------------------------------------
  * Algorithm 2 may start from any y0 >= 0 (the worked example of Section 3 starts from a nonzero

@@ -10,8 +10,8 @@
 //               q = -A^T B / s, and mirrors the tile into the lower triangle.  Split-K over the
 //               rows of A fills the GPU when there are few tiles; the partial tiles then go
 //               through gram_splitk_epilogue.
-//   batched     one workgroup per problem of an uneven batch, 128 x 128 tiles split while they
-//               are staged (gram_tile_bf16x3).
+//   batched     the tiles of an uneven batch of problems as independent work items, 64 x 64 or
+//               128 x 128 by size class, split while they are staged (gram_tile_bf16x3).
 //   gram_fma    the same product with plain FMAs in FP32 or FP64 (FP64 problems and the FP32
 //               accuracy cross-check).
 #include <algorithm>
@@ -118,24 +118,33 @@ __device__ __forceinline__ void decode_tile(int tile, int tiles_aug, int& ti, in
 }
 
 // ---------------------------------------------------------------------------------------------
-// BF16x3 Gram on the matrix cores.  128 x 128 tile per workgroup of 4 waves (2 x 2 waves of
-// 64 x 64), K staged 32 rows at a time through a two-slot LDS ring: while the waves run the
-// MFMAs of slot s, the next chunk (already in registers) is converted and written to slot s^1
-// and the chunk after it is fetched from memory, so one barrier per K step suffices.
-// LDS holds the hi and lo parts of both panels, column-major (32 consecutive k of one column
-// contiguous, padded to 40 bf16 = 80 bytes so the 16-byte accesses of 16 consecutive lanes hit
-// distinct banks).  The split uses the hardware packed conversion (round to nearest even).
+// BF16x3 Gram on the matrix cores for the uneven batch: a BM x BM tile (BM = 64 or 128) per
+// workgroup of 4 waves (2 x 2 waves of BM/2 x BM/2), K staged 32 rows at a time through a
+// two-slot LDS ring: while the waves run the MFMAs of slot s, the next chunk (already in
+// registers) is converted and written to slot s^1 and the chunk after it is fetched from
+// memory, so one barrier per K step suffices.  LDS holds the hi and lo parts of both panels,
+// column-major (32 consecutive k of one column contiguous, padded to 40 bf16 = 80 bytes so the
+// 16-byte accesses of 16 consecutive lanes hit distinct banks).  The split uses the hardware
+// packed conversion (round to nearest even).
 //
-// Tile schedule: workgroup b runs on XCD b % 8 (round-robin dispatch).  Tiles are grouped in
-// blocks of 4 tile rows x 8 tile columns; group g belongs to XCD g % 8, so the ~32 tiles an XCD
-// runs at a time read 4 + 8 panels through its own L2 instead of up to 64.
+// The single-problem schedule (gram_dma below) deals its tiles to XCDs in groups of 4 tile rows
+// x 8 tile columns, so the ~32 tiles an XCD runs at a time read 4 + 8 panels through its own L2
+// instead of up to 64.
 // ---------------------------------------------------------------------------------------------
-constexpr int GB_BM = 128;
 constexpr int GB_BK = 32;
 constexpr int GB_LDK = 40;  // padded k stride in bf16 units
-constexpr int GB_PANEL = GB_BM * GB_LDK;     // bf16 per panel part (hi or lo)
-constexpr int GB_SLOT = 4 * GB_PANEL;        // Xh, Xl, Yh, Yl
-constexpr int GB_LDS_BYTES = 2 * GB_SLOT * 2;
+
+template <int BM>
+struct GbTile {
+  static constexpr int MT = BM / 32;        // 16 x 16 blocks per wave in each direction
+  static constexpr int TPC = 256 / BM;      // threads staging one panel column
+  static constexpr int RPT = GB_BK / TPC;   // rows of a K chunk one staging thread loads
+  static constexpr int PANEL = BM * GB_LDK; // bf16 per panel part (hi or lo)
+  static constexpr int SLOT = 4 * PANEL;    // Xh, Xl, Yh, Yl
+  static constexpr int LDS_BYTES = 2 * SLOT * 2;
+  static_assert(BM == 64 || BM == 128, "tile size");
+  static_assert(RPT % 8 == 0 && RPT / 2 == 2 * MT, "staging split interleave");
+};
 constexpr int GB_GROUP_ROWS = 4;
 constexpr int GB_GROUP_COLS = 8;
 constexpr int GB_XCDS = 8;
@@ -232,28 +241,31 @@ static int schedule_blocks(int ntiles, int splits) {
   return (items + GB_XCDS - 1) / GB_XCDS * GB_XCDS;
 }
 
-// One 128 x 128 tile of [A | B]^T [A | B] over rows [r_begin, r_end): px / py locate the two
+// One BM x BM tile of [A | B]^T [A | B] over rows [r_begin, r_end): px / py locate the two
 // panels (this thread's column of each), diag marks px == py.  Leaves the FP32 accumulators in
 // acc (16x16 MFMA D layout) and LDS free for reuse.  Called by all 256 threads.
-__device__ __forceinline__ void gram_tile_bf16x3(f32x4 (&acc)[4][4], int64_t r_begin,
-                                                 int64_t r_end, GramPanelPtr px, GramPanelPtr py,
-                                                 bool diag, uint16_t* lds) {
+template <int BM>
+__device__ __forceinline__ void gram_tile_bf16x3(f32x4 (&acc)[BM / 32][BM / 32],
+                                                 int64_t r_begin, int64_t r_end, GramPanelPtr px,
+                                                 GramPanelPtr py, bool diag, uint16_t* lds) {
+  using G = GbTile<BM>;
+  constexpr int MT = G::MT, RPT = G::RPT, NP = RPT / 2;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int lc = tid & 127;     // column of the panel this thread stages
-  const int kh = tid >> 7;      // which 16-row half of the K chunk
+  const int lc = tid % BM;      // column of the panel this thread stages
+  const int kh = tid / BM;      // which RPT-row part of the K chunk
 
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < MT; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  float rx[16], ry[16];
+  float rx[RPT], ry[RPT];
   auto load_chunk = [&](int64_t r0) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int64_t r = r0 + kh * 16 + u;
+    for (int u = 0; u < RPT; ++u) {
+      const int64_t r = r0 + kh * RPT + u;
       const bool ok = r < r_end;
       rx[u] = (ok && px.base) ? px.base[r * px.ld] : 0.f;
       ry[u] = (!diag && ok && py.base) ? py.base[r * py.ld] : 0.f;
@@ -268,24 +280,27 @@ __device__ __forceinline__ void gram_tile_bf16x3(f32x4 (&acc)[4][4], int64_t r_b
     h = __builtin_bit_cast(uint32_t, hb);
     l = __builtin_bit_cast(uint32_t, lb);
   };
-  uint32_t hx[8], lx[8], hy[8], ly[8];
+  uint32_t hx[NP], lx[NP], hy[NP], ly[NP];
   auto write_chunk = [&](int slot) {
-    uint16_t* base = lds + slot * GB_SLOT;
-    const int off = lc * GB_LDK + kh * 16;
-    *(u32x4*)&base[off] = (u32x4){hx[0], hx[1], hx[2], hx[3]};
-    *(u32x4*)&base[off + 8] = (u32x4){hx[4], hx[5], hx[6], hx[7]};
-    *(u32x4*)&base[GB_PANEL + off] = (u32x4){lx[0], lx[1], lx[2], lx[3]};
-    *(u32x4*)&base[GB_PANEL + off + 8] = (u32x4){lx[4], lx[5], lx[6], lx[7]};
-    if (!diag) {
-      *(u32x4*)&base[2 * GB_PANEL + off] = (u32x4){hy[0], hy[1], hy[2], hy[3]};
-      *(u32x4*)&base[2 * GB_PANEL + off + 8] = (u32x4){hy[4], hy[5], hy[6], hy[7]};
-      *(u32x4*)&base[3 * GB_PANEL + off] = (u32x4){ly[0], ly[1], ly[2], ly[3]};
-      *(u32x4*)&base[3 * GB_PANEL + off + 8] = (u32x4){ly[4], ly[5], ly[6], ly[7]};
+    uint16_t* base = lds + slot * G::SLOT;
+    const int off = lc * GB_LDK + kh * RPT;
+#pragma unroll
+    for (int v = 0; v < NP / 4; ++v) {
+      const int o = off + 8 * v;
+      *(u32x4*)&base[o] = (u32x4){hx[4 * v], hx[4 * v + 1], hx[4 * v + 2], hx[4 * v + 3]};
+      *(u32x4*)&base[G::PANEL + o] =
+          (u32x4){lx[4 * v], lx[4 * v + 1], lx[4 * v + 2], lx[4 * v + 3]};
+      if (!diag) {
+        *(u32x4*)&base[2 * G::PANEL + o] =
+            (u32x4){hy[4 * v], hy[4 * v + 1], hy[4 * v + 2], hy[4 * v + 3]};
+        *(u32x4*)&base[3 * G::PANEL + o] =
+            (u32x4){ly[4 * v], ly[4 * v + 1], ly[4 * v + 2], ly[4 * v + 3]};
+      }
     }
   };
 
-  const int wm = (wave >> 1) * 64;
-  const int wn = (wave & 1) * 64;
+  const int wm = (wave >> 1) * (BM / 2);
+  const int wn = (wave & 1) * (BM / 2);
   const int frag_row = lane & 15;
   const int frag_k = (lane >> 4) * 8;
 
@@ -293,7 +308,7 @@ __device__ __forceinline__ void gram_tile_bf16x3(f32x4 (&acc)[4][4], int64_t r_b
   if (nsteps > 0) {
     load_chunk(r_begin);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < NP; ++u) {
       split_pair(rx[2 * u], rx[2 * u + 1], hx[u], lx[u]);
       split_pair(ry[2 * u], ry[2 * u + 1], hy[u], ly[u]);
     }
@@ -303,13 +318,13 @@ __device__ __forceinline__ void gram_tile_bf16x3(f32x4 (&acc)[4][4], int64_t r_b
   }
   for (int64_t step = 0; step < nsteps; ++step) {
     const int slot = (int)(step & 1);
-    const uint16_t* xh = lds + slot * GB_SLOT;
-    const uint16_t* xl = xh + GB_PANEL;
-    const uint16_t* yh = diag ? xh : xh + 2 * GB_PANEL;
-    const uint16_t* yl = diag ? xl : xh + 3 * GB_PANEL;
-    bf16x8 ah[4], al[4], bh[4], bl[4];
+    const uint16_t* xh = lds + slot * G::SLOT;
+    const uint16_t* xl = xh + G::PANEL;
+    const uint16_t* yh = diag ? xh : xh + 2 * G::PANEL;
+    const uint16_t* yl = diag ? xl : xh + 3 * G::PANEL;
+    bf16x8 ah[MT], al[MT], bh[MT], bl[MT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < MT; ++t) {
       const int xo = (wm + t * 16 + frag_row) * GB_LDK + frag_k;
       const int yo = (wn + t * 16 + frag_row) * GB_LDK + frag_k;
       ah[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&xh[xo]);
@@ -322,25 +337,24 @@ __device__ __forceinline__ void gram_tile_bf16x3(f32x4 (&acc)[4][4], int64_t r_b
     // last step the staged registers hold stale values; converting and writing them to the
     // idle slot is harmless.)
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < MT; ++a) {
 #pragma unroll
       for (int u = 2 * a; u < 2 * a + 2; ++u) {
         split_pair(rx[2 * u], rx[2 * u + 1], hx[u], lx[u]);
         split_pair(ry[2 * u], ry[2 * u + 1], hy[u], ly[u]);
       }
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
+      for (int b = 0; b < MT; ++b) {
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
       }
       // the staged registers are free once the last pair is split
-      if (a == 3 && step + 2 < nsteps) load_chunk(r_begin + (step + 2) * GB_BK);
+      if (a == MT - 1 && step + 2 < nsteps) load_chunk(r_begin + (step + 2) * GB_BK);
     }
     write_chunk(slot ^ 1);
     __syncthreads();
   }
-
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -600,114 +614,134 @@ __global__ __launch_bounds__(GD_NT, 1) void gram_dma_kernel(
 }
 
 // ---------------------------------------------------------------------------------------------
-// Uneven batch: one workgroup per problem walks that problem's tiles of [A | b]^T [A | b] with
-// the same BF16x3 tile routine.  Diagonal tiles go first; each yields the scales of its block
-// from its own diagonal (s_i = sqrt(H_ii), 1 where H_ii = 0), which the off-diagonal tiles and
-// the right-hand side column then use in the rescale epilogue.
+// Uneven batch.  The work items are tiles (problem p, ti, tj) of p's [A | b]^T [A | b] at the
+// tile size BM of p's size class, in two launches: the diagonal tiles first, each of which
+// yields the scales of its block from its own computed diagonal (s_i = sqrt(H_ii), 1 where
+// H_ii = 0) and emits its upper triangle rescaled; then the tiles above the diagonal (and the
+// right-hand-side column), which read the scales of both blocks back from s_pool.  Every tile is
+// an independent workgroup, so a large problem's tiles run side by side.
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ void batched_emit(int64_t i, int64_t j, float val, int64_t n,
-                                             const double* s_l, float* Q, float* q,
+                                             double si, double sj, float* Q, float* q,
                                              bool diag_tile) {
   if (i >= n) return;
   if (j < n) {
     if (diag_tile && i > j) return;
     float out;
     if (i == j) out = val > 0.f ? 1.f : 0.f;
-    else out = (float)((double)val / (s_l[i] * s_l[j]));
+    else out = (float)((double)val / (si * sj));
     Q[i * n + j] = out;
     if (i != j) Q[j * n + i] = out;
   } else if (j == n) {
-    q[i] = (float)(-(double)val / s_l[i]);
+    q[i] = (float)(-(double)val / si);
   }
 }
 
-constexpr int BG_MAX_N = 1024;
-
-__global__ __launch_bounds__(256, 1) void batched_gram_kernel(const BatchDesc* __restrict__ desc,
+template <int BM, bool DIAG>
+__global__ __launch_bounds__(256) void batched_gram_kernel(const BatchGramItem* __restrict__ items,
+                                                           const BatchDesc* __restrict__ desc,
                                                            const float* __restrict__ A_pool,
                                                            const float* __restrict__ B_pool,
                                                            float* __restrict__ Q_pool,
                                                            float* __restrict__ q_pool,
                                                            double* __restrict__ s_pool) {
   extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
-  double* s_l = (double*)((unsigned char*)lds + GB_LDS_BYTES);
-  float* dg = (float*)(s_l + BG_MAX_N);
-  const BatchDesc D = desc[blockIdx.x];
+  __shared__ double s_l[BM];
+  __shared__ float dg[BM];
+  const BatchGramItem it = items[blockIdx.x];
+  const BatchDesc D = desc[it.p];
   const int64_t n = D.n, d = D.d;
   const float* A = A_pool + D.offA;
   const float* B = B_pool + D.offB;
   float* Q = Q_pool + D.offQ;
   float* q = q_pool + D.offq;
-  const int T = (int)((n + GB_BM - 1) / GB_BM);
-  const int Taug = (int)((n + 1 + GB_BM - 1) / GB_BM);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, lc = tid & 127;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const double* sp = s_pool + D.offq;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int MT = BM / 32;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BM / 2);
   const int out_col = lane & 15, out_row = (lane >> 4) * 4;
-  f32x4 acc[4][4];
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int ti = 0; ti < T; ++ti) {
-      const int tj_lo = pass == 0 ? ti : ti + 1;
-      const int tj_hi = pass == 0 ? ti + 1 : Taug;
-      for (int tj = tj_lo; tj < tj_hi; ++tj) {
-        const bool diag = ti == tj;
-        const int64_t i0 = (int64_t)ti * GB_BM, j0 = (int64_t)tj * GB_BM;
-        const GramPanelPtr px = panel_column(i0 + lc, n, 1, A, n, B, 1);
-        const GramPanelPtr py = panel_column(j0 + lc, n, 1, A, n, B, 1);
-        gram_tile_bf16x3(acc, 0, d, px, py, diag, lds);
-        if (diag) {
-          // diagonal entries of the block -> scales
-          if (wm == wn) {
+  const int64_t i0 = (int64_t)it.ti * BM, j0 = (int64_t)it.tj * BM;
+  const GramPanelPtr px = panel_column(i0 + tid % BM, n, 1, A, n, B, 1);
+  const GramPanelPtr py = panel_column(j0 + tid % BM, n, 1, A, n, B, 1);
+  f32x4 acc[MT][MT];
+  gram_tile_bf16x3<BM>(acc, 0, d, px, py, DIAG, lds);
+  if (DIAG) {
+    // diagonal entries of the block -> scales of its rows
+    if (wm == wn) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-              const int e = out_col - out_row;
-              if (e >= 0 && e < 4) {
+      for (int a = 0; a < MT; ++a) {
+        const int e = out_col - out_row;
 #pragma unroll
-                for (int ee = 0; ee < 4; ++ee)
-                  if (ee == e) dg[wm + a * 16 + out_col] = acc[a][a][ee];
-              }
-            }
-          }
-          __syncthreads();
-          if (tid < GB_BM) {
-            const int64_t i = i0 + tid;
-            if (i < n) {
-              const float h = dg[tid];
-              const double si = h > 0.f ? sqrt((double)h) : 1.0;
-              s_l[i] = si;
-              s_pool[D.offq + i] = si;
-            }
-          }
-          __syncthreads();
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              batched_emit(i0 + wm + a * 16 + out_row + e, j0 + wn + b * 16 + out_col,
-                           acc[a][b][e], n, s_l, Q, q, diag);
+        for (int ee = 0; ee < 4; ++ee)
+          if (ee == e) dg[wm + a * 16 + out_col] = acc[a][a][ee];
       }
     }
+    __syncthreads();
+    if (tid < BM) {
+      const int64_t i = i0 + tid;
+      const float h = dg[tid];
+      const double si = h > 0.f ? sqrt((double)h) : 1.0;
+      s_l[tid] = si;
+      if (i < n) s_pool[D.offq + i] = si;
+    }
+    __syncthreads();
   }
+#pragma unroll
+  for (int a = 0; a < MT; ++a)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int li = wm + a * 16 + out_row + e;
+      const int64_t i = i0 + li;
+      if (i >= n) continue;
+      const double si = DIAG ? s_l[li] : sp[i];
+#pragma unroll
+      for (int b = 0; b < MT; ++b) {
+        const int lj = wn + b * 16 + out_col;
+        const int64_t j = j0 + lj;
+        const double sj = j < n ? (DIAG ? s_l[lj] : sp[j]) : 1.0;
+        batched_emit(i, j, acc[a][b][e], n, si, sj, Q, q, DIAG);
+      }
+    }
 }
 
-size_t batched_gram_lds_bytes() {
-  return GB_LDS_BYTES + sizeof(double) * BG_MAX_N + sizeof(float) * GB_BM;
+size_t batched_gram_lds_bytes(int bm) {
+  return bm == 64 ? (size_t)GbTile<64>::LDS_BYTES : (size_t)GbTile<128>::LDS_BYTES;
 }
 
 hipError_t prepare_batched_gram() {
-  return hipFuncSetAttribute((const void*)batched_gram_kernel,
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)batched_gram_lds_bytes());
+  hipError_t e = hipSuccess;
+  auto set = [&](const void* k, int bytes) {
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  };
+  set((const void*)batched_gram_kernel<64, true>, GbTile<64>::LDS_BYTES);
+  set((const void*)batched_gram_kernel<64, false>, GbTile<64>::LDS_BYTES);
+  set((const void*)batched_gram_kernel<128, true>, GbTile<128>::LDS_BYTES);
+  set((const void*)batched_gram_kernel<128, false>, GbTile<128>::LDS_BYTES);
+  return e;
 }
 
-hipError_t launch_batched_gram(const BatchDesc* desc, int64_t count, const float* A_pool,
-                               const float* B_pool, float* Q_pool, float* q_pool,
-                               double* s_pool, hipStream_t st) {
-  const size_t lds = batched_gram_lds_bytes();
-  hipLaunchKernelGGL(batched_gram_kernel, dim3((unsigned)count), dim3(256), lds, st, desc, A_pool,
-                     B_pool, Q_pool, q_pool, s_pool);
+hipError_t launch_batched_gram(int bm, bool diag, const BatchGramItem* items, int64_t count,
+                               const BatchDesc* desc, const float* A_pool, const float* B_pool,
+                               float* Q_pool, float* q_pool, double* s_pool, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const dim3 grid((unsigned)count), block(256);
+  const size_t lds = batched_gram_lds_bytes(bm);
+  if (bm == 64) {
+    if (diag)
+      hipLaunchKernelGGL((batched_gram_kernel<64, true>), grid, block, lds, st, items, desc,
+                         A_pool, B_pool, Q_pool, q_pool, s_pool);
+    else
+      hipLaunchKernelGGL((batched_gram_kernel<64, false>), grid, block, lds, st, items, desc,
+                         A_pool, B_pool, Q_pool, q_pool, s_pool);
+  } else {
+    if (diag)
+      hipLaunchKernelGGL((batched_gram_kernel<128, true>), grid, block, lds, st, items, desc,
+                         A_pool, B_pool, Q_pool, q_pool, s_pool);
+    else
+      hipLaunchKernelGGL((batched_gram_kernel<128, false>), grid, block, lds, st, items, desc,
+                         A_pool, B_pool, Q_pool, q_pool, s_pool);
+  }
   return hipGetLastError();
 }
 

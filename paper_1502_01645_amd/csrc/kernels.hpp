@@ -47,11 +47,18 @@ hipError_t launch_gram_fma(int64_t d, int64_t n, int64_t k, const T* A, int64_t 
                            int64_t ldb, const double* s, T* Q, T* q, hipStream_t st);
 
 constexpr int64_t BATCH_MAX_N = 1024;
-size_t batched_gram_lds_bytes();
+// One tile (ti, tj), ti <= tj, of problem p's [A | b]^T [A | b] in the batched Gram.
+struct BatchGramItem {
+  int32_t p;
+  int16_t ti, tj;
+};
+size_t batched_gram_lds_bytes(int bm);
 hipError_t prepare_batched_gram();
-hipError_t launch_batched_gram(const BatchDesc* desc, int64_t count, const float* A_pool,
-                               const float* B_pool, float* Q_pool, float* q_pool,
-                               double* s_pool, hipStream_t st);
+// The tiles of `items` (diagonal tiles when diag, else tiles above the diagonal, which need the
+// scales the diagonal launch wrote), at tile size bm = 64 or 128.
+hipError_t launch_batched_gram(int bm, bool diag, const BatchGramItem* items, int64_t count,
+                               const BatchDesc* desc, const float* A_pool, const float* B_pool,
+                               float* Q_pool, float* q_pool, double* s_pool, hipStream_t st);
 
 // solve_wg.hip
 size_t solve_wg_lds_bytes(int64_t n, int elem);

@@ -7,7 +7,7 @@
 // (each a contiguous row), and the incremental gradient reuses it:
 //     grad' = grad + Q (y' - y) = grad - alpha * (Q gbar) + Q[:, C] delta_C,
 // where C is the set of entries the projection clipped and delta = (y' - y) + alpha * gbar is
-// nonzero only there.  Threads own output entries i; each passive row j is read once, coalesced.
+// nonzero only there.  The products over a list of rows are list_product below.
 #pragma once
 
 #include "common.hpp"
@@ -15,7 +15,9 @@
 
 namespace nnls {
 
-constexpr int SW_NT = 256;
+constexpr int SW_NT = 256;   // threads of the per-column solver's workgroup
+constexpr int LP_VC = 4;     // entries per lane in a chunk of list_product
+constexpr int LP_CH = 64 * LP_VC;
 
 template <typename T>
 struct SolveCol {
@@ -33,30 +35,73 @@ struct SolveCol {
   int trace_len;
 };
 
-// sum over the compacted list (idx, val) of val_m * Q[idx_m, i]: row idx_m of Q is read at
-// column i, so consecutive threads read consecutive addresses of one row.
-template <typename T>
-__device__ __forceinline__ T row_combo(const T* __restrict__ Q, int64_t n, int64_t i,
-                                       const int* __restrict__ idx, const T* __restrict__ val,
-                                       int cnt) {
-  T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-  int m = 0;
-  for (; m + 3 < cnt; m += 4) {
-    const int j0 = idx[m], j1 = idx[m + 1], j2 = idx[m + 2], j3 = idx[m + 3];
-    a0 += val[m] * Q[(int64_t)j0 * n + i];
-    a1 += val[m + 1] * Q[(int64_t)j1 * n + i];
-    a2 += val[m + 2] * Q[(int64_t)j2 * n + i];
-    a3 += val[m + 3] * Q[(int64_t)j3 * n + i];
+// For every i < n: emit(i, sum over m < cnt of val[m] * Q[idx[m] * n + i]).  Q is symmetric, so
+// the list's rows of Q stand for its columns and each is read as a contiguous row.  The entries
+// go in chunks of LP_CH; in a chunk, a row is read by one wave (lane l takes entries l + 64 v),
+// the waves split the list (wave w takes m = w, w + NW, ..., four rows in flight, so a lane has
+// 4 LP_VC loads outstanding), and each wave leaves its partial sums in LDS part[NW][LP_CH].
+// The partials are added in wave order: the result does not depend on timing.  emit runs in
+// the thread that owns entry i of the chunk (i = c0 + tid + NT u); every thread calls this.
+template <typename T, int NT, typename Emit>
+__device__ __forceinline__ void list_product(const T* __restrict__ Q, int64_t n,
+                                             const int* __restrict__ idx,
+                                             const T* __restrict__ val, int cnt, T* part,
+                                             Emit emit) {
+  constexpr int NW = NT / kWave;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  for (int64_t c0 = 0; c0 < n; c0 += LP_CH) {
+    const int64_t rem = n - c0;
+    T acc[LP_VC];
+#pragma unroll
+    for (int v = 0; v < LP_VC; ++v) acc[v] = (T)0;
+    int m = wave;
+    for (; m + 3 * NW < cnt; m += 4 * NW) {
+      T a[4], x[4][LP_VC];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const T* row = Q + (int64_t)idx[m + u * NW] * n + c0;
+        a[u] = val[m + u * NW];
+#pragma unroll
+        for (int v = 0; v < LP_VC; ++v) {
+          const int e = lane + kWave * v;
+          x[u][v] = e < rem ? row[e] : (T)0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < LP_VC; ++v) acc[v] += a[u] * x[u][v];
+    }
+    for (; m < cnt; m += NW) {
+      const T* row = Q + (int64_t)idx[m] * n + c0;
+      const T a = val[m];
+#pragma unroll
+      for (int v = 0; v < LP_VC; ++v) {
+        const int e = lane + kWave * v;
+        acc[v] += a * (e < rem ? row[e] : (T)0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < LP_VC; ++v) part[wave * LP_CH + lane + kWave * v] = acc[v];
+    __syncthreads();
+    for (int e = threadIdx.x; e < LP_CH && e < rem; e += NT) {
+      T sum = (T)0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) sum += part[w * LP_CH + e];
+      emit(c0 + e, sum);
+    }
+    __syncthreads();
   }
-  for (; m < cnt; ++m) a0 += val[m] * Q[(int64_t)idx[m] * n + i];
-  return (a0 + a1) + (a2 + a3);
 }
 
-template <typename T>
+// Algorithm 2 on one column by a workgroup of NT threads.  LDS: the passive list (lds_val,
+// lds_idx) and the clipped / positive list (lds_val2, lds_idx2) of n entries each, the partial
+// sums of list_product (part, NT / 64 x LP_CH), and block-reduction scratch (NT / 64 each).
+template <typename T, int NT>
 __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int32_t* iters_out,
                              double* kkt_out, int32_t* status_out, int64_t* rows_out,
                              T* lds_val, int* lds_idx,
-                             T* lds_val2, int* lds_idx2, T* redT, int* redI) {
+                             T* lds_val2, int* lds_idx2, T* part, T* redT, int* redI) {
   const int tid = threadIdx.x;
   const int64_t n = P.n;
   const T* __restrict__ Q = P.Q;
@@ -66,7 +111,7 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
   // ||q|| for the relative residual; start point.
   T qq = 0;
   int nonfinite = 0;
-  for (int64_t i = tid; i < n; i += SW_NT) {
+  for (int64_t i = tid; i < n; i += NT) {
     const T qi = P.q[i * P.qs];
     qq += qi * qi;
     T yi = 0;
@@ -78,7 +123,7 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
     y[i] = yi;
     g[i] = qi;
   }
-  qq = block_sum<T, SW_NT>(qq, redT);
+  qq = block_sum<T, NT>(qq, redT);
   const T qnorm = sqrt(qq);
   const T scale = qnorm > (T)0 ? qnorm : (T)1;
   __syncthreads();
@@ -87,10 +132,10 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
   // Recompute grad = Q y + q exactly over the rows with y_j > 0.
   auto refresh_gradient = [&]() {
     int cnt = 0;
-    for (int64_t i = tid; i < n; i += SW_NT) cnt += (y[i] > (T)0);
+    for (int64_t i = tid; i < n; i += NT) cnt += (y[i] > (T)0);
     int total;
-    int off = block_exclusive_scan<SW_NT>(cnt, redI, total);
-    for (int64_t i = tid; i < n; i += SW_NT) {
+    int off = block_exclusive_scan<NT>(cnt, redI, total);
+    for (int64_t i = tid; i < n; i += NT) {
       const T yi = y[i];
       if (yi > (T)0) {
         lds_idx2[off] = (int)i;
@@ -99,10 +144,9 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
       }
     }
     __syncthreads();
-    for (int64_t i = tid; i < n; i += SW_NT)
-      g[i] = P.q[i * P.qs] + row_combo(Q, n, i, lds_idx2, lds_val2, total);
+    list_product<T, NT>(Q, n, lds_idx2, lds_val2, total, part,
+                        [&](int64_t i, T sum) { g[i] = P.q[i * P.qs] + sum; });
     rows += total;
-    __syncthreads();
   };
 
   int status = NNLS_MAXITER_DEV;
@@ -114,7 +158,7 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
   }
   {
     int nf = nonfinite;
-    T v = block_sum<T, SW_NT>((T)nf, redT);
+    T v = block_sum<T, NT>((T)nf, redT);
     if (v > (T)0) status = NNLS_NONFINITE_DEV;
   }
   double r_final = 0.0;
@@ -124,7 +168,7 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
     int cnt = 0;
     T num = 0, res = 0;
     int bad = 0;
-    for (int64_t i = tid; i < n; i += SW_NT) {
+    for (int64_t i = tid; i < n; i += NT) {
       const T yi = y[i], gi = g[i];
       bad |= !is_finite_val(yi) || !is_finite_val(gi);
       const bool pas = (yi > (T)0) || (gi < (T)0);
@@ -135,8 +179,8 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
       res += m * m;
     }
     int total;
-    int off = block_exclusive_scan<SW_NT>(cnt, redI, total);
-    for (int64_t i = tid; i < n; i += SW_NT) {
+    int off = block_exclusive_scan<NT>(cnt, redI, total);
+    for (int64_t i = tid; i < n; i += NT) {
       const T yi = y[i], gi = g[i];
       if ((yi > (T)0) || (gi < (T)0)) {
         lds_idx[off] = (int)i;
@@ -144,9 +188,9 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
         ++off;
       }
     }
-    num = block_sum<T, SW_NT>(num, redT);
-    res = block_sum<T, SW_NT>(res, redT);
-    const T badv = block_sum<T, SW_NT>((T)bad, redT);
+    num = block_sum<T, NT>(num, redT);
+    res = block_sum<T, NT>(res, redT);
+    const T badv = block_sum<T, NT>((T)bad, redT);
     if (badv > (T)0) {
       status = NNLS_NONFINITE_DEV;
       break;
@@ -179,14 +223,13 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
     // Line-search product w = Q gbar over the passive rows; den = gbar^T w.
     rows += total;
     T den = 0;
-    for (int64_t i = tid; i < n; i += SW_NT) {
-      const T w = row_combo(Q, n, i, lds_idx, lds_val, total);
+    list_product<T, NT>(Q, n, lds_idx, lds_val, total, part, [&](int64_t i, T w) {
       const T yi = y[i], gi = g[i];
       const T pi = ((yi > (T)0) || (gi < (T)0)) ? gi : (T)0;
       den += pi * w;
       P.w[i] = w;
-    }
-    den = block_sum<T, SW_NT>(den, redT);
+    });
+    den = block_sum<T, NT>(den, redT);
     if (!(den > (T)0) || !is_finite_val(den)) {
       status = NNLS_BREAKDOWN_DEV;
       break;
@@ -195,15 +238,15 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
 
     // Projected update and clipped set.
     int ccnt = 0;
-    for (int64_t i = tid; i < n; i += SW_NT) {
+    for (int64_t i = tid; i < n; i += NT) {
       const T yi = y[i], gi = g[i];
       const T pi = ((yi > (T)0) || (gi < (T)0)) ? gi : (T)0;
       const T v = yi - alpha * pi;
       ccnt += (v < (T)0);
     }
     int ctotal;
-    int coff = block_exclusive_scan<SW_NT>(ccnt, redI, ctotal);
-    for (int64_t i = tid; i < n; i += SW_NT) {
+    int coff = block_exclusive_scan<NT>(ccnt, redI, ctotal);
+    for (int64_t i = tid; i < n; i += NT) {
       const T yi = y[i], gi = g[i];
       const T pi = ((yi > (T)0) || (gi < (T)0)) ? gi : (T)0;
       const T v = yi - alpha * pi;
@@ -214,23 +257,26 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
       }
     }
     __syncthreads();
-    for (int64_t i = tid; i < n; i += SW_NT) {
+    // y' = [y - alpha gbar]_+, grad' = grad - alpha w + Q[:, C] delta_C
+    auto step_entry = [&](int64_t i, T corr) {
       const T yi = y[i], gi = g[i];
       const T pi = ((yi > (T)0) || (gi < (T)0)) ? gi : (T)0;
       const T v = yi - alpha * pi;
-      const T w = P.w[i];
-      T gn = gi - alpha * w;
-      if (ctotal > 0) gn += row_combo(Q, n, i, lds_idx2, lds_val2, ctotal);
       y[i] = v > (T)0 ? v : (T)0;
-      g[i] = gn;
+      g[i] = (gi - alpha * P.w[i]) + corr;
+    };
+    if (ctotal > 0) {
+      list_product<T, NT>(Q, n, lds_idx2, lds_val2, ctotal, part, step_entry);
+    } else {
+      for (int64_t i = tid; i < n; i += NT) step_entry(i, (T)0);
+      __syncthreads();
     }
     rows += ctotal;
-    __syncthreads();
     ++it;
     fresh = false;
   }
 
-  for (int64_t i = tid; i < n; i += SW_NT) {
+  for (int64_t i = tid; i < n; i += NT) {
     const T yi = y[i];
     P.x[i * P.qs] = P.s ? (T)((double)yi / P.s[i]) : yi;
   }
@@ -242,23 +288,25 @@ __device__ void solve_column(const SolveCol<T>& P, double tol, int max_iter, int
   }
 }
 
-// Byte offsets of the dynamic LDS of one workgroup: the compacted passive list (values, indices),
-// the clipped list (values, indices) and the block-reduction scratch, each 16-byte aligned.
+// Byte offsets of the dynamic LDS of one workgroup of NT threads: the compacted passive list
+// (values, indices), the clipped list (values, indices), the partial sums of list_product and
+// the block-reduction scratch, each 16-byte aligned.
 struct SwLdsLayout {
-  size_t val, val2, idx, idx2, redT, redI, total;
+  size_t val, val2, idx, idx2, part, redT, redI, total;
 };
 
 __host__ __device__ inline size_t sw_align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
-__host__ __device__ inline SwLdsLayout sw_lds_layout(int64_t n, size_t elem) {
+__host__ __device__ inline SwLdsLayout sw_lds_layout(int64_t n, size_t elem, int nt) {
   SwLdsLayout L;
   L.val = 0;
   L.val2 = sw_align16(L.val + elem * n);
   L.idx = sw_align16(L.val2 + elem * n);
   L.idx2 = sw_align16(L.idx + sizeof(int) * n);
-  L.redT = sw_align16(L.idx2 + sizeof(int) * n);
-  L.redI = sw_align16(L.redT + elem * (SW_NT / kWave));
-  L.total = sw_align16(L.redI + sizeof(int) * (SW_NT / kWave));
+  L.part = sw_align16(L.idx2 + sizeof(int) * n);
+  L.redT = sw_align16(L.part + elem * (size_t)(nt / kWave) * LP_CH);
+  L.redI = sw_align16(L.redT + elem * (nt / kWave));
+  L.total = sw_align16(L.redI + sizeof(int) * (nt / kWave));
   return L;
 }
 

@@ -15,7 +15,7 @@ __global__ __launch_bounds__(SW_NT) void solve_wg_kernel(int64_t n, int64_t k, c
                                                          float* trace, int trace_len, T* ws) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int64_t c = blockIdx.x;
-  const SwLdsLayout L = sw_lds_layout(n, sizeof(T));
+  const SwLdsLayout L = sw_lds_layout(n, sizeof(T), SW_NT);
   T* lds_val = (T*)(smem + L.val);
   T* lds_val2 = (T*)(smem + L.val2);
   int* lds_idx = (int*)(smem + L.idx);
@@ -35,12 +35,12 @@ __global__ __launch_bounds__(SW_NT) void solve_wg_kernel(int64_t n, int64_t k, c
   P.s = s;
   P.trace = trace ? trace + c * 2 * trace_len : nullptr;
   P.trace_len = trace_len;
-  solve_column<T>(P, tol, max_iter, iters + c, kkt + c, status + c,
-                  rows_read ? rows_read + c : nullptr, lds_val, lds_idx, lds_val2, lds_idx2, redT,
-                  redI);
+  solve_column<T, SW_NT>(P, tol, max_iter, iters + c, kkt + c, status + c,
+                         rows_read ? rows_read + c : nullptr, lds_val, lds_idx, lds_val2,
+                         lds_idx2, (T*)(smem + L.part), redT, redI);
 }
 
-size_t solve_wg_lds_bytes(int64_t n, int elem) { return sw_lds_layout(n, elem).total; }
+size_t solve_wg_lds_bytes(int64_t n, int elem) { return sw_lds_layout(n, elem, SW_NT).total; }
 
 template <typename T>
 hipError_t launch_solve_wg(int64_t n, int64_t k, const T* Q, const T* q, const double* s,

@@ -20,6 +20,7 @@ CONVERGED, MAXITER, BREAKDOWN, NONFINITE, FELL_BACK = 0, 1, 2, 3, 4
 GRAM_FP64, GRAM_FP32, GRAM_BF16X3 = 0, 1, 2
 F32, F64 = 0, 1
 OP_PREPARE, OP_SOLVE, OP_REFINE, OP_SCALES, OP_GRAM = 0, 1, 2, 3, 4
+TUNE_BATCHED = 1
 NOALLOC_SCRATCH_BYTES = 8 << 20   # NNLS_NOALLOC_SCRATCH_BYTES
 
 _ERRORS = {E_ARG: "invalid argument", E_WORKSPACE: "workspace too small",
@@ -77,8 +78,10 @@ def lib():
         L.nnls_batched_workspace_bytes.argtypes = [ctypes.POINTER(ProblemDesc), _i64]
         L.nnls_batched_workspace_bytes.restype = _sz
         L.nnls_batched_plan_create.argtypes = [ctypes.POINTER(ProblemDesc), _i64, ctypes.c_double,
-                                               _i32] + [_vp] * 11 + [_sz, _vp,
+                                               _i32, ctypes.c_char_p] + [_vp] * 11 + [_sz, _vp,
                                                ctypes.POINTER(ctypes.c_void_p)]
+        L.nnls_autotune.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(_i64), _i64, _vp]
+        L.nnls_autotune.restype = ctypes.c_int
         L.nnls_batched_plan_create.restype = ctypes.c_int
         L.nnls_batched_plan_launch.argtypes = [_vp, _vp]
         L.nnls_batched_plan_launch.restype = ctypes.c_int
@@ -394,11 +397,22 @@ def pack_problems(problems, device):
     return A_pool, B_pool, descs
 
 
+def autotune(cache_path, shapes, device=None, op=TUNE_BATCHED):
+    """nnls_autotune: measure the per-size-class parameters for problems of the given shapes
+    ((d, n) pairs) on the device and record them in the JSON cache at cache_path."""
+    flat = (_i64 * (2 * len(shapes)))()
+    for i, (d, n) in enumerate(shapes):
+        flat[2 * i], flat[2 * i + 1] = int(d), int(n)
+    dev = torch.device("cuda") if device is None else device
+    rc = lib().nnls_autotune(os.fsencode(cache_path), op, flat, len(shapes), _stream(dev))
+    _check(rc, "nnls_autotune")
+
+
 class BatchedPlan:
     """An uneven batch captured as one graph (nnls_batched_plan_*).  Outputs: Q, q, s, X pools
     and per-problem iters, kkt, status, rows_read."""
 
-    def __init__(self, A_pool, B_pool, descs, tol=1e-5, max_iter=0):
+    def __init__(self, A_pool, B_pool, descs, tol=1e-5, max_iter=0, tune_cache=None):
         dev = A_pool.device
         count = len(descs)
         sum_n = sum(int(descs[i].n) for i in range(count))
@@ -419,7 +433,8 @@ class BatchedPlan:
         torch.cuda.synchronize(dev)
         handle = ctypes.c_void_p()
         rc = lib().nnls_batched_plan_create(
-            descs, count, float(tol), int(max_iter), _ptr(A_pool), _ptr(B_pool),
+            descs, count, float(tol), int(max_iter),
+            None if tune_cache is None else os.fsencode(tune_cache), _ptr(A_pool), _ptr(B_pool),
             _ptr(self.Q_pool), _ptr(self.q_pool), _ptr(self.s_pool), _ptr(self.X_pool),
             _ptr(self.iters), _ptr(self.kkt), _ptr(self.status), _ptr(self.rows_read),
             _ptr(self.ws), wsb, ctypes.c_void_p(self._capture.cuda_stream), ctypes.byref(handle))

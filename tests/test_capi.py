@@ -203,7 +203,7 @@ def test_batched_plan_rejects_bad_arguments(L):
 
     def create(d=descs, count=2, tol=1e-5, mi=0, p=pools, ws=FAKE, wsb=big, stream=FAKE):
         out = ctypes.c_void_p()
-        return L.nnls_batched_plan_create(d, count, tol, mi, *p, ws, wsb, stream,
+        return L.nnls_batched_plan_create(d, count, tol, mi, None, *p, ws, wsb, stream,
                                           ctypes.byref(out))
 
     assert create(count=0) == N.E_ARG
@@ -221,6 +221,19 @@ def test_batched_plan_rejects_bad_arguments(L):
     assert create(d=big_n, count=1) == N.E_UNSUPPORTED
     assert create(ws=None) == N.E_WORKSPACE
     assert create(wsb=16) == N.E_WORKSPACE
+
+
+def test_autotune_rejects_bad_arguments(L):
+    from paper_1502_01645_amd import nnls as N
+    shapes = (ctypes.c_int64 * 4)(300, 100, 900, 300)
+    assert L.nnls_autotune(None, N.TUNE_BATCHED, shapes, 2, None) == N.E_ARG
+    assert L.nnls_autotune(b"/tmp/x.json", 7, shapes, 2, None) == N.E_ARG
+    assert L.nnls_autotune(b"/tmp/x.json", N.TUNE_BATCHED, None, 2, None) == N.E_ARG
+    assert L.nnls_autotune(b"/tmp/x.json", N.TUNE_BATCHED, shapes, 0, None) == N.E_ARG
+    bad = (ctypes.c_int64 * 2)(300, 0)
+    assert L.nnls_autotune(b"/tmp/x.json", N.TUNE_BATCHED, bad, 1, None) == N.E_ARG
+    big = (ctypes.c_int64 * 2)(3000, 2000)
+    assert L.nnls_autotune(b"/tmp/x.json", N.TUNE_BATCHED, big, 1, None) == N.E_UNSUPPORTED
 
 
 def test_mlp_sizes_and_argument_errors(L):

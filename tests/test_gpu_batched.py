@@ -1,4 +1,8 @@
-"""Uneven batch (one captured graph over many independent problems) against the FP64 oracle."""
+"""Uneven batch (one captured graph over many independent problems) against the FP64 oracle,
+with the default per-class parameters, with every Gram tile size and solver workgroup size set
+through a tuning cache, and with the parameters nnls_autotune measures."""
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -102,3 +106,88 @@ def test_batched_matches_per_problem_launches(solved):
                      tol=1e-5, max_iter=100000, inner_tol=3e-6, refine_step=False)
         r1, _ = orc().kkt_x(A, b.reshape(-1, 1), host(res["X"]))
         assert r1[0] <= 1e-5
+
+
+# every size class present in _problems(): n <= 64, 128, 256, 512
+_FORCED = {(1, 64): (64, 1024), (65, 128): (64, 512), (129, 256): (128, 1024),
+           (257, 512): (64, 256)}
+
+
+def _write_cache(path, params):
+    import torch as _t
+    arch = _t.cuda.get_device_properties(0).gcnArchName
+    lines = [json.dumps({"arch": arch, "op": "batched", "dtype": "f32", "n_lo": lo, "n_hi": hi,
+                         "gram_tile": t, "solve_threads": nt})
+             for (lo, hi), (t, nt) in params.items()]
+    with open(path, "w") as f:
+        f.write('{"format": "nnls-autotune-1", "entries": [\n' + ",\n".join(lines) + "\n]}\n")
+
+
+def _check_plan(probs, plan, ref_plan):
+    """Same Gram as the default plan bit for bit (a Gram entry's sum over d does not depend on
+    the tile size), every problem converged and within the tolerances against the oracle."""
+    assert np.array_equal(host(plan.Q_pool), host(ref_plan.Q_pool))
+    assert np.array_equal(host(plan.q_pool), host(ref_plan.q_pool))
+    assert np.array_equal(host(plan.s_pool), host(ref_plan.s_pool))
+    assert np.all(host(plan.status) == N.CONVERGED)
+    X = host(plan.X_pool)
+    for i, (A, b) in enumerate(probs):
+        dsc = plan.descs[i]
+        x = X[dsc.offX:dsc.offX + dsc.n].reshape(-1, 1)
+        r, F = orc().kkt_x(A, b.reshape(-1, 1), x)
+        gap = O.relative_gap(F, O.reference_solution(A, b.reshape(-1, 1)))
+        assert r[0] <= 1e-5 and gap[0] <= 1e-6, (i, dsc.n, r[0], gap[0])
+
+
+def test_batched_every_tile_and_workgroup_size(solved, tmp_path):
+    """A cache that sets 64-wide Gram tiles and 512- and 1024-thread solver workgroups for some
+    classes: the plan reads it and every kernel variant gives the default plan's Gram and
+    solutions within the tolerances."""
+    probs, ref = solved
+    path = str(tmp_path / "forced.json")
+    _write_cache(path, _FORCED)
+    A_pool, B_pool, descs = N.pack_problems(probs, DEV)
+    plan = N.BatchedPlan(A_pool, B_pool, descs, tol=3e-6, max_iter=100000, tune_cache=path)
+    plan.launch()
+    torch.cuda.synchronize()
+    _check_plan(probs, plan, ref)
+    # replays of the captured graph are deterministic
+    X0 = host(plan.X_pool).copy()
+    plan.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(host(plan.X_pool), X0)
+
+
+def test_autotune_writes_cache_the_plan_uses(solved, tmp_path):
+    """nnls_autotune through the C ABI on the shapes of the batch: the cache is JSON with one
+    entry per size class present (measured times for every candidate, the fastest chosen), a
+    second call keeps the entries of other keys, and a plan built from the cache solves the
+    batch within the tolerances."""
+    probs, ref = solved
+    path = str(tmp_path / "tune.json")
+    shapes = [(A.shape[0], A.shape[1]) for A, _ in probs]
+    say(f"autotune over {len(shapes)} shapes")
+    N.autotune(path, shapes)
+    with open(path) as f:
+        cache = json.load(f)
+    entries = cache["entries"]
+    say("  " + "; ".join(f"n<={e['n_hi']}: tile {e['gram_tile']} threads {e['solve_threads']}"
+                         for e in entries))
+    assert sorted((e["n_lo"], e["n_hi"]) for e in entries) == sorted(_FORCED)
+    for e in entries:
+        assert e["op"] == "batched" and e["dtype"] == "f32"
+        assert e["gram_tile"] in (64, 128) and e["solve_threads"] in (256, 512, 1024)
+        gm, sm = e["gram_ms"], e["solve_ms"]
+        assert e["gram_tile"] == min((64, 128), key=lambda t: gm[str(t)])
+        assert e["solve_threads"] == min((256, 512, 1024), key=lambda t: sm[str(t)])
+        assert all(v > 0 for v in list(gm.values()) + list(sm.values()))
+    # a second tuning of one class replaces only that class's entry
+    N.autotune(path, [s for s in shapes if s[1] <= 64])
+    with open(path) as f:
+        again = json.load(f)["entries"]
+    assert sorted((e["n_lo"], e["n_hi"]) for e in again) == sorted(_FORCED)
+    A_pool, B_pool, descs = N.pack_problems(probs, DEV)
+    plan = N.BatchedPlan(A_pool, B_pool, descs, tol=3e-6, max_iter=100000, tune_cache=path)
+    plan.launch()
+    torch.cuda.synchronize()
+    _check_plan(probs, plan, ref)
