@@ -99,8 +99,26 @@ int nnls_prepare(int64_t d, int64_t n, int64_t k, const void* A, int64_t lda, co
                  size_t ws_bytes, void* stream);
 
 /*
- * nnls_prepare is these two calls in sequence; they are exported so a caller can time or reuse
- * them separately.
+ * nnls_prepare with NNLS_GRAM_BF16X3 (FP32 data) in its two launches, for a caller that times
+ * or orders them separately; the workspace (nnls_workspace_bytes(NNLS_OP_PREPARE, ...,
+ * NNLS_GRAM_BF16X3, NNLS_F32)) carries the split operands from the first call to the second,
+ * so the same workspace must be passed to both and not be used in between.
+ *   nnls_prepare_split    [A | B] split once into BF16 hi and lo planes (stored by column, in
+ *                         ws), and s [n] FP64 = ||A_i||_2 (1 for a zero column) from the same
+ *                         read of A.  Arguments as for nnls_prepare.
+ *   nnls_prepare_product  Q [n, n] and q [n, k] from the planes in ws and s: the matrix-core
+ *                         Gram of Problem (2) with the rescale of Problem (5) in its epilogue.
+ * Errors as for nnls_prepare.
+ */
+int nnls_prepare_split(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
+                       const float* B, int64_t ldb, double* s, void* ws, size_t ws_bytes,
+                       void* stream);
+int nnls_prepare_product(int64_t d, int64_t n, int64_t k, const double* s, float* Q, float* q,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * nnls_prepare is also these two calls in sequence, in any mode; they are exported so a caller
+ * can time or reuse them separately.
  *
  * nnls_column_scales -- the scale vector of the rescaling (4): s_i = ||A_i||_2 in FP64, 1 where
  * the column is zero.  A [d, n] (lda >= n) of element type `dtype`; s out [n] FP64.

@@ -323,6 +323,30 @@ static int run_solve(int64_t n, int64_t k, int dtype, const void* Q, const void*
   return NNLS_OK;
 }
 
+int nnls_prepare_split(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
+                       const float* B, int64_t ldb, double* s, void* ws, size_t ws_bytes,
+                       void* stream) {
+  const float* fake_q = k > 0 ? (const float*)B : nullptr;  // Q, q are not written here
+  int rc = validate_gram(d, n, k, A, lda, B, ldb, NNLS_GRAM_BF16X3, NNLS_F32, A, fake_q);
+  if (rc != NNLS_OK) return rc;
+  if (!s) return NNLS_E_ARG;
+  const size_t need = prepare_ws(d, n, k, NNLS_GRAM_BF16X3);
+  if (ws_bytes < need || !ws) return NNLS_E_WORKSPACE;
+  hipError_t e = nnls::launch_prepare_split_bf16x3(d, n, k, A, lda, B, ldb, s, ws,
+                                                   (hipStream_t)stream);
+  return e == hipSuccess ? NNLS_OK : hip_fail(e);
+}
+
+int nnls_prepare_product(int64_t d, int64_t n, int64_t k, const double* s, float* Q, float* q,
+                         void* ws, size_t ws_bytes, void* stream) {
+  if (d < 1 || n < 1 || k < 0 || !s || !Q || (k > 0 && !q)) return NNLS_E_ARG;
+  if (n > (int64_t)1 << 30 || d > ((int64_t)1 << 40) / n) return NNLS_E_UNSUPPORTED;
+  const size_t need = prepare_ws(d, n, k, NNLS_GRAM_BF16X3);
+  if (ws_bytes < need || !ws) return NNLS_E_WORKSPACE;
+  hipError_t e = nnls::launch_prepare_product_bf16x3(d, n, k, s, Q, q, ws, (hipStream_t)stream);
+  return e == hipSuccess ? NNLS_OK : hip_fail(e);
+}
+
 int nnls_solve(int64_t n, int64_t k, int dtype, const void* Q, const void* q, const double* s,
                double tol, int32_t max_iter, const void* Y0, void* X, int32_t* iters,
                double* kkt, int32_t* status, int64_t* rows_read, float* trace,

@@ -941,29 +941,36 @@ size_t gram_bf16x3_ws_bytes(int64_t d, int64_t n, int64_t k) {
   return 2 * p.split_bytes + p.partial_bytes;
 }
 
-// s_out != nullptr: the operand split also forms the column norms (partials in colsq) and
-// writes them to s_out = s before the main kernel reads them; otherwise s is an input.
-static hipError_t gram_bf16x3_run(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
-                                  const float* B, int64_t ldb, const double* s, float* Q, float* q,
-                                  float* ws, double* colsq, double* s_out, hipStream_t st) {
-  const GramDmaPlan p = gram_dma_plan(d, n, k);
+// The operand split: [A | B] -> column-major BF16 hi / lo planes in ws.  With s_out !=
+// nullptr it also forms the column norms (partials in colsq) and writes them to s_out.
+static hipError_t split_bf16x3(const GramDmaPlan& p, int64_t d, int64_t n, int64_t k,
+                               const float* A, int64_t lda, const float* B, int64_t ldb,
+                               float* ws, double* colsq, double* s_out, hipStream_t st) {
   uint16_t* Ph = (uint16_t*)ws;
   uint16_t* Pl = (uint16_t*)((char*)ws + p.split_bytes);
-  float* partial = p.splits > 1 ? (float*)((char*)ws + 2 * p.split_bytes) : nullptr;
   dim3 g0((unsigned)(p.ncols_pad / PS_T), (unsigned)(p.dpad / PS_T));
   hipLaunchKernelGGL(presplit_kernel, g0, dim3(256), 0, st, d, n, k, A, lda, B, ldb, p.dpad, Ph,
                      Pl, s_out != nullptr ? colsq : nullptr);
   if (s_out != nullptr)
     hipLaunchKernelGGL(colnorm_finalize_kernel, dim3((unsigned)((n + CN_C - 1) / CN_C)),
                        dim3(256), 0, st, n, p.dpad / PS_T, (const double*)colsq, s_out);
+  return hipGetLastError();
+}
+
+// The matrix-core product from the planes in ws, with the rescale by s (or none) in the
+// epilogue (through the split-K partials in ws when the plan splits K).
+static hipError_t product_bf16x3(const GramDmaPlan& p, int64_t n, int64_t k, const double* s,
+                                 float* Q, float* q, float* ws, hipStream_t st) {
+  const uint16_t* Ph = (const uint16_t*)ws;
+  const uint16_t* Pl = (const uint16_t*)((char*)ws + p.split_bytes);
+  float* partial = p.splits > 1 ? (float*)((char*)ws + 2 * p.split_bytes) : nullptr;
   const int blocks = schedule_blocks(p.ntiles, p.splits);
-  dim3 grid((unsigned)blocks);
   hipError_t e = hipFuncSetAttribute((const void*)gram_dma_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, GD_LDS_BYTES);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gram_dma_kernel, grid, dim3(GD_NT), GD_LDS_BYTES, st, n, k,
-                     (const uint16_t*)Ph, (const uint16_t*)Pl, p.dpad, s, Q, q, partial, p.tiles_a,
-                     p.tiles_aug, p.ntiles, p.splits, p.rows_per_split);
+  hipLaunchKernelGGL(gram_dma_kernel, dim3((unsigned)blocks), dim3(GD_NT), GD_LDS_BYTES, st, n, k,
+                     Ph, Pl, p.dpad, s, Q, q, partial, p.tiles_a, p.tiles_aug, p.ntiles,
+                     p.splits, p.rows_per_split);
   if (p.splits > 1)
     hipLaunchKernelGGL(gram_splitk_epilogue_kernel<GD_T>,
                        dim3((unsigned)p.ntiles, GD_T / GE_BAND), dim3(GD_T), 0, st, n, k,
@@ -974,7 +981,10 @@ static hipError_t gram_bf16x3_run(int64_t d, int64_t n, int64_t k, const float* 
 hipError_t launch_gram_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
                               const float* B, int64_t ldb, const double* s, float* Q, float* q,
                               float* ws, hipStream_t st) {
-  return gram_bf16x3_run(d, n, k, A, lda, B, ldb, s, Q, q, ws, nullptr, nullptr, st);
+  const GramDmaPlan p = gram_dma_plan(d, n, k);
+  hipError_t e = split_bf16x3(p, d, n, k, A, lda, B, ldb, ws, nullptr, nullptr, st);
+  if (e != hipSuccess) return e;
+  return product_bf16x3(p, n, k, s, Q, q, ws, st);
 }
 
 size_t prepare_bf16x3_ws_bytes(int64_t d, int64_t n, int64_t k) {
@@ -983,13 +993,26 @@ size_t prepare_bf16x3_ws_bytes(int64_t d, int64_t n, int64_t k) {
   return gram + sizeof(double) * (size_t)(p.dpad / PS_T) * (size_t)n;
 }
 
-hipError_t launch_prepare_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
-                                 const float* B, int64_t ldb, double* s, float* Q, float* q,
-                                 void* ws, hipStream_t st) {
+hipError_t launch_prepare_split_bf16x3(int64_t d, int64_t n, int64_t k, const float* A,
+                                       int64_t lda, const float* B, int64_t ldb, double* s,
+                                       void* ws, hipStream_t st) {
   const GramDmaPlan p = gram_dma_plan(d, n, k);
   const size_t gram = (2 * p.split_bytes + p.partial_bytes + 255) / 256 * 256;
   double* colsq = (double*)((char*)ws + gram);
-  return gram_bf16x3_run(d, n, k, A, lda, B, ldb, s, Q, q, (float*)ws, colsq, s, st);
+  return split_bf16x3(p, d, n, k, A, lda, B, ldb, (float*)ws, colsq, s, st);
+}
+
+hipError_t launch_prepare_product_bf16x3(int64_t d, int64_t n, int64_t k, const double* s,
+                                         float* Q, float* q, void* ws, hipStream_t st) {
+  return product_bf16x3(gram_dma_plan(d, n, k), n, k, s, Q, q, (float*)ws, st);
+}
+
+hipError_t launch_prepare_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
+                                 const float* B, int64_t ldb, double* s, float* Q, float* q,
+                                 void* ws, hipStream_t st) {
+  hipError_t e = launch_prepare_split_bf16x3(d, n, k, A, lda, B, ldb, s, ws, st);
+  if (e != hipSuccess) return e;
+  return launch_prepare_product_bf16x3(d, n, k, s, Q, q, ws, st);
 }
 
 template <typename T>

@@ -39,6 +39,13 @@ size_t prepare_bf16x3_ws_bytes(int64_t d, int64_t n, int64_t k);
 hipError_t launch_prepare_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
                                  const float* B, int64_t ldb, double* s, float* Q, float* q,
                                  void* ws, hipStream_t st);
+// launch_prepare_bf16x3 in its two steps: the operand split with the column norms, then the
+// product from the split planes left in ws.
+hipError_t launch_prepare_split_bf16x3(int64_t d, int64_t n, int64_t k, const float* A,
+                                       int64_t lda, const float* B, int64_t ldb, double* s,
+                                       void* ws, hipStream_t st);
+hipError_t launch_prepare_product_bf16x3(int64_t d, int64_t n, int64_t k, const double* s,
+                                         float* Q, float* q, void* ws, hipStream_t st);
 hipError_t launch_gram_bf16x3(int64_t d, int64_t n, int64_t k, const float* A, int64_t lda,
                               const float* B, int64_t ldb, const double* s, float* Q, float* q,
                               float* ws, hipStream_t st);

@@ -59,6 +59,11 @@ def lib():
         L.nnls_solve_noalloc.argtypes = [_i64, _i64, ctypes.c_int, _vp, _vp, _vp, ctypes.c_double,
                                          _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]
         L.nnls_solve_noalloc.restype = ctypes.c_int
+        L.nnls_prepare_split.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _sz,
+                                         _vp]
+        L.nnls_prepare_split.restype = ctypes.c_int
+        L.nnls_prepare_product.argtypes = [_i64, _i64, _i64, _vp, _vp, _vp, _vp, _sz, _vp]
+        L.nnls_prepare_product.restype = ctypes.c_int
         L.nnls_column_scales.argtypes = [_i64, _i64, _vp, _i64, ctypes.c_int, _vp, _vp, _sz, _vp]
         L.nnls_column_scales.restype = ctypes.c_int
         L.nnls_gram_rescaled.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int,
@@ -192,6 +197,32 @@ def prepare(A: torch.Tensor, B: torch.Tensor | None = None, mode: int | None = N
                             _stream(A.device))
     _check(rc, "nnls_prepare")
     return Q, q, s
+
+
+def prepare_split(A: torch.Tensor, B: torch.Tensor, s: torch.Tensor, ws: torch.Tensor):
+    """nnls_prepare_split (FP32, BF16x3): the operand split into ws and the scales s."""
+    d, n = A.shape
+    if B is None or B.numel() == 0:
+        B, k, ldb = None, 0, 1
+    else:
+        B = B.reshape(d, -1)
+        k, ldb = B.shape[1], B.stride(0)
+        assert B.stride(1) == 1
+    assert A.dtype == torch.float32 and A.stride(1) == 1
+    wsb = workspace_bytes(OP_PREPARE, d, n, k, GRAM_BF16X3, F32)
+    assert ws.numel() >= wsb
+    _check(lib().nnls_prepare_split(d, n, k, _ptr(A), A.stride(0), _ptr(B), ldb, _ptr(s),
+                                    _ptr(ws), ws.numel(), _stream(A.device)),
+           "nnls_prepare_split")
+
+
+def prepare_product(d: int, s: torch.Tensor, Q: torch.Tensor, q: torch.Tensor, ws: torch.Tensor):
+    """nnls_prepare_product: Q, q from the split planes a prepare_split call left in ws."""
+    n = Q.shape[0]
+    k = 0 if q is None else (q.shape[1] if q.dim() == 2 else 1)
+    _check(lib().nnls_prepare_product(d, n, k, _ptr(s), _ptr(Q), _ptr(q if k else None),
+                                      _ptr(ws), ws.numel(), _stream(Q.device)),
+           "nnls_prepare_product")
 
 
 def column_scales(A: torch.Tensor, out=None, ws=None):

@@ -213,6 +213,29 @@ def test_refine_few_rhs_matches_oracle(dtype, d, n, k, start):
     _refine_case(dtype, d, n, k, start)
 
 
+@pytest.mark.parametrize("d,n,k", [(2000, 300, 1), (3000, 700, 5), (500, 1100, 0)])
+def test_prepare_split_then_product_equals_prepare(d, n, k):
+    """nnls_prepare_split followed by nnls_prepare_product on one workspace gives nnls_prepare's
+    Q, q and s bit for bit (they are its two launches)."""
+    say(f"split + product d={d} n={n} k={k}")
+    rng = np.random.default_rng(d + n)
+    A = dev(rng.random((d, n)).astype(np.float32))
+    B = dev(rng.random((d, max(k, 1))).astype(np.float32))[:, :k].contiguous() if k else \
+        torch.zeros((d, 0), dtype=torch.float32, device=DEV)
+    Q0, q0, s0 = N.prepare(A, B if k else None)
+    wsb = N.workspace_bytes(N.OP_PREPARE, d, n, k, N.GRAM_BF16X3, N.F32)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=DEV)
+    s = torch.empty(n, dtype=torch.float64, device=DEV)
+    Q = torch.empty((n, n), dtype=torch.float32, device=DEV)
+    q = torch.empty((n, k), dtype=torch.float32, device=DEV)
+    N.prepare_split(A, B, s, ws)
+    N.prepare_product(d, s, Q, q, ws)
+    np.testing.assert_array_equal(host(s), host(s0))
+    np.testing.assert_array_equal(host(Q), host(Q0))
+    if k:
+        np.testing.assert_array_equal(host(q), host(q0))
+
+
 @pytest.mark.parametrize("d,n,k", [(600, 96, 3), (900, 160, 40), (1100, 256, 70)])
 def test_refine_objective_noiseless(d, n, k):
     """Noiseless data b = A x*: F* = 0 and F at the returned x is tiny against 1/2 ||b||^2, so
