@@ -147,8 +147,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="large",
                     choices=["large", "manyrhs", "batched", "warm", "ablation", "paper", "nmf"])
-    ap.add_argument("--only", default=None, choices=["prepare"],
-                    help="large workload: time the Gram alone (no solver launch)")
+    ap.add_argument("--only", default=None, choices=["prepare", "copy"],
+                    help="large workload: time the Gram alone (no solver launch); copy: a "
+                         "256 MiB device copy, the reference for the HBM byte counters")
     ap.add_argument("--epochs", type=int, default=WARM_EPOCHS)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--cpu-sample-cols", type=int, default=1400)
@@ -158,10 +159,37 @@ def main():
                                    "multi-GPU layout is described, not built)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+    if args.only == "copy":
+        return bench_copy(args)
     fn = {"large": bench_large, "manyrhs": bench_manyrhs, "batched": bench_batched,
           "warm": bench_warm, "ablation": bench_ablation, "paper": bench_paper,
           "nmf": bench_nmf}[args.workload]
     return fn(args)
+
+
+def bench_copy(args):
+    """A 256 MiB device-to-device copy (torch copy_), timed with HIP events: the kernel of known
+    traffic (256 MiB read, 256 MiB written) whose FETCH_SIZE / WRITE_SIZE counter readings give
+    the scale factors for the other kernels' counters."""
+    import torch
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    marks = [[torch.cuda.Event(enable_timing=True) for _ in range(2)]
+             for _ in range(args.warmup + args.steps)]
+
+    def step(i):
+        marks[i][0].record()
+        dst.copy_(src)
+        marks[i][1].record()
+
+    wall = run_timed(step, args.warmup, args.steps)
+    ms = event_ms(marks[args.warmup:], ["copy"])["copy"]
+    print(json.dumps({"metric": "device copy GB/s (counter calibration)",
+                      "value": round(2 * nbytes / (ms * 1e-3) / 1e9, 1), "unit": "GB/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(wall * 1e3 / args.steps, 4), "bytes_read": nbytes,
+                      "bytes_written": nbytes}), flush=True)
 
 
 def large_baseline(A_h, b_h, x_gpu, it_gpu):

@@ -2,7 +2,8 @@
 //   queue reset -> batched Gram with fused rescale (gram.hip: the diagonal tiles of every
 //   problem, then the tiles above the diagonal) -> batched solve: per thread-count class a grid
 //   of resident workgroups that take the class's problems from an atomic queue in longest-first
-//   order and run Algorithm 2 on each (solve_core.hpp), then x = y / s.
+//   order and run Algorithm 2 on each (solve_core.hpp), then x = y / s; the classes are parallel
+//   branches of the graph.
 // Problems fall in size classes by n; each class has a Gram tile size (64 or 128) and a solver
 // workgroup size (256, 512 or 1024 threads).  nnls_autotune measures both per class on
 // synthetic problems of the caller's shapes and records the fastest in a JSON cache that
@@ -508,18 +509,42 @@ int nnls_batched_plan_create(const nnls_problem_desc* host_desc, int64_t count, 
   nnls_plan* plan = new (std::nothrow) nnls_plan();
   if (!plan) return NNLS_E_HIP;
   plan->count = count;
-  e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  // The solver classes are parallel branches of the graph after the Gram: each is a resident
+  // grid sized to fill the GPU, so a later class's workgroups start on the compute units the
+  // earlier class frees as its queue runs dry (its tail) instead of after it.  The side
+  // streams and events only carry the capture (default priority; released below).
+  hipStream_t side[nnls::kSolveClasses] = {};
+  hipEvent_t fork = nullptr, join[nnls::kSolveClasses] = {};
+  e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  for (int i = 1; i < nnls::kSolveClasses && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(nnls::batched_queue_reset, dim3(1), dim3(64), 0, st, counters,
                        nnls::kSolveClasses);
     hipError_t e1 = launch_gram_lists((const BatchGramItem*)(base + L.items), cnt, bb, st);
-    for (int i = 0; i < nnls::kSolveClasses && e1 == hipSuccess; ++i)
-      e1 = launch_solve_class(slots[i], args[slots[i]], lds[slots[i]], grid[slots[i]], st);
+    if (e1 == hipSuccess) e1 = hipEventRecord(fork, st);
+    for (int i = 0; i < nnls::kSolveClasses && e1 == hipSuccess; ++i) {
+      if (args[slots[i]].count <= 0) continue;
+      hipStream_t s_i = i == 0 ? st : side[i];
+      if (i > 0) e1 = hipStreamWaitEvent(s_i, fork, 0);
+      if (e1 == hipSuccess)
+        e1 = launch_solve_class(slots[i], args[slots[i]], lds[slots[i]], grid[slots[i]], s_i);
+      if (e1 == hipSuccess && i > 0) e1 = hipEventRecord(join[i], s_i);
+      if (e1 == hipSuccess && i > 0) e1 = hipStreamWaitEvent(st, join[i], 0);
+    }
     hipError_t e2 = hipGetLastError();
     e = hipStreamEndCapture(st, &plan->graph);
     if (e == hipSuccess && e1 != hipSuccess) e = e1;
     if (e == hipSuccess && e2 != hipSuccess) e = e2;
   }
+  for (int i = 1; i < nnls::kSolveClasses; ++i) {
+    if (join[i]) (void)hipEventDestroy(join[i]);
+    if (side[i]) (void)hipStreamDestroy(side[i]);
+  }
+  if (fork) (void)hipEventDestroy(fork);
   if (e == hipSuccess) e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     plan_fail(e);

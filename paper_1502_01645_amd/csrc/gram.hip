@@ -381,14 +381,15 @@ __device__ __forceinline__ void gram_tile_bf16x3(f32x4 (&acc)[BM / 32][BM / 32],
 constexpr int PS_T = 64;
 constexpr int GD_T = 256;
 constexpr int GD_BK = 32;
-constexpr int GD_NT = 512;
+constexpr int GD_WAVES_N = 4;               // waves across the tile's columns (2 across rows)
+constexpr int GD_NT = 2 * GD_WAVES_N * 64;
 constexpr int GD_PART = GD_T * GD_BK;        // bf16 per part
 constexpr int GD_STAGE = 4 * GD_PART;
 constexpr int GD_LDS_BYTES = 2 * GD_STAGE * 2;
 constexpr int GD_CPI = 512 / GD_BK;          // columns per load instruction (1 KB)
 constexpr int GD_IPP = GD_T / GD_CPI;        // instructions per part
 constexpr int GD_IPW = 4 * GD_IPP / (GD_NT / 64);
-constexpr int GD_MT = 8, GD_NTL = 4;         // 16 x 16 blocks per wave (rows, columns)
+constexpr int GD_MT = 8, GD_NTL = 16 / GD_WAVES_N;  // 16 x 16 blocks per wave (rows, columns)
 
 // LDS position of k-group g of column c (64 bytes per column, four 16-byte k-groups): g ^ swz(c).
 // Any 8 consecutive columns (and any 16) then put their 16-byte pieces on distinct bank groups
@@ -526,7 +527,7 @@ __global__ __launch_bounds__(GD_NT, 1) void gram_dma_kernel(
   for (int a = 0; a < GD_MT; ++a)
 #pragma unroll
     for (int b = 0; b < GD_NTL; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
+  const int wm = (wave / GD_WAVES_N) * 128, wn = (wave % GD_WAVES_N) * (GD_T / GD_WAVES_N);
   const int fr = lane & 15;
   const int fp = (lane >> 4) ^ gd_swz(fr);  // physical k-group of this lane's fragment
 

@@ -42,8 +42,9 @@ def _passive_and_clipped(Q, q, y):
 
 # (n, k): 160 and 192 take the 3-tile instance, 200 and 256 the 512-thread 4-tile instance,
 # 300 and 512 the instance that reads Q from L2; k leaves a ragged last group of 16 slots
+# (k = 2, 3, 4: one nearly empty group, n = 64, 128, 256: one to four register tiles).
 @pytest.mark.parametrize("n,k", [(160, 37), (192, 21), (200, 37), (256, 37), (300, 21),
-                                 (512, 19)])
+                                 (512, 19), (256, 19), (64, 2), (128, 4), (256, 3)])
 def test_mrhs_steps_match_oracle(n, k, monkeypatch):
     monkeypatch.setenv("NNLS_SOLVER", "mrhs")
     assert N.solver_name(n, k) == "mrhs"
@@ -135,3 +136,16 @@ def test_mrhs_end_to_end_warm_shape():
     res = N.nnls(dev(A), dev(B), tol=1e-5, max_iter=100000, inner_tol=3e-6)
     assert np.all(host(res["status"]) == N.CONVERGED)
     _check(A, B, res, np.arange(0, 6000, 125), "mrhs warm shape")
+
+
+@pytest.mark.parametrize("n,k", [(96, 3), (256, 4), (256, 20)])
+def test_mrhs_nearly_empty_groups_end_to_end(n, k, monkeypatch):
+    """Groups with few live columns (k <= 4, and the last group of k = 20) reach the
+    tolerances against the oracle."""
+    monkeypatch.setenv("NNLS_SOLVER", "mrhs")
+    A, B, _ = W.make_manyrhs(seed=9, d=3 * n, n=n, k=k)
+    say(f"mrhs few-column e2e {3 * n}x{n} k={k}")
+    assert N.solver_name(n, k) == "mrhs"
+    res = N.nnls(dev(A), dev(B), tol=1e-5, max_iter=100000, inner_tol=3e-6)
+    assert np.all(host(res["status"]) == N.CONVERGED)
+    _check(A, B, res, np.arange(k), f"mrhs few columns n={n}")
