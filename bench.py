@@ -863,8 +863,9 @@ def bench_batched(args):
     N.autotune(cache, shapes)
     t_tune = time.perf_counter() - t0
     with open(cache) as f:
-        tuned = [{kk: e[kk] for kk in ("n_lo", "n_hi", "gram_tile", "solve_threads", "gram_ms",
-                                       "solve_ms")} for e in json.load(f)["entries"]]
+        tuned = [{kk: e[kk] for kk in ("n_lo", "n_hi", "gram_tile", "solve_threads",
+                                       "solve_wgs_per_cu", "gram_ms", "solve_ms")}
+                 for e in json.load(f)["entries"]]
     # the paper's 5 n cap is too tight for the small problems of this batch; cap at 20000
     plans = {"tuned": N.BatchedPlan(A_pool, B_pool, descs, tol=BATCH_INNER_TOL,
                                     max_iter=BATCH_MAX_ITER, tune_cache=cache),

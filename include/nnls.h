@@ -291,7 +291,7 @@ enum nnls_tune_op {
  * an entry measured now replaces the old one with its key; the file is written to a temporary
  * name and renamed, and reads and writes of cache files in one process are serialised).
  *   shapes  host array of `count` pairs (d_i, n_i), 1 <= n_i <= 1024, d_i <= 16384: the
- *           problems the tuned plans will see (each class is measured on up to 256 of them).
+ *           problems the tuned plans will see (each class is measured on up to 1024 of them).
  * For NNLS_TUNE_BATCHED each class present is timed with HIP events on synthetic problems of
  * its shapes (A U[0, 1], x 60 % zeros else U[0, 1], b = A x with 1 % noise, drawn on the device
  * from SplitMix64): the batched Gram at tile sizes 64 and 128, then the batched solver at 256,

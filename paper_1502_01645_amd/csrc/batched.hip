@@ -45,6 +45,9 @@ struct BatchSolveArgs {
 
 constexpr int kSolveClasses = 3;
 constexpr int kSolveThreads[kSolveClasses] = {256, 512, 1024};
+// A solve group is a (workgroup size, resident-per-CU cap) pair: one persistent launch each.
+constexpr int kCaps = 2;  // cap index 0: as many as fit; 1: one per compute unit
+constexpr int kSolveGroups = kSolveClasses * kCaps;
 
 __global__ void batched_queue_reset(int* counters, int count) {
   if ((int)threadIdx.x < count) counters[threadIdx.x * 64] = 0;
@@ -148,9 +151,14 @@ int size_class(int64_t n) {
 struct ClassParams {
   int gram_tile;      // 64 or 128
   int solve_threads;  // 256, 512 or 1024
+  int solve_per_cu;   // resident solver workgroups per compute unit: 0 = as many as fit, else
+                      // this cap (fewer problems in flight keep their Q in the caches)
 };
-// Without a tuning record: 128-wide Gram tiles and 256-thread solver workgroups everywhere.
-constexpr ClassParams kDefault = {128, 256};
+// Without a tuning record: 128-wide Gram tiles and 256-thread solver workgroups everywhere,
+// as many resident as fit.
+constexpr ClassParams kDefault = {128, 256, 0};
+constexpr int kPerCuCaps[nnls::kCaps] = {0, 1};
+int cap_index(int cap) { return cap == 1 ? 1 : 0; }
 
 int solve_slot(int nt) {
   for (int i = 0; i < nnls::kSolveClasses; ++i)
@@ -190,7 +198,7 @@ PlanLayout plan_layout(int64_t count, int64_t sum_n, int64_t max_items) {
   L.items = align256(L.desc + sizeof(BatchDesc) * count);
   L.order = align256(L.items + sizeof(BatchGramItem) * max_items);
   L.counter = align256(L.order + sizeof(int) * count);
-  L.vec = align256(L.counter + sizeof(int) * 64 * nnls::kSolveClasses);
+  L.vec = align256(L.counter + sizeof(int) * 64 * nnls::kSolveGroups);
   L.total = align256(L.vec + sizeof(float) * 3 * sum_n);
   return L;
 }
@@ -203,7 +211,7 @@ std::mutex g_tune_mu;  // guards reads and writes of cache files in this process
 struct TuneEntry {
   std::string arch, op, dtype;
   int64_t lo = 0, hi = 0;
-  int gram_tile = 0, solve_threads = 0;
+  int gram_tile = 0, solve_threads = 0, solve_per_cu = 0;
   std::string line;  // the entry as written
 };
 
@@ -248,13 +256,15 @@ std::vector<TuneEntry> read_cache(const char* path) {
     while ((c = fgetc(f)) != EOF && c != '\n') line.push_back((char)c);
     if (line.find("\"op\": ") != std::string::npos) {
       TuneEntry e;
-      int64_t gt = 0, st = 0;
+      int64_t gt = 0, st = 0, pc = 0;
       if (json_str(line, "arch", e.arch) && json_str(line, "op", e.op) &&
           json_str(line, "dtype", e.dtype) && json_int(line, "n_lo", e.lo) &&
           json_int(line, "n_hi", e.hi) && json_int(line, "gram_tile", gt) &&
           json_int(line, "solve_threads", st)) {
+        if (!json_int(line, "solve_wgs_per_cu", pc)) pc = 0;
         e.gram_tile = (int)gt;
         e.solve_threads = (int)st;
+        e.solve_per_cu = (int)pc;
         e.line = line;
         while (!e.line.empty() && (e.line.back() == ',' || e.line.back() == ' '))
           e.line.pop_back();
@@ -295,8 +305,8 @@ void load_params(const char* path, ClassParams (&params)[kClasses]) {
     for (int c = 0; c < kClasses; ++c) {
       const int64_t lo = c == 0 ? 1 : kClassHi[c - 1] + 1;
       if (e.lo == lo && e.hi == kClassHi[c] && (e.gram_tile == 64 || e.gram_tile == 128) &&
-          solve_slot(e.solve_threads) >= 0)
-        params[c] = ClassParams{e.gram_tile, e.solve_threads};
+          solve_slot(e.solve_threads) >= 0 && e.solve_per_cu >= 0)
+        params[c] = ClassParams{e.gram_tile, e.solve_threads, e.solve_per_cu};
     }
   }
 }
@@ -335,9 +345,10 @@ const void* solve_kernel(int slot) {
   }
 }
 
-// Dynamic LDS and resident grid of the solver class `slot` for problems up to max_n.
-hipError_t solve_launch_shape(int slot, int64_t max_n, int64_t count, size_t& lds,
-                              int64_t& grid) {
+// Dynamic LDS and resident grid of the solver class `slot` for problems up to max_n, with at
+// most per_cu_cap workgroups per compute unit (0: as many as fit).
+hipError_t solve_launch_shape(int slot, int64_t max_n, int64_t count, int per_cu_cap,
+                              size_t& lds, int64_t& grid) {
   const int nt = nnls::kSolveThreads[slot];
   lds = nnls::sw_lds_layout(max_n, sizeof(float), nt).total;
   int dev = 0, cus = 256, per_cu = 1;
@@ -348,7 +359,9 @@ hipError_t solve_launch_shape(int slot, int64_t max_n, int64_t count, size_t& ld
   if (e == hipSuccess)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, solve_kernel(slot), nt, lds);
   if (e != hipSuccess) return e;
-  grid = std::min<int64_t>(count, (int64_t)cus * std::max(per_cu, 1));
+  per_cu = std::max(per_cu, 1);
+  if (per_cu_cap > 0) per_cu = std::min(per_cu, per_cu_cap);
+  grid = std::min<int64_t>(count, (int64_t)cus * per_cu);
   return hipSuccess;
 }
 
@@ -434,9 +447,9 @@ int nnls_batched_plan_create(const nnls_problem_desc* host_desc, int64_t count, 
   // longest-first order of each solver class
   std::vector<BatchDesc> dd(count);
   std::vector<BatchGramItem> lists[4];
-  std::vector<int> order[nnls::kSolveClasses];
+  std::vector<int> order[nnls::kSolveGroups];
   std::vector<double> cost(count);
-  int64_t class_max_n[nnls::kSolveClasses] = {0, 0, 0};
+  int64_t group_max_n[nnls::kSolveGroups] = {};
   for (int64_t i = 0; i < count; ++i) {
     const nnls_problem_desc& p = host_desc[i];
     dd[i] = BatchDesc{p.d, p.n, p.offA, p.offB, p.offQ, p.offq, p.offX, 0};
@@ -444,9 +457,9 @@ int nnls_batched_plan_create(const nnls_problem_desc* host_desc, int64_t count, 
     const ClassParams& cp = params[size_class(p.n)];
     const int li = cp.gram_tile == 128 ? 1 : 0;
     problem_items((int32_t)i, p.n, cp.gram_tile, lists[li], lists[2 + li]);
-    const int slot = solve_slot(cp.solve_threads);
-    order[slot].push_back((int)i);
-    class_max_n[slot] = std::max<int64_t>(class_max_n[slot], p.n);
+    const int grp = solve_slot(cp.solve_threads) * nnls::kCaps + cap_index(cp.solve_per_cu);
+    order[grp].push_back((int)i);
+    group_max_n[grp] = std::max<int64_t>(group_max_n[grp], p.n);
   }
   std::vector<BatchGramItem> items;
   int64_t cnt[4];
@@ -459,8 +472,8 @@ int nnls_batched_plan_create(const nnls_problem_desc* host_desc, int64_t count, 
     items.insert(items.end(), lists[l].begin(), lists[l].end());
   }
   std::vector<int> orders;
-  int64_t order_off[nnls::kSolveClasses];
-  for (int c = 0; c < nnls::kSolveClasses; ++c) {
+  int64_t order_off[nnls::kSolveGroups];
+  for (int c = 0; c < nnls::kSolveGroups; ++c) {
     std::stable_sort(order[c].begin(), order[c].end(),
                      [&](int a, int b) { return cost[a] > cost[b]; });
     order_off[c] = (int64_t)orders.size();
@@ -485,22 +498,25 @@ int nnls_batched_plan_create(const nnls_problem_desc* host_desc, int64_t count, 
   BatchBuffers bb{(const BatchDesc*)(base + L.desc), A_pool, B_pool, Q_pool, q_pool, X_pool,
                   (float*)(base + L.vec), s_pool, iters, status, kkt, rows_read};
   int* counters = (int*)(base + L.counter);
-  nnls::BatchSolveArgs args[nnls::kSolveClasses];
-  size_t lds[nnls::kSolveClasses] = {0, 0, 0};
-  int64_t grid[nnls::kSolveClasses] = {0, 0, 0};
-  for (int c = 0; c < nnls::kSolveClasses && e == hipSuccess; ++c) {
+  nnls::BatchSolveArgs args[nnls::kSolveGroups];
+  size_t lds[nnls::kSolveGroups] = {};
+  int64_t grid[nnls::kSolveGroups] = {};
+  for (int c = 0; c < nnls::kSolveGroups && e == hipSuccess; ++c) {
     args[c] = solve_args(bb, bb.desc, (const int*)(base + L.order) + order_off[c],
                          (int64_t)order[c].size(), counters + 64 * c, tol, max_iter);
-    if (!order[c].empty()) e = solve_launch_shape(c, class_max_n[c], args[c].count, lds[c], grid[c]);
+    if (!order[c].empty())
+      e = solve_launch_shape(c / nnls::kCaps, group_max_n[c], args[c].count,
+                             kPerCuCaps[c % nnls::kCaps], lds[c], grid[c]);
   }
   if (e == hipSuccess) e = nnls::prepare_batched_gram();  // attributes are set outside capture
   if (e != hipSuccess) {
     plan_fail(e);
     return NNLS_E_HIP;
   }
-  // the class with the most expensive problem runs first
-  int slots[nnls::kSolveClasses] = {0, 1, 2};
-  std::sort(slots, slots + nnls::kSolveClasses, [&](int a, int b) {
+  // the group with the most expensive problem goes first
+  int slots[nnls::kSolveGroups];
+  std::iota(slots, slots + nnls::kSolveGroups, 0);
+  std::sort(slots, slots + nnls::kSolveGroups, [&](int a, int b) {
     const double ca = order[a].empty() ? -1.0 : cost[order[a][0]];
     const double cb = order[b].empty() ? -1.0 : cost[order[b][0]];
     return ca > cb;
@@ -513,25 +529,26 @@ int nnls_batched_plan_create(const nnls_problem_desc* host_desc, int64_t count, 
   // grid sized to fill the GPU, so a later class's workgroups start on the compute units the
   // earlier class frees as its queue runs dry (its tail) instead of after it.  The side
   // streams and events only carry the capture (default priority; released below).
-  hipStream_t side[nnls::kSolveClasses] = {};
-  hipEvent_t fork = nullptr, join[nnls::kSolveClasses] = {};
+  hipStream_t side[nnls::kSolveGroups] = {};
+  hipEvent_t fork = nullptr, join[nnls::kSolveGroups] = {};
   e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-  for (int i = 1; i < nnls::kSolveClasses && e == hipSuccess; ++i) {
+  for (int i = 1; i < nnls::kSolveGroups && e == hipSuccess; ++i) {
     e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
   }
   if (e == hipSuccess) e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(nnls::batched_queue_reset, dim3(1), dim3(64), 0, st, counters,
-                       nnls::kSolveClasses);
+                       nnls::kSolveGroups);
     hipError_t e1 = launch_gram_lists((const BatchGramItem*)(base + L.items), cnt, bb, st);
     if (e1 == hipSuccess) e1 = hipEventRecord(fork, st);
-    for (int i = 0; i < nnls::kSolveClasses && e1 == hipSuccess; ++i) {
-      if (args[slots[i]].count <= 0) continue;
+    for (int i = 0; i < nnls::kSolveGroups && e1 == hipSuccess; ++i) {
+      const int g = slots[i];
+      if (args[g].count <= 0) continue;
       hipStream_t s_i = i == 0 ? st : side[i];
       if (i > 0) e1 = hipStreamWaitEvent(s_i, fork, 0);
       if (e1 == hipSuccess)
-        e1 = launch_solve_class(slots[i], args[slots[i]], lds[slots[i]], grid[slots[i]], s_i);
+        e1 = launch_solve_class(g / nnls::kCaps, args[g], lds[g], grid[g], s_i);
       if (e1 == hipSuccess && i > 0) e1 = hipEventRecord(join[i], s_i);
       if (e1 == hipSuccess && i > 0) e1 = hipStreamWaitEvent(st, join[i], 0);
     }
@@ -540,7 +557,7 @@ int nnls_batched_plan_create(const nnls_problem_desc* host_desc, int64_t count, 
     if (e == hipSuccess && e1 != hipSuccess) e = e1;
     if (e == hipSuccess && e2 != hipSuccess) e = e2;
   }
-  for (int i = 1; i < nnls::kSolveClasses; ++i) {
+  for (int i = 1; i < nnls::kSolveGroups; ++i) {
     if (join[i]) (void)hipEventDestroy(join[i]);
     if (side[i]) (void)hipStreamDestroy(side[i]);
   }
@@ -585,7 +602,7 @@ int nnls_autotune(const char* cache_path, int op, const int64_t* shapes, int64_t
   const std::string arch = device_arch();
   if (arch.empty()) return NNLS_E_HIP;
   hipStream_t st = (hipStream_t)stream;
-  constexpr int64_t kPerClass = 256;  // problems measured per size class
+  constexpr int64_t kPerClass = 1024;  // problems measured per size class
   constexpr int kReps = 3;
 
   // shapes of each class, thinned evenly to at most kPerClass
@@ -691,13 +708,14 @@ int nnls_autotune(const char* cache_path, int op, const int64_t* shapes, int64_t
                     hipMemcpyHostToDevice);
       if (e == hipSuccess) e = launch_gram_lists((const BatchGramItem*)buf[11], cnt, bb, st);
     }
-    // solver: each workgroup size over the class's problems (tolerance and cap of the
-    // batched workload)
-    float solve_ms[nnls::kSolveClasses] = {0.f, 0.f, 0.f};
-    for (int slot = 0; slot < nnls::kSolveClasses && e == hipSuccess; ++slot) {
+    // solver: each workgroup size, with as many resident workgroups as fit and with one per
+    // compute unit, over the class's problems (tolerance and cap of the batched workload)
+    float solve_ms[nnls::kSolveGroups] = {};
+    for (int g = 0; g < nnls::kSolveGroups && e == hipSuccess; ++g) {
+      const int slot = g / nnls::kCaps;
       size_t lds = 0;
       int64_t grid = 0;
-      e = solve_launch_shape(slot, max_n, m, lds, grid);
+      e = solve_launch_shape(slot, max_n, m, kPerCuCaps[g % nnls::kCaps], lds, grid);
       const nnls::BatchSolveArgs B =
           solve_args(bb, bb.desc, (const int*)buf[12], m, (int*)buf[13], 5e-6, 20000);
       if (e == hipSuccess)
@@ -707,14 +725,14 @@ int nnls_autotune(const char* cache_path, int op, const int64_t* shapes, int64_t
                                  (int*)buf[13], 1);
               return launch_solve_class(slot, B, lds, grid, st);
             },
-            solve_ms[slot]);
+            solve_ms[g]);
     }
     for (int b = 0; b < NB; ++b)
       if (buf[b]) (void)hipFree(buf[b]);
     if (e != hipSuccess) break;
-    int best_slot = 0;
-    for (int slot = 1; slot < nnls::kSolveClasses; ++slot)
-      if (solve_ms[slot] < solve_ms[best_slot]) best_slot = slot;
+    int best = 0;
+    for (int g = 1; g < nnls::kSolveGroups; ++g)
+      if (solve_ms[g] < solve_ms[best]) best = g;
     TuneEntry te;
     te.arch = arch;
     te.op = "batched";
@@ -722,15 +740,23 @@ int nnls_autotune(const char* cache_path, int op, const int64_t* shapes, int64_t
     te.lo = c == 0 ? 1 : kClassHi[c - 1] + 1;
     te.hi = kClassHi[c];
     te.gram_tile = best_tile;
-    te.solve_threads = nnls::kSolveThreads[best_slot];
-    char line[640];
+    te.solve_threads = nnls::kSolveThreads[best / nnls::kCaps];
+    te.solve_per_cu = kPerCuCaps[best % nnls::kCaps];
+    std::string sm;
+    for (int g = 0; g < nnls::kSolveGroups; ++g) {
+      char item[48];
+      snprintf(item, sizeof(item), "%s\"%d%s\": %.4f", g ? ", " : "",
+               nnls::kSolveThreads[g / nnls::kCaps], kPerCuCaps[g % nnls::kCaps] ? "/1" : "",
+               solve_ms[g]);
+      sm += item;
+    }
+    char line[800];
     snprintf(line, sizeof(line),
              "{\"arch\": \"%s\", \"op\": \"batched\", \"dtype\": \"f32\", \"n_lo\": %lld, "
-             "\"n_hi\": %lld, \"gram_tile\": %d, \"solve_threads\": %d, \"problems\": %lld, "
-             "\"gram_ms\": {\"64\": %.4f, \"128\": %.4f}, \"solve_ms\": {\"256\": %.4f, "
-             "\"512\": %.4f, \"1024\": %.4f}}",
+             "\"n_hi\": %lld, \"gram_tile\": %d, \"solve_threads\": %d, \"solve_wgs_per_cu\": %d, "
+             "\"problems\": %lld, \"gram_ms\": {\"64\": %.4f, \"128\": %.4f}, \"solve_ms\": {%s}}",
              arch.c_str(), (long long)te.lo, (long long)te.hi, te.gram_tile, te.solve_threads,
-             (long long)m, gram_ms[0], gram_ms[1], solve_ms[0], solve_ms[1], solve_ms[2]);
+             te.solve_per_cu, (long long)m, gram_ms[0], gram_ms[1], sm.c_str());
     te.line = line;
     fresh.push_back(te);
   }

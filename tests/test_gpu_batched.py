@@ -109,16 +109,17 @@ def test_batched_matches_per_problem_launches(solved):
 
 
 # every size class present in _problems(): n <= 64, 128, 256, 512
-_FORCED = {(1, 64): (64, 1024), (65, 128): (64, 512), (129, 256): (128, 1024),
-           (257, 512): (64, 256)}
+# (gram tile, solver workgroup threads, resident workgroups per compute unit: 0 = all that fit)
+_FORCED = {(1, 64): (64, 1024, 0), (65, 128): (64, 512, 1), (129, 256): (128, 1024, 1),
+           (257, 512): (64, 256, 0)}
 
 
 def _write_cache(path, params):
     import torch as _t
     arch = _t.cuda.get_device_properties(0).gcnArchName
     lines = [json.dumps({"arch": arch, "op": "batched", "dtype": "f32", "n_lo": lo, "n_hi": hi,
-                         "gram_tile": t, "solve_threads": nt})
-             for (lo, hi), (t, nt) in params.items()]
+                         "gram_tile": t, "solve_threads": nt, "solve_wgs_per_cu": pc})
+             for (lo, hi), (t, nt, pc) in params.items()]
     with open(path, "w") as f:
         f.write('{"format": "nnls-autotune-1", "entries": [\n' + ",\n".join(lines) + "\n]}\n")
 
@@ -172,14 +173,16 @@ def test_autotune_writes_cache_the_plan_uses(solved, tmp_path):
         cache = json.load(f)
     entries = cache["entries"]
     say("  " + "; ".join(f"n<={e['n_hi']}: tile {e['gram_tile']} threads {e['solve_threads']}"
-                         for e in entries))
+                         f" per CU {e['solve_wgs_per_cu']}" for e in entries))
     assert sorted((e["n_lo"], e["n_hi"]) for e in entries) == sorted(_FORCED)
     for e in entries:
         assert e["op"] == "batched" and e["dtype"] == "f32"
         assert e["gram_tile"] in (64, 128) and e["solve_threads"] in (256, 512, 1024)
+        assert e["solve_wgs_per_cu"] in (0, 1)
         gm, sm = e["gram_ms"], e["solve_ms"]
         assert e["gram_tile"] == min((64, 128), key=lambda t: gm[str(t)])
-        assert e["solve_threads"] == min((256, 512, 1024), key=lambda t: sm[str(t)])
+        chosen = f"{e['solve_threads']}" + ("/1" if e["solve_wgs_per_cu"] else "")
+        assert len(sm) == 6 and sm[chosen] == min(sm.values())
         assert all(v > 0 for v in list(gm.values()) + list(sm.values()))
     # a second tuning of one class replaces only that class's entry
     N.autotune(path, [s for s in shapes if s[1] <= 64])
