@@ -37,11 +37,12 @@ TOL = 1e-5
 GAP_TOL = 1e-6
 # The solve runs below tol in FP32 on the BF16x3 Q; the FP64 check against (A, b) is what must
 # meet tol (it differs from the FP32 residual by ~1e-7 at these workloads).  The large single
-# right-hand side needs r <= 5e-6 for its relative objective gap to stay under 1e-6 (at 8e-6
-# the gap is 1.6e-6: the gap shrinks like r^2); the many right-hand-side workloads meet the gap
-# bar by a factor 30 at 8e-6.
+# right-hand side needs a tighter stop for its relative objective gap to stay under 1e-6 (the
+# gap shrinks like r^2): 8e-6 gave gap 1.6e-6, 7e-6 1.2e-6, 6e-6 0.51e-6 (92 updates, FP64
+# KKT 4.6e-6 after the check's step); the many right-hand-side workloads meet the gap bar by a
+# factor 30 at 8e-6.
 INNER_TOL = 8e-6
-LARGE_INNER_TOL = 5e-6
+LARGE_INNER_TOL = 6e-6
 BATCH_INNER_TOL = 5e-6
 BATCH_MAX_ITER = 20000
 # tolerance of the oracle's continuation that yields f* for the gap (f - f* shrinks like the
@@ -150,6 +151,8 @@ def main():
     ap.add_argument("--only", default=None, choices=["prepare", "copy"],
                     help="large workload: time the Gram alone (no solver launch); copy: a "
                          "256 MiB device copy, the reference for the HBM byte counters")
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="FP32 stop tolerance of the solve (default: per workload)")
     ap.add_argument("--epochs", type=int, default=WARM_EPOCHS)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--cpu-sample-cols", type=int, default=1400)
@@ -275,6 +278,7 @@ def bench_large(args):
 
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     prep_only = args.only == "prepare"
+    inner_tol = LARGE_INNER_TOL if args.inner_tol is None else args.inner_tol
     names = ["split", "gram"] if prep_only else ["split", "gram", "solve", "refine"]
     marks = [[ev() for _ in range(len(names) + 1)] for _ in range(steps_total)]
 
@@ -287,7 +291,7 @@ def bench_large(args):
         e[2].record()
         if prep_only:
             return
-        N.solve(Q, q, s, tol=LARGE_INNER_TOL, max_iter=5 * n, out=(X, iters, kkt, status),
+        N.solve(Q, q, s, tol=inner_tol, max_iter=5 * n, out=(X, iters, kkt, status),
                 ws=ws_v, rows_read=rows)
         e[3].record()
         N.refine(A, b, X, out=(kkt64[i], obj64[i]), ws=ws_r)
@@ -356,7 +360,7 @@ def bench_large(args):
         "data": "synthetic",
         "config": {"workload": "large single RHS: A 20000x5000 FP32 U[0,1], x 70% zeros Exp(1), "
                                "1% noise, seed 0", "d": d, "n": n, "k": k, "tol": TOL,
-                   "parallelism": "single GPU"},
+                   "inner_tol": inner_tol, "parallelism": "single GPU"},
         "roofline": roofs[dom],
         "roofline_other": [roofs[nm] for nm in roofs if nm != dom],
         "gram_tflops": roof_gram["achieved"],
