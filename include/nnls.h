@@ -18,7 +18,9 @@
  *     ldb >= k; Q is [n, n]; q, Y0 and X are [n, k] (leading dimension k).
  *   - Every call is asynchronous and ordered on `stream` (a hipStream_t; NULL = the null stream).
  *     No call synchronises the device or allocates device memory: scratch space comes from the
- *     caller's workspace `ws` of `ws_bytes` bytes, sized by nnls_workspace_bytes().
+ *     caller's workspace `ws` of `ws_bytes` bytes, sized by nnls_workspace_bytes().  The
+ *     exceptions are set-up and file calls, each saying so: the batched plan's create and
+ *     destroy, nnls_autotune, and the checkpoint calls nnls_mlp_save / nnls_mlp_load.
  *   - Arguments are validated on the host before any HIP call.  The return value is a
  *     nnls_error code; NNLS_OK means the work was enqueued.  Per-column outcomes of a solve are
  *     written on the device as nnls_col_status values.
@@ -40,7 +42,10 @@ enum nnls_error {
     NNLS_E_ARG = -1,         /* a size, pointer, leading dimension or mode is invalid */
     NNLS_E_WORKSPACE = -2,   /* ws_bytes is smaller than nnls_workspace_bytes() */
     NNLS_E_HIP = -3,         /* a HIP runtime call failed (see nnls_last_hip_error) */
-    NNLS_E_UNSUPPORTED = -4  /* valid arguments this build does not handle (e.g. n too large) */
+    NNLS_E_UNSUPPORTED = -4, /* valid arguments this build does not handle (e.g. n too large) */
+    NNLS_E_IO = -5           /* a file could not be read or written, or is not a valid
+                                checkpoint of this network (nnls_autotune's cache,
+                                nnls_mlp_save / nnls_mlp_load) */
 };
 
 /* Per-column outcome of a solve, written to the device array `status`. */
@@ -298,7 +303,7 @@ enum nnls_tune_op {
  * 512 and 1024 threads per workgroup (tolerance 5e-6, at most 20000 updates), best of 3 runs
  * after a warm-up each.  Unlike the other calls this one is a setup step: it allocates and
  * frees its own device memory and synchronises `stream`.  Errors: NNLS_E_ARG (bad pointers,
- * shapes or op, or the cache could not be written), NNLS_E_UNSUPPORTED (n_i > 1024 or
+ * shapes or op), NNLS_E_IO (the cache could not be written), NNLS_E_UNSUPPORTED (n_i > 1024 or
  * d_i > 16384), NNLS_E_HIP.
  */
 int nnls_autotune(const char* cache_path, int op, const int64_t* shapes, int64_t count,
@@ -362,6 +367,24 @@ int nnls_mlp_gradients(int64_t batch, const void* blob, const float* u, const fl
 int nnls_mlp_train_step(int64_t batch, void* blob, const float* u, const float* target, float lr,
                         int64_t step, float lambda, float* loss_out, void* ws, size_t ws_bytes,
                         void* stream);
+
+/* Checkpoints of the network blob, so that training can stop and resume exactly.
+ * nnls_mlp_save copies the whole blob (master weights, both Adam moments, the BF16 copy and the
+ * input standardisation) to the host on `stream`, waits for the copy, and writes
+ *     64-byte header | blob (nnls_mlp_blob_bytes() bytes, the device layout above)
+ * to `path` (through `path`.tmp and a rename, so a reader never sees a partial file).  The
+ * header is little-endian: magic "NNLSCKP1", u32 version 1, u32 widths 256, 1024, 256,
+ * i64 parameter count, u64 blob bytes, i64 `step` (the number of Adam steps taken, which
+ * the next nnls_mlp_train_step continues from as step + 1), u64 FNV-1a hash of the blob, u64 0.
+ * nnls_mlp_load reads and checks the whole file (header fields, size, hash) before it touches
+ * the device, then copies the blob into `blob` on `stream`, waits for the copy, and stores the
+ * step in *step (may be NULL).  Both synchronise `stream` and allocate host memory only.
+ * Errors: NNLS_E_ARG (null blob or path), NNLS_E_IO (the file cannot be opened, read or
+ * written, or it is not a checkpoint of this network: wrong magic, version, widths or size, or
+ * a hash mismatch), NNLS_E_HIP.  The caller keeps `blob` alive and unused by other work on
+ * other streams during the call. */
+int nnls_mlp_save(const void* blob, int64_t step, const char* path, void* stream);
+int nnls_mlp_load(void* blob, int64_t* step, const char* path, void* stream);
 
 /* Network inputs and training targets from a rescaled problem with n = 256: for each column c
  * of q [256, k], U[c, :] = q[:, c] / ||q_c|| and, if Y [256, k] (a solution of Problem (5), e.g.

@@ -778,7 +778,7 @@ int nnls_autotune(const char* cache_path, int op, const int64_t* shapes, int64_t
       }
     if (!replaced) all.push_back(f);
   }
-  return write_cache(cache_path, all) ? NNLS_OK : NNLS_E_ARG;
+  return write_cache(cache_path, all) ? NNLS_OK : NNLS_E_IO;
 }
 
 }  // extern "C"

@@ -11,6 +11,12 @@
 // pre-activation, bias, plain FP32, GELU backward); the loss and its gradient; column sums for
 // bias gradients; Adam; and the warm-start assembly (line-search scale, and the fallback to y = 0
 // when v gives no descent).
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
 #include "../../include/nnls.h"
 #include "common.hpp"
 #include "kernels.hpp"
@@ -505,10 +511,97 @@ __global__ __launch_bounds__(256) void ws_assemble_kernel(int64_t k, const float
   }
 }
 
+// ---- checkpoints: 64-byte little-endian header, then the blob as it lies in device memory ----
+struct CkptHeader {
+  char magic[8];       // "NNLSCKP1"
+  uint32_t version;    // 1
+  uint32_t widths[3];  // ML_IN, ML_H, ML_OUT
+  int64_t params;      // ML_P
+  uint64_t bytes;      // ML_BLOB
+  int64_t step;        // Adam steps taken
+  uint64_t hash;       // FNV-1a 64 of the blob bytes
+  uint64_t reserved;   // 0
+};
+static_assert(sizeof(CkptHeader) == 64, "checkpoint header is 64 bytes");
+constexpr char kCkptMagic[8] = {'N', 'N', 'L', 'S', 'C', 'K', 'P', '1'};
+
+uint64_t fnv1a64(const unsigned char* p, size_t n) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
 }  // namespace nnls
 
 // ---- C ABI -------------------------------------------------------------------------------------
 extern "C" {
+
+int nnls_mlp_save(const void* blob, int64_t step, const char* path, void* stream) {
+  if (!blob || !path || !*path || step < 0) return NNLS_E_ARG;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "wb");
+  if (!f) return NNLS_E_IO;
+  std::vector<unsigned char> host(nnls::ML_BLOB);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(host.data(), blob, nnls::ML_BLOB, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    fclose(f);
+    remove(tmp.c_str());
+    nnls::record_hip_error(e);
+    return NNLS_E_HIP;
+  }
+  nnls::CkptHeader h;
+  memset(&h, 0, sizeof(h));
+  memcpy(h.magic, nnls::kCkptMagic, 8);
+  h.version = 1;
+  h.widths[0] = nnls::ML_IN;
+  h.widths[1] = nnls::ML_H;
+  h.widths[2] = nnls::ML_OUT;
+  h.params = nnls::ML_P;
+  h.bytes = nnls::ML_BLOB;
+  h.step = step;
+  h.hash = nnls::fnv1a64(host.data(), host.size());
+  bool ok = fwrite(&h, sizeof(h), 1, f) == 1 && fwrite(host.data(), 1, host.size(), f) == host.size();
+  ok = (fflush(f) == 0) && ok;
+  ok = (fclose(f) == 0) && ok;
+  if (!ok || rename(tmp.c_str(), path) != 0) {
+    remove(tmp.c_str());
+    return NNLS_E_IO;
+  }
+  return NNLS_OK;
+}
+
+int nnls_mlp_load(void* blob, int64_t* step, const char* path, void* stream) {
+  if (!blob || !path || !*path) return NNLS_E_ARG;
+  FILE* f = fopen(path, "rb");
+  if (!f) return NNLS_E_IO;
+  nnls::CkptHeader h;
+  std::vector<unsigned char> host;
+  bool ok = fread(&h, sizeof(h), 1, f) == 1 && memcmp(h.magic, nnls::kCkptMagic, 8) == 0 &&
+            h.version == 1 && h.widths[0] == (uint32_t)nnls::ML_IN &&
+            h.widths[1] == (uint32_t)nnls::ML_H && h.widths[2] == (uint32_t)nnls::ML_OUT &&
+            h.params == nnls::ML_P && h.bytes == (uint64_t)nnls::ML_BLOB && h.step >= 0;
+  if (ok) {
+    host.resize(nnls::ML_BLOB);
+    ok = fread(host.data(), 1, host.size(), f) == host.size() && fgetc(f) == EOF &&
+         nnls::fnv1a64(host.data(), host.size()) == h.hash;
+  }
+  fclose(f);
+  if (!ok) return NNLS_E_IO;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(blob, host.data(), nnls::ML_BLOB, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    nnls::record_hip_error(e);
+    return NNLS_E_HIP;
+  }
+  if (step) *step = h.step;
+  return NNLS_OK;
+}
 
 int64_t nnls_mlp_param_count(void) { return nnls::ML_P; }
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnnls.so")
 
 # enums of nnls.h
-OK, E_ARG, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4
+OK, E_ARG, E_WORKSPACE, E_HIP, E_UNSUPPORTED, E_IO = 0, -1, -2, -3, -4, -5
 CONVERGED, MAXITER, BREAKDOWN, NONFINITE, FELL_BACK = 0, 1, 2, 3, 4
 GRAM_FP64, GRAM_FP32, GRAM_BF16X3 = 0, 1, 2
 F32, F64 = 0, 1
@@ -24,7 +24,8 @@ TUNE_BATCHED = 1
 NOALLOC_SCRATCH_BYTES = 8 << 20   # NNLS_NOALLOC_SCRATCH_BYTES
 
 _ERRORS = {E_ARG: "invalid argument", E_WORKSPACE: "workspace too small",
-           E_HIP: "HIP runtime error", E_UNSUPPORTED: "unsupported shape"}
+           E_HIP: "HIP runtime error", E_UNSUPPORTED: "unsupported shape",
+           E_IO: "file error or not a checkpoint of this network"}
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -112,6 +113,10 @@ def lib():
         L.nnls_mlp_train_step.argtypes = [_i64, _vp, _vp, _vp, ctypes.c_float, _i64,
                                           ctypes.c_float, _vp, _vp, _sz, _vp]
         L.nnls_mlp_train_step.restype = ctypes.c_int
+        L.nnls_mlp_save.argtypes = [_vp, _i64, ctypes.c_char_p, _vp]
+        L.nnls_mlp_save.restype = ctypes.c_int
+        L.nnls_mlp_load.argtypes = [_vp, ctypes.POINTER(_i64), ctypes.c_char_p, _vp]
+        L.nnls_mlp_load.restype = ctypes.c_int
         L.nnls_mlp_inputs.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _vp]
         L.nnls_mlp_inputs.restype = ctypes.c_int
         L.nnls_warm_start_workspace_bytes.argtypes = [_i64, _i64]
@@ -514,7 +519,7 @@ class WarmStartNet:
     `params` are the initial FP32 master weights in the library's layout; shift and scale the
     input standardisation (default 0 and 1; nnls_mlp_fit_input fits them with fit_input)."""
 
-    def __init__(self, params, device, shift=None, scale=None):
+    def _alloc(self, device):
         L = lib()
         self.P = int(L.nnls_mlp_param_count())
         self.device = torch.device(device)
@@ -522,6 +527,12 @@ class WarmStartNet:
         self.master = self.blob[:4 * self.P].view(torch.float32)
         norm = self.blob[14 * self.P:14 * self.P + 8 * MLP_IN].view(torch.float32)
         self.shift, self.scale = norm[:MLP_IN], norm[MLP_IN:]
+        self.step = 0
+        self._ws = {}
+
+    def __init__(self, params, device, shift=None, scale=None):
+        L = lib()
+        self._alloc(device)
         p = torch.as_tensor(params, dtype=torch.float32).reshape(-1)
         if p.numel() != self.P:
             raise NNLSError(f"expected {self.P} parameters, got {p.numel()}")
@@ -530,8 +541,6 @@ class WarmStartNet:
                          .expand(MLP_IN).to(device))
         self.scale.copy_(torch.as_tensor(1.0 if scale is None else scale, dtype=torch.float32)
                          .expand(MLP_IN).to(device))
-        self.step = 0
-        self._ws = {}
         _check(L.nnls_mlp_reset_state(_ptr(self.blob), _stream(self.device)), "nnls_mlp_reset_state")
 
     def _wsb(self, key, nbytes):
@@ -580,6 +589,27 @@ class WarmStartNet:
                                          self.step, float(lam), _ptr(loss), _ptr(ws), nb,
                                          _stream(self.device)), "nnls_mlp_train_step")
         return loss
+
+    def save(self, path):
+        """Writes the whole blob and the Adam step count to a checkpoint file (nnls_mlp_save)."""
+        _check(lib().nnls_mlp_save(_ptr(self.blob), self.step, os.fsencode(path),
+                                   _stream(self.device)), "nnls_mlp_save")
+
+    def load(self, path):
+        """Replaces the blob and the step count by a checkpoint's (nnls_mlp_load); training
+        continues where the checkpointed run stopped."""
+        step = _i64(0)
+        _check(lib().nnls_mlp_load(_ptr(self.blob), ctypes.byref(step), os.fsencode(path),
+                                   _stream(self.device)), "nnls_mlp_load")
+        self.step = int(step.value)
+
+    @classmethod
+    def from_checkpoint(cls, path, device):
+        """A network restored from a checkpoint file."""
+        net = cls.__new__(cls)
+        net._alloc(device)
+        net.load(path)
+        return net
 
     def warm_start(self, Q, q, out=None):
         """(Y0 [256, k], fell_back [k] int32) for the rescaled problem (Q, q)."""

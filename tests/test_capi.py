@@ -275,3 +275,67 @@ def test_mlp_sizes_and_argument_errors(L):
     assert L.nnls_mlp_inputs(128, 4, FAKE, None, FAKE, None, None) == N.E_UNSUPPORTED
     assert L.nnls_mlp_inputs(256, 4, FAKE, FAKE, FAKE, None, None) == N.E_ARG
     assert L.nnls_mlp_inputs(256, 0, FAKE, None, FAKE, None, None) == N.E_ARG
+
+
+_PAYLOAD = {}
+
+
+def _checkpoint_bytes(L, **over):
+    """A checkpoint file as nnls.h describes it, with a valid FNV-1a hash of its payload (header
+    fields overridable)."""
+    import struct
+    nbytes = int(L.nnls_mlp_blob_bytes())
+    if nbytes not in _PAYLOAD:
+        payload = bytes(range(256)) * (nbytes // 256) + bytes(nbytes % 256)
+        h = 0xcbf29ce484222325
+        for c in payload:
+            h = ((h ^ c) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+        _PAYLOAD[nbytes] = (payload, h)
+    payload, h = _PAYLOAD[nbytes]
+    f = dict(magic=b"NNLSCKP1", version=1, widths=(256, 1024, 256),
+             params=int(L.nnls_mlp_param_count()), nbytes=nbytes, step=7, hash=h, reserved=0)
+    f.update(over)
+    head = struct.pack("<8sI3IqQqQQ", f["magic"], f["version"], *f["widths"], f["params"],
+                       f["nbytes"], f["step"], f["hash"], f["reserved"])
+    assert len(head) == 64
+    return head + payload
+
+
+def test_checkpoint_files_are_checked_before_any_device_copy(L, tmp_path):
+    """nnls_mlp_load reads and checks the whole file first: every damaged or foreign file is
+    refused with NNLS_E_IO before the (never dereferenced) device pointer is touched."""
+    from paper_1502_01645_amd import nnls as N
+    step = ctypes.c_int64(-1)
+    good = _checkpoint_bytes(L)
+    nbytes = int(L.nnls_mlp_blob_bytes())
+    cases = {
+        "missing": None,
+        "empty": b"",
+        "header only": good[:64],
+        "truncated": good[:-1],
+        "trailing byte": good + b"\0",
+        "magic": _checkpoint_bytes(L, magic=b"NNLSCKP2"),
+        "version": _checkpoint_bytes(L, version=2),
+        "widths": _checkpoint_bytes(L, widths=(256, 512, 256)),
+        "params": _checkpoint_bytes(L, params=12),
+        "size field": _checkpoint_bytes(L, nbytes=nbytes - 4),
+        "negative step": _checkpoint_bytes(L, step=-1),
+        "hash": good[:100] + bytes([good[100] ^ 1]) + good[101:],
+    }
+    for name, data in cases.items():
+        path = tmp_path / f"{name.replace(' ', '_')}.ckpt"
+        if data is not None:
+            path.write_bytes(data)
+        rc = L.nnls_mlp_load(FAKE, ctypes.byref(step), os.fsencode(path), None)
+        assert rc == N.E_IO, name
+        assert step.value == -1, name
+    # argument errors
+    p = os.fsencode(tmp_path / "x.ckpt")
+    assert L.nnls_mlp_load(None, None, p, None) == N.E_ARG
+    assert L.nnls_mlp_load(FAKE, None, None, None) == N.E_ARG
+    assert L.nnls_mlp_save(FAKE, 0, None, None) == N.E_ARG
+    assert L.nnls_mlp_save(None, 0, p, None) == N.E_ARG
+    assert L.nnls_mlp_save(FAKE, -1, p, None) == N.E_ARG
+    # an unwritable destination is found before the device copy
+    assert L.nnls_mlp_save(FAKE, 0, os.fsencode(tmp_path / "no" / "dir" / "x.ckpt"),
+                           None) == N.E_IO

@@ -132,6 +132,42 @@ def test_reset_state_clears_moments(params):
     assert np.all(mv == 0)
 
 
+def test_checkpoint_resumes_training_exactly(params, tmp_path):
+    """Training resumed from a checkpoint (nnls_mlp_save / nnls_mlp_load) takes the same steps,
+    bit for bit, as training that never stopped: the file holds the master weights, both Adam
+    moments, the BF16 copy, the input standardisation and the step count."""
+    say("mlp checkpoint save / load / resume")
+    shift, scale = _norm(9)
+    net = N.WarmStartNet(params, DEV, shift, scale)
+    batches = [_batch(64, 40 + i) for i in range(6)]
+    for u, t in batches[:3]:
+        net.train_step(dev(u), dev(t), 1e-3, LAM)
+    path = tmp_path / "net.ckpt"
+    net.save(path)
+    saved = host(net.blob).copy()
+    for u, t in batches[3:]:
+        net.train_step(dev(u), dev(t), 1e-3, LAM)
+    torch.cuda.synchronize()
+    straight = host(net.blob).copy()
+
+    back = N.WarmStartNet.from_checkpoint(path, DEV)
+    assert back.step == 3
+    assert np.array_equal(host(back.blob), saved)
+    for u, t in batches[3:]:
+        back.train_step(dev(u), dev(t), 1e-3, LAM)
+    torch.cuda.synchronize()
+    assert back.step == 6
+    assert np.array_equal(host(back.blob), straight)
+    # a damaged file is refused and leaves the blob as it was
+    raw = bytearray(path.read_bytes())
+    raw[64 + 1000] ^= 0x40
+    bad = tmp_path / "bad.ckpt"
+    bad.write_bytes(bytes(raw))
+    with pytest.raises(N.NNLSError):
+        back.load(bad)
+    assert np.array_equal(host(back.blob), straight)
+
+
 def _warm_problem(k, seed):
     A = W.make_warm_matrix()
     B, _ = W.make_warm_rhs(A, k, split=1, start=seed)
