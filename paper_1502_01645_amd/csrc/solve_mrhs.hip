@@ -2,16 +2,20 @@
 //
 // A workgroup owns 16 column slots.  Per update, for all its active columns at once:
 //   gbar = masked gradient (passive set per column), num_c = ||gbar_c||^2, residual r_c;
-//   W = Q * Gbar on the FP32 matrix cores (v_mfma_f32_16x16x4f32): 16 output columns; for
-//   n <= 256 Q is held in the registers of each workgroup (256 per lane), otherwise it is read
-//   from L2 (every workgroup streams the same n x n matrix);
+//   W = Q * Gbar on the matrix cores: 16 output columns.  For n <= 256 Q is held in the
+//   registers of each workgroup as FP16 hi and lo parts and the product is the three-term split
+//   Q_lo V_hi + Q_hi V_lo + Q_hi V_hi on v_mfma_f32_16x16x32_f16 (below); for n > 256 Q is read
+//   from L2 in FP32 (every workgroup streams the same n x n matrix) for v_mfma_f32_16x16x4f32;
 //   den_c = gbar_c^T W_c, alpha_c = num_c / den_c;  y' = [y - alpha gbar]_+;
 //   grad' = grad + Q (y' - y), the second product of Algorithm 2, again on the matrix cores
 //   (with 16 columns per product the dense form beats gathering the clipped rows of Q).
 // A column whose residual meets tol has its gradient recomputed exactly (Q y + q, one more
-// matrix-core product over all slots) before it retires; it then writes x = y / s, its
+// matrix-core product over all slots, always on the FP32 Q) before it retires; it then writes x = y / s, its
 // iteration count, residual and status, and the slot takes the next column from a queue.
 // State lives in LDS as [row][slot] arrays; rows are padded to a multiple of 16.
+#include <stdlib.h>
+#include <string.h>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -19,6 +23,92 @@ namespace nnls {
 
 constexpr int MR_NT = 256;
 constexpr int MR_SLOTS = 16;
+
+// Split products for Q held in registers.  A value x in FP32 is written as hi + lo with
+// hi = fp16(x) and lo = fp16(x - hi): both are FP16 (11-bit significands), so |x - hi - lo| is
+// at most 2^-22 |x| (the rounding of lo) as long as lo stays in FP16's normal range, and the
+// dropped term lo_Q lo_V is at most 2^-22 |Q_ij V_j|.  The products are exact in the matrix
+// core and summed in FP32, so each term of Q V carries at most 3 2^-22 relative error, against
+// the 2^-24 roundings of the FP32 product's sums.  That is close enough for the two products of
+// an update, which steer the iteration; the exact gradient that decides the stop test, where
+// Q y and q nearly cancel, is formed from the FP32 Q instead.  To keep both parts in FP16's range every row i of Q is scaled by a power of two r_i that
+// brings its largest entry to [2^13, 2^14), and every column c of the vector operand by a power
+// of two sigma_c from a bound on its largest entry (the slot's ||gbar|| or alpha ||gbar||);
+// W = (scaled product) / (r_i sigma_c) exactly.  One v_mfma_f32_16x16x32_f16 (16
+// cycles) covers the k range of eight v_mfma_f32_16x16x4f32 (32 cycles each), so the three
+// split products take 3/16 of the matrix-core time of the FP32 product.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+constexpr int MR_H3_EXP = 14;  // scaled entries stay below 2^14 (FP16 max is 65504)
+
+// sigma with bound * sigma in [2^13, 2^14): a power of two, 1 for a bound that is 0 or not
+// finite
+__device__ __forceinline__ float mr_pow2_scale(float bound) {
+  if (!(bound > 0.f) || !__builtin_isfinite(bound)) return 1.f;
+  int e = 0;
+  (void)frexpf(bound, &e);  // bound = m 2^e, m in [0.5, 1)
+  int x = MR_H3_EXP - e;
+  x = x < -126 ? -126 : (x > 126 ? 126 : x);
+  return ldexpf(1.f, x);
+}
+
+// FP16 hi and lo parts of V [np][16] (LDS) scaled per column by sig[c], in the B-operand order
+// of v_mfma_f32_16x16x32_f16: entry (kh, lane) of Vh / Vl holds rows 32 kh + 8 (lane / 16) +
+// 0..7 of column lane % 16, so a product reads one 16-byte word per lane and k block.
+template <int NT>
+__device__ __forceinline__ void split_h3(const float* V, const float* sig, f16x8* Vh, f16x8* Vl,
+                                         int np) {
+  const int chunks = np / 32 * 64;
+  for (int qi = threadIdx.x; qi < chunks; qi += NT) {
+    const int kh = qi >> 6, ln = qi & 63, c = ln & 15;
+    const int r0 = 32 * kh + 8 * (ln >> 4);
+    const float sc = sig[c];
+    f16x8 h, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float x = V[(r0 + e) * MR_SLOTS + c] * sc;
+      const _Float16 hx = (_Float16)x;
+      h[e] = hx;
+      l[e] = (_Float16)(x - (float)hx);
+    }
+    Vh[qi] = h;
+    Vl[qi] = l;
+  }
+}
+
+// W = Q * V from the register-held split Q (rows scaled by r, rinv = 1 / r in LDS) and the split
+// V (columns scaled by sigma, sinv = 1 / sigma in LDS): wave w owns the row tiles w + NW tt,
+// lane l holds rows 16 t + l % 16 at columns 32 kh + 8 (l / 16) + 0..7 (the A operand).
+template <int TW, int KH, int NW>
+__device__ __forceinline__ void mfma_product_h3(const f16x8 (&qh)[TW][KH],
+                                                const f16x8 (&ql)[TW][KH], const f16x8* Vh,
+                                                const f16x8* Vl, const float* rinv,
+                                                const float* sinv, float* W) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  f32x4 acc[TW];
+#pragma unroll
+  for (int tt = 0; tt < TW; ++tt) acc[tt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kh = 0; kh < KH; ++kh) {
+    const f16x8 bh = Vh[kh * 64 + lane], bl = Vl[kh * 64 + lane];
+#pragma unroll
+    for (int tt = 0; tt < TW; ++tt) {
+      acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ql[tt][kh], bh, acc[tt], 0, 0, 0);
+      acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(qh[tt][kh], bl, acc[tt], 0, 0, 0);
+      acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(qh[tt][kh], bh, acc[tt], 0, 0, 0);
+    }
+  }
+  const float cs = sinv[lr];
+#pragma unroll
+  for (int tt = 0; tt < TW; ++tt) {
+    const int t = wave + NW * tt;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = t * 16 + 4 * lg + e;
+      W[row * MR_SLOTS + lr] = (acc[tt][e] * rinv[row]) * cs;
+    }
+  }
+}
 
 struct MrArgs {
   int n, np, k;
@@ -39,17 +129,18 @@ struct MrArgs {
 };
 
 // W[0..np)[0..16) = Q * V (V: [np][16] in LDS), rows and columns of Q beyond n read as 0.
-// Wave w computes row tiles w, w + 4, ...; for each 16-wide k block a lane loads 4 consecutive
-// Q entries of one row (16 bytes) and feeds them to 4 MFMAs; the k index of MFMA e for lane
-// group g is k0 + 4 g + e, for both operands.  Eight k blocks are loaded before their MFMAs so
-// the L2 latency is paid once per eight.
+// Wave w computes row tiles w, w + NT / 64, ...; for each 16-wide k block a lane loads 4
+// consecutive Q entries of one row (16 bytes) and feeds them to 4 MFMAs; the k index of MFMA e
+// for lane group g is k0 + 4 g + e, for both operands.  Eight k blocks are loaded before their
+// MFMAs so the L2 latency is paid once per eight.
+template <int NT>
 __device__ void mfma_product(const MrArgs& A, const float* V, float* W) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = A.n, np = A.np;
   const int tiles = np / 16;
   const int lr = lane & 15, lg = lane >> 4;
   constexpr int KB = 8;  // k blocks (of 16) whose Q fragments are in flight together
-  for (int t = wave; t < tiles; t += MR_NT / kWave) {
+  for (int t = wave; t < tiles; t += NT / kWave) {
     const int m = t * 16 + lr;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     const float* qrow = A.Q + (int64_t)m * n;
@@ -106,20 +197,27 @@ __device__ __forceinline__ void mfma_product_reg(const float (&qa)[TW][KS], cons
   }
 }
 
-// TPW > 0: Q in registers (n <= 64 TPW); TPW == 0: Q read from L2 by mfma_product.  NT threads
-// per workgroup: 256, or 512 for TPW = 4, where 8 waves of two row tiles each hold Q with 128
-// registers per lane and two waves per SIMD let one wave's vector work run beside the other's
-// matrix-core products.
-template <int TPW, int NT>
+// TPW > 0: Q in registers (n <= 64 TPW), as FP16 hi and lo parts (H3) or in FP32; TPW == 0: Q
+// read from L2 by mfma_product.  NT threads per workgroup: 256, or 512 for TPW = 4, where 8
+// waves of two row tiles each hold Q with 128 registers per lane and two waves per SIMD let one
+// wave's vector work run beside the other's matrix-core products.
+template <int TPW, int NT, bool H3>
 __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrArgs A) {
   static_assert(TPW == 0 ? NT == MR_NT : (4 * TPW) % (NT / 64) == 0, "row tiles per wave");
+  static_assert(!H3 || TPW > 0, "split products need Q in registers");
   extern __shared__ __attribute__((aligned(16))) float sm[];
   const int np = A.np, n = A.n;
   float* Y = sm;                       // [np][16]
   float* Gr = Y + np * MR_SLOTS;       // [np][16] gradient
   float* P = Gr + np * MR_SLOTS;       // [np][16] masked gradient / product operand
   float* W = P + np * MR_SLOTS;        // [np][16] product result
-  float* colf = W + np * MR_SLOTS;     // per-slot floats [8][16]
+  // split products: the operand's FP16 parts, 1 / r per row of Q, sigma and 1 / sigma per slot
+  f16x8* Vh = (f16x8*)(W + np * MR_SLOTS);       // [np / 32][64]
+  f16x8* Vl = Vh + (H3 ? np / 32 * 64 : 0);      // [np / 32][64]
+  float* rinv = (float*)(Vl + (H3 ? np / 32 * 64 : 0));  // [np]
+  float* s_sig = rinv + (H3 ? np : 0);           // [16]
+  float* s_sinv = s_sig + (H3 ? MR_SLOTS : 0);   // [16]
+  float* colf = s_sinv + (H3 ? MR_SLOTS : 0);    // per-slot floats [8][16]
   int* coli = (int*)(colf + 8 * MR_SLOTS);  // per-slot ints [9][16]
   float* red = (float*)(coli + 9 * MR_SLOTS);  // [NT / 64 waves][16 slots][4]
   int* s_anyclip = (int*)(red + (NT / kWave) * MR_SLOTS * 4);  // some slot clipped this update
@@ -147,12 +245,45 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
   const int slot = tid & 15;              // elementwise mapping: slot = tid % 16,
   const int row0 = tid >> 4;              // rows row0 + 16 m
 
-  // Q in registers for the matrix-core products (TPW > 0): TW row tiles per wave, KS k steps
+  // Q in registers for the matrix-core products (TPW > 0): TW row tiles per wave, KS k steps of
+  // 4 (FP32) or KH k steps of 32 (split FP16)
   constexpr int NW = NT / kWave;
   constexpr int TW = TPW > 0 ? 4 * TPW / NW : 1;
-  constexpr int KS = TPW > 0 ? 16 * TPW : 1;
-  float qa[TW][KS];
-  if (TPW > 0) {
+  constexpr int KS = (TPW > 0 && !H3) ? 16 * TPW : 1;
+  constexpr int KH = H3 ? 2 * TPW : 1;
+  float qa[H3 ? 1 : TW][KS];
+  f16x8 qh[H3 ? TW : 1][KH], ql[H3 ? TW : 1][KH];
+  if constexpr (H3) {
+    const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int tt = 0; tt < TW; ++tt) {
+      const int m = (wave + NW * tt) * 16 + lr;
+      float v[KH][8];
+      float mx = 0.f;
+#pragma unroll
+      for (int kh = 0; kh < KH; ++kh)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int kk = 32 * kh + 8 * lg + e;
+          v[kh][e] = (m < n && kk < n) ? A.Q[(int64_t)m * n + kk] : 0.f;
+          mx = fmaxf(mx, fabsf(v[kh][e]));
+        }
+      // the row's largest entry: the four lanes l % 16 == lr of the wave hold the whole row
+      mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+      const float r = mr_pow2_scale(mx);
+      if (lg == 0) rinv[m] = 1.f / r;
+#pragma unroll
+      for (int kh = 0; kh < KH; ++kh)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float x = v[kh][e] * r;
+          const _Float16 hx = (_Float16)x;
+          qh[tt][kh][e] = hx;
+          ql[tt][kh][e] = (_Float16)(x - (float)hx);
+        }
+    }
+  } else if constexpr (TPW > 0) {
     const int lr = lane & 15, lg = lane >> 4;
 #pragma unroll
     for (int tt = 0; tt < TW; ++tt) {
@@ -164,9 +295,26 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
       }
     }
   }
+  // W = Q V for V [np][16] in LDS.  Split products first split V with the per-slot scales
+  // s_sig, which the caller has set (and made visible with a barrier) beforehand.
   auto product = [&](const float* V, float* Wout) {
-    if constexpr (TPW > 0) mfma_product_reg<TW, KS, NW>(qa, V, Wout);
-    else mfma_product(A, V, Wout);
+    if constexpr (H3) {
+      split_h3<NT>(V, s_sig, Vh, Vl, np);
+      __syncthreads();
+      mfma_product_h3<TW, KH, NW>(qh, ql, Vh, Vl, rinv, s_sinv, Wout);
+    } else if constexpr (TPW > 0) {
+      mfma_product_reg<TW, KS, NW>(qa, V, Wout);
+    } else {
+      mfma_product<NT>(A, V, Wout);
+    }
+  };
+  // per-slot operand scale from a bound on the column's largest entry (threads 0..15)
+  auto set_scale = [&](int sl, float bound) {
+    if constexpr (H3) {
+      const float sg = mr_pow2_scale(bound);
+      s_sig[sl] = sg;
+      s_sinv[sl] = 1.f / sg;
+    }
   };
 
   // -- load a column into a slot: y = max(Y0, 0) or 0, gradient = q (exact for a cold start)
@@ -270,7 +418,10 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
     if (any_slot(s_ref, true)) {
       for (int e = tid; e < np * MR_SLOTS; e += NT) P[e] = Y[e];
       __syncthreads();
-      product(P, W);
+      // The exact gradient decides the stop test, where Q y and q nearly cancel: with split
+      // products it is formed from the FP32 Q in L2 instead (a few refreshes per column)
+      if constexpr (H3) mfma_product<NT>(A, P, W);
+      else product(P, W);
       __syncthreads();
       if (s_ref[slot] && s_col[slot] >= 0) {
         const int col = s_col[slot];
@@ -311,6 +462,7 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
     // ---- per-slot decisions (threads 0..15): finish, refresh, or update
     if (tid < MR_SLOTS) {
       s_act[tid] = 0;
+      set_scale(tid, sqrtf(s_num[tid]));  // |gbar_i| <= ||gbar||
       // the clip flag was last read before the barriers of the statistics reduction
       if (tid == 0) *s_anyclip = 0;
       const int col = s_col[tid];
@@ -410,6 +562,8 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
         s_ref[tid] = 0;
       } else {
         s_alpha[tid] = s_num[tid] / den;
+        // |y'_i - y_i| <= alpha |gbar_i| <= alpha ||gbar|| (a clipped entry moves less)
+        set_scale(tid, s_alpha[tid] * sqrtf(s_num[tid]));
       }
     }
     __syncthreads();
@@ -483,16 +637,28 @@ static int mr_np(int64_t n) {
 // threads per workgroup of the kernel instance that serves n
 static int mr_nt(int64_t n) { return mr_tpw(n) == 4 ? 512 : MR_NT; }
 
-size_t solve_mrhs_lds_bytes(int64_t n) {
+// split FP16 products for the register-held Q, unless NNLS_MRHS_PRODUCT=fp32 asks for the FP32
+// products (kept for comparison)
+static bool mr_h3(int64_t n) {
+  if (mr_tpw(n) == 0) return false;
+  const char* v = getenv("NNLS_MRHS_PRODUCT");
+  return !(v && strcmp(v, "fp32") == 0);
+}
+
+static size_t mr_lds_bytes(int64_t n, bool split) {
   const size_t np = (size_t)mr_np(n);
   const size_t nw = (size_t)mr_nt(n) / kWave;
-  return sizeof(float) * 4 * np * MR_SLOTS +
+  const size_t h3 = split ? 2 * sizeof(f16x8) * (np / 32 * 64) + sizeof(float) * np +
+                                sizeof(float) * 2 * MR_SLOTS
+                          : 0;
+  return sizeof(float) * 4 * np * MR_SLOTS + h3 +
          sizeof(float) * 8 * MR_SLOTS + sizeof(int) * 9 * MR_SLOTS +
          sizeof(float) * nw * MR_SLOTS * 4 + sizeof(int) * 8 + 64;
 }
 
 bool solve_mrhs_supported(int64_t n, int64_t k) {
-  return k >= 2 && n >= 1 && (n % 4) == 0 && solve_mrhs_lds_bytes(n) <= 160 * 1024;
+  // (the larger of the two layouts, so the answer does not depend on the product form)
+  return k >= 2 && n >= 1 && (n % 4) == 0 && mr_lds_bytes(n, mr_tpw(n) > 0) <= 160 * 1024;
 }
 
 size_t solve_mrhs_ws_bytes() { return 256; }
@@ -505,14 +671,27 @@ hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* 
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const size_t lds = solve_mrhs_lds_bytes(n);
+  const bool h3 = mr_h3(n);
+  const size_t lds = mr_lds_bytes(n, h3);  // the layout of the instance picked below
   const void* kern = nullptr;
   switch (mr_tpw(n)) {
-    case 1: kern = (const void*)solve_mrhs_kernel<1, MR_NT>; break;
-    case 2: kern = (const void*)solve_mrhs_kernel<2, MR_NT>; break;
-    case 3: kern = (const void*)solve_mrhs_kernel<3, MR_NT>; break;
-    case 4: kern = (const void*)solve_mrhs_kernel<4, 512>; break;
-    default: kern = (const void*)solve_mrhs_kernel<0, MR_NT>; break;
+    case 1:
+      kern = h3 ? (const void*)solve_mrhs_kernel<1, MR_NT, true>
+                : (const void*)solve_mrhs_kernel<1, MR_NT, false>;
+      break;
+    case 2:
+      kern = h3 ? (const void*)solve_mrhs_kernel<2, MR_NT, true>
+                : (const void*)solve_mrhs_kernel<2, MR_NT, false>;
+      break;
+    case 3:
+      kern = h3 ? (const void*)solve_mrhs_kernel<3, MR_NT, true>
+                : (const void*)solve_mrhs_kernel<3, MR_NT, false>;
+      break;
+    case 4:
+      kern = h3 ? (const void*)solve_mrhs_kernel<4, 512, true>
+                : (const void*)solve_mrhs_kernel<4, 512, false>;
+      break;
+    default: kern = (const void*)solve_mrhs_kernel<0, MR_NT, false>; break;
   }
   const int nt = mr_nt(n);
   int per_cu = 1;

@@ -2,10 +2,12 @@
 
 The solver has one instance per register shape of Q: n <= 64, 128, 192 (Q in registers, 256
 threads), n in (192, 256] (Q in registers over 8 waves, 512 threads) and n > 256 (Q read from
-L2).  Each instance is checked one update at a time from the oracle's own iterates (both
-products of Algorithm 2: the line-search product Q gbar and the gradient correction Q (y' - y),
-including the clip-free form -alpha Q gbar), and end to end on the shapes of the many-RHS and
-warm-start workloads with more columns than resident slots, so the column queue refills.
+L2).  With Q in registers the products run as split FP16 products by default and as FP32
+products under NNLS_MRHS_PRODUCT=fp32; both forms are checked.  Each instance is checked one
+update at a time from the oracle's own iterates (both products of Algorithm 2: the line-search
+product Q gbar and the gradient correction Q (y' - y), including the clip-free form
+-alpha Q gbar), and end to end on the shapes of the many-RHS and warm-start workloads with more
+columns than resident slots, so the column queue refills.
 """
 import numpy as np
 import pytest
@@ -43,12 +45,17 @@ def _passive_and_clipped(Q, q, y):
 # (n, k): 160 and 192 take the 3-tile instance, 200 and 256 the 512-thread 4-tile instance,
 # 300 and 512 the instance that reads Q from L2; k leaves a ragged last group of 16 slots
 # (k = 2, 3, 4: one nearly empty group, n = 64, 128, 256: one to four register tiles).
+@pytest.mark.parametrize("product", ["split16", "fp32"])
 @pytest.mark.parametrize("n,k", [(160, 37), (192, 21), (200, 37), (256, 37), (300, 21),
                                  (512, 19), (256, 19), (64, 2), (128, 4), (256, 3)])
-def test_mrhs_steps_match_oracle(n, k, monkeypatch):
+def test_mrhs_steps_match_oracle(n, k, product, monkeypatch):
     monkeypatch.setenv("NNLS_SOLVER", "mrhs")
+    if product == "fp32":
+        if n > 256:
+            pytest.skip("Q read from L2 has only the FP32 product")
+        monkeypatch.setenv("NNLS_MRHS_PRODUCT", "fp32")
     assert N.solver_name(n, k) == "mrhs"
-    say(f"mrhs single steps n={n} k={k}")
+    say(f"mrhs single steps n={n} k={k} product={product}")
     A, B = _uniform_case(500 + n, 3 * n, n, k)
     Q, q, s = N.prepare(dev(A), dev(B))
     Qh, qh = host(Q).astype(np.float64), host(q).astype(np.float64)
@@ -85,6 +92,48 @@ def test_mrhs_steps_match_oracle(n, k, monkeypatch):
         say(f"  m={m}: worst rel err {worst:.2e}")
     # the gradient correction with clipped entries (the second product) was exercised
     assert clipped_total > 0
+
+
+def _one_update(Q, q, Y0):
+    Y, iters, _, st = N.solve(Q, q, None, tol=0.0, max_iter=1, Y0=Y0)
+    assert np.all(host(iters) == 1) and np.all(host(st) == N.MAXITER)
+    return host(Y).astype(np.float64)
+
+
+def test_mrhs_split_products_on_unscaled_lopsided_gram(monkeypatch):
+    """Algorithm 2 on the unscaled problem (H, h) = (A^T A, -A^T B) with column lengths spread
+    over four decades: rows of H differ by up to 10^8 and its largest entries exceed FP16's
+    range, so only the per-row scales of the split products keep them representable.  One
+    update from the oracle's iterates agrees with the FP64 step as closely as the FP32
+    products' update does."""
+    monkeypatch.setenv("NNLS_SOLVER", "mrhs")
+    n, k, d = 256, 37, 768
+    rng = np.random.default_rng(77)
+    A = (rng.random((d, n)) * 10.0 ** rng.uniform(-2, 2, n)).astype(np.float32)
+    X = np.where(rng.random((n, k)) < 0.6, 0.0, rng.random((n, k)))
+    B = (A.astype(np.float64) @ X).astype(np.float32)
+    H, h = N.gram(dev(A), dev(B))
+    Hh, hh = host(H).astype(np.float64), host(h).astype(np.float64)
+    assert np.abs(Hh).max() > 65504.0
+    say(f"mrhs split products on the unscaled Gram: max |H| {np.abs(Hh).max():.3e}")
+    for m in [0, 5, 40]:
+        Ym = np.zeros((n, k))
+        if m:
+            for c in range(k):
+                Ym[:, c] = orc().nqp(Hh, hh[:, c], 0.0, m)[0]
+        Ystart = Ym.astype(np.float32)
+        Y0 = dev(Ystart) if m else None
+        Ys = _one_update(H, h, Y0)
+        monkeypatch.setenv("NNLS_MRHS_PRODUCT", "fp32")
+        Yf = _one_update(H, h, Y0)
+        monkeypatch.delenv("NNLS_MRHS_PRODUCT")
+        for c in range(k):
+            yn = orc().nqp(Hh, hh[:, c], 0.0, 1, y0=Ystart[:, c].astype(np.float64))[0]
+            scale = np.abs(Ystart[:, c]).max() + np.abs(yn).max()
+            err_s = np.abs(Ys[:, c] - yn).max()
+            err_f = np.abs(Yf[:, c] - yn).max()
+            assert np.isfinite(err_s), (m, c)
+            assert err_s <= max(8 * n * 2.0 ** -23 * scale, 4 * err_f), (m, c, err_s, err_f)
 
 
 def _check(A, B, res, sample, what):
