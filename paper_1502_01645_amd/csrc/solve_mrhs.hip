@@ -16,6 +16,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -23,6 +25,18 @@ namespace nnls {
 
 constexpr int MR_NT = 256;
 constexpr int MR_SLOTS = 16;
+
+// Line-search denominators from a product's epilogue: den_c = V_c^T W_c, summed per lane over
+// the output entries it writes (Vd[row][c] * W[row][c]), then over the four lanes of the wave
+// that share the slot; lanes 0..15 of each wave write the wave's partial to redw[wave][slot].
+// Every wave calls it (with 0 when it wrote nothing).  Products that form no denominator are
+// instantiated with DEN = false and leave redw alone.
+__device__ __forceinline__ void den_publish(float dp, float* redw) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  dp += __shfl_xor(dp, 16, 64);
+  dp += __shfl_xor(dp, 32, 64);
+  if (lane < MR_SLOTS) redw[wave * MR_SLOTS + lane] = dp;
+}
 
 // Split products for Q held in registers.  A value x in FP32 is written as hi + lo with
 // hi = fp16(x) and lo = fp16(x - hi): both are FP16 (11-bit significands), so |x - hi - lo| is
@@ -78,11 +92,12 @@ __device__ __forceinline__ void split_h3(const float* V, const float* sig, f16x8
 // W = Q * V from the register-held split Q (rows scaled by r, rinv = 1 / r in LDS) and the split
 // V (columns scaled by sigma, sinv = 1 / sigma in LDS): wave w owns the row tiles w + NW tt,
 // lane l holds rows 16 t + l % 16 at columns 32 kh + 8 (l / 16) + 0..7 (the A operand).
-template <int TW, int KH, int NW>
+template <int TW, int KH, int NW, bool DEN>
 __device__ __forceinline__ void mfma_product_h3(const f16x8 (&qh)[TW][KH],
                                                 const f16x8 (&ql)[TW][KH], const f16x8* Vh,
                                                 const f16x8* Vl, const float* rinv,
-                                                const float* sinv, float* W) {
+                                                const float* sinv, float* W, const float* Vd,
+                                                float* redw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   f32x4 acc[TW];
@@ -99,15 +114,19 @@ __device__ __forceinline__ void mfma_product_h3(const f16x8 (&qh)[TW][KH],
     }
   }
   const float cs = sinv[lr];
+  float dp = 0.f;
 #pragma unroll
   for (int tt = 0; tt < TW; ++tt) {
     const int t = wave + NW * tt;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int row = t * 16 + 4 * lg + e;
-      W[row * MR_SLOTS + lr] = (acc[tt][e] * rinv[row]) * cs;
+      const float w = (acc[tt][e] * rinv[row]) * cs;
+      W[row * MR_SLOTS + lr] = w;
+      if constexpr (DEN) dp += Vd[row * MR_SLOTS + lr] * w;
     }
   }
+  if constexpr (DEN) den_publish(dp, redw);
 }
 
 struct MrArgs {
@@ -131,15 +150,17 @@ struct MrArgs {
 // W[0..np)[0..16) = Q * V (V: [np][16] in LDS), rows and columns of Q beyond n read as 0.
 // Wave w computes row tiles w, w + NT / 64, ...; for each 16-wide k block a lane loads 4
 // consecutive Q entries of one row (16 bytes) and feeds them to 4 MFMAs; the k index of MFMA e
-// for lane group g is k0 + 4 g + e, for both operands.  Eight k blocks are loaded before their
-// MFMAs so the L2 latency is paid once per eight.
-template <int NT>
-__device__ void mfma_product(const MrArgs& A, const float* V, float* W) {
+// for lane group g is k0 + 4 g + e, for both operands.  KB k blocks (8 by default) are loaded
+// before their MFMAs so the L2 latency is paid once per KB.
+template <int NT, bool DEN, int KB = 8>
+__device__ void mfma_product(const MrArgs& A, const float* V, float* W, const float* Vd,
+                             float* redw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n = A.n, np = A.np;
   const int tiles = np / 16;
   const int lr = lane & 15, lg = lane >> 4;
-  constexpr int KB = 8;  // k blocks (of 16) whose Q fragments are in flight together
+  float dp = 0.f;
+  // KB: k blocks (of 16) whose Q fragments are in flight together
   for (int t = wave; t < tiles; t += NT / kWave) {
     const int m = t * 16 + lr;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -165,8 +186,13 @@ __device__ void mfma_product(const MrArgs& A, const float* V, float* W) {
     }
     // D layout: lane holds column (lane & 15), rows 4 * (lane >> 4) + e of the tile
 #pragma unroll
-    for (int e = 0; e < 4; ++e) W[(t * 16 + 4 * lg + e) * MR_SLOTS + lr] = acc[e];
+    for (int e = 0; e < 4; ++e) {
+      const int row = t * 16 + 4 * lg + e;
+      W[row * MR_SLOTS + lr] = acc[e];
+      if constexpr (DEN) dp += Vd[row * MR_SLOTS + lr] * acc[e];
+    }
   }
+  if constexpr (DEN) den_publish(dp, redw);
 }
 
 // W = Q * V with Q held in registers (n <= 256): of NW waves, wave w owns the row tiles
@@ -174,9 +200,9 @@ __device__ void mfma_product(const MrArgs& A, const float* V, float* W) {
 // ks < KS (np = 4 KS), the A operand of MFMA ks, so a product reads only V from LDS (lane l: row
 // 4 ks + l / 16, slot l % 16; 16 consecutive lanes hit 16 consecutive banks) and one V value
 // feeds TW MFMAs.
-template <int TW, int KS, int NW>
+template <int TW, int KS, int NW, bool DEN>
 __device__ __forceinline__ void mfma_product_reg(const float (&qa)[TW][KS], const float* V,
-                                                 float* W) {
+                                                 float* W, const float* Vd, float* redw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   f32x4 acc[TW];
@@ -189,12 +215,18 @@ __device__ __forceinline__ void mfma_product_reg(const float (&qa)[TW][KS], cons
     for (int tt = 0; tt < TW; ++tt)
       acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[tt][ks], b, acc[tt], 0, 0, 0);
   }
+  float dp = 0.f;
 #pragma unroll
   for (int tt = 0; tt < TW; ++tt) {
     const int t = wave + NW * tt;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) W[(t * 16 + 4 * lg + e) * MR_SLOTS + lr] = acc[tt][e];
+    for (int e = 0; e < 4; ++e) {
+      const int row = t * 16 + 4 * lg + e;
+      W[row * MR_SLOTS + lr] = acc[tt][e];
+      if constexpr (DEN) dp += Vd[row * MR_SLOTS + lr] * acc[tt][e];
+    }
   }
+  if constexpr (DEN) den_publish(dp, redw);
 }
 
 // TPW > 0: Q in registers (n <= 64 TPW), as FP16 hi and lo parts (H3) or in FP32; TPW == 0: Q
@@ -221,6 +253,10 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
   int* coli = (int*)(colf + 8 * MR_SLOTS);  // per-slot ints [9][16]
   float* red = (float*)(coli + 9 * MR_SLOTS);  // [NT / 64 waves][16 slots][4]
   int* s_anyclip = (int*)(red + (NT / kWave) * MR_SLOTS * 4);  // some slot clipped this update
+  // bit masks over the slots, rebuilt by wave 0 whenever the slot flags change: live (holds a
+  // column), act (takes an update this pass), ref (needs an exact gradient), done (retired)
+  int* s_mask = s_anyclip + 1;  // [4]
+  enum { M_LIVE = 0, M_ACT = 1, M_REF = 2, M_DONE = 3 };
 
   // per-slot state in LDS
   float* s_num = colf + 0 * MR_SLOTS;
@@ -295,17 +331,19 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
       }
     }
   }
-  // W = Q V for V [np][16] in LDS.  Split products first split V with the per-slot scales
-  // s_sig, which the caller has set (and made visible with a barrier) beforehand.
-  auto product = [&](const float* V, float* Wout) {
+  // W = Q V for V [np][16] in LDS; with den, also the partials of V_c^T W_c per wave and slot
+  // in red[wave][slot].  Split products first split V with the per-slot scales s_sig, which the
+  // caller has set (and made visible with a barrier) beforehand.
+  auto product = [&](const float* V, float* Wout, auto den) {
+    constexpr bool DEN = decltype(den)::value;
     if constexpr (H3) {
       split_h3<NT>(V, s_sig, Vh, Vl, np);
       __syncthreads();
-      mfma_product_h3<TW, KH, NW>(qh, ql, Vh, Vl, rinv, s_sinv, Wout);
+      mfma_product_h3<TW, KH, NW, DEN>(qh, ql, Vh, Vl, rinv, s_sinv, Wout, V, red);
     } else if constexpr (TPW > 0) {
-      mfma_product_reg<TW, KS, NW>(qa, V, Wout);
+      mfma_product_reg<TW, KS, NW, DEN>(qa, V, Wout, V, red);
     } else {
-      mfma_product<NT>(A, V, Wout);
+      mfma_product<NT, DEN>(A, V, Wout, V, red);
     }
   };
   // per-slot operand scale from a bound on the column's largest entry (threads 0..15)
@@ -314,6 +352,27 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
       const float sg = mr_pow2_scale(bound);
       s_sig[sl] = sg;
       s_sinv[sl] = 1.f / sg;
+    }
+  };
+
+  // The slot flags are written by threads 0..15 (lanes 0..15 of wave 0).  Wave 0 then folds
+  // them into s_mask with ballots; the caller's next barrier makes the masks visible, and every
+  // other thread reads one word instead of sixteen flags.
+  auto publish_masks = [&]() {
+    if (wave == 0) {
+      __builtin_amdgcn_wave_barrier();
+      const bool in = lane < MR_SLOTS;
+      const bool live = in && s_col[lane] >= 0;
+      const unsigned long long mlive = __ballot(live);
+      const unsigned long long mact = __ballot(in && s_act[lane] != 0);
+      const unsigned long long mref = __ballot(live && s_ref[lane] != 0);
+      const unsigned long long mdone = __ballot(live && s_done[lane] != 0);
+      if (lane == 0) {
+        s_mask[M_LIVE] = (int)mlive;
+        s_mask[M_ACT] = (int)mact;
+        s_mask[M_REF] = (int)mref;
+        s_mask[M_DONE] = (int)mdone;
+      }
     }
   };
 
@@ -344,8 +403,10 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
     s_rowsh[tid] = 0;
     s_done[tid] = 0;
     s_clip[tid] = 0;
+    s_act[tid] = 0;
     if (tid == 0) *s_anyclip = 0;
   }
+  publish_masks();
   __syncthreads();
   load_slot(slot, s_col[slot]);
   __syncthreads();
@@ -389,15 +450,6 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
     if (sync_after) __syncthreads();
   };
 
-  // OR over the 16 slots of a per-slot predicate read from LDS by every thread (the slot state
-  // is written by threads 0..15 only, and every read follows a barrier after those writes)
-  auto any_slot = [&](const int* flag, bool need_col) {
-    int r = 0;
-#pragma unroll
-    for (int t2 = 0; t2 < MR_SLOTS; ++t2) r |= (flag[t2] != 0 && (!need_col || s_col[t2] >= 0));
-    return r;
-  };
-
   // ||q_c|| of every slot
   auto slot_qnorm = [&]() {
     float acc = 0.f;
@@ -415,13 +467,14 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
 
   for (;;) {
     // ---- exact gradient for slots that asked for it: W = Q Y, grad = W + q
-    if (any_slot(s_ref, true)) {
+    if (s_mask[M_REF]) {
       for (int e = tid; e < np * MR_SLOTS; e += NT) P[e] = Y[e];
       __syncthreads();
       // The exact gradient decides the stop test, where Q y and q nearly cancel: with split
       // products it is formed from the FP32 Q in L2 instead (a few refreshes per column)
-      if constexpr (H3) mfma_product<NT>(A, P, W);
-      else product(P, W);
+      // (four k blocks in flight where the split Q leaves few registers free)
+      if constexpr (H3) mfma_product<NT, false, (TPW == 3 ? 4 : 8)>(A, P, W, nullptr, nullptr);
+      else product(P, W, std::false_type{});
       __syncthreads();
       if (s_ref[slot] && s_col[slot] >= 0) {
         const int col = s_col[slot];
@@ -436,6 +489,7 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
         if (r < (unsigned)s_rows[tid]) s_rowsh[tid] += 1;
         s_rows[tid] = (int)r;
       }
+      publish_masks();
       __syncthreads();
     }
 
@@ -456,10 +510,11 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
         cnt += pas ? 1.f : 0.f;
         bad += (valid && (!__builtin_isfinite(yi) || !__builtin_isfinite(gi))) ? 1.f : 0.f;
       }
-      slot_reduce4(num, res, cnt, bad, s_num, s_res, s_cnt, s_bad);
+      slot_reduce4(num, res, cnt, bad, s_num, s_res, s_cnt, s_bad, false);
     }
 
-    // ---- per-slot decisions (threads 0..15): finish, refresh, or update
+    // ---- per-slot decisions (threads 0..15, right after they summed their slot's statistics):
+    // finish, refresh, or update
     if (tid < MR_SLOTS) {
       s_act[tid] = 0;
       set_scale(tid, sqrtf(s_num[tid]));  // |gbar_i| <= ||gbar||
@@ -496,8 +551,9 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
         }
       }
     }
+    publish_masks();
     __syncthreads();
-    if (any_slot(s_done, true)) {
+    if (s_mask[M_DONE]) {
       // write x = y / s of finished slots, then give each a new column from the queue
       const bool fin = s_col[slot] >= 0 && s_done[slot];
       if (fin) {
@@ -519,35 +575,27 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
         s_rowsh[tid] = 0;
         s_clip[tid] = 0;
       }
+      publish_masks();
       __syncthreads();
       if (fin) load_slot(slot, s_col[slot]);
       __syncthreads();
       slot_qnorm();
       continue;  // evaluate the new columns before any update
     }
-    {
-      int work = 0;
-#pragma unroll
-      for (int t2 = 0; t2 < MR_SLOTS; ++t2) work |= s_col[t2] >= 0;
-      if (!work) break;  // every slot empty: the queue is exhausted
-    }
-    if (!any_slot(s_act, false)) continue;  // only exact-gradient refreshes are pending
+    if (!s_mask[M_LIVE]) break;   // every slot empty: the queue is exhausted
+    if (!s_mask[M_ACT]) continue;  // only exact-gradient refreshes are pending
 
-    // ---- W = Q Gbar on the matrix cores.  The columns of W are independent, so the columns of
-    // slots that take no update need no clearing: their W is never used.  (P was written before
-    // the barriers of the statistics reduction; W was last read before them.)
-    product(P, W);
+    // ---- W = Q Gbar on the matrix cores, with den_c = gbar_c^T W_c from its epilogue.  The
+    // columns of W are independent, so the columns of slots that take no update need no
+    // clearing: their W is never used.  (P was written before the barrier of the statistics
+    // reduction; W and red were last read before the barrier after the decisions.)
+    product(P, W, std::true_type{});
     __syncthreads();
-    {
-      float den = 0.f;
-      for (int i = row0; i < np; i += NT / MR_SLOTS) {
-        const int e = i * MR_SLOTS + slot;
-        den += P[e] * W[e];
-      }
-      slot_reduce4(den, 0.f, 0.f, 0.f, s_den, nullptr, nullptr, nullptr, false);
-    }
     if (tid < MR_SLOTS && s_act[tid]) {
-      const float den = s_den[tid];
+      float den = 0.f;
+#pragma unroll
+      for (int w = 0; w < NT / kWave; ++w) den += red[w * MR_SLOTS + tid];
+      s_den[tid] = den;
       if (!(den > 0.f) || !__builtin_isfinite(den)) {
         // breakdown: retire the column with its current iterate
         const int col = s_col[tid];
@@ -566,6 +614,7 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
         set_scale(tid, s_alpha[tid] * sqrtf(s_num[tid]));
       }
     }
+    publish_masks();
     __syncthreads();
 
     // ---- projected update y' = [y - alpha gbar]_+; P becomes d = y' - y
@@ -597,7 +646,7 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
       // barriers of the next statistics reduction, so no barrier is needed after the adds)
       if (*s_anyclip) {
         // grad' = grad + Q d, the second product of Algorithm 2, on the matrix cores
-        product(P, W);
+        product(P, W, std::false_type{});
         __syncthreads();
         if (act)
           for (int i = row0; i < n; i += NT / MR_SLOTS)
