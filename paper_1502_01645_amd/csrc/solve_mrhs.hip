@@ -35,7 +35,10 @@ __device__ __forceinline__ void den_publish(float dp, float* redw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   dp += __shfl_xor(dp, 16, 64);
   dp += __shfl_xor(dp, 32, 64);
-  if (lane < MR_SLOTS) redw[wave * MR_SLOTS + lane] = dp;
+  // (the index is formed here each time rather than kept in a register through the solve)
+  int at = wave * MR_SLOTS + lane;
+  asm volatile("" : "+v"(at));
+  if (lane < MR_SLOTS) redw[at] = dp;
 }
 
 // Split products for Q held in registers.  A value x in FP32 is written as hi + lo with
@@ -65,39 +68,33 @@ __device__ __forceinline__ float mr_pow2_scale(float bound) {
   return ldexpf(1.f, x);
 }
 
-// FP16 hi and lo parts of V [np][16] (LDS) scaled per column by sig[c], in the B-operand order
-// of v_mfma_f32_16x16x32_f16: entry (kh, lane) of Vh / Vl holds rows 32 kh + 8 (lane / 16) +
-// 0..7 of column lane % 16, so a product reads one 16-byte word per lane and k block.
-template <int NT>
-__device__ __forceinline__ void split_h3(const float* V, const float* sig, f16x8* Vh, f16x8* Vl,
-                                         int np) {
-  const int chunks = np / 32 * 64;
-  for (int qi = threadIdx.x; qi < chunks; qi += NT) {
-    const int kh = qi >> 6, ln = qi & 63, c = ln & 15;
-    const int r0 = 32 * kh + 8 * (ln >> 4);
-    const float sc = sig[c];
-    f16x8 h, l;
+// FP16 hi and lo parts of 8 consecutive rows of one column, scaled by sig, as one entry of the
+// B operand of v_mfma_f32_16x16x32_f16: entry 16 rb + c of Vh / Vl holds rows 8 rb + 0..7 of
+// column c (so k block kh, lane l of a product reads entry 64 kh + l: rows 32 kh + 8 (l / 16) +
+// 0..7 of column l % 16).
+__device__ __forceinline__ void split_chunk(const float (&v)[8], float sig, f16x8* h_out,
+                                            f16x8* l_out) {
+  f16x8 h, l;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float x = V[(r0 + e) * MR_SLOTS + c] * sc;
-      const _Float16 hx = (_Float16)x;
-      h[e] = hx;
-      l[e] = (_Float16)(x - (float)hx);
-    }
-    Vh[qi] = h;
-    Vl[qi] = l;
+  for (int e = 0; e < 8; ++e) {
+    const float x = v[e] * sig;
+    const _Float16 hx = (_Float16)x;
+    h[e] = hx;
+    l[e] = (_Float16)(x - (float)hx);
   }
+  *h_out = h;
+  *l_out = l;
 }
 
 // W = Q * V from the register-held split Q (rows scaled by r, rinv = 1 / r in LDS) and the split
-// V (columns scaled by sigma, sinv = 1 / sigma in LDS): wave w owns the row tiles w + NW tt,
-// lane l holds rows 16 t + l % 16 at columns 32 kh + 8 (l / 16) + 0..7 (the A operand).
-template <int TW, int KH, int NW, bool DEN>
+// V (columns scaled by sigma; cs = 1 / sigma of the lane's column): wave w owns the row tiles
+// w + NW tt, lane l holds rows 16 t + l % 16 at columns 32 kh + 8 (l / 16) + 0..7 (the A
+// operand).  W and Vd are [np][S] in LDS.
+template <int TW, int KH, int NW, int S, bool DEN>
 __device__ __forceinline__ void mfma_product_h3(const f16x8 (&qh)[TW][KH],
                                                 const f16x8 (&ql)[TW][KH], const f16x8* Vh,
-                                                const f16x8* Vl, const float* rinv,
-                                                const float* sinv, float* W, const float* Vd,
-                                                float* redw) {
+                                                const f16x8* Vl, const float* rinv, float cs,
+                                                float* W, const float* Vd, float* redw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   f32x4 acc[TW];
@@ -113,17 +110,19 @@ __device__ __forceinline__ void mfma_product_h3(const f16x8 (&qh)[TW][KH],
       acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(qh[tt][kh], bh, acc[tt], 0, 0, 0);
     }
   }
-  const float cs = sinv[lr];
   float dp = 0.f;
+  // the lane's first output row, formed here rather than kept in a register through the solve;
+  // the other rows are constant offsets from it
+  int row0 = wave * 16 + 4 * lg;
+  asm volatile("" : "+v"(row0));
 #pragma unroll
   for (int tt = 0; tt < TW; ++tt) {
-    const int t = wave + NW * tt;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int row = t * 16 + 4 * lg + e;
+      const int row = row0 + NW * 16 * tt + e;
       const float w = (acc[tt][e] * rinv[row]) * cs;
-      W[row * MR_SLOTS + lr] = w;
-      if constexpr (DEN) dp += Vd[row * MR_SLOTS + lr] * w;
+      W[row * S + lr] = w;
+      if constexpr (DEN) dp += Vd[row * S + lr] * w;
     }
   }
   if constexpr (DEN) den_publish(dp, redw);
@@ -147,12 +146,13 @@ struct MrArgs {
   int* queue;  // next unassigned column (starts at 16 * gridDim.x)
 };
 
-// W[0..np)[0..16) = Q * V (V: [np][16] in LDS), rows and columns of Q beyond n read as 0.
+// W[0..np)[0..16) = Q * V (V: [np][16] in LDS, rows S floats apart), rows and columns of Q
+// beyond n read as 0.
 // Wave w computes row tiles w, w + NT / 64, ...; for each 16-wide k block a lane loads 4
 // consecutive Q entries of one row (16 bytes) and feeds them to 4 MFMAs; the k index of MFMA e
 // for lane group g is k0 + 4 g + e, for both operands.  KB k blocks (8 by default) are loaded
 // before their MFMAs so the L2 latency is paid once per KB.
-template <int NT, bool DEN, int KB = 8>
+template <int NT, bool DEN, int KB = 8, int S = MR_SLOTS>
 __device__ void mfma_product(const MrArgs& A, const float* V, float* W, const float* Vd,
                              float* redw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -178,7 +178,7 @@ __device__ void mfma_product(const MrArgs& A, const float* V, float* W, const fl
         if (k0 + 16 * u < np) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const float b = V[(kk + e) * MR_SLOTS + lr];
+            const float b = V[(kk + e) * S + lr];
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][e], b, acc, 0, 0, 0);
           }
         }
@@ -188,8 +188,8 @@ __device__ void mfma_product(const MrArgs& A, const float* V, float* W, const fl
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int row = t * 16 + 4 * lg + e;
-      W[row * MR_SLOTS + lr] = acc[e];
-      if constexpr (DEN) dp += Vd[row * MR_SLOTS + lr] * acc[e];
+      W[row * S + lr] = acc[e];
+      if constexpr (DEN) dp += Vd[row * S + lr] * acc[e];
     }
   }
   if constexpr (DEN) den_publish(dp, redw);
@@ -229,27 +229,20 @@ __device__ __forceinline__ void mfma_product_reg(const float (&qa)[TW][KS], cons
   if constexpr (DEN) den_publish(dp, redw);
 }
 
-// TPW > 0: Q in registers (n <= 64 TPW), as FP16 hi and lo parts (H3) or in FP32; TPW == 0: Q
-// read from L2 by mfma_product.  NT threads per workgroup: 256, or 512 for TPW = 4, where 8
+// FP32 products.  TPW > 0: Q in registers (n <= 64 TPW); TPW == 0: Q read from L2 by
+// mfma_product.  NT threads per workgroup: 256, or 512 for TPW = 4, where 8
 // waves of two row tiles each hold Q with 128 registers per lane and two waves per SIMD let one
 // wave's vector work run beside the other's matrix-core products.
-template <int TPW, int NT, bool H3>
+template <int TPW, int NT>
 __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrArgs A) {
   static_assert(TPW == 0 ? NT == MR_NT : (4 * TPW) % (NT / 64) == 0, "row tiles per wave");
-  static_assert(!H3 || TPW > 0, "split products need Q in registers");
   extern __shared__ __attribute__((aligned(16))) float sm[];
   const int np = A.np, n = A.n;
   float* Y = sm;                       // [np][16]
   float* Gr = Y + np * MR_SLOTS;       // [np][16] gradient
   float* P = Gr + np * MR_SLOTS;       // [np][16] masked gradient / product operand
   float* W = P + np * MR_SLOTS;        // [np][16] product result
-  // split products: the operand's FP16 parts, 1 / r per row of Q, sigma and 1 / sigma per slot
-  f16x8* Vh = (f16x8*)(W + np * MR_SLOTS);       // [np / 32][64]
-  f16x8* Vl = Vh + (H3 ? np / 32 * 64 : 0);      // [np / 32][64]
-  float* rinv = (float*)(Vl + (H3 ? np / 32 * 64 : 0));  // [np]
-  float* s_sig = rinv + (H3 ? np : 0);           // [16]
-  float* s_sinv = s_sig + (H3 ? MR_SLOTS : 0);   // [16]
-  float* colf = s_sinv + (H3 ? MR_SLOTS : 0);    // per-slot floats [8][16]
+  float* colf = W + np * MR_SLOTS;     // per-slot floats [8][16]
   int* coli = (int*)(colf + 8 * MR_SLOTS);  // per-slot ints [9][16]
   float* red = (float*)(coli + 9 * MR_SLOTS);  // [NT / 64 waves][16 slots][4]
   int* s_anyclip = (int*)(red + (NT / kWave) * MR_SLOTS * 4);  // some slot clipped this update
@@ -281,45 +274,12 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
   const int slot = tid & 15;              // elementwise mapping: slot = tid % 16,
   const int row0 = tid >> 4;              // rows row0 + 16 m
 
-  // Q in registers for the matrix-core products (TPW > 0): TW row tiles per wave, KS k steps of
-  // 4 (FP32) or KH k steps of 32 (split FP16)
+  // Q in registers for the matrix-core products (TPW > 0): TW row tiles per wave, KS k steps
   constexpr int NW = NT / kWave;
   constexpr int TW = TPW > 0 ? 4 * TPW / NW : 1;
-  constexpr int KS = (TPW > 0 && !H3) ? 16 * TPW : 1;
-  constexpr int KH = H3 ? 2 * TPW : 1;
-  float qa[H3 ? 1 : TW][KS];
-  f16x8 qh[H3 ? TW : 1][KH], ql[H3 ? TW : 1][KH];
-  if constexpr (H3) {
-    const int lr = lane & 15, lg = lane >> 4;
-#pragma unroll
-    for (int tt = 0; tt < TW; ++tt) {
-      const int m = (wave + NW * tt) * 16 + lr;
-      float v[KH][8];
-      float mx = 0.f;
-#pragma unroll
-      for (int kh = 0; kh < KH; ++kh)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int kk = 32 * kh + 8 * lg + e;
-          v[kh][e] = (m < n && kk < n) ? A.Q[(int64_t)m * n + kk] : 0.f;
-          mx = fmaxf(mx, fabsf(v[kh][e]));
-        }
-      // the row's largest entry: the four lanes l % 16 == lr of the wave hold the whole row
-      mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
-      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-      const float r = mr_pow2_scale(mx);
-      if (lg == 0) rinv[m] = 1.f / r;
-#pragma unroll
-      for (int kh = 0; kh < KH; ++kh)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float x = v[kh][e] * r;
-          const _Float16 hx = (_Float16)x;
-          qh[tt][kh][e] = hx;
-          ql[tt][kh][e] = (_Float16)(x - (float)hx);
-        }
-    }
-  } else if constexpr (TPW > 0) {
+  constexpr int KS = TPW > 0 ? 16 * TPW : 1;
+  float qa[TW][KS];
+  if constexpr (TPW > 0) {
     const int lr = lane & 15, lg = lane >> 4;
 #pragma unroll
     for (int tt = 0; tt < TW; ++tt) {
@@ -332,27 +292,11 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
     }
   }
   // W = Q V for V [np][16] in LDS; with den, also the partials of V_c^T W_c per wave and slot
-  // in red[wave][slot].  Split products first split V with the per-slot scales s_sig, which the
-  // caller has set (and made visible with a barrier) beforehand.
+  // in red[wave][slot]
   auto product = [&](const float* V, float* Wout, auto den) {
     constexpr bool DEN = decltype(den)::value;
-    if constexpr (H3) {
-      split_h3<NT>(V, s_sig, Vh, Vl, np);
-      __syncthreads();
-      mfma_product_h3<TW, KH, NW, DEN>(qh, ql, Vh, Vl, rinv, s_sinv, Wout, V, red);
-    } else if constexpr (TPW > 0) {
-      mfma_product_reg<TW, KS, NW, DEN>(qa, V, Wout, V, red);
-    } else {
-      mfma_product<NT, DEN>(A, V, Wout, V, red);
-    }
-  };
-  // per-slot operand scale from a bound on the column's largest entry (threads 0..15)
-  auto set_scale = [&](int sl, float bound) {
-    if constexpr (H3) {
-      const float sg = mr_pow2_scale(bound);
-      s_sig[sl] = sg;
-      s_sinv[sl] = 1.f / sg;
-    }
+    if constexpr (TPW > 0) mfma_product_reg<TW, KS, NW, DEN>(qa, V, Wout, V, red);
+    else mfma_product<NT, DEN>(A, V, Wout, V, red);
   };
 
   // The slot flags are written by threads 0..15 (lanes 0..15 of wave 0).  Wave 0 then folds
@@ -470,11 +414,7 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
     if (s_mask[M_REF]) {
       for (int e = tid; e < np * MR_SLOTS; e += NT) P[e] = Y[e];
       __syncthreads();
-      // The exact gradient decides the stop test, where Q y and q nearly cancel: with split
-      // products it is formed from the FP32 Q in L2 instead (a few refreshes per column)
-      // (four k blocks in flight where the split Q leaves few registers free)
-      if constexpr (H3) mfma_product<NT, false, (TPW == 3 ? 4 : 8)>(A, P, W, nullptr, nullptr);
-      else product(P, W, std::false_type{});
+      product(P, W, std::false_type{});
       __syncthreads();
       if (s_ref[slot] && s_col[slot] >= 0) {
         const int col = s_col[slot];
@@ -517,7 +457,6 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
     // finish, refresh, or update
     if (tid < MR_SLOTS) {
       s_act[tid] = 0;
-      set_scale(tid, sqrtf(s_num[tid]));  // |gbar_i| <= ||gbar||
       // the clip flag was last read before the barriers of the statistics reduction
       if (tid == 0) *s_anyclip = 0;
       const int col = s_col[tid];
@@ -610,8 +549,6 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
         s_ref[tid] = 0;
       } else {
         s_alpha[tid] = s_num[tid] / den;
-        // |y'_i - y_i| <= alpha |gbar_i| <= alpha ||gbar|| (a clipped entry moves less)
-        set_scale(tid, s_alpha[tid] * sqrtf(s_num[tid]));
       }
     }
     publish_masks();
@@ -672,6 +609,378 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
   }
 }
 
+
+// Split-product instances (n <= 256): the update of solve_mrhs_kernel, arranged so that most of
+// it runs in registers.  Thread t works on slot c = t % 16 and on the row blocks
+// rb = t / 16 + (NT / 16) j of 8 consecutive rows, which are exactly the operand chunks a split
+// writes; its rows of y, of the gradient and of the product operand stay in its registers.  The
+// state of a slot (column, update count, flags, ||q||) is kept, the same, by every thread of the
+// slot: each of them sums the slot's partial statistics and line-search denominator in the same
+// order and takes the same decisions, and every wave forms the masks over the 16 slots with one
+// ballot (lanes 0..15 of every wave hold slots 0..15).  Threads 0..15 write the outputs.  LDS
+// holds the gradient (each thread reads and writes only its own rows of it), the products'
+// operands and results and the partial sums, and an update takes four barriers (five when a
+// slot clipped).
+constexpr int MR_PS = 20;  // row stride (floats) of the operand and result arrays: the product's
+                           // result writes (rows 4 (l / 16) + e, column l % 16) hit 64 banks
+
+template <int TPW, int NT>
+__global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_split_kernel(MrArgs A) {
+  constexpr int NW = NT / kWave;
+  constexpr int TW = 4 * TPW / NW;            // row tiles of Q per wave
+  constexpr int KH = 2 * TPW;                 // k blocks of 32
+  constexpr int NP = 64 * TPW;                // rows, padded
+  constexpr int NB = NT / MR_SLOTS;           // row-block groups
+  constexpr int RB = NP / 8;                  // row blocks of 8
+  constexpr int JB = (RB + NB - 1) / NB;      // row blocks per thread
+  constexpr int S = MR_PS;
+  static_assert(TPW > 0 && (4 * TPW) % NW == 0, "row tiles per wave");
+  extern __shared__ __attribute__((aligned(16))) float sm[];
+  float* P = sm;                                   // [NP][S] product operand (FP32)
+  float* W = P + NP * S;                           // [NP][S] product result
+  float* G = W + NP * S;                           // [NP][S] gradient
+  f16x8* Vh = (f16x8*)(G + NP * S);                // [RB][16] split operand, hi parts
+  f16x8* Vl = Vh + RB * MR_SLOTS;                  // [RB][16] lo parts
+  float* rinv = (float*)(Vl + RB * MR_SLOTS);      // [NP] 1 / r per row of Q
+  float* red = rinv + NP;                          // [NW][16][4] statistics partials
+  float* red2 = red + NW * MR_SLOTS * 4;           // [NW][16] denominator / ||q||^2 partials
+  int* s_newcol = (int*)(red2 + NW * MR_SLOTS);    // [16] next column of a retired slot
+  int* s_clip = s_newcol + MR_SLOTS;               // [16] clipped rows so far (rows_read)
+  int* s_anyclip = s_clip + MR_SLOTS;              // some slot clipped this update
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = tid & 15, b = tid >> 4;
+  const bool leader = tid < MR_SLOTS;
+  const int n = A.n, k = A.k;
+
+  // ---- Q as FP16 hi and lo parts, each row scaled by a power of two
+  f16x8 qh[TW][KH], ql[TW][KH];
+  {
+    const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int tt = 0; tt < TW; ++tt) {
+      const int m = (wave + NW * tt) * 16 + lr;
+      float v[KH][8];
+      float mx = 0.f;
+#pragma unroll
+      for (int kh = 0; kh < KH; ++kh)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int kk = 32 * kh + 8 * lg + e;
+          v[kh][e] = (m < n && kk < n) ? A.Q[(int64_t)m * n + kk] : 0.f;
+          mx = fmaxf(mx, fabsf(v[kh][e]));
+        }
+      // the row's largest entry: the four lanes l % 16 == lr of the wave hold the whole row
+      mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+      const float r = mr_pow2_scale(mx);
+      if (lg == 0) rinv[m] = 1.f / r;
+#pragma unroll
+      for (int kh = 0; kh < KH; ++kh)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float x = v[kh][e] * r;
+          const _Float16 hx = (_Float16)x;
+          qh[tt][kh][e] = hx;
+          ql[tt][kh][e] = (_Float16)(x - (float)hx);
+        }
+    }
+  }
+
+  // ---- slot state, the same in every thread of the slot
+  int col = blockIdx.x * MR_SLOTS + c;
+  col = col < k ? col : -1;
+  int it = 0;
+  bool fresh = A.Y0 == nullptr, ref = A.Y0 != nullptr && col >= 0, done = false;
+  int64_t rows = 0;
+  float qn = 1.f;
+
+  // ---- own rows: blocks blk(j), rows 8 blk(j) + e
+  float yv[JB][8], pv[JB][8];
+  // k made opaque where the column arrays are addressed, so that the eight row offsets i k are
+  // formed at each use instead of being kept in registers through the whole solve
+  auto opaque_k = [&]() {
+    int kk = k;
+    asm volatile("" : "+s"(kk));
+    return kk;
+  };
+  auto blk = [&](int j) { return b + NB * j; };
+  auto load_rows = [&]() {
+    const int kk = opaque_k();
+#pragma unroll
+    for (int j = 0; j < JB; ++j)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int i = 8 * blk(j) + e;
+        float yi = 0.f, gi = 0.f;
+        if (blk(j) < RB && col >= 0 && i < n) {
+          gi = A.q[(int64_t)i * kk + col];
+          if (A.Y0) {
+            yi = A.Y0[(int64_t)i * kk + col];
+            yi = yi > 0.f ? yi : 0.f;
+          }
+        }
+        yv[j][e] = yi;
+        if (blk(j) < RB) G[i * S + c] = gi;
+      }
+  };
+  // a predicate over the 16 slots as a bit mask, the same in every wave
+  auto mask16 = [&](bool pred) -> unsigned {
+    return (unsigned)(__ballot(lane < MR_SLOTS && pred) & 0xffffull);
+  };
+  // the slot's sum of one value per thread (a barrier inside; red2 is free at every call)
+  auto slot_sum1 = [&](float v) -> float {
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (lane < MR_SLOTS) red2[wave * MR_SLOTS + lane] = v;
+    __syncthreads();
+    float a = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) a += red2[w * MR_SLOTS + c];
+    return a;
+  };
+  auto qnorm = [&]() {
+    const int kk = opaque_k();
+    float a = 0.f;
+    if (col >= 0)
+#pragma unroll
+      for (int j = 0; j < JB; ++j)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int i = 8 * blk(j) + e;
+          if (blk(j) < RB && i < n) {
+            const float qi = A.q[(int64_t)i * kk + col];
+            a += qi * qi;
+          }
+        }
+    const float t2 = slot_sum1(a);
+    qn = t2 > 0.f ? sqrtf(t2) : 1.f;
+  };
+  auto write_rows_lds = [&](float* dst, const float (&v)[JB][8]) {
+#pragma unroll
+    for (int j = 0; j < JB; ++j)
+      if (blk(j) < RB)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dst[(8 * blk(j) + e) * S + c] = v[j][e];
+  };
+  auto split_rows = [&](float sig) {
+#pragma unroll
+    for (int j = 0; j < JB; ++j)
+      if (blk(j) < RB) split_chunk(pv[j], sig, Vh + blk(j) * MR_SLOTS + c, Vl + blk(j) * MR_SLOTS + c);
+  };
+  auto retire = [&](int st, double r) {  // the leader writes the slot's outputs
+    if (leader) {
+      A.iters[col] = it;
+      A.kkt[col] = st == NNLS_NONFINITE_DEV ? __builtin_nan("") : r;
+      A.status[col] = st;
+      if (A.rows_read) A.rows_read[col] = rows + s_clip[c];
+    }
+    done = true;
+  };
+
+  if (leader) s_clip[c] = 0;
+  if (tid == 0) *s_anyclip = 0;
+  load_rows();
+  qnorm();  // (its barrier also publishes rinv)
+
+  for (;;) {
+    // ---- exact gradient for the slots that ask for it, from the FP32 Q in L2: it decides the
+    // stop test, where Q y and q nearly cancel (a few refreshes per column)
+    if (mask16(ref && col >= 0 && !done)) {
+      write_rows_lds(P, yv);
+      __syncthreads();
+      // (four k blocks in flight: the split Q leaves few registers free)
+      mfma_product<NT, false, 4, S>(A, P, W, nullptr, nullptr);
+      __syncthreads();
+      if (ref && col >= 0 && !done) {
+        const int kk = opaque_k();
+#pragma unroll
+        for (int j = 0; j < JB; ++j)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int i = 8 * blk(j) + e;
+            if (blk(j) < RB && i < n) G[i * S + c] = W[i * S + c] + A.q[(int64_t)i * kk + col];
+          }
+        ref = false;
+        fresh = true;
+        rows += n;
+      }
+    }
+
+    // ---- passive set, masked gradient, statistics of the own rows, then summed over the slot
+    const bool live = col >= 0 && !done;
+    float num = 0.f, res = 0.f, cnt = 0.f, bad = 0.f;
+    {
+      float t0 = 0.f, t1 = 0.f, t2 = 0.f, t3 = 0.f;
+#pragma unroll
+      for (int j = 0; j < JB; ++j)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int i = 8 * blk(j) + e;
+          const bool ok = blk(j) < RB && live && i < n;
+          const float yi = yv[j][e], gi = blk(j) < RB ? G[i * S + c] : 0.f;
+          const bool pas = ok && ((yi > 0.f) || (gi < 0.f));
+          const float pi = pas ? gi : 0.f;
+          pv[j][e] = pi;
+          t0 += pi * pi;
+          const float m = yi < gi ? yi : gi;
+          t1 += ok ? m * m : 0.f;
+          t2 += pas ? 1.f : 0.f;
+          t3 += (ok && (!__builtin_isfinite(yi) || !__builtin_isfinite(gi))) ? 1.f : 0.f;
+        }
+#pragma unroll
+      for (int off = 16; off < 64; off <<= 1) {
+        t0 += __shfl_xor(t0, off, 64);
+        t1 += __shfl_xor(t1, off, 64);
+        t2 += __shfl_xor(t2, off, 64);
+        t3 += __shfl_xor(t3, off, 64);
+      }
+      if (lane < MR_SLOTS) *(f32x4*)(red + (wave * MR_SLOTS + lane) * 4) = (f32x4){t0, t1, t2, t3};
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const f32x4 v = *(const f32x4*)(red + (w * MR_SLOTS + c) * 4);
+        num += v[0];
+        res += v[1];
+        cnt += v[2];
+        bad += v[3];
+      }
+    }
+
+    // ---- decisions: finish, refresh, or update
+    bool act = false;
+    double r = 0.0;
+    if (live) {
+      r = sqrt((double)res) / (double)qn;
+      if (leader && A.trace != nullptr && it < A.trace_len) {
+        float* tr = A.trace + ((int64_t)col * A.trace_len + it) * 2;
+        tr[0] = (float)r;
+        tr[1] = num;
+      }
+      if (bad > 0.f) {
+        retire(NNLS_NONFINITE_DEV, r);
+      } else if (cnt == 0.f || r <= A.tol) {
+        if (fresh) retire(NNLS_CONVERGED_DEV, r);
+        else ref = true;
+      } else if (it >= A.max_iter) {
+        if (fresh) retire(NNLS_MAXITER_DEV, r);
+        else ref = true;
+      } else {
+        act = true;
+      }
+    }
+    if (mask16(col >= 0 && done)) {
+      // retired slots write x = y / s and take the next column from the queue
+      if (col >= 0 && done) {
+        const int kk = opaque_k();
+#pragma unroll
+        for (int j = 0; j < JB; ++j)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int i = 8 * blk(j) + e;
+            if (blk(j) < RB && i < n)
+              A.X[(int64_t)i * kk + col] = A.s ? (float)((double)yv[j][e] / A.s[i]) : yv[j][e];
+          }
+        if (leader) {
+          const int next = atomicAdd(A.queue, 1);
+          s_newcol[c] = next < k ? next : -1;
+          s_clip[c] = 0;
+        }
+      }
+      __syncthreads();
+      if (col >= 0 && done) {
+        col = s_newcol[c];
+        it = 0;
+        done = false;
+        fresh = A.Y0 == nullptr;
+        ref = A.Y0 != nullptr && col >= 0;
+        rows = 0;
+        load_rows();
+      }
+      qnorm();
+      continue;  // evaluate the new columns before any update
+    }
+    if (!mask16(col >= 0)) break;  // every slot empty: the queue is exhausted
+    if (!mask16(act)) continue;    // only exact-gradient refreshes are pending
+
+    // ---- W = Q gbar on the matrix cores, with den_c = gbar_c^T W_c from its epilogue
+    if (tid == 0) *s_anyclip = 0;
+    const float sg = act ? mr_pow2_scale(sqrtf(num)) : 1.f;  // |gbar_i| <= ||gbar||
+    write_rows_lds(P, pv);
+    split_rows(sg);
+    __syncthreads();
+    mfma_product_h3<TW, KH, NW, S, true>(qh, ql, Vh, Vl, rinv, 1.f / sg, W, P, red2);
+    __syncthreads();
+
+    // ---- step length, projected update y' = [y - alpha gbar]_+ of the own rows, d = y' - y
+    float alpha = 0.f;
+    if (act) {
+      float den = 0.f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) den += red2[w * MR_SLOTS + c];
+      if (!(den > 0.f) || !__builtin_isfinite(den)) {
+        retire(NNLS_BREAKDOWN_DEV, r);  // the column keeps its current iterate
+        act = false;
+      } else {
+        alpha = num / den;
+      }
+    }
+    int clip_mine = 0;
+#pragma unroll
+    for (int j = 0; j < JB; ++j)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int i = 8 * blk(j) + e;
+        float d = 0.f;
+        if (act && blk(j) < RB && i < n) {
+          const float yo = yv[j][e];
+          const float v = yo - alpha * pv[j][e];
+          const float yn = v > 0.f ? v : 0.f;
+          clip_mine += (v < 0.f) ? 1 : 0;
+          yv[j][e] = yn;
+          d = yn - yo;
+        }
+        pv[j][e] = d;
+      }
+    if (clip_mine) {
+      atomicAdd(&s_clip[c], clip_mine);
+      *s_anyclip = 1;
+    }
+    // |y'_i - y_i| <= alpha |gbar_i| <= alpha ||gbar|| (a clipped entry moves less)
+    const float sd = act ? mr_pow2_scale(alpha * sqrtf(num)) : 1.f;
+    split_rows(sd);
+    __syncthreads();
+
+    // ---- gradient g' = g + Q d, the second product of Algorithm 2; when no slot clipped,
+    // d = -alpha gbar in every slot and Q d = -alpha W from the line-search product
+    if (*s_anyclip) {
+      mfma_product_h3<TW, KH, NW, S, false>(qh, ql, Vh, Vl, rinv, 1.f / sd, W, nullptr, nullptr);
+      __syncthreads();
+      if (act)
+#pragma unroll
+        for (int j = 0; j < JB; ++j)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int i = 8 * blk(j) + e;
+            if (blk(j) < RB && i < n) G[i * S + c] += W[i * S + c];
+          }
+    } else if (act) {
+#pragma unroll
+      for (int j = 0; j < JB; ++j)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int i = 8 * blk(j) + e;
+          if (blk(j) < RB && i < n) G[i * S + c] -= alpha * W[i * S + c];
+        }
+    }
+    if (act) {
+      it += 1;
+      fresh = false;
+      rows += (int64_t)cnt;  // the passive rows of the line-search product
+    }
+  }
+}
+
 __global__ void solve_mrhs_queue_init(int* queue, int first_free) {
   if (threadIdx.x == 0) queue[0] = first_free;
 }
@@ -683,8 +992,13 @@ static int mr_np(int64_t n) {
   return tpw > 0 ? 64 * tpw : (int)((n + 15) / 16 * 16);
 }
 
-// threads per workgroup of the kernel instance that serves n
-static int mr_nt(int64_t n) { return mr_tpw(n) == 4 ? 512 : MR_NT; }
+// threads per workgroup of the kernel instance that serves n: 512 for four row tiles per wave
+// group; with split products also 384 for three (6 waves of two tiles, which leaves the
+// registers the FP16 parts of Q and the own rows need)
+static int mr_nt(int64_t n, bool split) {
+  const int tpw = mr_tpw(n);
+  return tpw == 4 ? 512 : (split && tpw == 3 ? 384 : MR_NT);
+}
 
 // split FP16 products for the register-held Q, unless NNLS_MRHS_PRODUCT=fp32 asks for the FP32
 // products (kept for comparison)
@@ -696,11 +1010,12 @@ static bool mr_h3(int64_t n) {
 
 static size_t mr_lds_bytes(int64_t n, bool split) {
   const size_t np = (size_t)mr_np(n);
-  const size_t nw = (size_t)mr_nt(n) / kWave;
-  const size_t h3 = split ? 2 * sizeof(f16x8) * (np / 32 * 64) + sizeof(float) * np +
-                                sizeof(float) * 2 * MR_SLOTS
-                          : 0;
-  return sizeof(float) * 4 * np * MR_SLOTS + h3 +
+  const size_t nw = (size_t)mr_nt(n, split) / kWave;
+  if (split)  // solve_mrhs_split_kernel's layout
+    return sizeof(float) * 3 * np * MR_PS + 2 * sizeof(f16x8) * (np / 8) * MR_SLOTS +
+           sizeof(float) * np + sizeof(float) * nw * MR_SLOTS * 5 + sizeof(int) * 2 * MR_SLOTS +
+           64;
+  return sizeof(float) * 4 * np * MR_SLOTS +
          sizeof(float) * 8 * MR_SLOTS + sizeof(int) * 9 * MR_SLOTS +
          sizeof(float) * nw * MR_SLOTS * 4 + sizeof(int) * 8 + 64;
 }
@@ -725,24 +1040,24 @@ hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* 
   const void* kern = nullptr;
   switch (mr_tpw(n)) {
     case 1:
-      kern = h3 ? (const void*)solve_mrhs_kernel<1, MR_NT, true>
-                : (const void*)solve_mrhs_kernel<1, MR_NT, false>;
+      kern = h3 ? (const void*)solve_mrhs_split_kernel<1, MR_NT>
+                : (const void*)solve_mrhs_kernel<1, MR_NT>;
       break;
     case 2:
-      kern = h3 ? (const void*)solve_mrhs_kernel<2, MR_NT, true>
-                : (const void*)solve_mrhs_kernel<2, MR_NT, false>;
+      kern = h3 ? (const void*)solve_mrhs_split_kernel<2, MR_NT>
+                : (const void*)solve_mrhs_kernel<2, MR_NT>;
       break;
     case 3:
-      kern = h3 ? (const void*)solve_mrhs_kernel<3, MR_NT, true>
-                : (const void*)solve_mrhs_kernel<3, MR_NT, false>;
+      kern = h3 ? (const void*)solve_mrhs_split_kernel<3, 384>
+                : (const void*)solve_mrhs_kernel<3, MR_NT>;
       break;
     case 4:
-      kern = h3 ? (const void*)solve_mrhs_kernel<4, 512, true>
-                : (const void*)solve_mrhs_kernel<4, 512, false>;
+      kern = h3 ? (const void*)solve_mrhs_split_kernel<4, 512>
+                : (const void*)solve_mrhs_kernel<4, 512>;
       break;
-    default: kern = (const void*)solve_mrhs_kernel<0, MR_NT, false>; break;
+    default: kern = (const void*)solve_mrhs_kernel<0, MR_NT>; break;
   }
-  const int nt = mr_nt(n);
+  const int nt = mr_nt(n, h3);
   int per_cu = 1;
   hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
