@@ -623,6 +623,7 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
 // slot clipped).
 constexpr int MR_PS = 20;  // row stride (floats) of the operand and result arrays: the product's
                            // result writes (rows 4 (l / 16) + e, column l % 16) hit 64 banks
+constexpr int MR_REF_BATCH = 4;  // waiting slots that trigger an exact-gradient refresh
 
 template <int TPW, int NT>
 __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_split_kernel(MrArgs A) {
@@ -785,8 +786,14 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_split_kernel
 
   for (;;) {
     // ---- exact gradient for the slots that ask for it, from the FP32 Q in L2: it decides the
-    // stop test, where Q y and q nearly cancel (a few refreshes per column)
-    if (mask16(ref && col >= 0 && !done)) {
+    // stop test, where Q y and q nearly cancel.  A refresh costs about as much as one and a half
+    // updates, so requests that confirm a stop are gathered: the product runs once MR_REF_BATCH
+    // slots wait, or no slot is left to update, or a new column needs its first gradient (a
+    // waiting slot only idles meanwhile; it takes no update).
+    const unsigned mwait = mask16(ref && col >= 0 && !done);
+    const unsigned mbusy = mask16(col >= 0 && !done && !ref);
+    if (mwait && (__builtin_popcount(mwait) >= MR_REF_BATCH || mbusy == 0 ||
+                  mask16(ref && col >= 0 && !done && it == 0))) {
       write_rows_lds(P, yv);
       __syncthreads();
       // (four k blocks in flight: the split Q leaves few registers free)
@@ -847,10 +854,10 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_split_kernel
       }
     }
 
-    // ---- decisions: finish, refresh, or update
+    // ---- decisions: finish, refresh, or update (a slot waiting for its refresh idles)
     bool act = false;
     double r = 0.0;
-    if (live) {
+    if (live && !ref) {
       r = sqrt((double)res) / (double)qn;
       if (leader && A.trace != nullptr && it < A.trace_len) {
         float* tr = A.trace + ((int64_t)col * A.trace_len + it) * 2;
