@@ -31,7 +31,10 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2516.6
 PEAK_BF16X3_TFLOPS = PEAK_BF16_TFLOPS / 3.0   # three bf16 products per FP32-equivalent product
-PEAK_FP32_MFMA_TFLOPS = 157.3
+# the many-RHS solver's products with Q in registers: three FP16 products (hi/lo parts) per
+# FP32-class product, against FP16's dense matrix-core peak (the same 2516.6 TF as BF16)
+PEAK_F16X3_TFLOPS = PEAK_BF16_TFLOPS / 3.0
+MRHS_KERNEL = "solve_mrhs_split_kernel"
 PEAK_FP64_TFLOPS = 78.6
 TOL = 1e-5
 GAP_TOL = 1e-6
@@ -475,10 +478,9 @@ def bench_manyrhs(args):
     solve_flop = 2.0 * n * rows_sum
     dense_flop = 2.0 * 2.0 * n * n * float(it.sum())
     roofs = {
-        "solve": roofline("solve_mrhs_kernel", "nnls_solve call (solve_mrhs_kernel and its 4 us "
-                          "queue reset)", "mfma", solve_flop, "TFLOP/s", ms["solve"] * 1e-3,
-                          PEAK_FP32_MFMA_TFLOPS, traffic_record("solve_mrhs_kernel",
-                                                                "solve_mrhs.hip"),
+        "solve": roofline(MRHS_KERNEL, f"nnls_solve call ({MRHS_KERNEL} and its 4 us queue "
+                          "reset)", "mfma", solve_flop, "TFLOP/s", ms["solve"] * 1e-3,
+                          PEAK_F16X3_TFLOPS, traffic_record(MRHS_KERNEL, "solve_mrhs.hip"),
                           work_note="algorithmic: 2 n flop per row of Q the products read "
                                     "(Section 4's n S(n) per update, summed over columns)",
                           dense_tflops=round(dense_flop / (ms["solve"] * 1e-3) / 1e12, 2),
@@ -496,7 +498,7 @@ def bench_manyrhs(args):
         "value": round(k * args.steps / wall, 1) if ok else 0.0,
         "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3-gram/f32-mfma-iter/f64-check",
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3-gram/f16x3-mfma-iter/f64-check",
         "data": "synthetic",
         "config": {"workload": "many RHS: A 10000x256 |N(0,1)|, X 80% zeros Gamma(2,1), "
                                "B = AX + 1% noise, k=4096, seed 0", "d": d, "n": n, "k": k,
@@ -812,13 +814,13 @@ def bench_nmf(args):
         "value": round((m + p) * 1e3 / ms_step, 1) if ok else 0.0,
         "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16x3-gram/f32-mfma-iter/f64-check", "data": "synthetic",
+        "vs_baseline": None, "dtype": "bf16x3-gram/f16x3-mfma-iter/f64-check", "data": "synthetic",
         "config": {"workload": "NMF by alternating NNLS: V 10000x4096 = max(W* H* + 1% noise, 0), "
                                "W* U[0,1] 30% zeros, H* 70% zeros Exp(1), rank 256, W0 U[0,1]",
                    "m": m, "p": p, "r": r, "tol": TOL},
-        "roofline": {"kernel": "solve_mrhs_kernel", "bound": "mfma", "achieved": round(ach, 2),
-                     "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None},
+        "roofline": {"kernel": MRHS_KERNEL, "bound": "mfma", "achieved": round(ach, 2),
+                     "peak": round(PEAK_F16X3_TFLOPS, 1), "unit": "TFLOP/s",
+                     "frac": round(ach / PEAK_F16X3_TFLOPS, 4), "traffic": None},
         "ms": {kk: round(v, 4) for kk, v in ms.items()},
         "history": hist,
     }
@@ -1179,8 +1181,8 @@ def bench_warm(args):
     mlp_flop = MLP_FWD_FLOP * kb
     refine_flop = 2.0 * d * n * (n + k) + 3 * 2.0 * n * n * k
     cand = {
-        "solve": {"kernel": "solve_mrhs_kernel", "bound": "mfma", "flop": solve_flop,
-                  "peak": PEAK_FP32_MFMA_TFLOPS},
+        "solve": {"kernel": MRHS_KERNEL, "bound": "mfma", "flop": solve_flop,
+                  "peak": PEAK_F16X3_TFLOPS},
         "prepare": {"kernel": "gram_dma_kernel", "bound": "mfma", "flop": gram_flop,
                     "peak": PEAK_BF16X3_TFLOPS},
         "warm_start": {"kernel": "mlp_gemm_kernel", "bound": "mfma", "flop": mlp_flop,
@@ -1188,7 +1190,7 @@ def bench_warm(args):
         "refine": {"kernel": "gemm_tn_f64_kernel", "bound": "mfma", "flop": refine_flop,
                    "peak": PEAK_FP64_TFLOPS},
     }
-    timed_as = {"solve": "nnls_solve call (solve_mrhs_kernel and its queue reset), warm",
+    timed_as = {"solve": f"nnls_solve call ({MRHS_KERNEL} and its queue reset), warm",
                 "prepare": "nnls_prepare call (operand split + product)",
                 "warm_start": "nnls_warm_start call (network forward + line-search start)",
                 "refine": "nnls_refine call (FP64 Gram path, no objective)"}
@@ -1214,7 +1216,7 @@ def bench_warm(args):
         "value": round(v_warm, 1), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(warm["wall"] * 1e3 / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16-mlp/bf16x3-gram/f32-mfma-iter/f64-check", "data": "synthetic",
+        "dtype": "bf16-mlp/bf16x3-gram/f16x3-mfma-iter/f64-check", "data": "synthetic",
         "config": {"workload": f"learned warm start: A {d}x{n} |N(0,1)|, noiseless b = A x, "
                                "x 85% zeros Gamma(1.5,1); trained on 200k method solves, "
                                f"evaluated on {k} held-out", "d": d, "n": n, "k": k, "tol": TOL},
