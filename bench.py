@@ -315,6 +315,7 @@ def bench_large(args):
     roof_split = roofline("presplit_kernel", "nnls_prepare_split call (presplit_kernel + "
                           "colnorm_finalize_kernel)", "hbm", split_bytes, "GB/s",
                           ms["split"] * 1e-3, PEAK_HBM_GBS,
+                          traffic_record("presplit_kernel", "gram.hip"),
                           work_note="FP32 [A | b] read once, BF16 hi and lo planes written")
     if prep_only:
         out = {"metric": "Gram TFLOP/s (BF16x3, large single RHS prepare only)",
