@@ -162,7 +162,8 @@ int nnls_gram_rescaled(int64_t d, int64_t n, int64_t k, const void* A, int64_t l
  *   max_iter  cap on updates per column; 0 means 5 n
  *   Y0        [n, k] start in the rescaled variables, or NULL for y = 0 (negative entries are
  *             clipped to 0)
- *   X         out [n, k]: x = y / s
+ *   X         out [n, k]: x = y / s (the many-right-hand-side solver also keeps the start
+ *             gradients of a warm start there until each column is done; X may be Y0 itself)
  *   iters     out [k] int32 updates done; kkt out [k] FP64 r(y) of the returned iterate in the
  *             arithmetic of the solve; status out [k] int32 nnls_col_status
  *   rows_read out [k] int64, may be NULL: rows of Q the solve's products read in total (passive

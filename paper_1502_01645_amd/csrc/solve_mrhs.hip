@@ -144,6 +144,7 @@ struct MrArgs {
   float* trace;  // [k][trace_len][2] per-update record (r, ||gbar||^2), or nullptr
   int trace_len;
   int* queue;  // next unassigned column (starts at 16 * gridDim.x)
+  const float* G0;  // [n, k] exact gradients Q max(Y0, 0) + q at the start, or nullptr
 };
 
 // W[0..np)[0..16) = Q * V (V: [np][16] in LDS, rows S floats apart), rows and columns of Q
@@ -193,6 +194,37 @@ __device__ void mfma_product(const MrArgs& A, const float* V, float* W, const fl
     }
   }
   if constexpr (DEN) den_publish(dp, redw);
+}
+
+// Start gradients of a warm-started solve, G0 = Q max(Y0, 0) + q, for every column at once:
+// the exact gradient the solver would otherwise form for each slot group whenever a column
+// enters a slot.  One workgroup per 16 columns: their max(Y0, 0) staged in LDS, the product on
+// the FP32 matrix cores with Q read from L2 (mfma_product, the solver's own exact-gradient
+// arithmetic), q added in the write-out.  np <= 256.
+constexpr int SG_NP = 256;
+__global__ __launch_bounds__(MR_NT) void mrhs_start_grad_kernel(MrArgs A, float* G0) {
+  __shared__ float V[SG_NP * MR_SLOTS];
+  __shared__ float Wt[SG_NP * MR_SLOTS];
+  const int n = A.n, np = A.np, k = A.k;
+  const int64_t c0 = (int64_t)blockIdx.x * MR_SLOTS;
+  for (int e = threadIdx.x; e < np * MR_SLOTS; e += MR_NT) {
+    const int i = e / MR_SLOTS;
+    const int64_t col = c0 + e % MR_SLOTS;
+    float v = 0.f;
+    if (i < n && col < k) {
+      v = A.Y0[(int64_t)i * k + col];
+      v = v > 0.f ? v : 0.f;  // the solver's own reading of a start entry
+    }
+    V[e] = v;
+  }
+  __syncthreads();
+  mfma_product<MR_NT, false>(A, V, Wt, nullptr, nullptr);
+  __syncthreads();
+  for (int e = threadIdx.x; e < np * MR_SLOTS; e += MR_NT) {
+    const int i = e / MR_SLOTS;
+    const int64_t col = c0 + e % MR_SLOTS;
+    if (i < n && col < k) G0[(int64_t)i * k + col] = Wt[e] + A.q[(int64_t)i * k + col];
+  }
 }
 
 // W = Q * V with Q held in registers (n <= 256): of NW waves, wave w owns the row tiles
@@ -692,8 +724,10 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_split_kernel
   int col = blockIdx.x * MR_SLOTS + c;
   col = col < k ? col : -1;
   int it = 0;
-  bool fresh = A.Y0 == nullptr, ref = A.Y0 != nullptr && col >= 0, done = false;
-  int64_t rows = 0;
+  // a warm start needs an exact gradient first, unless it was formed before the launch (G0)
+  const bool start_exact = A.Y0 == nullptr || A.G0 != nullptr;
+  bool fresh = start_exact, ref = !start_exact && col >= 0, done = false;
+  int64_t rows = (A.G0 != nullptr && col >= 0) ? n : 0;
   float qn = 1.f;
 
   // ---- own rows: blocks blk(j), rows 8 blk(j) + e
@@ -715,7 +749,7 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_split_kernel
         const int i = 8 * blk(j) + e;
         float yi = 0.f, gi = 0.f;
         if (blk(j) < RB && col >= 0 && i < n) {
-          gi = A.q[(int64_t)i * kk + col];
+          gi = A.G0 ? A.G0[(int64_t)i * kk + col] : A.q[(int64_t)i * kk + col];
           if (A.Y0) {
             yi = A.Y0[(int64_t)i * kk + col];
             yi = yi > 0.f ? yi : 0.f;
@@ -899,9 +933,9 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_split_kernel
         col = s_newcol[c];
         it = 0;
         done = false;
-        fresh = A.Y0 == nullptr;
-        ref = A.Y0 != nullptr && col >= 0;
-        rows = 0;
+        fresh = start_exact;
+        ref = !start_exact && col >= 0;
+        rows = (A.G0 != nullptr && col >= 0) ? n : 0;
         load_rows();
       }
       qnorm();
@@ -1092,6 +1126,17 @@ hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* 
   A.trace = trace;
   A.trace_len = trace_len;
   A.queue = (int*)ws;
+  A.G0 = nullptr;
+  // Split kernel, warm start: the start gradients of all columns in one pass, written to X
+  // (each column's entries are read when it enters a slot and overwritten only when it
+  // retires, by the same workgroup).  Not when X overlaps Y0.
+  const size_t nk = (size_t)n * (size_t)k;
+  const bool overlap = Y0 != nullptr && (const float*)X < Y0 + nk && Y0 < (const float*)X + nk;
+  if (h3 && Y0 != nullptr && !overlap && A.np <= SG_NP) {
+    A.G0 = X;
+    hipLaunchKernelGGL(mrhs_start_grad_kernel, dim3((unsigned)((k + MR_SLOTS - 1) / MR_SLOTS)),
+                       dim3(MR_NT), 0, st, A, X);
+  }
   hipLaunchKernelGGL(solve_mrhs_queue_init, dim3(1), dim3(64), 0, st, A.queue,
                      (int)(groups * MR_SLOTS));
   void* args[] = {&A};
