@@ -53,80 +53,101 @@ __device__ __forceinline__ float gelu_grad(float x) {
 enum { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_GELU = 2, EPI_GELU_BWD = 3 };
 
 struct GemmEpi {
-  float* out_f32;        // EPI_F32, EPI_BIAS_F32, EPI_BIAS_GELU (pre-activation)
+  float* out_f32;        // EPI_F32, EPI_BIAS_F32, EPI_BIAS_GELU (pre-activation; may be
+                         // null there when no backward pass follows)
   bf16_t* out_bf16;      // EPI_BIAS_GELU (activation), EPI_GELU_BWD (gradient)
   const float* bias;     // EPI_BIAS_*
   const float* pre;      // EPI_GELU_BWD: pre-activation of the layer
   int64_t ldc;
 };
 
-constexpr int MG_T = 64;   // tile
 constexpr int MG_BK = 32;
 constexpr int MG_LDK = 40;
 
 // C[M, N] = op(A)[M, K] op(B)[K, N], bf16 inputs, FP32 accumulation.
 // op(A)(m, k) = TA ? A[k * lda + m] : A[m * lda + k];  op(B)(k, n) = TB ? B[n * ldb + k] : B[k * ldb + n].
-// Requires M, N multiples of 64 and K a multiple of 32 (checked on the host).
-template <bool TA, bool TB, int EPI>
+// T x T output tiles (T = 64 or 128) on 4 waves of T/2 x T/2 (FT x FT fragments of
+// v_mfma_f32_16x16x32_bf16); K in steps of 32, the next step's operands loaded into registers
+// while the current step's MFMAs run.  Requires M, N multiples of T and K a multiple of 32
+// (checked on the host).
+template <bool TA, bool TB, int EPI, int T>
 __global__ __launch_bounds__(256) void mlp_gemm_kernel(int M, int N, int K,
                                                        const bf16_t* __restrict__ A, int64_t lda,
                                                        const bf16_t* __restrict__ B, int64_t ldb,
                                                        GemmEpi E) {
-  __shared__ __attribute__((aligned(16))) bf16_t sA[MG_T * MG_LDK];
-  __shared__ __attribute__((aligned(16))) bf16_t sB[MG_T * MG_LDK];
-  const int m0 = blockIdx.x * MG_T, n0 = blockIdx.y * MG_T;
+  constexpr int FT = T / 32;        // fragments per wave and dimension
+  constexpr int LV = T * MG_BK / 8 / 256;  // 16-byte loads per thread and operand per step
+  __shared__ __attribute__((aligned(16))) bf16_t sA[T * MG_LDK];
+  __shared__ __attribute__((aligned(16))) bf16_t sB[T * MG_LDK];
+  const int m0 = blockIdx.x * T, n0 = blockIdx.y * T;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  f32x4 acc[2][2];
+  const int wm = (wave >> 1) * (T / 2), wn = (wave & 1) * (T / 2);
+  f32x4 acc[FT][FT];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < FT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < FT; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
+  u32x4 ra[LV], rb[LV];
+  // load v of a step: !TA: row m = q / 4 of the tile, k = (q % 4) * 8 .. + 7; TA: k = q / (T/8),
+  // m = (q % (T/8)) * 8 .. + 7, with q = tid + 256 v (the same for B with n in place of m)
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int v = 0; v < LV; ++v) {
+      const int qd = tid + 256 * v;
+      if (!TA) ra[v] = *(const u32x4*)(A + (int64_t)(m0 + (qd >> 2)) * lda + k0 + (qd & 3) * 8);
+      else ra[v] = *(const u32x4*)(A + (int64_t)(k0 + qd / (T / 8)) * lda + m0 + (qd % (T / 8)) * 8);
+      if (TB) rb[v] = *(const u32x4*)(B + (int64_t)(n0 + (qd >> 2)) * ldb + k0 + (qd & 3) * 8);
+      else rb[v] = *(const u32x4*)(B + (int64_t)(k0 + qd / (T / 8)) * ldb + n0 + (qd % (T / 8)) * 8);
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int v = 0; v < LV; ++v) {
+      const int qd = tid + 256 * v;
+      if (!TA) {
+        *(u32x4*)&sA[(qd >> 2) * MG_LDK + (qd & 3) * 8] = ra[v];
+      } else {
+        const int kk = qd / (T / 8), mm = (qd % (T / 8)) * 8;
+        const bf16_t* e = (const bf16_t*)&ra[v];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sA[(mm + j) * MG_LDK + kk] = e[j];
+      }
+      if (TB) {
+        *(u32x4*)&sB[(qd >> 2) * MG_LDK + (qd & 3) * 8] = rb[v];
+      } else {
+        const int kk = qd / (T / 8), nn = (qd % (T / 8)) * 8;
+        const bf16_t* e = (const bf16_t*)&rb[v];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sB[(nn + j) * MG_LDK + kk] = e[j];
+      }
+    }
+  };
+
+  load(0);
   for (int k0 = 0; k0 < K; k0 += MG_BK) {
-    // A tile: 64 rows (m) x 32 k
-    if (!TA) {  // k contiguous: 8 bf16 per thread
-      const int mm = tid >> 2, kk = (tid & 3) * 8;
-      const u32x4 v = *(const u32x4*)(A + (int64_t)(m0 + mm) * lda + k0 + kk);
-      *(u32x4*)&sA[mm * MG_LDK + kk] = v;
-    } else {    // m contiguous: 8 consecutive m of one k
-      const int kk = tid >> 3, mm = (tid & 7) * 8;
-      const u32x4 v = *(const u32x4*)(A + (int64_t)(k0 + kk) * lda + m0 + mm);
-      const bf16_t* e = (const bf16_t*)&v;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) sA[(mm + j) * MG_LDK + kk] = e[j];
-    }
-    if (TB) {   // k contiguous along a row of B (n fixed)
-      const int nn = tid >> 2, kk = (tid & 3) * 8;
-      const u32x4 v = *(const u32x4*)(B + (int64_t)(n0 + nn) * ldb + k0 + kk);
-      *(u32x4*)&sB[nn * MG_LDK + kk] = v;
-    } else {    // n contiguous
-      const int kk = tid >> 3, nn = (tid & 7) * 8;
-      const u32x4 v = *(const u32x4*)(B + (int64_t)(k0 + kk) * ldb + n0 + nn);
-      const bf16_t* e = (const bf16_t*)&v;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) sB[(nn + j) * MG_LDK + kk] = e[j];
-    }
+    store();
     __syncthreads();
+    if (k0 + MG_BK < K) load(k0 + MG_BK);  // in flight during the MFMAs below
     const int fr = lane & 15, fk = (lane >> 4) * 8;
-    bf16x8 af[2], bf[2];
+    bf16x8 af[FT], bf[FT];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < FT; ++t) {
       af[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&sA[(wm + t * 16 + fr) * MG_LDK + fk]);
       bf[t] = __builtin_bit_cast(bf16x8, *(const u32x4*)&sB[(wn + t * 16 + fr) * MG_LDK + fk]);
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FT; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < FT; ++b)
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
     __syncthreads();
   }
   const int oc = lane & 15, orow = (lane >> 4) * 4;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < FT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < FT; ++b)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int64_t m = m0 + wm + a * 16 + orow + e;
@@ -139,7 +160,7 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(int M, int N, int K,
           E.out_f32[o] = v + E.bias[n];
         } else if (EPI == EPI_BIAS_GELU) {
           const float pre = v + E.bias[n];
-          E.out_f32[o] = pre;
+          if (E.out_f32) E.out_f32[o] = pre;  // kept for the backward pass only
           E.out_bf16[o] = to_bf16(gelu(pre));
         } else {
           E.out_bf16[o] = to_bf16(v * gelu_grad(E.pre[o]));
@@ -147,12 +168,21 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(int M, int N, int K,
       }
 }
 
+// 128 x 128 tiles where M and N allow it and there are at least 512 of them (a wave then runs
+// 16 MFMAs per K step instead of 4), else 64 x 64 (the small products of training would leave
+// most of the GPU idle with the larger tiles).
 template <bool TA, bool TB, int EPI>
 static void gemm(int M, int N, int K, const bf16_t* A, int64_t lda, const bf16_t* B, int64_t ldb,
                  GemmEpi E, hipStream_t st) {
-  dim3 grid((unsigned)(M / MG_T), (unsigned)(N / MG_T));  // N / 64 <= 16
-  hipLaunchKernelGGL((mlp_gemm_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B,
-                     ldb, E);
+  if (M % 128 == 0 && N % 128 == 0 && (int64_t)(M / 128) * (N / 128) >= 512) {
+    dim3 grid((unsigned)(M / 128), (unsigned)(N / 128));
+    hipLaunchKernelGGL((mlp_gemm_kernel<TA, TB, EPI, 128>), grid, dim3(256), 0, st, M, N, K, A,
+                       lda, B, ldb, E);
+  } else {
+    dim3 grid((unsigned)(M / 64), (unsigned)(N / 64));
+    hipLaunchKernelGGL((mlp_gemm_kernel<TA, TB, EPI, 64>), grid, dim3(256), 0, st, M, N, K, A,
+                       lda, B, ldb, E);
+  }
 }
 
 // X[b, j] = bf16((u[b, j] - shift[j]) * scale[j]): the input standardisation, applied in FP32
@@ -318,7 +348,7 @@ __global__ void reset_state_kernel(int64_t count, const float* __restrict__ w,
 
 // ---- workspace layout ------------------------------------------------------------------------
 struct MlpWs {
-  bf16_t *X, *A1, *A2, *dZ, *dH2, *dH1;
+  bf16_t *X, *A1, *A2, *dZ, *dH2, *dH1, *WT;
   float *H1, *H2, *Z, *grad, *loss_part, *loss, *colpart;
 };
 
@@ -339,6 +369,7 @@ static MlpWs mlp_layout(void* ws, int64_t batch, bool train, size_t* total) {
   W.H2 = (float*)take(4 * batch * ML_H);
   W.A2 = (bf16_t*)take(2 * batch * ML_H);
   W.Z = (float*)take(4 * batch * ML_OUT);
+  W.WT = (bf16_t*)take(2 * ML_P);  // the BF16 weights transposed, for the forward products
   if (train) {
     W.dZ = (bf16_t*)take(2 * batch * ML_OUT);
     W.dH2 = (bf16_t*)take(2 * batch * ML_H);
@@ -358,6 +389,18 @@ size_t mlp_ws_bytes(int64_t batch, bool train) {
   return t;
 }
 
+// dst[c, r] = src[r, c] for a bf16 [rows, cols] matrix (rows, cols multiples of 32), through a
+// 32 x 33 LDS tile.
+__global__ __launch_bounds__(256) void bf16_transpose_kernel(int64_t rows, int64_t cols,
+                                                             const bf16_t* __restrict__ src,
+                                                             bf16_t* __restrict__ dst) {
+  __shared__ bf16_t t[32][33];
+  const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+  for (int y = threadIdx.y; y < 32; y += 8) t[y][threadIdx.x] = src[(r0 + y) * cols + c0 + threadIdx.x];
+  __syncthreads();
+  for (int y = threadIdx.y; y < 32; y += 8) dst[(c0 + y) * rows + r0 + threadIdx.x] = t[threadIdx.x][y];
+}
+
 static const bf16_t* wcopy(const void* blob) {
   return (const bf16_t*)((const char*)blob + sizeof(float) * 3 * ML_P);
 }
@@ -366,20 +409,29 @@ static const float* norm_shift(const void* blob) {
 }
 static const float* norm_scale(const void* blob) { return norm_shift(blob) + ML_IN; }
 
-// forward pass; leaves H1, A1, H2, A2 and Z in the workspace
+// forward pass; leaves A1, A2 and Z in the workspace, and the pre-activations H1, H2 when a
+// backward pass follows (keep_pre).  The products read each weight matrix as W^T (rows of W^T
+// are k-contiguous, the layout the staging copies into LDS as is), from a transposed copy made
+// first.
 static void forward(int64_t batch, const void* blob, const float* u, const MlpWs& W,
-                    hipStream_t st) {
+                    hipStream_t st, bool keep_pre) {
   const bf16_t* Wb = wcopy(blob);
   const float* master = (const float*)blob;
   const int M = (int)batch;
+  struct {
+    int64_t off, rows, cols;
+  } const mats[3] = {{ML_W1, ML_IN, ML_H}, {ML_W2, ML_H, ML_H}, {ML_W3, ML_H, ML_OUT}};
+  for (const auto& m : mats)
+    hipLaunchKernelGGL(bf16_transpose_kernel, dim3((unsigned)(m.cols / 32), (unsigned)(m.rows / 32)),
+                       dim3(32, 8), 0, st, m.rows, m.cols, Wb + m.off, W.WT + m.off);
   hipLaunchKernelGGL(input_kernel, dim3((unsigned)((batch * ML_IN + 255) / 256)), dim3(256), 0,
                      st, batch * ML_IN, u, norm_shift(blob), norm_scale(blob), W.X);
-  GemmEpi e1{W.H1, W.A1, master + ML_B1, nullptr, ML_H};
-  gemm<false, false, EPI_BIAS_GELU>(M, ML_H, ML_IN, W.X, ML_IN, Wb + ML_W1, ML_H, e1, st);
-  GemmEpi e2{W.H2, W.A2, master + ML_B2, nullptr, ML_H};
-  gemm<false, false, EPI_BIAS_GELU>(M, ML_H, ML_H, W.A1, ML_H, Wb + ML_W2, ML_H, e2, st);
+  GemmEpi e1{keep_pre ? W.H1 : nullptr, W.A1, master + ML_B1, nullptr, ML_H};
+  gemm<false, true, EPI_BIAS_GELU>(M, ML_H, ML_IN, W.X, ML_IN, W.WT + ML_W1, ML_IN, e1, st);
+  GemmEpi e2{keep_pre ? W.H2 : nullptr, W.A2, master + ML_B2, nullptr, ML_H};
+  gemm<false, true, EPI_BIAS_GELU>(M, ML_H, ML_H, W.A1, ML_H, W.WT + ML_W2, ML_H, e2, st);
   GemmEpi e3{W.Z, nullptr, master + ML_B3, nullptr, ML_OUT};
-  gemm<false, false, EPI_BIAS_F32>(M, ML_OUT, ML_H, W.A2, ML_H, Wb + ML_W3, ML_OUT, e3, st);
+  gemm<false, true, EPI_BIAS_F32>(M, ML_OUT, ML_H, W.A2, ML_H, W.WT + ML_W3, ML_H, e3, st);
 }
 
 // loss, then gradients of every parameter into W.grad (same layout as the parameters)
@@ -661,7 +713,7 @@ int nnls_mlp_forward(int64_t batch, const void* blob, const float* u, float* z, 
   if (!ws || ws_bytes < need) return NNLS_E_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   nnls::MlpWs W = nnls::mlp_layout(ws, batch, false, nullptr);
-  nnls::forward(batch, blob, u, W, st);
+  nnls::forward(batch, blob, u, W, st, false);
   hipError_t e = hipMemcpyAsync(z, W.Z, sizeof(float) * batch * nnls::ML_OUT,
                                 hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipGetLastError();
@@ -681,7 +733,7 @@ int nnls_mlp_gradients(int64_t batch, const void* blob, const float* u, const fl
   if (!ws || ws_bytes < need) return NNLS_E_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   nnls::MlpWs W = nnls::mlp_layout(ws, batch, true, nullptr);
-  nnls::forward(batch, blob, u, W, st);
+  nnls::forward(batch, blob, u, W, st, true);
   nnls::backward(batch, blob, target, lambda, W, st);
   hipError_t e = hipSuccess;
   if (grad_out)
@@ -750,7 +802,7 @@ int nnls_warm_start(int64_t n, int64_t k, const float* Q, const float* q, const 
   float* U = (float*)(p + nnls::mlp_ws_bytes(kb, false));
   hipLaunchKernelGGL(nnls::ws_normalise_kernel, dim3((unsigned)(kb / nnls::WS_C)), dim3(256), 0,
                      st, k, kb, q, (const float*)nullptr, U, (float*)nullptr);
-  nnls::forward(kb, blob, U, W, st);
+  nnls::forward(kb, blob, U, W, st, false);
   hipLaunchKernelGGL(nnls::ws_assemble_kernel, dim3((unsigned)((k + nnls::WS_C - 1) / nnls::WS_C)),
                      dim3(256), 0, st, k, Q, q, (const float*)W.Z, Y0, fell_back);
   hipError_t e = hipGetLastError();
