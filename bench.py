@@ -31,11 +31,34 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2516.6
 PEAK_BF16X3_TFLOPS = PEAK_BF16_TFLOPS / 3.0   # three bf16 products per FP32-equivalent product
-# the many-RHS solver's products with Q in registers: three FP16 products (hi/lo parts) per
-# FP32-class product, against FP16's dense matrix-core peak (the same 2516.6 TF as BF16)
+# the many-RHS solver with Q in registers: FP32 products by default; the split form
+# (NNLS_MRHS_PRODUCT=split16: three FP16 products of hi/lo parts per product, against FP16's
+# dense matrix-core peak, the same 2516.6 TF as BF16) is measured beside it
 PEAK_F16X3_TFLOPS = PEAK_BF16_TFLOPS / 3.0
-MRHS_KERNEL = "solve_mrhs_split_kernel"
+MRHS_KERNEL = "solve_mrhs_reg_kernel"
+
+
+class mrhs_products:
+    """Context: the many-RHS solver's product form for the calls inside (the library reads
+    NNLS_MRHS_PRODUCT at each launch); None = the default FP32 products."""
+
+    def __init__(self, form):
+        self.form = form
+
+    def __enter__(self):
+        self.old = os.environ.get("NNLS_MRHS_PRODUCT")
+        if self.form is None:
+            os.environ.pop("NNLS_MRHS_PRODUCT", None)
+        else:
+            os.environ["NNLS_MRHS_PRODUCT"] = self.form
+
+    def __exit__(self, *exc):
+        if self.old is None:
+            os.environ.pop("NNLS_MRHS_PRODUCT", None)
+        else:
+            os.environ["NNLS_MRHS_PRODUCT"] = self.old
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_MFMA_TFLOPS = 157.3
 TOL = 1e-5
 GAP_TOL = 1e-6
 # The solve runs below tol in FP32 on the BF16x3 Q; the FP64 check against (A, b) is what must
@@ -454,34 +477,39 @@ def bench_manyrhs(args):
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     total = args.warmup + args.steps
     names = ["split", "gram", "solve", "refine"]
-    marks = [[ev() for _ in range(5)] for _ in range(total)]
 
-    def step(i):
-        e = marks[i]
-        e[0].record()
-        N.prepare_split(A, B, s, ws_p)
-        e[1].record()
-        N.prepare_product(d, s, Q, q, ws_p)
-        e[2].record()
-        rows.zero_()
-        N.solve(Q, q, s, tol=INNER_TOL, max_iter=5 * n, out=(X, iters, kkt, status), ws=ws_v,
-                rows_read=rows)
-        e[3].record()
-        N.refine(A, B, X, out=(kkt64, None), ws=ws_r)
-        e[4].record()
+    def measure(form):
+        marks = [[ev() for _ in range(5)] for _ in range(total)]
 
-    wall = run_timed(step, args.warmup, args.steps)
-    ms = event_ms(marks[args.warmup:], names)
-    r64 = kkt64.cpu().numpy()
-    it = iters.cpu().numpy()
+        def step(i):
+            e = marks[i]
+            e[0].record()
+            N.prepare_split(A, B, s, ws_p)
+            e[1].record()
+            N.prepare_product(d, s, Q, q, ws_p)
+            e[2].record()
+            rows.zero_()
+            N.solve(Q, q, s, tol=INNER_TOL, max_iter=5 * n, out=(X, iters, kkt, status),
+                    ws=ws_v, rows_read=rows)
+            e[3].record()
+            N.refine(A, B, X, out=(kkt64, None), ws=ws_r)
+            e[4].record()
+
+        with mrhs_products(form):
+            wall = run_timed(step, args.warmup, args.steps)
+        return (wall, event_ms(marks[args.warmup:], names), kkt64.cpu().numpy(),
+                iters.cpu().numpy(), int(rows.sum().item()), X.cpu().numpy())
+
+    # the split FP16 products first, so that X holds the default form's result afterwards
+    wall_s, ms_s, r64_s, it_s, rows_s, X_s = measure("split16")
+    wall, ms, r64, it, rows_sum, X_h = measure(None)
     ok = bool(np.all(r64 <= TOL))
-    rows_sum = int(rows.sum().item())
     solve_flop = 2.0 * n * rows_sum
     dense_flop = 2.0 * 2.0 * n * n * float(it.sum())
     roofs = {
-        "solve": roofline(MRHS_KERNEL, f"nnls_solve call ({MRHS_KERNEL} and its 4 us queue "
-                          "reset)", "mfma", solve_flop, "TFLOP/s", ms["solve"] * 1e-3,
-                          PEAK_F16X3_TFLOPS, traffic_record(MRHS_KERNEL, "solve_mrhs.hip"),
+        "solve": roofline(MRHS_KERNEL, f"nnls_solve call ({MRHS_KERNEL}, FP32 products, and its "
+                          "4 us queue reset)", "mfma", solve_flop, "TFLOP/s", ms["solve"] * 1e-3,
+                          PEAK_FP32_MFMA_TFLOPS, traffic_record(MRHS_KERNEL, "solve_mrhs.hip"),
                           work_note="algorithmic: 2 n flop per row of Q the products read "
                                     "(Section 4's n S(n) per update, summed over columns)",
                           dense_tflops=round(dense_flop / (ms["solve"] * 1e-3) / 1e12, 2),
@@ -499,7 +527,7 @@ def bench_manyrhs(args):
         "value": round(k * args.steps / wall, 1) if ok else 0.0,
         "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3-gram/f16x3-mfma-iter/f64-check",
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3-gram/f32-mfma-iter/f64-check",
         "data": "synthetic",
         "config": {"workload": "many RHS: A 10000x256 |N(0,1)|, X 80% zeros Gamma(2,1), "
                                "B = AX + 1% noise, k=4096, seed 0", "d": d, "n": n, "k": k,
@@ -512,12 +540,32 @@ def bench_manyrhs(args):
                   "max": int(it.max())},
         "kkt64": dist(r64),
         "all_columns_meet_tol": ok,
+        "split_products": split_products_record(k, args.steps, wall_s, ms_s, r64_s, it_s, rows_s,
+                                                n),
     }
     if not args.no_cpu_baseline:
-        cb = multi_rhs_baseline(A_h, B_h, X.cpu().numpy(), 256, "right-hand sides")
+        cb = multi_rhs_baseline(A_h, B_h, X_h, 256, "right-hand sides")
         out["cpu_baseline"] = cb
         gate_on_gap(out, cb)
+        from oracle import oracle as O
+        out["split_products"]["gap"] = sample_gap(O.load(), A_h, B_h, X_s, np.arange(256),
+                                                  "the same 256 columns")
     print(json.dumps(out), flush=True)
+
+
+def split_products_record(k, steps, wall, ms, r64, it, rows_sum, n):
+    """The same workload with the many-RHS solver's split FP16 products
+    (NNLS_MRHS_PRODUCT=split16): each product term within 3 2^-22 of the FP32 one, the exact
+    gradient of every accepted stop still FP32; certified by the same FP64 check."""
+    ok = bool(np.all(r64 <= TOL))
+    return {"form": "split16: Q as FP16 hi + lo parts, three v_mfma_f32_16x16x32_f16 per "
+                    "product, FP32 accumulation",
+            "value": round(k * steps / wall, 1) if ok else 0.0, "unit": "solves/s",
+            "ms": {kk: round(v, 4) for kk, v in ms.items()},
+            "solve_tflops_algorithmic": round(2.0 * n * rows_sum / (ms["solve"] * 1e-3) / 1e12, 2),
+            "peak_f16x3_tflops": round(PEAK_F16X3_TFLOPS, 1),
+            "iters": {"mean": float(it.mean()), "max": int(it.max())},
+            "kkt64": dist(r64), "all_columns_meet_tol": ok}
 
 
 def stage_rooflines(N, d, n, k, ms, rows_read):
@@ -787,43 +835,57 @@ def bench_nmf(args):
     m, p = V_h.shape
     r = W0_h.shape[1]
     V = torch.from_numpy(V_h).to(dev)
-    alt = F.AlternatingNNLS(V, torch.from_numpy(W0_h).to(dev))
     vnorm2 = float(np.sum(V_h.astype(np.float64) ** 2))
     names = ["H prepare", "H solve", "H check", "H transpose", "W prepare", "W solve", "W check",
              "W transpose"]
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    hist, marks = [], []
-    for i in range(args.warmup + args.steps):
-        e = [ev() for _ in range(9)]
-        alt.step(e)
-        torch.cuda.synchronize()
-        marks.append(e)
-        oh, ow = alt.objective()
-        hist.append({"step": i, "rel_residual_after_H": (2 * oh / vnorm2) ** 0.5,
-                     "rel_residual_after_W": (2 * ow / vnorm2) ** 0.5, **alt.stats()})
-    timed = marks[args.warmup:]
-    ms = {nm: float(np.mean([e[j].elapsed_time(e[j + 1]) for e in timed]))
-          for j, nm in enumerate(names)}
-    ms_step = float(np.mean([e[0].elapsed_time(e[8]) for e in timed]))
-    ok = all(h["H"]["kkt64_max"] <= TOL and h["W"]["kkt64_max"] <= TOL for h in hist)
-    # matrix-core roofline of the two solves: 2 r flops per row of Q the products read
-    rows = sum(h["H"]["rows_read"] + h["W"]["rows_read"] for h in hist[args.warmup:])
-    t_solve = float(sum(e[1].elapsed_time(e[2]) + e[5].elapsed_time(e[6]) for e in timed))
-    ach = 2.0 * r * rows / (t_solve * 1e-3) / 1e12
+
+    def run(form):
+        alt = F.AlternatingNNLS(V, torch.from_numpy(W0_h).to(dev))
+        hist, marks = [], []
+        with mrhs_products(form):
+            for i in range(args.warmup + args.steps):
+                e = [ev() for _ in range(9)]
+                alt.step(e)
+                torch.cuda.synchronize()
+                marks.append(e)
+                oh, ow = alt.objective()
+                hist.append({"step": i, "rel_residual_after_H": (2 * oh / vnorm2) ** 0.5,
+                             "rel_residual_after_W": (2 * ow / vnorm2) ** 0.5, **alt.stats()})
+        timed = marks[args.warmup:]
+        ms = {nm: float(np.mean([e[j].elapsed_time(e[j + 1]) for e in timed]))
+              for j, nm in enumerate(names)}
+        ms_step = float(np.mean([e[0].elapsed_time(e[8]) for e in timed]))
+        ok = all(h["H"]["kkt64_max"] <= TOL and h["W"]["kkt64_max"] <= TOL for h in hist)
+        # matrix-core work of the two solves: 2 r flops per row of Q the products read
+        rows = sum(h["H"]["rows_read"] + h["W"]["rows_read"] for h in hist[args.warmup:])
+        t_solve = float(sum(e[1].elapsed_time(e[2]) + e[5].elapsed_time(e[6]) for e in timed))
+        return hist, ms, ms_step, ok, 2.0 * r * rows / (t_solve * 1e-3) / 1e12
+
+    hist_s, ms_sp, step_s, ok_s, ach_s = run("split16")
+    hist, ms, ms_step, ok, ach = run(None)
     out = {
         "metric": "NNLS column solves/sec in alternating NNLS for NMF (both halves, FP64-checked)",
         "value": round((m + p) * 1e3 / ms_step, 1) if ok else 0.0,
         "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16x3-gram/f16x3-mfma-iter/f64-check", "data": "synthetic",
+        "vs_baseline": None, "dtype": "bf16x3-gram/f32-mfma-iter/f64-check", "data": "synthetic",
         "config": {"workload": "NMF by alternating NNLS: V 10000x4096 = max(W* H* + 1% noise, 0), "
                                "W* U[0,1] 30% zeros, H* 70% zeros Exp(1), rank 256, W0 U[0,1]",
                    "m": m, "p": p, "r": r, "tol": TOL},
         "roofline": {"kernel": MRHS_KERNEL, "bound": "mfma", "achieved": round(ach, 2),
-                     "peak": round(PEAK_F16X3_TFLOPS, 1), "unit": "TFLOP/s",
-                     "frac": round(ach / PEAK_F16X3_TFLOPS, 4), "traffic": None},
+                     "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(ach / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None},
         "ms": {kk: round(v, 4) for kk, v in ms.items()},
         "history": hist,
+        "split_products": {
+            "form": "split16 (NNLS_MRHS_PRODUCT=split16): Q as FP16 hi + lo parts, FP32 "
+                    "accumulation, the same FP64 check",
+            "value": round((m + p) * 1e3 / step_s, 1) if ok_s else 0.0, "unit": "solves/s",
+            "ms_per_step": round(step_s, 4), "ms": {kk: round(v, 4) for kk, v in ms_sp.items()},
+            "solve_tflops_algorithmic": round(ach_s, 2),
+            "peak_f16x3_tflops": round(PEAK_F16X3_TFLOPS, 1), "all_columns_meet_tol": ok_s,
+            "rel_residual_after_W": [h["rel_residual_after_W"] for h in hist_s]},
     }
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -1166,6 +1228,11 @@ def bench_warm(args):
                "fell_back": float(fb.float().mean().item()) if warm else None}
         return res
 
+    # the split FP16 products first, so that X holds the default form's warm result afterwards
+    with mrhs_products("split16"):
+        cold_s = run(False)
+        warm_s = run(True)
+    log(f"warm (split16 products): cold {cold_s['ms']} warm {warm_s['ms']}")
     cold = run(False)
     warm = run(True)
     log(f"warm: cold {cold['ms']} warm {warm['ms']}")
@@ -1183,7 +1250,7 @@ def bench_warm(args):
     refine_flop = 2.0 * d * n * (n + k) + 3 * 2.0 * n * n * k
     cand = {
         "solve": {"kernel": MRHS_KERNEL, "bound": "mfma", "flop": solve_flop,
-                  "peak": PEAK_F16X3_TFLOPS},
+                  "peak": PEAK_FP32_MFMA_TFLOPS},
         "prepare": {"kernel": "gram_dma_kernel", "bound": "mfma", "flop": gram_flop,
                     "peak": PEAK_BF16X3_TFLOPS},
         "warm_start": {"kernel": "mlp_gemm_kernel", "bound": "mfma", "flop": mlp_flop,
@@ -1191,7 +1258,8 @@ def bench_warm(args):
         "refine": {"kernel": "gemm_tn_f64_kernel", "bound": "mfma", "flop": refine_flop,
                    "peak": PEAK_FP64_TFLOPS},
     }
-    timed_as = {"solve": f"nnls_solve call ({MRHS_KERNEL} and its queue reset), warm",
+    timed_as = {"solve": f"nnls_solve call ({MRHS_KERNEL}, FP32 products, and its queue "
+                         "reset), warm",
                 "prepare": "nnls_prepare call (operand split + product)",
                 "warm_start": "nnls_warm_start call (network forward + line-search start)",
                 "refine": "nnls_refine call (FP64 Gram path, no objective)"}
@@ -1217,7 +1285,7 @@ def bench_warm(args):
         "value": round(v_warm, 1), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(warm["wall"] * 1e3 / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16-mlp/bf16x3-gram/f16x3-mfma-iter/f64-check", "data": "synthetic",
+        "dtype": "bf16-mlp/bf16x3-gram/f32-mfma-iter/f64-check", "data": "synthetic",
         "config": {"workload": f"learned warm start: A {d}x{n} |N(0,1)|, noiseless b = A x, "
                                "x 85% zeros Gamma(1.5,1); trained on 200k method solves, "
                                f"evaluated on {k} held-out", "d": d, "n": n, "k": k, "tol": TOL},
@@ -1227,6 +1295,14 @@ def bench_warm(args):
         "cold": stats(cold),
         "speedup_vs_cold": round(v_warm / v_cold, 3) if v_cold > 0 else None,
         "fallback_rate": warm["fell_back"],
+        "split_products": {
+            "form": "split16 (NNLS_MRHS_PRODUCT=split16): Q as FP16 hi + lo parts, FP32 "
+                    "accumulation, the same FP64 check",
+            "value": round(rate(warm_s), 1), "unit": "solves/s",
+            "solve_tflops_algorithmic": round(2.0 * n * warm_s["rows"] /
+                                              (warm_s["ms"]["solve"] * 1e-3) / 1e12, 2),
+            "peak_f16x3_tflops": round(PEAK_F16X3_TFLOPS, 1),
+            "warm": stats(warm_s), "cold": stats(cold_s)},
         "training": {"samples": WARM_TRAIN, "epochs": args.epochs, "batch": WARM_BATCH,
                      "lr": WARM_LR, "lambda": WARM_LAMBDA, "target_tol": WARM_TARGET_TOL,
                      "target_solve_ms": round(targets_ms, 1),

@@ -181,11 +181,12 @@ int nnls_gram_rescaled(int64_t d, int64_t n, int64_t k, const void* A, int64_t l
  * the current device.  The environment variable NNLS_SOLVER=wg|regq|persistent|mrhs forces
  * the one-workgroup-per-column solver, the whole-GPU single-right-hand-side solver with Q held
  * in registers (n <= 5120) or streamed from memory, or the matrix-core many-right-hand-side
- * solver, where valid.  For n <= 256 the many-right-hand-side solver holds Q in registers as
- * FP16 hi and lo parts (rows scaled by powers of two) and forms its two products per update as
- * three FP16 matrix-core products, each term within 3 2^-22 of the FP32 product; the exact
- * gradient behind every accepted stop is formed from the FP32 Q.  NNLS_MRHS_PRODUCT=fp32 selects
- * FP32 products throughout.  Every wait of the whole-GPU solvers is bounded (2^24 polls; the
+ * solver, where valid.  The many-right-hand-side solver forms its products in FP32 on the
+ * matrix cores (for n <= 256 with Q held in registers).  NNLS_MRHS_PRODUCT=split16 opts into a
+ * faster form for n <= 256: Q held as FP16 hi and lo parts (rows scaled by powers of two), each
+ * update's two products formed as three FP16 matrix-core products with FP32 accumulation, every
+ * term within 3 2^-22 of the FP32 product; the exact gradient behind every accepted stop is
+ * still formed from the FP32 Q.  Every wait of the whole-GPU solvers is bounded (2^24 polls; the
  * environment variable NNLS_SPIN_LIMIT=m, 0 <= m <= 2^24, lowers it to test the give-up path):
  * a workgroup that gives up sets an abort word that ends the waits of all the others, and the
  * solve reports BREAKDOWN with iters = -1.

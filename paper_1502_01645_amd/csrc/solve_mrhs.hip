@@ -232,7 +232,7 @@ __global__ __launch_bounds__(MR_NT) void mrhs_start_grad_kernel(MrArgs A, float*
 // ks < KS (np = 4 KS), the A operand of MFMA ks, so a product reads only V from LDS (lane l: row
 // 4 ks + l / 16, slot l % 16; 16 consecutive lanes hit 16 consecutive banks) and one V value
 // feeds TW MFMAs.
-template <int TW, int KS, int NW, bool DEN>
+template <int TW, int KS, int NW, bool DEN, int S = MR_SLOTS>
 __device__ __forceinline__ void mfma_product_reg(const float (&qa)[TW][KS], const float* V,
                                                  float* W, const float* Vd, float* redw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -242,32 +242,32 @@ __device__ __forceinline__ void mfma_product_reg(const float (&qa)[TW][KS], cons
   for (int tt = 0; tt < TW; ++tt) acc[tt] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
-    const float b = V[(4 * ks + lg) * MR_SLOTS + lr];
+    const float b = V[(4 * ks + lg) * S + lr];
 #pragma unroll
     for (int tt = 0; tt < TW; ++tt)
       acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[tt][ks], b, acc[tt], 0, 0, 0);
   }
   float dp = 0.f;
+  // (the first output row formed here, not kept in a register through the solve)
+  int row0 = wave * 16 + 4 * lg;
+  asm volatile("" : "+v"(row0));
 #pragma unroll
   for (int tt = 0; tt < TW; ++tt) {
-    const int t = wave + NW * tt;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int row = t * 16 + 4 * lg + e;
-      W[row * MR_SLOTS + lr] = acc[tt][e];
-      if constexpr (DEN) dp += Vd[row * MR_SLOTS + lr] * acc[tt][e];
+      const int row = row0 + NW * 16 * tt + e;
+      W[row * S + lr] = acc[tt][e];
+      if constexpr (DEN) dp += Vd[row * S + lr] * acc[tt][e];
     }
   }
   if constexpr (DEN) den_publish(dp, redw);
 }
 
-// FP32 products.  TPW > 0: Q in registers (n <= 64 TPW); TPW == 0: Q read from L2 by
-// mfma_product.  NT threads per workgroup: 256, or 512 for TPW = 4, where 8
-// waves of two row tiles each hold Q with 128 registers per lane and two waves per SIMD let one
-// wave's vector work run beside the other's matrix-core products.
-template <int TPW, int NT>
-__global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_kernel(MrArgs A) {
-  static_assert(TPW == 0 ? NT == MR_NT : (4 * TPW) % (NT / 64) == 0, "row tiles per wave");
+// n > 256: Q does not fit in registers and every product reads it from L2 (mfma_product, FP32).
+// Slot state in LDS; threads 0..15 take the slots' decisions and wave 0 folds the slot flags
+// into masks.  (n <= 256 runs solve_mrhs_reg_kernel below.)
+template <int NT>
+__global__ __launch_bounds__(NT, 2) void solve_mrhs_kernel(MrArgs A) {
   extern __shared__ __attribute__((aligned(16))) float sm[];
   const int np = A.np, n = A.n;
   float* Y = sm;                       // [np][16]
@@ -306,29 +306,11 @@ __global__ __launch_bounds__(NT, NT == 512 || TPW == 4 ? 1 : 2) void solve_mrhs_
   const int slot = tid & 15;              // elementwise mapping: slot = tid % 16,
   const int row0 = tid >> 4;              // rows row0 + 16 m
 
-  // Q in registers for the matrix-core products (TPW > 0): TW row tiles per wave, KS k steps
-  constexpr int NW = NT / kWave;
-  constexpr int TW = TPW > 0 ? 4 * TPW / NW : 1;
-  constexpr int KS = TPW > 0 ? 16 * TPW : 1;
-  float qa[TW][KS];
-  if constexpr (TPW > 0) {
-    const int lr = lane & 15, lg = lane >> 4;
-#pragma unroll
-    for (int tt = 0; tt < TW; ++tt) {
-      const int m = (wave + NW * tt) * 16 + lr;
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int kk = 4 * ks + lg;
-        qa[tt][ks] = (m < n && kk < n) ? A.Q[(int64_t)m * n + kk] : 0.f;
-      }
-    }
-  }
   // W = Q V for V [np][16] in LDS; with den, also the partials of V_c^T W_c per wave and slot
   // in red[wave][slot]
   auto product = [&](const float* V, float* Wout, auto den) {
     constexpr bool DEN = decltype(den)::value;
-    if constexpr (TPW > 0) mfma_product_reg<TW, KS, NW, DEN>(qa, V, Wout, V, red);
-    else mfma_product<NT, DEN>(A, V, Wout, V, red);
+    mfma_product<NT, DEN>(A, V, Wout, V, red);
   };
 
   // The slot flags are written by threads 0..15 (lanes 0..15 of wave 0).  Wave 0 then folds
@@ -657,11 +639,12 @@ constexpr int MR_PS = 20;  // row stride (floats) of the operand and result arra
                            // result writes (rows 4 (l / 16) + e, column l % 16) hit 64 banks
 constexpr int MR_REF_BATCH = 4;  // waiting slots that trigger an exact-gradient refresh
 
-template <int TPW, int NT>
-__global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_split_kernel(MrArgs A) {
+template <int TPW, int NT, bool SPLIT>
+__global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(MrArgs A) {
   constexpr int NW = NT / kWave;
   constexpr int TW = 4 * TPW / NW;            // row tiles of Q per wave
-  constexpr int KH = 2 * TPW;                 // k blocks of 32
+  constexpr int KH = SPLIT ? 2 * TPW : 1;     // k blocks of 32 (split products)
+  constexpr int KS = SPLIT ? 1 : 16 * TPW;    // k steps of 4 (FP32 products)
   constexpr int NP = 64 * TPW;                // rows, padded
   constexpr int NB = NT / MR_SLOTS;           // row-block groups
   constexpr int RB = NP / 8;                  // row blocks of 8
@@ -673,9 +656,9 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_split_kernel
   float* W = P + NP * S;                           // [NP][S] product result
   float* G = W + NP * S;                           // [NP][S] gradient
   f16x8* Vh = (f16x8*)(G + NP * S);                // [RB][16] split operand, hi parts
-  f16x8* Vl = Vh + RB * MR_SLOTS;                  // [RB][16] lo parts
-  float* rinv = (float*)(Vl + RB * MR_SLOTS);      // [NP] 1 / r per row of Q
-  float* red = rinv + NP;                          // [NW][16][4] statistics partials
+  f16x8* Vl = Vh + (SPLIT ? RB * MR_SLOTS : 0);    // [RB][16] lo parts
+  float* rinv = (float*)(Vl + (SPLIT ? RB * MR_SLOTS : 0));  // [NP] 1 / r per row of Q
+  float* red = rinv + (SPLIT ? NP : 0);            // [NW][16][4] statistics partials
   float* red2 = red + NW * MR_SLOTS * 4;           // [NW][16] denominator / ||q||^2 partials
   int* s_newcol = (int*)(red2 + NW * MR_SLOTS);    // [16] next column of a retired slot
   int* s_clip = s_newcol + MR_SLOTS;               // [16] clipped rows so far (rows_read)
@@ -686,9 +669,22 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_split_kernel
   const bool leader = tid < MR_SLOTS;
   const int n = A.n, k = A.k;
 
-  // ---- Q as FP16 hi and lo parts, each row scaled by a power of two
-  f16x8 qh[TW][KH], ql[TW][KH];
-  {
+  // ---- Q in registers: FP16 hi and lo parts, each row scaled by a power of two (split
+  // products), or FP32 (lane l holds Q[16 t + l % 16][4 ks + l / 16], the A operand of step ks)
+  f16x8 qh[SPLIT ? TW : 1][KH], ql[SPLIT ? TW : 1][KH];
+  float qa[SPLIT ? 1 : TW][KS];
+  if constexpr (!SPLIT) {
+    const int lr = lane & 15, lg = lane >> 4;
+#pragma unroll
+    for (int tt = 0; tt < TW; ++tt) {
+      const int m = (wave + NW * tt) * 16 + lr;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int kk = 4 * ks + lg;
+        qa[tt][ks] = (m < n && kk < n) ? A.Q[(int64_t)m * n + kk] : 0.f;
+      }
+    }
+  } else {
     const int lr = lane & 15, lg = lane >> 4;
 #pragma unroll
     for (int tt = 0; tt < TW; ++tt) {
@@ -830,8 +826,12 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_split_kernel
                   mask16(ref && col >= 0 && !done && it == 0))) {
       write_rows_lds(P, yv);
       __syncthreads();
-      // (four k blocks in flight: the split Q leaves few registers free)
-      mfma_product<NT, false, 4, S>(A, P, W, nullptr, nullptr);
+      if constexpr (SPLIT) {
+        // from the FP32 Q in L2 (four k blocks in flight: the split Q leaves few registers free)
+        mfma_product<NT, false, 4, S>(A, P, W, nullptr, nullptr);
+      } else {
+        mfma_product_reg<TW, KS, NW, false, S>(qa, P, W, nullptr, nullptr);
+      }
       __syncthreads();
       if (ref && col >= 0 && !done) {
         const int kk = opaque_k();
@@ -948,9 +948,10 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_split_kernel
     if (tid == 0) *s_anyclip = 0;
     const float sg = act ? mr_pow2_scale(sqrtf(num)) : 1.f;  // |gbar_i| <= ||gbar||
     write_rows_lds(P, pv);
-    split_rows(sg);
+    if constexpr (SPLIT) split_rows(sg);
     __syncthreads();
-    mfma_product_h3<TW, KH, NW, S, true>(qh, ql, Vh, Vl, rinv, 1.f / sg, W, P, red2);
+    if constexpr (SPLIT) mfma_product_h3<TW, KH, NW, S, true>(qh, ql, Vh, Vl, rinv, 1.f / sg, W, P, red2);
+    else mfma_product_reg<TW, KS, NW, true, S>(qa, P, W, P, red2);
     __syncthreads();
 
     // ---- step length, projected update y' = [y - alpha gbar]_+ of the own rows, d = y' - y
@@ -989,13 +990,17 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_split_kernel
     }
     // |y'_i - y_i| <= alpha |gbar_i| <= alpha ||gbar|| (a clipped entry moves less)
     const float sd = act ? mr_pow2_scale(alpha * sqrtf(num)) : 1.f;
-    split_rows(sd);
+    if constexpr (SPLIT) split_rows(sd);
+    else write_rows_lds(P, pv);  // (the epilogue's last read of P was before the barrier above)
     __syncthreads();
 
     // ---- gradient g' = g + Q d, the second product of Algorithm 2; when no slot clipped,
     // d = -alpha gbar in every slot and Q d = -alpha W from the line-search product
     if (*s_anyclip) {
-      mfma_product_h3<TW, KH, NW, S, false>(qh, ql, Vh, Vl, rinv, 1.f / sd, W, nullptr, nullptr);
+      if constexpr (SPLIT)
+        mfma_product_h3<TW, KH, NW, S, false>(qh, ql, Vh, Vl, rinv, 1.f / sd, W, nullptr, nullptr);
+      else
+        mfma_product_reg<TW, KS, NW, false, S>(qa, P, W, nullptr, nullptr);
       __syncthreads();
       if (act)
 #pragma unroll
@@ -1033,37 +1038,38 @@ static int mr_np(int64_t n) {
   return tpw > 0 ? 64 * tpw : (int)((n + 15) / 16 * 16);
 }
 
-// threads per workgroup of the kernel instance that serves n: 512 for four row tiles per wave
-// group; with split products also 384 for three (6 waves of two tiles, which leaves the
-// registers the FP16 parts of Q and the own rows need)
-static int mr_nt(int64_t n, bool split) {
+// n <= 256: solve_mrhs_reg_kernel (Q in registers); threads per workgroup 512 for four row tiles
+// per wave group, 384 for three (6 waves of two tiles, which leaves the registers Q and the own
+// rows need), else 256.  n > 256: solve_mrhs_kernel, 256 threads.
+static int mr_nt(int64_t n) {
   const int tpw = mr_tpw(n);
-  return tpw == 4 ? 512 : (split && tpw == 3 ? 384 : MR_NT);
+  return tpw == 4 ? 512 : (tpw == 3 ? 384 : MR_NT);
 }
 
-// split FP16 products for the register-held Q, unless NNLS_MRHS_PRODUCT=fp32 asks for the FP32
-// products (kept for comparison)
-static bool mr_h3(int64_t n) {
+// Products of the register kernel: FP32 (v_mfma_f32_16x16x4f32) by default, or the split FP16
+// form (three v_mfma_f32_16x16x32_f16 per product, each term within 3 2^-22 of the FP32 one)
+// with NNLS_MRHS_PRODUCT=split16.
+static bool mr_split(int64_t n) {
   if (mr_tpw(n) == 0) return false;
   const char* v = getenv("NNLS_MRHS_PRODUCT");
-  return !(v && strcmp(v, "fp32") == 0);
+  return v != nullptr && strcmp(v, "split16") == 0;
 }
 
 static size_t mr_lds_bytes(int64_t n, bool split) {
   const size_t np = (size_t)mr_np(n);
-  const size_t nw = (size_t)mr_nt(n, split) / kWave;
-  if (split)  // solve_mrhs_split_kernel's layout
-    return sizeof(float) * 3 * np * MR_PS + 2 * sizeof(f16x8) * (np / 8) * MR_SLOTS +
-           sizeof(float) * np + sizeof(float) * nw * MR_SLOTS * 5 + sizeof(int) * 2 * MR_SLOTS +
-           64;
+  const size_t nw = (size_t)mr_nt(n) / kWave;
+  if (mr_tpw(n) > 0)  // solve_mrhs_reg_kernel's layout
+    return sizeof(float) * 3 * np * MR_PS +
+           (split ? 2 * sizeof(f16x8) * (np / 8) * MR_SLOTS + sizeof(float) * np : 0) +
+           sizeof(float) * nw * MR_SLOTS * 5 + sizeof(int) * 2 * MR_SLOTS + 64;
   return sizeof(float) * 4 * np * MR_SLOTS +
          sizeof(float) * 8 * MR_SLOTS + sizeof(int) * 9 * MR_SLOTS +
          sizeof(float) * nw * MR_SLOTS * 4 + sizeof(int) * 8 + 64;
 }
 
 bool solve_mrhs_supported(int64_t n, int64_t k) {
-  // (the larger of the two layouts, so the answer does not depend on the product form)
-  return k >= 2 && n >= 1 && (n % 4) == 0 && mr_lds_bytes(n, mr_tpw(n) > 0) <= 160 * 1024;
+  // (the larger layout, so the answer does not depend on the product form)
+  return k >= 2 && n >= 1 && (n % 4) == 0 && mr_lds_bytes(n, true) <= 160 * 1024;
 }
 
 size_t solve_mrhs_ws_bytes() { return 256; }
@@ -1076,29 +1082,21 @@ hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* 
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const bool h3 = mr_h3(n);
-  const size_t lds = mr_lds_bytes(n, h3);  // the layout of the instance picked below
+  const bool split = mr_split(n);
+  const size_t lds = mr_lds_bytes(n, split);  // the layout of the instance picked below
   const void* kern = nullptr;
+#define MR_REG(TPW, NT)                                                    \
+  kern = split ? (const void*)solve_mrhs_reg_kernel<TPW, NT, true>        \
+               : (const void*)solve_mrhs_reg_kernel<TPW, NT, false>
   switch (mr_tpw(n)) {
-    case 1:
-      kern = h3 ? (const void*)solve_mrhs_split_kernel<1, MR_NT>
-                : (const void*)solve_mrhs_kernel<1, MR_NT>;
-      break;
-    case 2:
-      kern = h3 ? (const void*)solve_mrhs_split_kernel<2, MR_NT>
-                : (const void*)solve_mrhs_kernel<2, MR_NT>;
-      break;
-    case 3:
-      kern = h3 ? (const void*)solve_mrhs_split_kernel<3, 384>
-                : (const void*)solve_mrhs_kernel<3, MR_NT>;
-      break;
-    case 4:
-      kern = h3 ? (const void*)solve_mrhs_split_kernel<4, 512>
-                : (const void*)solve_mrhs_kernel<4, 512>;
-      break;
-    default: kern = (const void*)solve_mrhs_kernel<0, MR_NT>; break;
+    case 1: MR_REG(1, MR_NT); break;
+    case 2: MR_REG(2, MR_NT); break;
+    case 3: MR_REG(3, 384); break;
+    case 4: MR_REG(4, 512); break;
+    default: kern = (const void*)solve_mrhs_kernel<MR_NT>; break;
   }
-  const int nt = mr_nt(n, h3);
+#undef MR_REG
+  const int nt = mr_nt(n);
   int per_cu = 1;
   hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -1127,12 +1125,12 @@ hipError_t launch_solve_mrhs(int64_t n, int64_t k, const float* Q, const float* 
   A.trace_len = trace_len;
   A.queue = (int*)ws;
   A.G0 = nullptr;
-  // Split kernel, warm start: the start gradients of all columns in one pass, written to X
+  // Register kernel, warm start: the start gradients of all columns in one pass, written to X
   // (each column's entries are read when it enters a slot and overwritten only when it
   // retires, by the same workgroup).  Not when X overlaps Y0.
   const size_t nk = (size_t)n * (size_t)k;
   const bool overlap = Y0 != nullptr && (const float*)X < Y0 + nk && Y0 < (const float*)X + nk;
-  if (h3 && Y0 != nullptr && !overlap && A.np <= SG_NP) {
+  if (mr_tpw(n) > 0 && Y0 != nullptr && !overlap && A.np <= SG_NP) {
     A.G0 = X;
     hipLaunchKernelGGL(mrhs_start_grad_kernel, dim3((unsigned)((k + MR_SLOTS - 1) / MR_SLOTS)),
                        dim3(MR_NT), 0, st, A, X);

@@ -2,8 +2,8 @@
 
 The solver has one instance per register shape of Q: n <= 64, 128, 192 (Q in registers, 256
 threads), n in (192, 256] (Q in registers over 8 waves, 512 threads) and n > 256 (Q read from
-L2).  With Q in registers the products run as split FP16 products by default and as FP32
-products under NNLS_MRHS_PRODUCT=fp32; both forms are checked.  Each instance is checked one
+L2).  With Q in registers the products run in FP32 by default and as split FP16 products under
+NNLS_MRHS_PRODUCT=split16; both forms are checked.  Each instance is checked one
 update at a time from the oracle's own iterates (both products of Algorithm 2: the line-search
 product Q gbar and the gradient correction Q (y' - y), including the clip-free form
 -alpha Q gbar), and end to end on the shapes of the many-RHS and warm-start workloads with more
@@ -50,10 +50,10 @@ def _passive_and_clipped(Q, q, y):
                                  (512, 19), (256, 19), (64, 2), (128, 4), (256, 3)])
 def test_mrhs_steps_match_oracle(n, k, product, monkeypatch):
     monkeypatch.setenv("NNLS_SOLVER", "mrhs")
-    if product == "fp32":
+    if product == "split16":
         if n > 256:
             pytest.skip("Q read from L2 has only the FP32 product")
-        monkeypatch.setenv("NNLS_MRHS_PRODUCT", "fp32")
+        monkeypatch.setenv("NNLS_MRHS_PRODUCT", "split16")
     assert N.solver_name(n, k) == "mrhs"
     say(f"mrhs single steps n={n} k={k} product={product}")
     A, B = _uniform_case(500 + n, 3 * n, n, k)
@@ -123,6 +123,7 @@ def test_mrhs_split_products_on_unscaled_lopsided_gram(monkeypatch):
                 Ym[:, c] = orc().nqp(Hh, hh[:, c], 0.0, m)[0]
         Ystart = Ym.astype(np.float32)
         Y0 = dev(Ystart) if m else None
+        monkeypatch.setenv("NNLS_MRHS_PRODUCT", "split16")
         Ys = _one_update(H, h, Y0)
         monkeypatch.setenv("NNLS_MRHS_PRODUCT", "fp32")
         Yf = _one_update(H, h, Y0)
@@ -151,12 +152,14 @@ def _check(A, B, res, sample, what):
     np.testing.assert_allclose(host(res["kkt64"]), r, rtol=1e-6, atol=1e-14)
 
 
-def test_mrhs_end_to_end_manyrhs_shape():
+@pytest.mark.parametrize("product", ["fp32", "split16"])
+def test_mrhs_end_to_end_manyrhs_shape(product, monkeypatch):
     """The many-RHS recipe (|N(0,1)| dictionary, Gamma(2,1) codes, 1 % noise) at n = 256 with
     8192 columns: twice the 4096 slots resident on 256 compute units, so every group refills
     from the queue."""
+    monkeypatch.setenv("NNLS_MRHS_PRODUCT", product)
     A, B, _ = W.make_manyrhs(seed=7, d=3000, n=256, k=8192)
-    say("mrhs e2e 3000x256 k=8192")
+    say(f"mrhs e2e 3000x256 k=8192 product={product}")
     assert N.solver_name(256, 8192) == "mrhs"
     res = N.nnls(dev(A), dev(B), tol=1e-5, max_iter=100000, inner_tol=3e-6)
     assert np.all(host(res["status"]) == N.CONVERGED)
@@ -176,9 +179,11 @@ def test_mrhs_end_to_end_other_instances(n, k):
     _check(A, B, res, np.arange(0, k, max(1, k // 48)), f"mrhs n={n}")
 
 
-def test_mrhs_end_to_end_warm_shape():
+@pytest.mark.parametrize("product", ["fp32", "split16"])
+def test_mrhs_end_to_end_warm_shape(product, monkeypatch):
     """The warm-start recipe (A 4096 x 256 |N(0,1)|, noiseless b = A x, 85 % zeros) from the
     cold start, 6000 held-out columns."""
+    monkeypatch.setenv("NNLS_MRHS_PRODUCT", product)
     A = W.make_warm_matrix()
     B, _ = W.make_warm_rhs(A, 6000, split=1, start=0)
     say("mrhs e2e warm shape 4096x256 k=6000")
