@@ -89,8 +89,8 @@ __device__ __forceinline__ void split_chunk(const float (&v)[8], float sig, f16x
 // W = Q * V from the register-held split Q (rows scaled by r, rinv = 1 / r in LDS) and the split
 // V (columns scaled by sigma; cs = 1 / sigma of the lane's column): wave w owns the row tiles
 // w + NW tt, lane l holds rows 16 t + l % 16 at columns 32 kh + 8 (l / 16) + 0..7 (the A
-// operand).  W and Vd are [np][S] in LDS.
-template <int TW, int KH, int NW, int S, bool DEN>
+// operand).  W is [np][S] and Vd [np][SV] in LDS.
+template <int TW, int KH, int NW, int S, bool DEN, int SV = S>
 __device__ __forceinline__ void mfma_product_h3(const f16x8 (&qh)[TW][KH],
                                                 const f16x8 (&ql)[TW][KH], const f16x8* Vh,
                                                 const f16x8* Vl, const float* rinv, float cs,
@@ -122,7 +122,7 @@ __device__ __forceinline__ void mfma_product_h3(const f16x8 (&qh)[TW][KH],
       const int row = row0 + NW * 16 * tt + e;
       const float w = (acc[tt][e] * rinv[row]) * cs;
       W[row * S + lr] = w;
-      if constexpr (DEN) dp += Vd[row * S + lr] * w;
+      if constexpr (DEN) dp += Vd[row * SV + lr] * w;
     }
   }
   if constexpr (DEN) den_publish(dp, redw);
@@ -147,13 +147,14 @@ struct MrArgs {
   const float* G0;  // [n, k] exact gradients Q max(Y0, 0) + q at the start, or nullptr
 };
 
-// W[0..np)[0..16) = Q * V (V: [np][16] in LDS, rows S floats apart), rows and columns of Q
+// W[0..np)[0..16) = Q * V (V and Vd: [np][16] in LDS, rows SV floats apart; W rows S floats
+// apart), rows and columns of Q
 // beyond n read as 0.
 // Wave w computes row tiles w, w + NT / 64, ...; for each 16-wide k block a lane loads 4
 // consecutive Q entries of one row (16 bytes) and feeds them to 4 MFMAs; the k index of MFMA e
 // for lane group g is k0 + 4 g + e, for both operands.  KB k blocks (8 by default) are loaded
 // before their MFMAs so the L2 latency is paid once per KB.
-template <int NT, bool DEN, int KB = 8, int S = MR_SLOTS>
+template <int NT, bool DEN, int KB = 8, int S = MR_SLOTS, int SV = S>
 __device__ void mfma_product(const MrArgs& A, const float* V, float* W, const float* Vd,
                              float* redw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -179,7 +180,7 @@ __device__ void mfma_product(const MrArgs& A, const float* V, float* W, const fl
         if (k0 + 16 * u < np) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const float b = V[(kk + e) * S + lr];
+            const float b = V[(kk + e) * SV + lr];
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][e], b, acc, 0, 0, 0);
           }
         }
@@ -190,7 +191,7 @@ __device__ void mfma_product(const MrArgs& A, const float* V, float* W, const fl
     for (int e = 0; e < 4; ++e) {
       const int row = t * 16 + 4 * lg + e;
       W[row * S + lr] = acc[e];
-      if constexpr (DEN) dp += Vd[row * S + lr] * acc[e];
+      if constexpr (DEN) dp += Vd[row * SV + lr] * acc[e];
     }
   }
   if constexpr (DEN) den_publish(dp, redw);
@@ -231,8 +232,8 @@ __global__ __launch_bounds__(MR_NT) void mrhs_start_grad_kernel(MrArgs A, float*
 // t = w + NW tt (tt < TW); lane l holds Q[16 t + l % 16][4 ks + l / 16] for every k step
 // ks < KS (np = 4 KS), the A operand of MFMA ks, so a product reads only V from LDS (lane l: row
 // 4 ks + l / 16, slot l % 16; 16 consecutive lanes hit 16 consecutive banks) and one V value
-// feeds TW MFMAs.
-template <int TW, int KS, int NW, bool DEN, int S = MR_SLOTS>
+// feeds TW MFMAs.  V and Vd rows are SV floats apart, W rows S.
+template <int TW, int KS, int NW, bool DEN, int S = MR_SLOTS, int SV = S>
 __device__ __forceinline__ void mfma_product_reg(const float (&qa)[TW][KS], const float* V,
                                                  float* W, const float* Vd, float* redw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -242,7 +243,7 @@ __device__ __forceinline__ void mfma_product_reg(const float (&qa)[TW][KS], cons
   for (int tt = 0; tt < TW; ++tt) acc[tt] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
-    const float b = V[(4 * ks + lg) * S + lr];
+    const float b = V[(4 * ks + lg) * SV + lr];
 #pragma unroll
     for (int tt = 0; tt < TW; ++tt)
       acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[tt][ks], b, acc[tt], 0, 0, 0);
@@ -257,7 +258,7 @@ __device__ __forceinline__ void mfma_product_reg(const float (&qa)[TW][KS], cons
     for (int e = 0; e < 4; ++e) {
       const int row = row0 + NW * 16 * tt + e;
       W[row * S + lr] = acc[tt][e];
-      if constexpr (DEN) dp += Vd[row * S + lr] * acc[tt][e];
+      if constexpr (DEN) dp += Vd[row * SV + lr] * acc[tt][e];
     }
   }
   if constexpr (DEN) den_publish(dp, redw);
@@ -635,8 +636,14 @@ __global__ __launch_bounds__(NT, 2) void solve_mrhs_kernel(MrArgs A) {
 // holds the gradient (each thread reads and writes only its own rows of it), the products'
 // operands and results and the partial sums, and an update takes four barriers (five when a
 // slot clipped).
-constexpr int MR_PS = 20;  // row stride (floats) of the operand and result arrays: the product's
-                           // result writes (rows 4 (l / 16) + e, column l % 16) hit 64 banks
+// Row strides (floats) of the LDS arrays, chosen for their most frequent access.  Product
+// results: the epilogue writes rows 4 (l / 16) + e, column l % 16 (lane l), so 20.  Product
+// operands: the matrix-core steps read rows 4 ks + l / 16, column l % 16, so 16.  Gradient: the
+// update reads rows 8 (t / 16) + e, column t % 16 (thread t), so 18.  Each then hits 64
+// distinct banks.
+constexpr int MR_PS = 20;
+constexpr int MR_PV = 16;
+constexpr int MR_PG = 18;
 constexpr int MR_REF_BATCH = 4;  // waiting slots that trigger an exact-gradient refresh
 
 template <int TPW, int NT, bool SPLIT>
@@ -649,13 +656,13 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
   constexpr int NB = NT / MR_SLOTS;           // row-block groups
   constexpr int RB = NP / 8;                  // row blocks of 8
   constexpr int JB = (RB + NB - 1) / NB;      // row blocks per thread
-  constexpr int S = MR_PS;
+  constexpr int S = MR_PS, SV = MR_PV, SG = MR_PG;
   static_assert(TPW > 0 && (4 * TPW) % NW == 0, "row tiles per wave");
   extern __shared__ __attribute__((aligned(16))) float sm[];
-  float* P = sm;                                   // [NP][S] product operand (FP32)
-  float* W = P + NP * S;                           // [NP][S] product result
-  float* G = W + NP * S;                           // [NP][S] gradient
-  f16x8* Vh = (f16x8*)(G + NP * S);                // [RB][16] split operand, hi parts
+  float* P = sm;                                   // [NP][SV] product operand (FP32)
+  float* W = P + NP * SV;                          // [NP][S] product result
+  float* G = W + NP * S;                           // [NP][SG] gradient
+  f16x8* Vh = (f16x8*)(G + NP * SG);               // [RB][16] split operand, hi parts
   f16x8* Vl = Vh + (SPLIT ? RB * MR_SLOTS : 0);    // [RB][16] lo parts
   float* rinv = (float*)(Vl + (SPLIT ? RB * MR_SLOTS : 0));  // [NP] 1 / r per row of Q
   float* red = rinv + (SPLIT ? NP : 0);            // [NW][16][4] statistics partials
@@ -752,7 +759,7 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
           }
         }
         yv[j][e] = yi;
-        if (blk(j) < RB) G[i * S + c] = gi;
+        if (blk(j) < RB) G[i * SG + c] = gi;
       }
   };
   // a predicate over the 16 slots as a bit mask, the same in every wave
@@ -792,7 +799,7 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
     for (int j = 0; j < JB; ++j)
       if (blk(j) < RB)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) dst[(8 * blk(j) + e) * S + c] = v[j][e];
+        for (int e = 0; e < 8; ++e) dst[(8 * blk(j) + e) * SV + c] = v[j][e];
   };
   auto split_rows = [&](float sig) {
 #pragma unroll
@@ -828,9 +835,9 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
       __syncthreads();
       if constexpr (SPLIT) {
         // from the FP32 Q in L2 (four k blocks in flight: the split Q leaves few registers free)
-        mfma_product<NT, false, 4, S>(A, P, W, nullptr, nullptr);
+        mfma_product<NT, false, 4, S, SV>(A, P, W, nullptr, nullptr);
       } else {
-        mfma_product_reg<TW, KS, NW, false, S>(qa, P, W, nullptr, nullptr);
+        mfma_product_reg<TW, KS, NW, false, S, SV>(qa, P, W, nullptr, nullptr);
       }
       __syncthreads();
       if (ref && col >= 0 && !done) {
@@ -840,7 +847,7 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
             const int i = 8 * blk(j) + e;
-            if (blk(j) < RB && i < n) G[i * S + c] = W[i * S + c] + A.q[(int64_t)i * kk + col];
+            if (blk(j) < RB && i < n) G[i * SG + c] = W[i * S + c] + A.q[(int64_t)i * kk + col];
           }
         ref = false;
         fresh = true;
@@ -859,7 +866,7 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
         for (int e = 0; e < 8; ++e) {
           const int i = 8 * blk(j) + e;
           const bool ok = blk(j) < RB && live && i < n;
-          const float yi = yv[j][e], gi = blk(j) < RB ? G[i * S + c] : 0.f;
+          const float yi = yv[j][e], gi = blk(j) < RB ? G[i * SG + c] : 0.f;
           const bool pas = ok && ((yi > 0.f) || (gi < 0.f));
           const float pi = pas ? gi : 0.f;
           pv[j][e] = pi;
@@ -950,8 +957,8 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
     write_rows_lds(P, pv);
     if constexpr (SPLIT) split_rows(sg);
     __syncthreads();
-    if constexpr (SPLIT) mfma_product_h3<TW, KH, NW, S, true>(qh, ql, Vh, Vl, rinv, 1.f / sg, W, P, red2);
-    else mfma_product_reg<TW, KS, NW, true, S>(qa, P, W, P, red2);
+    if constexpr (SPLIT) mfma_product_h3<TW, KH, NW, S, true, SV>(qh, ql, Vh, Vl, rinv, 1.f / sg, W, P, red2);
+    else mfma_product_reg<TW, KS, NW, true, S, SV>(qa, P, W, P, red2);
     __syncthreads();
 
     // ---- step length, projected update y' = [y - alpha gbar]_+ of the own rows, d = y' - y
@@ -1000,7 +1007,7 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
       if constexpr (SPLIT)
         mfma_product_h3<TW, KH, NW, S, false>(qh, ql, Vh, Vl, rinv, 1.f / sd, W, nullptr, nullptr);
       else
-        mfma_product_reg<TW, KS, NW, false, S>(qa, P, W, nullptr, nullptr);
+        mfma_product_reg<TW, KS, NW, false, S, SV>(qa, P, W, nullptr, nullptr);
       __syncthreads();
       if (act)
 #pragma unroll
@@ -1008,7 +1015,7 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
             const int i = 8 * blk(j) + e;
-            if (blk(j) < RB && i < n) G[i * S + c] += W[i * S + c];
+            if (blk(j) < RB && i < n) G[i * SG + c] += W[i * S + c];
           }
     } else if (act) {
 #pragma unroll
@@ -1016,7 +1023,7 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int i = 8 * blk(j) + e;
-          if (blk(j) < RB && i < n) G[i * S + c] -= alpha * W[i * S + c];
+          if (blk(j) < RB && i < n) G[i * SG + c] -= alpha * W[i * S + c];
         }
     }
     if (act) {
@@ -1059,7 +1066,7 @@ static size_t mr_lds_bytes(int64_t n, bool split) {
   const size_t np = (size_t)mr_np(n);
   const size_t nw = (size_t)mr_nt(n) / kWave;
   if (mr_tpw(n) > 0)  // solve_mrhs_reg_kernel's layout
-    return sizeof(float) * 3 * np * MR_PS +
+    return sizeof(float) * np * (MR_PV + MR_PS + MR_PG) +
            (split ? 2 * sizeof(f16x8) * (np / 8) * MR_SLOTS + sizeof(float) * np : 0) +
            sizeof(float) * nw * MR_SLOTS * 5 + sizeof(int) * 2 * MR_SLOTS + 64;
   return sizeof(float) * 4 * np * MR_SLOTS +

@@ -4,9 +4,9 @@ The solver has one instance per register shape of Q: n <= 64, 128, 192 (Q in reg
 threads), n in (192, 256] (Q in registers over 8 waves, 512 threads) and n > 256 (Q read from
 L2).  With Q in registers the products run in FP32 by default and as split FP16 products under
 NNLS_MRHS_PRODUCT=split16; both forms are checked.  Each instance is checked one
-update at a time from the oracle's own iterates (both products of Algorithm 2: the line-search
-product Q gbar and the gradient correction Q (y' - y), including the clip-free form
--alpha Q gbar), and end to end on the shapes of the many-RHS and warm-start workloads with more
+update at a time from the oracle's own iterates (the line-search product Q gbar), two updates at
+a time (the gradient carried from one update to the next through the correction product
+Q (y' - y), or -alpha Q gbar when no slot clipped), and end to end on the shapes of the many-RHS and warm-start workloads with more
 columns than resident slots, so the column queue refills.
 """
 import numpy as np
@@ -91,6 +91,46 @@ def test_mrhs_steps_match_oracle(n, k, product, monkeypatch):
             assert abs(int(rows_h[c]) - want) <= 2, (m, c, int(rows_h[c]), want)
         say(f"  m={m}: worst rel err {worst:.2e}")
     # the gradient correction with clipped entries (the second product) was exercised
+    assert clipped_total > 0
+
+
+# Two updates from the oracle's iterates: the second update's line search runs on the gradient
+# the first one carried forward (g + Q (y' - y), or g - alpha Q gbar when no slot clipped), so
+# it checks the gradient correction product, in both product forms.
+@pytest.mark.parametrize("product", ["split16", "fp32"])
+@pytest.mark.parametrize("n,k", [(64, 2), (128, 19), (192, 21), (200, 37), (256, 37), (300, 21)])
+def test_mrhs_two_updates_match_oracle(n, k, product, monkeypatch):
+    monkeypatch.setenv("NNLS_SOLVER", "mrhs")
+    if product == "split16":
+        if n > 256:
+            pytest.skip("Q read from L2 has only the FP32 product")
+        monkeypatch.setenv("NNLS_MRHS_PRODUCT", "split16")
+    say(f"mrhs two updates n={n} k={k} product={product}")
+    A, B = _uniform_case(900 + n, 3 * n, n, k)
+    Q, q, _ = N.prepare(dev(A), dev(B))
+    Qh, qh = host(Q).astype(np.float64), host(q).astype(np.float64)
+    eps = 2.0 ** -23
+    clipped_total = 0
+    for m in [0, 3, 12]:
+        Ym = np.zeros((n, k))
+        if m:
+            for c in range(k):
+                Ym[:, c] = orc().nqp(Qh, qh[:, c], 0.0, m)[0]
+        Ystart = Ym.astype(np.float32).astype(np.float64)
+        Y, iters, _, st = N.solve(Q, q, None, tol=0.0, max_iter=2,
+                                  Y0=dev(Ym.astype(np.float32)) if m else None)
+        Yh = host(Y).astype(np.float64)
+        assert np.all(host(iters) == 2)
+        assert np.all(host(st) == N.MAXITER)
+        worst = 0.0
+        for c in range(k):
+            clipped_total += _passive_and_clipped(Qh, qh[:, c], Ystart[:, c])[1]
+            yn = orc().nqp(Qh, qh[:, c], 0.0, 2, y0=Ystart[:, c])[0]
+            err = np.abs(Yh[:, c] - yn).max()
+            scale = np.abs(Ystart[:, c]).max() + np.abs(yn).max()
+            worst = max(worst, err / scale)
+            assert err <= 16 * n * eps * scale, (m, c, err / scale)
+        say(f"  m={m}: worst rel err {worst:.2e}")
     assert clipped_total > 0
 
 
