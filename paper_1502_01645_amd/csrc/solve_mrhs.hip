@@ -264,6 +264,82 @@ __device__ __forceinline__ void mfma_product_reg(const float (&qa)[TW][KS], cons
   if constexpr (DEN) den_publish(dp, redw);
 }
 
+// W = Q V for the columns of V whose bits are set in `live` (at most 4 npass of them), with Q in
+// registers as for mfma_product_reg, on v_mfma_f32_4x4x1f32: that instruction treats the wave
+// as 16 blocks b = l / 4 of 4 x 4, lane 4 b + i giving row i of the A block and lane 4 b + j
+// column j of the B block, and lane 4 b + j receiving column j of the block's result (row i in
+// element i).  Lane l's Q value for step ks (row 16 t + l % 16, column 4 ks + l / 16) thus
+// makes block b a 4-row piece of the tile (rows 16 t + 4 (b % 4) + i) at one column k = 4 ks +
+// b / 4, and lane 4 b + j supplies V[k][slot j]: each block accumulates the k of one residue
+// mod 4 for 4 slots, and the four residues (lane groups l / 16) are summed by two shuffles.  A
+// pass covers 4 slots at a quarter of the matrix-core time of the 16-slot product.  Results of
+// other columns are not written; with DEN, the partial denominators of the live slots only.
+template <int TW, int KS, int NW, bool DEN, int S, int SV>
+__device__ __forceinline__ void mfma_product_few(const float (&qa)[TW][KS], const float* V,
+                                                 float* W, const float* Vd, float* redw,
+                                                 unsigned live, int npass) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4, j = lane & 3;
+  for (int p = 0; p < npass; ++p) {
+    // the lane's slot: the (4 p + j)-th set bit of live, or -1 past the last
+    int slot = -1;
+    {
+      unsigned m = live;
+      for (int skip = 4 * p + j; skip > 0 && m; --skip) m &= m - 1u;
+      if (m) slot = __builtin_ctz(m);
+    }
+    const int sv = slot < 0 ? 0 : slot;  // (a lane without a slot computes a column never written)
+    f32x4 acc[TW];
+#pragma unroll
+    for (int tt = 0; tt < TW; ++tt) acc[tt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    // (the V values of the next 4 steps are read while the current 4 are multiplied: a step
+    // here is too short to cover the LDS latency by itself)
+    constexpr int KC = 4;
+    static_assert(KS % KC == 0, "k steps per chunk");
+    float bn[KC];
+#pragma unroll
+    for (int u = 0; u < KC; ++u) bn[u] = V[(4 * u + lg) * SV + sv];
+#pragma unroll
+    for (int k0 = 0; k0 < KS; k0 += KC) {
+      float bc[KC];
+#pragma unroll
+      for (int u = 0; u < KC; ++u) bc[u] = bn[u];
+      if (k0 + KC < KS)
+#pragma unroll
+        for (int u = 0; u < KC; ++u) bn[u] = V[(4 * (k0 + KC + u) + lg) * SV + sv];
+#pragma unroll
+      for (int u = 0; u < KC; ++u)
+#pragma unroll
+        for (int tt = 0; tt < TW; ++tt)
+          acc[tt] = __builtin_amdgcn_mfma_f32_4x4x1f32(qa[tt][k0 + u], bc[u], acc[tt], 0, 0, 0);
+    }
+    float dp = 0.f;
+#pragma unroll
+    for (int tt = 0; tt < TW; ++tt) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc[tt][e] += __shfl_xor(acc[tt][e], 16, 64);
+        acc[tt][e] += __shfl_xor(acc[tt][e], 32, 64);
+      }
+      // every lane group holds the sums: group g writes row 4 (l % 16 / 4) + g of the tile
+      const float w = lg == 0 ? acc[tt][0] : lg == 1 ? acc[tt][1] : lg == 2 ? acc[tt][2] : acc[tt][3];
+      const int row = (wave + NW * tt) * 16 + 4 * (lr >> 2) + lg;
+      if (slot >= 0) {
+        W[row * S + slot] = w;
+        if constexpr (DEN) dp += Vd[row * SV + slot] * w;
+      }
+    }
+    if constexpr (DEN) {
+      // the wave's partial for slot j of the pass: the 16 lanes with l % 4 == j
+      dp += __shfl_xor(dp, 4, 64);
+      dp += __shfl_xor(dp, 8, 64);
+      dp += __shfl_xor(dp, 16, 64);
+      dp += __shfl_xor(dp, 32, 64);
+      if (lane < 4 && slot >= 0) redw[wave * MR_SLOTS + slot] = dp;
+    }
+  }
+}
+
 // n > 256: Q does not fit in registers and every product reads it from L2 (mfma_product, FP32).
 // Slot state in LDS; threads 0..15 take the slots' decisions and wave 0 folds the slot flags
 // into masks.  (n <= 256 runs solve_mrhs_reg_kernel below.)
@@ -645,6 +721,8 @@ constexpr int MR_PS = 20;
 constexpr int MR_PV = 16;
 constexpr int MR_PG = 18;
 constexpr int MR_REF_BATCH = 4;  // waiting slots that trigger an exact-gradient refresh
+constexpr int MR_FEW_PASS = 2;   // FP32 products for at most 4 MR_FEW_PASS slots (updating, or
+                                 // waiting for a refresh) take mfma_product_few
 
 template <int TPW, int NT, bool SPLIT>
 __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(MrArgs A) {
@@ -837,7 +915,11 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
         // from the FP32 Q in L2 (four k blocks in flight: the split Q leaves few registers free)
         mfma_product<NT, false, 4, S, SV>(A, P, W, nullptr, nullptr);
       } else {
-        mfma_product_reg<TW, KS, NW, false, S, SV>(qa, P, W, nullptr, nullptr);
+        const int np4 = (__builtin_popcount(mwait) + 3) / 4;
+        if (np4 <= MR_FEW_PASS)
+          mfma_product_few<TW, KS, NW, false, S, SV>(qa, P, W, nullptr, nullptr, mwait, np4);
+        else
+          mfma_product_reg<TW, KS, NW, false, S, SV>(qa, P, W, nullptr, nullptr);
       }
       __syncthreads();
       if (ref && col >= 0 && !done) {
@@ -958,7 +1040,12 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
     if constexpr (SPLIT) split_rows(sg);
     __syncthreads();
     if constexpr (SPLIT) mfma_product_h3<TW, KH, NW, S, true, SV>(qh, ql, Vh, Vl, rinv, 1.f / sg, W, P, red2);
-    else mfma_product_reg<TW, KS, NW, true, S, SV>(qa, P, W, P, red2);
+    else {
+      const unsigned ma = mask16(act);
+      const int np4 = (__builtin_popcount(ma) + 3) / 4;
+      if (np4 <= MR_FEW_PASS) mfma_product_few<TW, KS, NW, true, S, SV>(qa, P, W, P, red2, ma, np4);
+      else mfma_product_reg<TW, KS, NW, true, S, SV>(qa, P, W, P, red2);
+    }
     __syncthreads();
 
     // ---- step length, projected update y' = [y - alpha gbar]_+ of the own rows, d = y' - y
@@ -1006,8 +1093,14 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
     if (*s_anyclip) {
       if constexpr (SPLIT)
         mfma_product_h3<TW, KH, NW, S, false>(qh, ql, Vh, Vl, rinv, 1.f / sd, W, nullptr, nullptr);
-      else
-        mfma_product_reg<TW, KS, NW, false, S, SV>(qa, P, W, nullptr, nullptr);
+      else {
+        const unsigned ma = mask16(act);
+        const int np4 = (__builtin_popcount(ma) + 3) / 4;
+        if (np4 <= MR_FEW_PASS)
+          mfma_product_few<TW, KS, NW, false, S, SV>(qa, P, W, nullptr, nullptr, ma, np4);
+        else
+          mfma_product_reg<TW, KS, NW, false, S, SV>(qa, P, W, nullptr, nullptr);
+      }
       __syncthreads();
       if (act)
 #pragma unroll
