@@ -241,12 +241,26 @@ __device__ __forceinline__ void mfma_product_reg(const float (&qa)[TW][KS], cons
   f32x4 acc[TW];
 #pragma unroll
   for (int tt = 0; tt < TW; ++tt) acc[tt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  // (the V values of the next 4 steps are read while the current 4 are multiplied)
+  constexpr int KC = 4;
+  static_assert(KS % KC == 0, "k steps per chunk");
+  float bn[KC];
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    const float b = V[(4 * ks + lg) * SV + lr];
+  for (int u = 0; u < KC; ++u) bn[u] = V[(4 * u + lg) * SV + lr];
 #pragma unroll
-    for (int tt = 0; tt < TW; ++tt)
-      acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[tt][ks], b, acc[tt], 0, 0, 0);
+  for (int k0 = 0; k0 < KS; k0 += KC) {
+    float bc[KC];
+#pragma unroll
+    for (int u = 0; u < KC; ++u) bc[u] = bn[u];
+    if (k0 + KC < KS)
+#pragma unroll
+      for (int u = 0; u < KC; ++u) bn[u] = V[(4 * (k0 + KC + u) + lg) * SV + lr];
+    __builtin_amdgcn_sched_barrier(0);  // (keeps the reads ahead of the products)
+#pragma unroll
+    for (int u = 0; u < KC; ++u)
+#pragma unroll
+      for (int tt = 0; tt < TW; ++tt)
+        acc[tt] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[tt][k0 + u], bc[u], acc[tt], 0, 0, 0);
   }
   float dp = 0.f;
   // (the first output row formed here, not kept in a register through the solve)
@@ -307,6 +321,7 @@ __device__ __forceinline__ void mfma_product_few(const float (&qa)[TW][KS], cons
       if (k0 + KC < KS)
 #pragma unroll
         for (int u = 0; u < KC; ++u) bn[u] = V[(4 * (k0 + KC + u) + lg) * SV + sv];
+      __builtin_amdgcn_sched_barrier(0);  // (keeps the reads ahead of the products)
 #pragma unroll
       for (int u = 0; u < KC; ++u)
 #pragma unroll
