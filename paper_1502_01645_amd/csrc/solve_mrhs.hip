@@ -2,15 +2,16 @@
 //
 // A workgroup owns 16 column slots.  Per update, for all its active columns at once:
 //   gbar = masked gradient (passive set per column), num_c = ||gbar_c||^2, residual r_c;
-//   W = Q * Gbar on the matrix cores: 16 output columns.  For n <= 256 Q is held in the
-//   registers of each workgroup as FP16 hi and lo parts and the product is the three-term split
-//   Q_lo V_hi + Q_hi V_lo + Q_hi V_hi on v_mfma_f32_16x16x32_f16 (below); for n > 256 Q is read
-//   from L2 in FP32 (every workgroup streams the same n x n matrix) for v_mfma_f32_16x16x4f32;
+//   W = Q * Gbar on the FP32 matrix cores: 16 output columns.  For n <= 256 Q is held in the
+//   registers of each workgroup (v_mfma_f32_16x16x4f32 for 16 slots; v_mfma_f32_4x4x1f32 passes
+//   of 4 slots when at most 8 update), or on request as FP16 hi and lo parts with the three-term
+//   split Q_lo V_hi + Q_hi V_lo + Q_hi V_hi on v_mfma_f32_16x16x32_f16 (below); for n > 256 Q is
+//   read from L2 (every workgroup streams the same n x n matrix) for v_mfma_f32_16x16x4f32;
 //   den_c = gbar_c^T W_c, alpha_c = num_c / den_c;  y' = [y - alpha gbar]_+;
 //   grad' = grad + Q (y' - y), the second product of Algorithm 2, again on the matrix cores
-//   (with 16 columns per product the dense form beats gathering the clipped rows of Q).
+//   (with 16 columns per product the full product beats gathering the clipped rows of Q).
 // A column whose residual meets tol has its gradient recomputed exactly (Q y + q, one more
-// matrix-core product over all slots, always on the FP32 Q) before it retires; it then writes x = y / s, its
+// matrix-core product, always on the FP32 Q) before it retires; it then writes x = y / s, its
 // iteration count, residual and status, and the slot takes the next column from a queue.
 // State lives in LDS as [row][slot] arrays; rows are padded to a multiple of 16.
 #include <stdlib.h>
