@@ -307,9 +307,9 @@ __device__ __forceinline__ void mfma_product_few(const float (&qa)[TW][KS], cons
     f32x4 acc[TW];
 #pragma unroll
     for (int tt = 0; tt < TW; ++tt) acc[tt] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    // (the V values of the next 4 steps are read while the current 4 are multiplied: a step
+    // (the V values of the next 8 steps are read while the current 8 are multiplied: a step
     // here is too short to cover the LDS latency by itself)
-    constexpr int KC = 4;
+    constexpr int KC = 8;
     static_assert(KS % KC == 0, "k steps per chunk");
     float bn[KC];
 #pragma unroll
