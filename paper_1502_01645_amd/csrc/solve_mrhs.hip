@@ -42,15 +42,17 @@ __device__ __forceinline__ void den_publish(float dp, float* redw) {
   if (lane < MR_SLOTS) redw[at] = dp;
 }
 
-// Split products for Q held in registers.  A value x in FP32 is written as hi + lo with
+// Split products for Q held in registers (the form NNLS_MRHS_PRODUCT=split16 selects; the
+// default products are FP32).  A value x in FP32 is written as hi + lo with
 // hi = fp16(x) and lo = fp16(x - hi): both are FP16 (11-bit significands), so |x - hi - lo| is
 // at most 2^-22 |x| (the rounding of lo) as long as lo stays in FP16's normal range, and the
 // dropped term lo_Q lo_V is at most 2^-22 |Q_ij V_j|.  The products are exact in the matrix
 // core and summed in FP32, so each term of Q V carries at most 3 2^-22 relative error, against
 // the 2^-24 roundings of the FP32 product's sums.  That is close enough for the two products of
 // an update, which steer the iteration; the exact gradient that decides the stop test, where
-// Q y and q nearly cancel, is formed from the FP32 Q instead.  To keep both parts in FP16's range every row i of Q is scaled by a power of two r_i that
-// brings its largest entry to [2^13, 2^14), and every column c of the vector operand by a power
+// Q y and q nearly cancel, is formed from the FP32 Q instead.  To keep both parts in FP16's
+// range every row i of Q is scaled by a power of two r_i that brings its largest entry to
+// [2^13, 2^14), and every column c of the vector operand by a power
 // of two sigma_c from a bound on its largest entry (the slot's ||gbar|| or alpha ||gbar||);
 // W = (scaled product) / (r_i sigma_c) exactly.  One v_mfma_f32_16x16x32_f16 (16
 // cycles) covers the k range of eight v_mfma_f32_16x16x4f32 (32 cycles each), so the three
@@ -717,10 +719,11 @@ __global__ __launch_bounds__(NT, 2) void solve_mrhs_kernel(MrArgs A) {
 }
 
 
-// Split-product instances (n <= 256): the update of solve_mrhs_kernel, arranged so that most of
-// it runs in registers.  Thread t works on slot c = t % 16 and on the row blocks
-// rb = t / 16 + (NT / 16) j of 8 consecutive rows, which are exactly the operand chunks a split
-// writes; its rows of y, of the gradient and of the product operand stay in its registers.  The
+// Register instances (n <= 256, Q in registers in FP32, or as split FP16 parts with SPLIT): the
+// update of solve_mrhs_kernel, arranged so that most of it runs in registers.  Thread t works on
+// slot c = t % 16 and on the row blocks rb = t / 16 + (NT / 16) j of 8 consecutive rows, which are
+// exactly the operand chunks a split writes; its rows of y and of the product operand stay in its
+// registers.  The
 // state of a slot (column, update count, flags, ||q||) is kept, the same, by every thread of the
 // slot: each of them sums the slot's partial statistics and line-search denominator in the same
 // order and takes the same decisions, and every wave forms the masks over the 16 slots with one
