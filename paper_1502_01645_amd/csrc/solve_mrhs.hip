@@ -985,6 +985,9 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
         t3 += __shfl_xor(t3, off, 64);
       }
       if (lane < MR_SLOTS) *(f32x4*)(red + (wave * MR_SLOTS + lane) * 4) = (f32x4){t0, t1, t2, t3};
+      // FP32 products: the line-search operand goes to LDS before the statistics barrier, which
+      // then also publishes it (a column that will not update has only its own result wasted)
+      if constexpr (!SPLIT) write_rows_lds(P, pv);
       __syncthreads();
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
@@ -1055,9 +1058,11 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
     // ---- W = Q gbar on the matrix cores, with den_c = gbar_c^T W_c from its epilogue
     if (tid == 0) *s_anyclip = 0;
     const float sg = act ? mr_pow2_scale(sqrtf(num)) : 1.f;  // |gbar_i| <= ||gbar||
-    write_rows_lds(P, pv);
-    if constexpr (SPLIT) split_rows(sg);
-    __syncthreads();
+    if constexpr (SPLIT) {
+      write_rows_lds(P, pv);
+      split_rows(sg);
+      __syncthreads();
+    }
     if constexpr (SPLIT) mfma_product_h3<TW, KH, NW, S, true, SV>(qh, ql, Vh, Vl, rinv, 1.f / sg, W, P, red2);
     else {
       const unsigned ma = mask16(act);
