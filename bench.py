@@ -78,7 +78,7 @@ REF_TOL = 1e-9
 WARM_TRAIN = 200000
 WARM_EVAL = 32768
 WARM_TARGET_TOL = 3e-6
-WARM_EPOCHS = 60
+WARM_EPOCHS = 120  # (60: 46.7 mean updates on the held-out set, 120: 40.5, 200: 39.6)
 WARM_BATCH = 512
 WARM_LR = 1e-3
 WARM_LAMBDA = 1e-4
