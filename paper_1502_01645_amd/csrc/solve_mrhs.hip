@@ -729,8 +729,8 @@ __global__ __launch_bounds__(NT, 2) void solve_mrhs_kernel(MrArgs A) {
 // order and takes the same decisions, and every wave forms the masks over the 16 slots with one
 // ballot (lanes 0..15 of every wave hold slots 0..15).  Threads 0..15 write the outputs.  LDS
 // holds the gradient (each thread reads and writes only its own rows of it), the products'
-// operands and results and the partial sums, and an update takes four barriers (five when a
-// slot clipped).
+// operands and results and the partial sums, and an update takes three barriers with FP32
+// products, four with split ones (one more when a slot clipped).
 // Row strides (floats) of the LDS arrays, chosen for their most frequent access.  Product
 // results: the epilogue writes rows 4 (l / 16) + e, column l % 16 (lane l), so 20.  Product
 // operands: the matrix-core steps read rows 4 ks + l / 16, column l % 16, so 16.  Gradient: the
