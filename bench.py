@@ -36,27 +36,6 @@ PEAK_BF16X3_TFLOPS = PEAK_BF16_TFLOPS / 3.0   # three bf16 products per FP32-equ
 # dense matrix-core peak, the same 2516.6 TF as BF16) is measured beside it
 PEAK_F16X3_TFLOPS = PEAK_BF16_TFLOPS / 3.0
 MRHS_KERNEL = "solve_mrhs_reg_kernel"
-
-
-class mrhs_products:
-    """Context: the many-RHS solver's product form for the calls inside (the library reads
-    NNLS_MRHS_PRODUCT at each launch); None = the default FP32 products."""
-
-    def __init__(self, form):
-        self.form = form
-
-    def __enter__(self):
-        self.old = os.environ.get("NNLS_MRHS_PRODUCT")
-        if self.form is None:
-            os.environ.pop("NNLS_MRHS_PRODUCT", None)
-        else:
-            os.environ["NNLS_MRHS_PRODUCT"] = self.form
-
-    def __exit__(self, *exc):
-        if self.old is None:
-            os.environ.pop("NNLS_MRHS_PRODUCT", None)
-        else:
-            os.environ["NNLS_MRHS_PRODUCT"] = self.old
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_MFMA_TFLOPS = 157.3
 TOL = 1e-5
@@ -86,6 +65,27 @@ MLP_FWD_FLOP = 2.0 * (256 * 1024 + 1024 * 1024 + 1024 * 256)   # per sample
 
 
 CSRC = os.path.join(ROOT, "paper_1502_01645_amd", "csrc")
+
+
+class mrhs_products:
+    """Context: the many-RHS solver's product form for the calls inside (the library reads
+    NNLS_MRHS_PRODUCT at each launch); None = the default FP32 products."""
+
+    def __init__(self, form):
+        self.form = form
+
+    def __enter__(self):
+        self.old = os.environ.get("NNLS_MRHS_PRODUCT")
+        if self.form is None:
+            os.environ.pop("NNLS_MRHS_PRODUCT", None)
+        else:
+            os.environ["NNLS_MRHS_PRODUCT"] = self.form
+
+    def __exit__(self, *exc):
+        if self.old is None:
+            os.environ.pop("NNLS_MRHS_PRODUCT", None)
+        else:
+            os.environ["NNLS_MRHS_PRODUCT"] = self.old
 
 
 def _src_sha(src):
