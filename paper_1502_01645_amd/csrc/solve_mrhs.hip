@@ -27,6 +27,24 @@ namespace nnls {
 constexpr int MR_NT = 256;
 constexpr int MR_SLOTS = 16;
 
+// v[l] + v[l ^ 16] and v[l] + v[l ^ 32] for every lane l, on the vector ALU (the LDS crossbar of
+// a lane shuffle costs a round trip).  v_permlane16_swap_b32 exchanges the odd 16-lane rows of
+// its first register with the even rows of its second, v_permlane32_swap_b32 the upper 32 lanes
+// of its first with the lower 32 of its second: applied to two copies of v, the two registers
+// then hold the lower and the upper value of each lane's pair, and their sum is bitwise the same
+// in both lanes of the pair.  Every lane must be active.  (s_nop 1: the swap reads registers that
+// the instructions just before may have written.)
+__device__ __forceinline__ float add_xor16(float v) {
+  float a = v, b = v;
+  asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+  return a + b;
+}
+__device__ __forceinline__ float add_xor32(float v) {
+  float a = v, b = v;
+  asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+  return a + b;
+}
+
 // Line-search denominators from a product's epilogue: den_c = V_c^T W_c, summed per lane over
 // the output entries it writes (Vd[row][c] * W[row][c]), then over the four lanes of the wave
 // that share the slot; lanes 0..15 of each wave write the wave's partial to redw[wave][slot].
@@ -34,8 +52,7 @@ constexpr int MR_SLOTS = 16;
 // instantiated with DEN = false and leave redw alone.
 __device__ __forceinline__ void den_publish(float dp, float* redw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  dp += __shfl_xor(dp, 16, 64);
-  dp += __shfl_xor(dp, 32, 64);
+  dp = add_xor32(add_xor16(dp));
   // (the index is formed here each time rather than kept in a register through the solve)
   int at = wave * MR_SLOTS + lane;
   asm volatile("" : "+v"(at));
@@ -336,8 +353,7 @@ __device__ __forceinline__ void mfma_product_few(const float (&qa)[TW][KS], cons
     for (int tt = 0; tt < TW; ++tt) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        acc[tt][e] += __shfl_xor(acc[tt][e], 16, 64);
-        acc[tt][e] += __shfl_xor(acc[tt][e], 32, 64);
+        acc[tt][e] = add_xor32(add_xor16(acc[tt][e]));
       }
       // every lane group holds the sums: group g writes row 4 (l % 16 / 4) + g of the tile
       const float w = lg == 0 ? acc[tt][0] : lg == 1 ? acc[tt][1] : lg == 2 ? acc[tt][2] : acc[tt][3];
@@ -351,8 +367,7 @@ __device__ __forceinline__ void mfma_product_few(const float (&qa)[TW][KS], cons
       // the wave's partial for slot j of the pass: the 16 lanes with l % 4 == j
       dp += __shfl_xor(dp, 4, 64);
       dp += __shfl_xor(dp, 8, 64);
-      dp += __shfl_xor(dp, 16, 64);
-      dp += __shfl_xor(dp, 32, 64);
+      dp = add_xor32(add_xor16(dp));
       if (lane < 4 && slot >= 0) redw[wave * MR_SLOTS + slot] = dp;
     }
   }
@@ -470,13 +485,10 @@ __global__ __launch_bounds__(NT, 2) void solve_mrhs_kernel(MrArgs A) {
   auto slot_reduce4 = [&](float v0, float v1, float v2, float v3, float* o0, float* o1,
                           float* o2, float* o3, bool sync_after = true) {
     // lanes with equal (lane & 15) share a slot within a wave: xor 16, 32
-#pragma unroll
-    for (int off = 16; off < 64; off <<= 1) {
-      v0 += __shfl_xor(v0, off, 64);
-      v1 += __shfl_xor(v1, off, 64);
-      v2 += __shfl_xor(v2, off, 64);
-      v3 += __shfl_xor(v3, off, 64);
-    }
+    v0 = add_xor32(add_xor16(v0));
+    v1 = add_xor32(add_xor16(v1));
+    v2 = add_xor32(add_xor16(v2));
+    v3 = add_xor32(add_xor16(v3));
     if (lane < 16) {
       float* r = red + (wave * MR_SLOTS + lane) * 4;
       r[0] = v0;
@@ -865,8 +877,7 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
   };
   // the slot's sum of one value per thread (a barrier inside; red2 is free at every call)
   auto slot_sum1 = [&](float v) -> float {
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
+    v = add_xor32(add_xor16(v));
     if (lane < MR_SLOTS) red2[wave * MR_SLOTS + lane] = v;
     __syncthreads();
     float a = 0.f;
@@ -977,13 +988,10 @@ __global__ __launch_bounds__(NT, NT >= 384 ? 1 : 2) void solve_mrhs_reg_kernel(M
           t2 += pas ? 1.f : 0.f;
           t3 += (ok && (!__builtin_isfinite(yi) || !__builtin_isfinite(gi))) ? 1.f : 0.f;
         }
-#pragma unroll
-      for (int off = 16; off < 64; off <<= 1) {
-        t0 += __shfl_xor(t0, off, 64);
-        t1 += __shfl_xor(t1, off, 64);
-        t2 += __shfl_xor(t2, off, 64);
-        t3 += __shfl_xor(t3, off, 64);
-      }
+      t0 = add_xor32(add_xor16(t0));
+      t1 = add_xor32(add_xor16(t1));
+      t2 = add_xor32(add_xor16(t2));
+      t3 = add_xor32(add_xor16(t3));
       if (lane < MR_SLOTS) *(f32x4*)(red + (wave * MR_SLOTS + lane) * 4) = (f32x4){t0, t1, t2, t3};
       // FP32 products: the line-search operand goes to LDS before the statistics barrier, which
       // then also publishes it (a column that will not update has only its own result wasted)
