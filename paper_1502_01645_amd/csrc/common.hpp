@@ -31,6 +31,33 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// FP32 wave sum without the LDS crossbar: quad sums by DPP quad permutations, row sums by DPP row
+// rotations, the four rows by v_permlane16_swap_b32 / v_permlane32_swap_b32 (each exchanges half
+// of one register with half of another, so the sum of two swapped copies pairs lanes l and
+// l ^ 16, or l ^ 32), then lane 0's total broadcast, so every lane returns the same value.  Every
+// lane must be active.  (s_nop 1: the swaps read registers the instructions just before may
+// have written.)
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <>
+__device__ __forceinline__ float wave_sum<float>(float v) {
+  v += dpp_f32<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_f32<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f32<0x124>(v);  // row_ror 4
+  v += dpp_f32<0x128>(v);  // row_ror 8
+  float a = v, b = v;
+  asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+  v = a + b;
+  a = v;
+  b = v;
+  asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+  v = a + b;
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
 // Sum over the block; every thread gets the result.  `red` is LDS scratch of >= nwaves entries.
 // Contains two barriers.
 template <typename T, int NT>
